@@ -1,0 +1,304 @@
+/*
+ * rgs.h - C ABI of an MI355X (gfx950) tile-based 3D Gaussian Splatting renderer.
+ *
+ * The library renders one image of a scene of N 3D Gaussians (mean, rotation,
+ * scale, opacity, degree-3 spherical-harmonic colour) seen by a pinhole camera,
+ * with the tile-based forward pipeline of 3D Gaussian Splatting as analysed and
+ * accelerated in "RoofGS: Roofline-Guided End-to-End Acceleration of 3D
+ * Gaussian Splatting" (Sec. II-A, III, IV):
+ *   preprocess (EWA projection, frustum/opacity culling, SH colour)
+ *   -> duplicate one (key, index) entry per covered 16x16 tile
+ *   -> radix sort on the key -> per-tile ranges -> per-tile alpha blending.
+ *
+ * Two paths render the same image definition:
+ *   RGS_PATH_PLAIN  the 3DGS baseline: FP32 attributes, 64-bit (tile | FP32
+ *                   depth) key, exact exponential, one pixel per thread.
+ *   RGS_PATH_FAST   the paper's optimisations: INT8 SH with per-degree,
+ *                   per-channel scales and FP16 rotation/scale/opacity
+ *                   (Sec. IV-A, Eq. quant); 32-bit (tile | quantised depth)
+ *                   key with a resolution-adaptive bit split (Eq. depth_quant);
+ *                   preprocess, duplication and key generation fused in one
+ *                   kernel with opacity culling; coefficient folding,
+ *                   dual-pixel evaluation and the bit-level exponential in the
+ *                   rasterizer (Sec. IV-B, Eqs. coeff, dot, dual_pixel, fma_exp).
+ *
+ * Conventions shared by every call:
+ *   - every call returns an rgs_status; outputs are written only on RGS_OK;
+ *     nothing throws or aborts across the ABI; rgs_last_error() gives a
+ *     message for the calling thread's last failure;
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP
+ *     device memory of the context's device;
+ *   - GPU work is enqueued on the context's stream (a hipStream_t passed as
+ *     void*; NULL means the default stream) and is asynchronous unless a
+ *     call says it synchronises;
+ *   - camera space is OpenCV-like (x right, y down, z forward); pixel (i, j)
+ *     is sampled at image-plane position (i, j); images are float32 planar
+ *     [3][H][W].
+ */
+#ifndef RGS_H
+#define RGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rgs_status;
+#define RGS_OK            0
+#define RGS_E_INVALID    -1   /* bad argument; nothing was enqueued                        */
+#define RGS_E_OOM        -2   /* device or host allocation failed                          */
+#define RGS_E_HIP        -3   /* a HIP runtime call failed                                 */
+#define RGS_E_CAPACITY   -4   /* more duplicated entries than the workspace holds          */
+#define RGS_E_NODEVICE   -5   /* no usable GPU                                             */
+#define RGS_E_UNSUPPORTED -6  /* entry point or option not available in this build         */
+#define RGS_E_DEVICE     -7   /* a kernel reported an internal failure (bounded wait hit)  */
+
+#define RGS_ABI_VERSION 1
+
+#define RGS_FMT_PLAIN 1u      /* FP32 structure-of-arrays, 236 bytes per Gaussian          */
+#define RGS_FMT_FAST  2u      /* compact structure-of-arrays, 100 bytes per Gaussian       */
+
+#define RGS_PATH_PLAIN 0
+#define RGS_PATH_FAST  1
+
+#define RGS_TILE 16
+#define RGS_MAX_DIM 16384     /* largest accepted image width or height                    */
+#define RGS_MAX_ENTRIES ((1ull << 30) - 1) /* largest entry capacity of one frame        */
+
+/* Stages timed when a context has timing switched on (rgs_ctx_set_timing). */
+#define RGS_STAGE_FRONTEND  0 /* plain: preprocess; fast: fused front end                  */
+#define RGS_STAGE_DUPLICATE 1 /* plain: ordered duplication with keys; fast: unused (0)    */
+#define RGS_STAGE_SORT      2 /* digit histogram + radix passes                            */
+#define RGS_STAGE_RANGES    3 /* per-tile ranges                                           */
+#define RGS_STAGE_RASTER    4 /* per-tile blending                                         */
+#define RGS_N_STAGES        5
+
+typedef struct rgs_ctx rgs_ctx;
+typedef struct rgs_scene rgs_scene;
+
+/* ABI version of the loaded library (RGS_ABI_VERSION of its build). */
+int32_t rgs_abi_version(void);
+
+/* Message of the calling thread's last failed call ("" if none).  The string
+ * stays valid until that thread's next call into the library. */
+const char* rgs_last_error(void);
+
+/* Static name of a status code. */
+const char* rgs_status_string(rgs_status s);
+
+/* ---------------------------------------------------------------------------
+ * Frame plan (host-only arithmetic, usable without a GPU).
+ * Sec. IV-A, "Resolution-Adaptive Sorting-Key Encoding": N_t = T_x T_y tiles of
+ * 16x16 pixels; the 32-bit key gives the tile index b_t = max(1, ceil(log2 N_t))
+ * high bits and the quantised depth the b_d = 32 - b_t low bits.  The plain
+ * 64-bit key has 32 + b_t significant bits.
+ */
+typedef struct {
+    int32_t width, height;
+    int32_t tiles_x, tiles_y, n_tiles;
+    int32_t b_t, b_d;
+    int32_t plain_key_bits;   /* 32 + b_t                                      */
+    int32_t plain_passes;     /* ceil(plain_key_bits / 8) radix passes         */
+    int32_t fast_passes;      /* 4 radix passes of the 32-bit key              */
+} rgs_plan;
+
+/* W, H in [1, RGS_MAX_DIM]; otherwise RGS_E_INVALID. */
+rgs_status rgs_frame_plan(int32_t width, int32_t height, rgs_plan* out);
+
+/* ---------------------------------------------------------------------------
+ * Context: one device and one stream.  Create one per host thread.
+ */
+/* device: HIP ordinal; hip_stream: hipStream_t or NULL.  RGS_E_NODEVICE when
+ * no GPU is present (safe to call on a machine without one). */
+rgs_status rgs_ctx_create(int32_t device, void* hip_stream, rgs_ctx** out);
+/* Releases the context (scenes must be released first).  NULL is a no-op. */
+void rgs_ctx_destroy(rgs_ctx* ctx);
+/* Re-targets later work to another stream of the same device. */
+rgs_status rgs_ctx_set_stream(rgs_ctx* ctx, void* hip_stream);
+/* enable != 0: record HIP events around each stage of every render on the
+ * context's stream.  Switching it on clears the accumulated times. */
+rgs_status rgs_ctx_set_timing(rgs_ctx* ctx, int32_t enable);
+/* Synchronises the stream, then returns per-stage time summed over the
+ * renders recorded since timing was switched on (stage_ms[RGS_N_STAGES], ms)
+ * and the number of renders.  Clears the accumulators. */
+rgs_status rgs_ctx_collect_timing(rgs_ctx* ctx, double* stage_ms, int64_t* n_frames);
+
+/* ---------------------------------------------------------------------------
+ * Scene upload (once per scene, not per frame).
+ * Inputs are the activated parameters a trained 3DGS scene holds, all host
+ * float32, row-major; the library copies them and keeps its own device
+ * copies (structure-of-arrays, one plane per scalar attribute).
+ */
+typedef struct {
+    int64_t n;                /* number of Gaussians, >= 1                              */
+    int32_t sh_degree;        /* must be 3 (16 coefficients per channel)                */
+    int32_t reserved;         /* 0                                                      */
+    const float* means;       /* host [n][3]                                            */
+    const float* scales;      /* host [n][3], > 0 (already exp-activated)               */
+    const float* quats;       /* host [n][4] as (w, x, y, z), not all zero              */
+    const float* opacity;     /* host [n], in (0, 1] (already sigmoid-activated)        */
+    const float* sh;          /* host [n][16][3], coefficient l*l+l+m then RGB channel  */
+} rgs_scene_desc;
+
+/* formats: RGS_FMT_PLAIN and/or RGS_FMT_FAST.  The fast format is built on
+ * the host in float64 (Sec. IV-A, Eq. quant; see rgs_quantize_host) and then
+ * copied.  Synchronous.  Errors: RGS_E_INVALID for a non-finite value, a
+ * non-positive scale, a zero quaternion, opacity outside (0, 1], n < 1, a
+ * degree other than 3, or an SH block whose FP16 scale would overflow;
+ * RGS_E_OOM. */
+rgs_status rgs_scene_upload(rgs_ctx* ctx, const rgs_scene_desc* desc, uint32_t formats,
+                            rgs_scene** out);
+/* Frees the scene's device memory.  NULL is a no-op. */
+rgs_status rgs_scene_release(rgs_ctx* ctx, rgs_scene* scene);
+/* Number of Gaussians, formats held, and device bytes held by the scene. */
+rgs_status rgs_scene_info(const rgs_scene* scene, int64_t* n, uint32_t* formats,
+                          uint64_t* device_bytes);
+
+/* Compact storage of Sec. IV-A computed on the host (usable without a GPU):
+ *   quats_f16  [n][4]     FP16 bits, round-to-nearest-even of the FP32 input
+ *   scales_f16 [n][3]     FP16 bits
+ *   lnopa_f16  [n]        FP16 bits of ln(opacity) evaluated in float64
+ *   sh_q       [n][16][3] INT8, clamp(rint(sh / s), -127, 127), 0 when s = 0
+ *   sh_scale_f16 [n][4][3] FP16 bits of s = max |sh| / 127 over the coefficients
+ *                          of each degree, per Gaussian and channel (round to
+ *                          nearest even); q is taken against the stored s.
+ * All output arrays are caller-owned host memory. */
+typedef struct {
+    uint16_t* quats_f16;
+    uint16_t* scales_f16;
+    uint16_t* lnopa_f16;
+    int8_t* sh_q;
+    uint16_t* sh_scale_f16;
+} rgs_fast_host;
+rgs_status rgs_quantize_host(const rgs_scene_desc* desc, rgs_fast_host* out);
+
+/* ---------------------------------------------------------------------------
+ * Camera.  A world point p maps to camera space as R p + t (R row-major).
+ * fx, fy, cx, cy are pinhole intrinsics in pixels; tan_half_fov{x,y} bound the
+ * EWA Jacobian (3DGS clamps t_x/t_z to 1.3 tan(fovx/2)); [z_near, z_far] is
+ * the predefined depth interval: Gaussians outside (z_near, z_far] are culled
+ * and the fast key quantises depth over it (Eq. depth_quant).  bg is the
+ * background colour added with the final transmittance.
+ */
+typedef struct {
+    double R[9];
+    double t[3];
+    double fx, fy, cx, cy;
+    double tan_half_fovx, tan_half_fovy;
+    double z_near, z_far;
+    float bg[3];
+    float reserved;
+} rgs_camera;
+
+/* Per-frame statistics, filled when a non-NULL pointer is passed to render. */
+typedef struct {
+    int64_t n_gaussians;
+    int64_t n_visible;        /* Gaussians that survived culling                          */
+    int64_t n_entries;        /* duplicated (key, index) entries requested                */
+    int64_t capacity;         /* entries the workspace holds                              */
+    int32_t path;
+    int32_t passes;           /* radix passes run                                         */
+    int32_t overflow;         /* n_entries > capacity                                     */
+    int32_t device_error;     /* a bounded wait in a kernel gave up                        */
+} rgs_frame_stats;
+
+/* ---------------------------------------------------------------------------
+ * Workspace: caller-owned device memory that holds one frame's transients
+ * (per-Gaussian records, keys and indices, sort state, tile ranges, per-pixel
+ * final transmittance and pair counts).  Its size depends on N, W, H, the path
+ * and the entry capacity; render derives the capacity back from ws_bytes.
+ * Host-only arithmetic.  max_entries in [1, RGS_MAX_ENTRIES].
+ */
+rgs_status rgs_workspace_size(int64_t n_gaussians, int32_t width, int32_t height, int32_t path,
+                              int64_t max_entries, uint64_t* bytes);
+/* Entry capacity a workspace of ws_bytes provides (0 if too small). */
+rgs_status rgs_workspace_capacity(int64_t n_gaussians, int32_t width, int32_t height,
+                                  int32_t path, uint64_t ws_bytes, int64_t* capacity);
+
+/* ---------------------------------------------------------------------------
+ * Render one image (Sec. II-A, III, IV).
+ *   workspace  device, >= rgs_workspace_size(..., 1) bytes, 256-byte aligned,
+ *              not used by another render until this one has finished
+ *   out_chw    device float32 [3][H][W], caller-owned
+ *   stats      NULL: fully asynchronous.  Non-NULL: synchronises the stream,
+ *              fills *stats and returns RGS_E_CAPACITY when the frame needed
+ *              more entries than the workspace holds (the image is then
+ *              incomplete; retry with a larger workspace) or RGS_E_DEVICE.
+ * Without stats an overflow is still recorded in the workspace and reported by
+ * rgs_workspace_check.  Kernels never write past the workspace or the image.
+ * Errors: RGS_E_INVALID (W or H outside [1, RGS_MAX_DIM], z_near <= 0,
+ * z_near >= z_far, non-finite camera values, path not held by the scene,
+ * workspace too small or misaligned), RGS_E_HIP.
+ */
+rgs_status rgs_render(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
+                      int32_t width, int32_t height, int32_t path,
+                      void* workspace, uint64_t ws_bytes, float* out_chw,
+                      rgs_frame_stats* stats);
+
+/* Synchronises the stream and reports the last frame rendered into the
+ * workspace (its header sits at offset 0): RGS_E_CAPACITY on overflow,
+ * RGS_E_DEVICE on a kernel failure.  stats may be NULL; n_gaussians only fills
+ * stats->n_gaussians. */
+rgs_status rgs_workspace_check(rgs_ctx* ctx, const void* workspace, rgs_frame_stats* stats,
+                               int64_t n_gaussians);
+
+/* ---------------------------------------------------------------------------
+ * Parity access: render as rgs_render, then copy the frame's intermediates
+ * into caller-owned device buffers (any pointer may be NULL).  Synchronous.
+ *   per Gaussian [n]:  depth, u, v (float64); cov2d [n][3] (Sigma'_00,
+ *                      Sigma'_01, Sigma'_11, float64); rect [n][4] inclusive
+ *                      tile bounds x0,x1,y0,y1 (int32, zeros when culled);
+ *                      visible (uint8); color [n][3] (float32)
+ *   entries [entry_capacity]: keys in emission order and sorted (uint64; the
+ *                      fast path's 32-bit keys zero-extended), Gaussian index
+ *                      per entry (uint32)
+ *   ranges [n_tiles][2] (uint32 start, end); T_final, n_proc [H][W]
+ * RGS_E_CAPACITY if entry_capacity is smaller than the frame's entry count.
+ */
+typedef struct {
+    double* depth;
+    double* u;
+    double* v;
+    double* cov2d;
+    int32_t* rect;
+    uint8_t* visible;
+    float* color;
+    uint64_t* keys_unsorted;
+    uint32_t* vals_unsorted;
+    uint64_t* keys_sorted;
+    uint32_t* vals_sorted;
+    int64_t entry_capacity;
+    uint32_t* ranges;
+    float* T_final;
+    uint32_t* n_proc;
+} rgs_debug_out;
+
+rgs_status rgs_render_debug(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
+                            int32_t width, int32_t height, int32_t path,
+                            void* workspace, uint64_t ws_bytes, float* out_chw,
+                            rgs_debug_out* dbg, rgs_frame_stats* stats);
+
+/* ---------------------------------------------------------------------------
+ * Gradients of a loss with respect to the activated scene parameters
+ * (means, scales, quats, opacity, sh) given dL/d(image).  Not part of the
+ * paper, which renders only (Sec. V names training as future work).
+ * Reserved: returns RGS_E_UNSUPPORTED in this build.
+ */
+typedef struct {
+    float* d_means;   /* device [n][3]     */
+    float* d_scales;  /* device [n][3]     */
+    float* d_quats;   /* device [n][4]     */
+    float* d_opacity; /* device [n]        */
+    float* d_sh;      /* device [n][16][3] */
+} rgs_grads;
+
+rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
+                               int32_t width, int32_t height, const float* dL_dimg,
+                               void* workspace, uint64_t ws_bytes, rgs_grads* grads);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RGS_H */

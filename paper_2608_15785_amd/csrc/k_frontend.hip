@@ -1,0 +1,439 @@
+// Front-end kernels: per-Gaussian preprocess, ordered duplication with keys,
+// and the fused fast front end.
+//
+// Plain path (the 3DGS baseline, Sec. III-A/B): `preprocess_plain` projects,
+// culls and colours every Gaussian and writes its record, tile rectangle,
+// depth and tile count to global memory; `duplicate_plain` reads them back,
+// scans the counts and emits one (64-bit key, index) entry per covered tile.
+//
+// Fast path (Sec. IV-A, "Preprocessing Kernel Fusion"): `frontend_fast` does
+// all of it in one pass over the compact attributes.  Each thread projects one
+// Gaussian and keeps its rectangle and quantised depth on chip; the block
+// computes a prefix sum of the tile counts in LDS and obtains its global
+// offset with one ticket atomic and a decoupled look-back over earlier blocks,
+// which keeps allocation in Gaussian-index order (a plain atomic per block
+// would make the order, and with it the tie order of equal keys,
+// nondeterministic).  The block's entries are then written cooperatively:
+// consecutive threads write consecutive entries, whatever the per-Gaussian
+// tile counts, so a large Gaussian does not stall its wave and the stores are
+// coalesced.  Only the records of visible Gaussians and the key/index arrays
+// reach global memory.
+#include "rgs_internal.h"
+
+namespace rgs {
+
+// ---------------------------------------------------------------------------
+// Spherical harmonics, degree 3, real basis with the Condon-Shortley phase
+// (index l*l + l + m), evaluated in float32 (Sec. III-A: SH colour).
+
+struct ShBasis { float y[16]; };
+
+__device__ inline ShBasis sh_basis(float x, float y, float z) {
+    ShBasis b;
+    const float C0 = 0.28209479177387814f;
+    const float C1 = 0.4886025119029199f;
+    const float C2a = 1.0925484305920792f, C2b = 0.31539156525252005f, C2c = 0.5462742152960396f;
+    const float C3a = 0.5900435899266435f, C3b = 2.890611442640554f, C3c = 0.4570457994644658f;
+    const float C3d = 0.3731763325901154f, C3e = 1.445305721320277f;
+    float xx = x * x, yy = y * y, zz = z * z;
+    b.y[0] = C0;
+    b.y[1] = -C1 * y;
+    b.y[2] = C1 * z;
+    b.y[3] = -C1 * x;
+    b.y[4] = C2a * x * y;
+    b.y[5] = -C2a * y * z;
+    b.y[6] = C2b * (2.0f * zz - xx - yy);
+    b.y[7] = -C2a * x * z;
+    b.y[8] = C2c * (xx - yy);
+    b.y[9] = -C3a * y * (3.0f * xx - yy);
+    b.y[10] = C3b * x * y * z;
+    b.y[11] = -C3c * y * (4.0f * zz - xx - yy);
+    b.y[12] = C3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    b.y[13] = -C3c * x * (4.0f * zz - xx - yy);
+    b.y[14] = C3e * z * (xx - yy);
+    b.y[15] = -C3a * x * (xx - 3.0f * yy);
+    return b;
+}
+
+__device__ inline ShBasis view_basis(float mx, float my, float mz, const CamDev& cam) {
+    float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
+    float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    return sh_basis(dx * inv, dy * inv, dz * inv);
+}
+
+__device__ inline float half_lo(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+}
+__device__ inline float half_hi(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
+
+__device__ inline uint64_t pack_rect(const Projected& p) {
+    return (uint64_t)(uint32_t)p.x0 | ((uint64_t)(uint32_t)p.x1 << 16) |
+           ((uint64_t)(uint32_t)p.y0 << 32) | ((uint64_t)(uint32_t)p.y1 << 48);
+}
+
+__device__ inline uint32_t rect_count(uint64_t rc) {
+    uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff, y1 = rc >> 48;
+    return (x1 - x0 + 1) * (y1 - y0 + 1);
+}
+
+__device__ inline void write_record(Record* rec, const Projected& p, float opa, float r, float g,
+                                    float b) {
+    float uh = (float)p.u, vh = (float)p.v;
+    float4 a = make_float4(uh, (float)(p.u - (double)uh), vh, (float)(p.v - (double)vh));
+    float4 m = make_float4((float)(p.c11 / p.det), (float)(-p.c01 / p.det), (float)(p.c00 / p.det), opa);
+    float4 c = make_float4(r, g, b, (float)p.d);
+    float4* dst = reinterpret_cast<float4*>(rec);
+    dst[0] = a;
+    dst[1] = m;
+    dst[2] = c;
+}
+
+__device__ inline void write_debug(const DebugDev& dbg, int64_t i, const Projected& p, bool vis,
+                                   float r, float g, float b) {
+    if (dbg.depth) dbg.depth[i] = p.d;
+    if (dbg.u) dbg.u[i] = vis ? p.u : 0.0;
+    if (dbg.v) dbg.v[i] = vis ? p.v : 0.0;
+    if (dbg.cov2d) {
+        dbg.cov2d[3 * i + 0] = vis ? p.c00 : 0.0;
+        dbg.cov2d[3 * i + 1] = vis ? p.c01 : 0.0;
+        dbg.cov2d[3 * i + 2] = vis ? p.c11 : 0.0;
+    }
+    if (dbg.rect) {
+        dbg.rect[4 * i + 0] = vis ? (int32_t)p.x0 : 0;
+        dbg.rect[4 * i + 1] = vis ? (int32_t)p.x1 : 0;
+        dbg.rect[4 * i + 2] = vis ? (int32_t)p.y0 : 0;
+        dbg.rect[4 * i + 3] = vis ? (int32_t)p.y1 : 0;
+    }
+    if (dbg.visible) dbg.visible[i] = vis ? 1 : 0;
+    if (dbg.color) {
+        dbg.color[3 * i + 0] = vis ? r : 0.0f;
+        dbg.color[3 * i + 1] = vis ? g : 0.0f;
+        dbg.color[3 * i + 2] = vis ? b : 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Frame reset: zero the header, the tile ranges and the front-end scan state.
+
+__global__ void k_reset(uint32_t* base, uint64_t n_words, uint32_t capacity, uint32_t path,
+                        uint32_t passes) {
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride) {
+        uint32_t v = 0;
+        if (i == offsetof(WsHeader, capacity) / 4) v = capacity;
+        if (i == offsetof(WsHeader, path) / 4) v = path;
+        if (i == offsetof(WsHeader, passes) / 4) v = passes;
+        base[i] = v;
+    }
+}
+
+void launch_reset(hipStream_t s, const WsDev& ws, uint64_t zero_bytes, const FrameDev& f,
+                  uint32_t path) {
+    uint64_t words = zero_bytes / 4;
+    uint32_t blocks = (uint32_t)((words + 255) / 256);
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, s, reinterpret_cast<uint32_t*>(ws.header),
+                       words, f.capacity, path, (uint32_t)f.passes);
+}
+
+// ---------------------------------------------------------------------------
+// Chained scan across blocks (decoupled look-back, one wave).  Block vb
+// publishes its aggregate, then sums predecessors' aggregates until it meets
+// an inclusive prefix; blocks take vb from a ticket counter, so every block
+// waits only on blocks that are already running.
+
+__device__ uint64_t chained_exclusive(uint64_t* states, uint32_t vb, uint64_t aggregate,
+                                      WsHeader* hdr) {
+    uint32_t lane = lane_id();
+    if (vb == 0) {
+        if (lane == 0) st_state(&states[0], ST_PRE | aggregate);
+        return 0;
+    }
+    if (lane == 0) st_state(&states[vb], ST_AGG | aggregate);
+    uint64_t excl = 0;
+    int64_t top = (int64_t)vb - 1;
+    uint32_t spins = 0;
+    uint64_t my_bit = 1ull << lane;
+    while (true) {
+        int64_t idx = top - (int64_t)lane;
+        uint64_t s = idx >= 0 ? ld_state(&states[idx]) : ST_PRE;
+        uint64_t flag = s & ~ST_VAL;
+        uint64_t pre = __ballot(flag == ST_PRE);
+        uint64_t none = __ballot(flag == 0);
+        // lanes up to and including the nearest inclusive prefix (all lanes if none)
+        uint64_t upto = pre ? ((pre & (~pre + 1)) << 1) - 1 : ~0ull;
+        if (none & upto) {
+            if (++spins > SPIN_LIMIT) {
+                if (lane == 0) atomicOr(&hdr->error, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        uint64_t v = (my_bit & upto) ? (s & ST_VAL) : 0ull;
+        excl += wave_sum(v);
+        if (pre) break;
+        top -= 64;
+    }
+    if (lane == 0) st_state(&states[vb], ST_PRE | (excl + aggregate));
+    return excl;
+}
+
+// Block-wide inclusive scan of one count per thread (FE_BLOCK threads), then
+// the block's global base by chained scan.  Leaves s_incl[t] = inclusive
+// prefix of thread t and returns the block total.
+__device__ inline uint32_t block_scan_and_chain(uint32_t count, uint32_t vb, WsDev& ws,
+                                                uint32_t* s_incl, uint32_t* s_wtot,
+                                                uint64_t* s_base) {
+    uint32_t lane = lane_id();
+    uint32_t wave = threadIdx.x / 64;
+    uint32_t incl = wave_inclusive_scan(count);
+    if (lane == 63) s_wtot[wave] = incl;
+    __syncthreads();
+    uint32_t total = 0, before = 0;
+#pragma unroll
+    for (int w = 0; w < FE_BLOCK / 64; ++w) {
+        uint32_t t = s_wtot[w];
+        if ((uint32_t)w < wave) before += t;
+        total += t;
+    }
+    s_incl[threadIdx.x] = incl + before;
+    if (wave == 0) {
+        uint64_t excl = chained_exclusive(ws.fe_state, vb, total, ws.header);
+        if (lane == 0) *s_base = excl;
+    }
+    __syncthreads();
+    return total;
+}
+
+// Entry e of the block belongs to the thread t with s_incl[t-1] <= e < s_incl[t]
+// and is the (e - s_incl[t-1])-th tile of t's rectangle in row-major order.
+template <typename KeyT, typename KeyFn>
+__device__ inline void emit_entries(uint32_t total, uint64_t base, const uint32_t* s_incl,
+                                    const uint64_t* s_rect, uint32_t first_gauss, int tiles_x,
+                                    uint32_t capacity, KeyT* keys, uint32_t* vals, KeyFn key_of) {
+    for (uint32_t e = threadIdx.x; e < total; e += FE_BLOCK) {
+        int lo = 0, hi = FE_BLOCK - 1;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (s_incl[mid] > e) hi = mid;
+            else lo = mid + 1;
+        }
+        uint32_t t = (uint32_t)lo;
+        uint32_t local = e - (t ? s_incl[t - 1] : 0u);
+        uint64_t rc = s_rect[t];
+        uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff;
+        uint32_t w = x1 - x0 + 1;
+        uint32_t ty = y0 + local / w;
+        uint32_t tx = x0 + local % w;
+        uint32_t tile = ty * (uint32_t)tiles_x + tx;
+        uint64_t pos = base + e;
+        if (pos < capacity) {
+            keys[pos] = key_of(tile, t);
+            vals[pos] = first_gauss + t;
+        }
+    }
+}
+
+__device__ inline void finish_block(WsDev& ws, uint32_t vb, uint32_t n_blocks, uint64_t base,
+                                    uint32_t total, uint32_t capacity, uint32_t visible) {
+    uint32_t lane = lane_id();
+    uint32_t vis = wave_sum(visible);
+    if (lane == 0 && vis) atomicAdd(&ws.header->n_visible, vis);
+    if (vb == n_blocks - 1 && threadIdx.x == 0) {
+        uint64_t n = base + total;
+        ws.header->n_entries = n;
+        ws.header->overflow = n > capacity ? 1u : 0u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Plain preprocess: one thread per Gaussian over the FP32 planes.
+
+template <bool DEBUG>
+__global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, CamDev cam, FrameDev f,
+                                                          WsDev ws, DebugDev dbg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool in = i < sc.n;
+    bool vis = false;
+    if (in) {
+        const float* P = sc.base;
+        const uint64_t np = sc.n_pad;
+        float mx = P[P_MX * np + i], my = P[P_MY * np + i], mz = P[P_MZ * np + i];
+        Projected pr;
+        vis = project_gaussian(cam, mx, my, mz, P[P_QW * np + i], P[P_QX * np + i],
+                               P[P_QY * np + i], P[P_QZ * np + i], P[P_SX * np + i],
+                               P[P_SY * np + i], P[P_SZ * np + i], false, 0.0,
+                               (double)f.tiles_x, (double)f.tiles_y, pr);
+        float r = 0.f, g = 0.f, b = 0.f;
+        if (vis) {
+            ShBasis y = view_basis(mx, my, mz, cam);
+            float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch)
+                    acc[ch] = fmaf(y.y[k], P[(P_SH0 + 3 * k + ch) * np + i], acc[ch]);
+            r = fmaxf(acc[0], 0.f);
+            g = fmaxf(acc[1], 0.f);
+            b = fmaxf(acc[2], 0.f);
+            write_record(&ws.records[i], pr, P[P_OPA * np + i], r, g, b);
+            uint64_t rc = pack_rect(pr);
+            ws.rects[i] = rc;
+            ws.depths[i] = (float)pr.d;
+            ws.counts[i] = rect_count(rc);
+        } else {
+            ws.counts[i] = 0;
+        }
+        if (DEBUG) write_debug(dbg, i, pr, vis, r, g, b);
+    }
+    uint32_t vcount = wave_sum(vis ? 1u : 0u);
+    if (lane_id() == 0 && vcount) atomicAdd(&ws.header->n_visible, vcount);
+}
+
+void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam,
+                             const FrameDev& f, const WsDev& ws, const DebugDev* dbg) {
+    uint32_t blocks = (uint32_t)((sc.n + 255) / 256);
+    if (dbg)
+        hipLaunchKernelGGL(k_preprocess_plain<true>, dim3(blocks), dim3(256), 0, s, sc, cam, f, ws, *dbg);
+    else
+        hipLaunchKernelGGL(k_preprocess_plain<false>, dim3(blocks), dim3(256), 0, s, sc, cam, f, ws,
+                           DebugDev{});
+}
+
+// ---------------------------------------------------------------------------
+// Plain duplication: ordered allocation over the stored counts, 64-bit keys.
+
+__global__ __launch_bounds__(FE_BLOCK) void k_duplicate_plain(int64_t n, FrameDev f, WsDev ws,
+                                                              uint32_t n_blocks) {
+    __shared__ uint32_t s_vb;
+    __shared__ uint32_t s_incl[FE_BLOCK];
+    __shared__ uint64_t s_rect[FE_BLOCK];
+    __shared__ uint32_t s_dbits[FE_BLOCK];
+    __shared__ uint32_t s_wtot[FE_BLOCK / 64];
+    __shared__ uint64_t s_base;
+    if (threadIdx.x == 0) s_vb = atomicAdd(&ws.header->fe_ticket, 1u);
+    __syncthreads();
+    uint32_t vb = s_vb;
+    int64_t i = (int64_t)vb * FE_BLOCK + threadIdx.x;
+    uint32_t count = 0;
+    if (i < n) {
+        count = ws.counts[i];
+        if (count) {
+            s_rect[threadIdx.x] = ws.rects[i];
+            s_dbits[threadIdx.x] = __float_as_uint(ws.depths[i]);
+        }
+    }
+    uint32_t total = block_scan_and_chain(count, vb, ws, s_incl, s_wtot, &s_base);
+    uint64_t base = s_base;
+    uint64_t* keys = reinterpret_cast<uint64_t*>(ws.keys_a);
+    emit_entries<uint64_t>(total, base, s_incl, s_rect, vb * FE_BLOCK, f.tiles_x, f.capacity, keys,
+                           ws.vals_a, [&](uint32_t tile, uint32_t t) {
+                               return ((uint64_t)tile << 32) | (uint64_t)s_dbits[t];
+                           });
+    finish_block(ws, vb, n_blocks, base, total, f.capacity, 0u);
+}
+
+void launch_duplicate_plain(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws,
+                            uint32_t fe_blocks) {
+    hipLaunchKernelGGL(k_duplicate_plain, dim3(fe_blocks), dim3(FE_BLOCK), 0, s, n, f, ws, fe_blocks);
+}
+
+// ---------------------------------------------------------------------------
+// Fused fast front end over the compact planes: project, cull, colour, scan,
+// allocate in order and emit 32-bit (tile << b_d | q_d) keys.
+
+template <bool DEBUG>
+__global__ __launch_bounds__(FE_BLOCK) void k_frontend_fast(FastSceneDev sc, CamDev cam, FrameDev f,
+                                                            WsDev ws, uint32_t n_blocks,
+                                                            DebugDev dbg) {
+    __shared__ uint32_t s_vb;
+    __shared__ uint32_t s_incl[FE_BLOCK];
+    __shared__ uint64_t s_rect[FE_BLOCK];
+    __shared__ uint32_t s_qd[FE_BLOCK];
+    __shared__ uint32_t s_wtot[FE_BLOCK / 64];
+    __shared__ uint64_t s_base;
+    if (threadIdx.x == 0) s_vb = atomicAdd(&ws.header->fe_ticket, 1u);
+    __syncthreads();
+    uint32_t vb = s_vb;
+    int64_t i = (int64_t)vb * FE_BLOCK + threadIdx.x;
+    uint32_t count = 0;
+    bool vis = false;
+    if (i < sc.n) {
+        const uint32_t* W = sc.base;
+        const uint64_t np = sc.n_pad;
+        float mx = __uint_as_float(W[F_MX * np + i]);
+        float my = __uint_as_float(W[F_MY * np + i]);
+        float mz = __uint_as_float(W[F_MZ * np + i]);
+        uint32_t qwx = W[F_QWX * np + i], qyz = W[F_QYZ * np + i];
+        uint32_t sxy = W[F_SXY * np + i], szl = W[F_SZL * np + i];
+        float lno = half_hi(szl);
+        Projected pr;
+        vis = project_gaussian(cam, mx, my, mz, half_lo(qwx), half_hi(qwx), half_lo(qyz),
+                               half_hi(qyz), half_lo(sxy), half_hi(sxy), half_lo(szl), true,
+                               (double)lno, (double)f.tiles_x, (double)f.tiles_y, pr);
+        float r = 0.f, g = 0.f, b = 0.f;
+        if (vis) {
+            uint32_t qw[12], sw[6];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) qw[k] = W[(F_SHQ0 + k) * np + i];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sw[k] = W[(F_SHS0 + k) * np + i];
+            ShBasis y = view_basis(mx, my, mz, cam);
+            float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int deg = k == 0 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3));
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const int v = 3 * k + ch;
+                    float q = (float)(int8_t)((qw[v >> 2] >> (8 * (v & 3))) & 0xffu);
+                    const int si = 3 * deg + ch;
+                    float sc_ = (si & 1) ? half_hi(sw[si >> 1]) : half_lo(sw[si >> 1]);
+                    acc[ch] = fmaf(y.y[k], q * sc_, acc[ch]);
+                }
+            }
+            r = fmaxf(acc[0], 0.f);
+            g = fmaxf(acc[1], 0.f);
+            b = fmaxf(acc[2], 0.f);
+            write_record(&ws.records[i], pr, lno, r, g, b);
+            uint64_t rc = pack_rect(pr);
+            s_rect[threadIdx.x] = rc;
+            s_qd[threadIdx.x] = quantize_depth(pr.d, cam.zn, cam.zf, f.b_d);
+            count = rect_count(rc);
+        }
+        if (DEBUG) write_debug(dbg, i, pr, vis, r, g, b);
+    }
+    uint32_t total = block_scan_and_chain(count, vb, ws, s_incl, s_wtot, &s_base);
+    uint64_t base = s_base;
+    const int bd = f.b_d;
+    emit_entries<uint32_t>(total, base, s_incl, s_rect, vb * FE_BLOCK, f.tiles_x, f.capacity,
+                           reinterpret_cast<uint32_t*>(ws.keys_a), ws.vals_a,
+                           [&](uint32_t tile, uint32_t t) { return (tile << bd) | s_qd[t]; });
+    finish_block(ws, vb, n_blocks, base, total, f.capacity, vis ? 1u : 0u);
+}
+
+void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const CamDev& cam,
+                          const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
+                          const DebugDev* dbg) {
+    if (dbg)
+        hipLaunchKernelGGL(k_frontend_fast<true>, dim3(fe_blocks), dim3(FE_BLOCK), 0, s, sc, cam, f, ws,
+                           fe_blocks, *dbg);
+    else
+        hipLaunchKernelGGL(k_frontend_fast<false>, dim3(fe_blocks), dim3(FE_BLOCK), 0, s, sc, cam, f,
+                           ws, fe_blocks, DebugDev{});
+}
+
+__global__ void k_widen_keys(const uint32_t* in, uint64_t* out, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i];
+}
+
+void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(k_widen_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, in, out, n);
+}
+
+}  // namespace rgs

@@ -1,0 +1,776 @@
+// Host side of the C ABI declared in rgs.h: argument checks, the compact-storage
+// quantiser, scene upload, workspace layout and the per-frame kernel sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rgs.h"
+#include "rgs_internal.h"
+
+using namespace rgs;
+
+// ---------------------------------------------------------------------------
+// Errors
+
+static thread_local std::string g_last_error;
+
+static rgs_status fail(rgs_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+static rgs_status ok() {
+    g_last_error.clear();
+    return RGS_OK;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? RGS_E_OOM : RGS_E_HIP, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                             \
+    } while (0)
+
+extern "C" int32_t rgs_abi_version(void) { return RGS_ABI_VERSION; }
+
+extern "C" const char* rgs_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* rgs_status_string(rgs_status s) {
+    switch (s) {
+        case RGS_OK: return "RGS_OK";
+        case RGS_E_INVALID: return "RGS_E_INVALID";
+        case RGS_E_OOM: return "RGS_E_OOM";
+        case RGS_E_HIP: return "RGS_E_HIP";
+        case RGS_E_CAPACITY: return "RGS_E_CAPACITY";
+        case RGS_E_NODEVICE: return "RGS_E_NODEVICE";
+        case RGS_E_UNSUPPORTED: return "RGS_E_UNSUPPORTED";
+        case RGS_E_DEVICE: return "RGS_E_DEVICE";
+        default: return "RGS_E_UNKNOWN";
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Frame plan (Sec. IV-A, Resolution-Adaptive Sorting-Key Encoding)
+
+static int ceil_log2(uint32_t n) {
+    int b = 0;
+    while ((1ull << b) < n) ++b;
+    return b;
+}
+
+extern "C" rgs_status rgs_frame_plan(int32_t width, int32_t height, rgs_plan* out) {
+    if (!out) return fail(RGS_E_INVALID, "rgs_frame_plan: out is NULL");
+    if (width < 1 || height < 1 || width > RGS_MAX_DIM || height > RGS_MAX_DIM)
+        return fail(RGS_E_INVALID, "rgs_frame_plan: image %dx%d outside [1, %d]", width, height,
+                    RGS_MAX_DIM);
+    rgs_plan p;
+    p.width = width;
+    p.height = height;
+    p.tiles_x = (width + TILE - 1) / TILE;
+    p.tiles_y = (height + TILE - 1) / TILE;
+    p.n_tiles = p.tiles_x * p.tiles_y;
+    p.b_t = std::max(1, ceil_log2((uint32_t)p.n_tiles));
+    p.b_d = 32 - p.b_t;
+    p.plain_key_bits = 32 + p.b_t;
+    p.plain_passes = (p.plain_key_bits + RADIX_BITS - 1) / RADIX_BITS;
+    p.fast_passes = 32 / RADIX_BITS;
+    *out = p;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Compact storage (Sec. IV-A, Compact Attribute Storage, Eq. quant)
+
+// float64 -> binary16, round to nearest even, with subnormals and overflow to inf.
+static uint16_t to_half(double x) {
+    uint16_t sign = std::signbit(x) ? 0x8000 : 0;
+    double ax = std::fabs(x);
+    if (std::isnan(x)) return sign | 0x7e00;
+    if (ax == 0.0) return sign;
+    int e2;
+    std::frexp(ax, &e2);              // ax = m 2^e2, m in [0.5, 1): leading bit at 2^(e2-1)
+    int E = std::max(e2 - 1, -14);
+    double units = std::nearbyint(std::ldexp(ax, 10 - E));   // ax in units of 2^(E-10)
+    uint32_t mant = (uint32_t)units;
+    if (mant >= 2048) {               // rounded up to the next binade
+        mant >>= 1;
+        E += 1;
+    }
+    if (mant < 1024) return sign | (uint16_t)mant;           // subnormal (E == -14)
+    if (E > 15) return sign | 0x7c00;                        // overflow
+    return sign | (uint16_t)(((E + 15) << 10) | (mant - 1024));
+}
+
+static double from_half(uint16_t h) {
+    int e = (h >> 10) & 0x1f;
+    int m = h & 0x3ff;
+    double v;
+    if (e == 0) v = std::ldexp((double)m, -24);
+    else if (e == 31) v = m ? NAN : INFINITY;
+    else v = std::ldexp((double)(m + 1024), e - 25);
+    return (h & 0x8000) ? -v : v;
+}
+
+static const int kDegreeStart[5] = {0, 1, 4, 9, 16};
+
+static rgs_status validate_desc(const rgs_scene_desc* d) {
+    if (!d) return fail(RGS_E_INVALID, "scene desc is NULL");
+    if (d->n < 1) return fail(RGS_E_INVALID, "scene has n = %lld < 1", (long long)d->n);
+    if (d->n > (int64_t)0x7fffffff) return fail(RGS_E_INVALID, "scene too large");
+    if (d->sh_degree != 3) return fail(RGS_E_INVALID, "sh_degree %d != 3", d->sh_degree);
+    if (!d->means || !d->scales || !d->quats || !d->opacity || !d->sh)
+        return fail(RGS_E_INVALID, "scene desc has a NULL array");
+    const int64_t n = d->n;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < 3; ++k) {
+            if (!std::isfinite(d->means[3 * i + k]))
+                return fail(RGS_E_INVALID, "mean %lld is not finite", (long long)i);
+            float s = d->scales[3 * i + k];
+            if (!std::isfinite(s) || !(s > 0.0f))
+                return fail(RGS_E_INVALID, "scale %lld is not finite and positive", (long long)i);
+        }
+        bool nonzero = false;
+        for (int k = 0; k < 4; ++k) {
+            float q = d->quats[4 * i + k];
+            if (!std::isfinite(q)) return fail(RGS_E_INVALID, "quaternion %lld not finite", (long long)i);
+            nonzero |= q != 0.0f;
+        }
+        if (!nonzero) return fail(RGS_E_INVALID, "quaternion %lld is zero", (long long)i);
+        float o = d->opacity[i];
+        if (!(o > 0.0f && o <= 1.0f))
+            return fail(RGS_E_INVALID, "opacity %lld = %g outside (0, 1]", (long long)i, (double)o);
+        for (int k = 0; k < 48; ++k)
+            if (!std::isfinite(d->sh[48 * i + k]))
+                return fail(RGS_E_INVALID, "SH of %lld not finite", (long long)i);
+    }
+    return RGS_OK;
+}
+
+static rgs_status quantize_into(const rgs_scene_desc* d, rgs_fast_host* o) {
+    const int64_t n = d->n;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int k = 0; k < 4; ++k) o->quats_f16[4 * i + k] = to_half((double)d->quats[4 * i + k]);
+        for (int k = 0; k < 3; ++k) {
+            uint16_t h = to_half((double)d->scales[3 * i + k]);
+            if ((h & 0x7c00) == 0x7c00)
+                return fail(RGS_E_INVALID, "scale of %lld overflows FP16", (long long)i);
+            o->scales_f16[3 * i + k] = h;
+        }
+        o->lnopa_f16[i] = to_half(std::log((double)d->opacity[i]));
+        const float* sh = d->sh + 48 * i;
+        for (int deg = 0; deg < 4; ++deg) {
+            for (int c = 0; c < 3; ++c) {
+                double m = 0.0;
+                for (int k = kDegreeStart[deg]; k < kDegreeStart[deg + 1]; ++k)
+                    m = std::max(m, std::fabs((double)sh[3 * k + c]));
+                uint16_t sh16 = to_half(m / 127.0);
+                if ((sh16 & 0x7c00) == 0x7c00)
+                    return fail(RGS_E_INVALID, "SH scale of %lld overflows FP16", (long long)i);
+                o->sh_scale_f16[12 * i + 3 * deg + c] = sh16;
+                double s = from_half(sh16);
+                for (int k = kDegreeStart[deg]; k < kDegreeStart[deg + 1]; ++k) {
+                    double q = s > 0.0 ? std::nearbyint((double)sh[3 * k + c] / s) : 0.0;
+                    q = std::min(127.0, std::max(-127.0, q));
+                    o->sh_q[48 * i + 3 * k + c] = (int8_t)q;
+                }
+            }
+        }
+    }
+    return RGS_OK;
+}
+
+extern "C" rgs_status rgs_quantize_host(const rgs_scene_desc* desc, rgs_fast_host* out) {
+    rgs_status s = validate_desc(desc);
+    if (s != RGS_OK) return s;
+    if (!out || !out->quats_f16 || !out->scales_f16 || !out->lnopa_f16 || !out->sh_q ||
+        !out->sh_scale_f16)
+        return fail(RGS_E_INVALID, "rgs_quantize_host: NULL output array");
+    s = quantize_into(desc, out);
+    return s == RGS_OK ? ok() : s;
+}
+
+// ---------------------------------------------------------------------------
+// Context
+
+struct FrameEvents {
+    hipEvent_t ev[RGS_N_STAGES + 1];
+};
+
+struct rgs_ctx {
+    int device;
+    hipStream_t stream;
+    bool timing;
+    std::vector<FrameEvents> events;
+    size_t events_used;
+    double stage_ms[RGS_N_STAGES];
+    int64_t frames;
+};
+
+extern "C" rgs_status rgs_ctx_create(int32_t device, void* hip_stream, rgs_ctx** out) {
+    if (!out) return fail(RGS_E_INVALID, "rgs_ctx_create: out is NULL");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+        return fail(RGS_E_NODEVICE, "no HIP device available");
+    if (device < 0 || device >= count)
+        return fail(RGS_E_INVALID, "device %d outside [0, %d)", device, count);
+    HIP_TRY(hipSetDevice(device));
+    rgs_ctx* c = new rgs_ctx();
+    c->device = device;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->timing = false;
+    c->events_used = 0;
+    std::fill(c->stage_ms, c->stage_ms + RGS_N_STAGES, 0.0);
+    c->frames = 0;
+    *out = c;
+    return ok();
+}
+
+extern "C" void rgs_ctx_destroy(rgs_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    for (auto& fe : ctx->events)
+        for (auto& e : fe.ev) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+extern "C" rgs_status rgs_ctx_set_stream(rgs_ctx* ctx, void* hip_stream) {
+    if (!ctx) return fail(RGS_E_INVALID, "ctx is NULL");
+    ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return ok();
+}
+
+extern "C" rgs_status rgs_ctx_set_timing(rgs_ctx* ctx, int32_t enable) {
+    if (!ctx) return fail(RGS_E_INVALID, "ctx is NULL");
+    ctx->timing = enable != 0;
+    ctx->events_used = 0;
+    std::fill(ctx->stage_ms, ctx->stage_ms + RGS_N_STAGES, 0.0);
+    ctx->frames = 0;
+    return ok();
+}
+
+static rgs_status harvest_events(rgs_ctx* ctx) {
+    if (ctx->events_used == 0) return RGS_OK;
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    for (size_t f = 0; f < ctx->events_used; ++f) {
+        for (int s = 0; s < RGS_N_STAGES; ++s) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, ctx->events[f].ev[s], ctx->events[f].ev[s + 1]));
+            ctx->stage_ms[s] += ms;
+        }
+        ctx->frames += 1;
+    }
+    ctx->events_used = 0;
+    return RGS_OK;
+}
+
+extern "C" rgs_status rgs_ctx_collect_timing(rgs_ctx* ctx, double* stage_ms, int64_t* n_frames) {
+    if (!ctx || !stage_ms || !n_frames) return fail(RGS_E_INVALID, "rgs_ctx_collect_timing: NULL argument");
+    HIP_TRY(hipSetDevice(ctx->device));
+    rgs_status s = harvest_events(ctx);
+    if (s != RGS_OK) return s;
+    std::copy(ctx->stage_ms, ctx->stage_ms + RGS_N_STAGES, stage_ms);
+    *n_frames = ctx->frames;
+    std::fill(ctx->stage_ms, ctx->stage_ms + RGS_N_STAGES, 0.0);
+    ctx->frames = 0;
+    return ok();
+}
+
+// Events of the next timed frame (the pool grows on demand; full pools are
+// harvested, which synchronises the stream only every 1024 frames).
+static rgs_status next_events(rgs_ctx* ctx, FrameEvents** fe) {
+    if (ctx->events_used == 1024) {
+        rgs_status s = harvest_events(ctx);
+        if (s != RGS_OK) return s;
+    }
+    if (ctx->events_used == ctx->events.size()) {
+        FrameEvents f;
+        for (auto& e : f.ev) HIP_TRY(hipEventCreate(&e));
+        ctx->events.push_back(f);
+    }
+    *fe = &ctx->events[ctx->events_used++];
+    return RGS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scenes
+
+struct rgs_scene {
+    int device;
+    int64_t n;
+    uint64_t n_pad;
+    uint32_t formats;
+    float* plain;        // P_COUNT planes of n_pad floats
+    uint32_t* fast;      // F_COUNT planes of n_pad words
+    uint64_t bytes;
+};
+
+extern "C" rgs_status rgs_scene_upload(rgs_ctx* ctx, const rgs_scene_desc* d, uint32_t formats,
+                                       rgs_scene** out) {
+    if (!ctx || !out) return fail(RGS_E_INVALID, "rgs_scene_upload: NULL argument");
+    *out = nullptr;
+    if (formats == 0 || (formats & ~(RGS_FMT_PLAIN | RGS_FMT_FAST)))
+        return fail(RGS_E_INVALID, "formats 0x%x invalid", formats);
+    rgs_status s = validate_desc(d);
+    if (s != RGS_OK) return s;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int64_t n = d->n;
+    const uint64_t np = ((uint64_t)n + 63) & ~63ull;
+    rgs_scene* sc = new rgs_scene();
+    sc->device = ctx->device;
+    sc->n = n;
+    sc->n_pad = np;
+    sc->formats = formats;
+    sc->plain = nullptr;
+    sc->fast = nullptr;
+    sc->bytes = 0;
+    auto cleanup = [&]() {
+        if (sc->plain) (void)hipFree(sc->plain);
+        if (sc->fast) (void)hipFree(sc->fast);
+        delete sc;
+    };
+    if (formats & RGS_FMT_PLAIN) {
+        std::vector<float> h((size_t)np * P_COUNT, 0.0f);
+        for (int64_t i = 0; i < n; ++i) {
+            for (int k = 0; k < 3; ++k) h[(P_MX + k) * np + i] = d->means[3 * i + k];
+            for (int k = 0; k < 3; ++k) h[(P_SX + k) * np + i] = d->scales[3 * i + k];
+            for (int k = 0; k < 4; ++k) h[(P_QW + k) * np + i] = d->quats[4 * i + k];
+            h[P_OPA * np + i] = d->opacity[i];
+            for (int k = 0; k < 48; ++k) h[(P_SH0 + k) * np + i] = d->sh[48 * i + k];
+        }
+        size_t bytes = h.size() * sizeof(float);
+        if (hipMalloc(&sc->plain, bytes) != hipSuccess) {
+            cleanup();
+            return fail(RGS_E_OOM, "plain scene: %zu bytes", bytes);
+        }
+        if (hipMemcpy(sc->plain, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            cleanup();
+            return fail(RGS_E_HIP, "plain scene copy failed");
+        }
+        sc->bytes += bytes;
+    }
+    if (formats & RGS_FMT_FAST) {
+        std::vector<uint16_t> q16((size_t)n * 4), s16((size_t)n * 3), l16((size_t)n), ss16((size_t)n * 12);
+        std::vector<int8_t> shq((size_t)n * 48);
+        rgs_fast_host fh{q16.data(), s16.data(), l16.data(), shq.data(), ss16.data()};
+        s = quantize_into(d, &fh);
+        if (s != RGS_OK) {
+            cleanup();
+            return s;
+        }
+        std::vector<uint32_t> h((size_t)np * F_COUNT, 0u);
+        auto pair = [](uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); };
+        for (int64_t i = 0; i < n; ++i) {
+            for (int k = 0; k < 3; ++k) {
+                uint32_t w;
+                std::memcpy(&w, &d->means[3 * i + k], 4);
+                h[(F_MX + k) * np + i] = w;
+            }
+            h[F_QWX * np + i] = pair(q16[4 * i + 0], q16[4 * i + 1]);
+            h[F_QYZ * np + i] = pair(q16[4 * i + 2], q16[4 * i + 3]);
+            h[F_SXY * np + i] = pair(s16[3 * i + 0], s16[3 * i + 1]);
+            h[F_SZL * np + i] = pair(s16[3 * i + 2], l16[i]);
+            for (int k = 0; k < 12; ++k) {
+                uint32_t w = 0;
+                for (int b = 0; b < 4; ++b) w |= (uint32_t)(uint8_t)shq[48 * i + 4 * k + b] << (8 * b);
+                h[(F_SHQ0 + k) * np + i] = w;
+            }
+            for (int k = 0; k < 6; ++k)
+                h[(F_SHS0 + k) * np + i] = pair(ss16[12 * i + 2 * k], ss16[12 * i + 2 * k + 1]);
+        }
+        size_t bytes = h.size() * sizeof(uint32_t);
+        if (hipMalloc(&sc->fast, bytes) != hipSuccess) {
+            cleanup();
+            return fail(RGS_E_OOM, "fast scene: %zu bytes", bytes);
+        }
+        if (hipMemcpy(sc->fast, h.data(), bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            cleanup();
+            return fail(RGS_E_HIP, "fast scene copy failed");
+        }
+        sc->bytes += bytes;
+    }
+    *out = sc;
+    return ok();
+}
+
+extern "C" rgs_status rgs_scene_release(rgs_ctx* ctx, rgs_scene* sc) {
+    if (!sc) return ok();
+    if (ctx) (void)hipSetDevice(ctx->device);
+    if (sc->plain) (void)hipFree(sc->plain);
+    if (sc->fast) (void)hipFree(sc->fast);
+    delete sc;
+    return ok();
+}
+
+extern "C" rgs_status rgs_scene_info(const rgs_scene* sc, int64_t* n, uint32_t* formats,
+                                     uint64_t* device_bytes) {
+    if (!sc) return fail(RGS_E_INVALID, "scene is NULL");
+    if (n) *n = sc->n;
+    if (formats) *formats = sc->formats;
+    if (device_bytes) *device_bytes = sc->bytes;
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// Workspace layout
+
+static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t capacity, WsLayout& L) {
+    const bool plain = path == RGS_PATH_PLAIN;
+    L.capacity = capacity;
+    L.key_bytes = plain ? 8 : 4;
+    L.passes = plain ? (uint32_t)p.plain_passes : (uint32_t)p.fast_passes;
+    L.fe_blocks = (uint32_t)((n + FE_BLOCK - 1) / FE_BLOCK);
+    L.sort_blocks_max = (uint32_t)((capacity + SORT_TILE - 1) / SORT_TILE);
+    uint64_t off = 0;
+    L.header = off;
+    off = align256(off + sizeof(WsHeader));
+    L.ranges = off;
+    off = align256(off + (uint64_t)p.n_tiles * 8);
+    L.fe_state = off;
+    off = align256(off + (uint64_t)L.fe_blocks * 8);
+    L.hist = off;
+    off = align256(off + (uint64_t)MAX_PASSES * RADIX * 4);
+    L.zero_end = off;
+    L.records = off;
+    off = align256(off + (uint64_t)n * sizeof(Record));
+    L.counts = L.rects = L.depths = 0;
+    if (plain) {
+        L.counts = off;
+        off = align256(off + (uint64_t)n * 4);
+        L.rects = off;
+        off = align256(off + (uint64_t)n * 8);
+        L.depths = off;
+        off = align256(off + (uint64_t)n * 4);
+    }
+    L.keys_a = off;
+    off = align256(off + capacity * L.key_bytes);
+    L.keys_b = off;
+    off = align256(off + capacity * L.key_bytes);
+    L.vals_a = off;
+    off = align256(off + capacity * 4);
+    L.vals_b = off;
+    off = align256(off + capacity * 4);
+    L.lookback = off;
+    off = align256(off + (uint64_t)L.passes * L.sort_blocks_max * RADIX * 4);
+    L.t_final = off;
+    off = align256(off + (uint64_t)p.width * p.height * 4);
+    L.n_proc = off;
+    off = align256(off + (uint64_t)p.width * p.height * 4);
+    L.total = off;
+}
+
+static rgs_status check_path(int32_t path) {
+    if (path != RGS_PATH_PLAIN && path != RGS_PATH_FAST)
+        return fail(RGS_E_INVALID, "path %d is neither RGS_PATH_PLAIN nor RGS_PATH_FAST", path);
+    return RGS_OK;
+}
+
+extern "C" rgs_status rgs_workspace_size(int64_t n, int32_t width, int32_t height, int32_t path,
+                                         int64_t max_entries, uint64_t* bytes) {
+    if (!bytes) return fail(RGS_E_INVALID, "bytes is NULL");
+    if (n < 1) return fail(RGS_E_INVALID, "n < 1");
+    if (max_entries < 1 || (uint64_t)max_entries > RGS_MAX_ENTRIES)
+        return fail(RGS_E_INVALID, "max_entries %lld outside [1, 2^30 - 1]", (long long)max_entries);
+    rgs_status s = check_path(path);
+    if (s != RGS_OK) return s;
+    rgs_plan p;
+    s = rgs_frame_plan(width, height, &p);
+    if (s != RGS_OK) return s;
+    WsLayout L;
+    make_layout(n, p, path, (uint64_t)max_entries, L);
+    *bytes = L.total;
+    return ok();
+}
+
+// Largest capacity whose layout fits in ws_bytes (0 if none).
+static uint64_t capacity_for(int64_t n, const rgs_plan& p, int32_t path, uint64_t ws_bytes) {
+    uint64_t lo = 0, hi = RGS_MAX_ENTRIES;
+    WsLayout L;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo + 1) / 2;
+        make_layout(n, p, path, mid, L);
+        if (L.total <= ws_bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+extern "C" rgs_status rgs_workspace_capacity(int64_t n, int32_t width, int32_t height, int32_t path,
+                                             uint64_t ws_bytes, int64_t* capacity) {
+    if (!capacity) return fail(RGS_E_INVALID, "capacity is NULL");
+    if (n < 1) return fail(RGS_E_INVALID, "n < 1");
+    rgs_status s = check_path(path);
+    if (s != RGS_OK) return s;
+    rgs_plan p;
+    s = rgs_frame_plan(width, height, &p);
+    if (s != RGS_OK) return s;
+    *capacity = (int64_t)capacity_for(n, p, path, ws_bytes);
+    return ok();
+}
+
+static WsDev ws_pointers(void* base, const WsLayout& L) {
+    char* b = static_cast<char*>(base);
+    WsDev w;
+    w.header = reinterpret_cast<WsHeader*>(b + L.header);
+    w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
+    w.fe_state = reinterpret_cast<uint64_t*>(b + L.fe_state);
+    w.records = reinterpret_cast<Record*>(b + L.records);
+    w.counts = L.counts ? reinterpret_cast<uint32_t*>(b + L.counts) : nullptr;
+    w.rects = L.rects ? reinterpret_cast<uint64_t*>(b + L.rects) : nullptr;
+    w.depths = L.depths ? reinterpret_cast<float*>(b + L.depths) : nullptr;
+    w.keys_a = b + L.keys_a;
+    w.keys_b = b + L.keys_b;
+    w.vals_a = reinterpret_cast<uint32_t*>(b + L.vals_a);
+    w.vals_b = reinterpret_cast<uint32_t*>(b + L.vals_b);
+    w.hist = reinterpret_cast<uint32_t*>(b + L.hist);
+    w.lookback = reinterpret_cast<uint32_t*>(b + L.lookback);
+    w.t_final = reinterpret_cast<float*>(b + L.t_final);
+    w.n_proc = reinterpret_cast<uint32_t*>(b + L.n_proc);
+    return w;
+}
+
+// ---------------------------------------------------------------------------
+// Render
+
+static rgs_status check_camera(const rgs_camera* c) {
+    if (!c) return fail(RGS_E_INVALID, "camera is NULL");
+    const double* all[] = {c->R, c->t};
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(all[0][k])) return fail(RGS_E_INVALID, "camera R not finite");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(all[1][k])) return fail(RGS_E_INVALID, "camera t not finite");
+    double v[] = {c->fx, c->fy, c->cx, c->cy, c->tan_half_fovx, c->tan_half_fovy, c->z_near, c->z_far};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(RGS_E_INVALID, "camera intrinsics not finite");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(c->bg[k])) return fail(RGS_E_INVALID, "camera background not finite");
+    if (!(c->fx > 0.0 && c->fy > 0.0)) return fail(RGS_E_INVALID, "focal lengths must be positive");
+    if (!(c->tan_half_fovx > 0.0 && c->tan_half_fovy > 0.0))
+        return fail(RGS_E_INVALID, "tan_half_fov must be positive");
+    if (!(c->z_near > 0.0 && c->z_near < c->z_far))
+        return fail(RGS_E_INVALID, "need 0 < z_near < z_far (got %g, %g)", c->z_near, c->z_far);
+    return RGS_OK;
+}
+
+static CamDev cam_dev(const rgs_camera* c) {
+    CamDev d;
+    for (int k = 0; k < 9; ++k) d.r[k] = c->R[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = c->t[k];
+    d.fx = c->fx;
+    d.fy = c->fy;
+    d.cx = c->cx;
+    d.cy = c->cy;
+    d.tanx = c->tan_half_fovx;
+    d.tany = c->tan_half_fovy;
+    d.zn = c->z_near;
+    d.zf = c->z_far;
+    for (int k = 0; k < 3; ++k) {
+        // camera centre -R^T t
+        double pos = -(c->R[0 + k] * c->t[0] + c->R[3 + k] * c->t[1] + c->R[6 + k] * c->t[2]);
+        d.campos[k] = (float)pos;
+        d.bg[k] = c->bg[k];
+    }
+    return d;
+}
+
+static rgs_status read_header(rgs_ctx* ctx, const void* ws, WsHeader* h) {
+    HIP_TRY(hipMemcpyAsync(h, ws, sizeof(WsHeader), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return RGS_OK;
+}
+
+static rgs_status header_status(const WsHeader& h, rgs_frame_stats* st, int64_t n) {
+    if (st) {
+        st->n_gaussians = n;
+        st->n_visible = h.n_visible;
+        st->n_entries = (int64_t)h.n_entries;
+        st->capacity = h.capacity;
+        st->path = (int32_t)h.path;
+        st->passes = (int32_t)h.passes;
+        st->overflow = (int32_t)h.overflow;
+        st->device_error = (int32_t)h.error;
+    }
+    if (h.error)
+        return fail(RGS_E_DEVICE, "a kernel's bounded wait gave up (flags 0x%x)", h.error);
+    if (h.overflow)
+        return fail(RGS_E_CAPACITY, "frame needs %llu entries, workspace holds %u",
+                    (unsigned long long)h.n_entries, h.capacity);
+    return RGS_OK;
+}
+
+static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camera* cam, int32_t W,
+                              int32_t H, int32_t path, void* ws, uint64_t ws_bytes, float* out,
+                              rgs_debug_out* dbg, rgs_frame_stats* stats) {
+    if (!ctx || !sc) return fail(RGS_E_INVALID, "ctx or scene is NULL");
+    rgs_status s = check_path(path);
+    if (s != RGS_OK) return s;
+    if (path == RGS_PATH_PLAIN && !(sc->formats & RGS_FMT_PLAIN))
+        return fail(RGS_E_INVALID, "scene was uploaded without the plain format");
+    if (path == RGS_PATH_FAST && !(sc->formats & RGS_FMT_FAST))
+        return fail(RGS_E_INVALID, "scene was uploaded without the fast format");
+    s = check_camera(cam);
+    if (s != RGS_OK) return s;
+    rgs_plan p;
+    s = rgs_frame_plan(W, H, &p);
+    if (s != RGS_OK) return s;
+    if (!ws || !out) return fail(RGS_E_INVALID, "workspace or output is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(RGS_E_INVALID, "workspace must be 256-byte aligned");
+    uint64_t cap = capacity_for(sc->n, p, path, ws_bytes);
+    if (cap == 0) return fail(RGS_E_INVALID, "workspace of %llu bytes is too small", (unsigned long long)ws_bytes);
+    WsLayout L;
+    make_layout(sc->n, p, path, cap, L);
+    HIP_TRY(hipSetDevice(ctx->device));
+
+    WsDev w = ws_pointers(ws, L);
+    FrameDev f;
+    f.width = W;
+    f.height = H;
+    f.tiles_x = p.tiles_x;
+    f.tiles_y = p.tiles_y;
+    f.n_tiles = p.n_tiles;
+    f.b_t = p.b_t;
+    f.b_d = p.b_d;
+    f.passes = (int32_t)L.passes;
+    f.capacity = (uint32_t)cap;
+    f.n_gaussians = (uint32_t)sc->n;
+    CamDev cd = cam_dev(cam);
+    DebugDev dd{};
+    if (dbg) {
+        dd.depth = dbg->depth;
+        dd.u = dbg->u;
+        dd.v = dbg->v;
+        dd.cov2d = dbg->cov2d;
+        dd.rect = dbg->rect;
+        dd.visible = dbg->visible;
+        dd.color = dbg->color;
+    }
+    hipStream_t st = ctx->stream;
+    FrameEvents* fe = nullptr;
+    if (ctx->timing) {
+        s = next_events(ctx, &fe);
+        if (s != RGS_OK) return s;
+    }
+    auto mark = [&](int k) {
+        if (fe) (void)hipEventRecord(fe->ev[k], st);
+    };
+
+    mark(0);
+    launch_reset(st, w, L.zero_end, f, (uint32_t)path);
+    if (path == RGS_PATH_PLAIN) {
+        PlainSceneDev psd{sc->plain, sc->n_pad, sc->n};
+        launch_preprocess_plain(st, psd, cd, f, w, dbg ? &dd : nullptr);
+        mark(1);
+        launch_duplicate_plain(st, sc->n, f, w, L.fe_blocks);
+        mark(2);
+    } else {
+        FastSceneDev fsd{sc->fast, sc->n_pad, sc->n};
+        launch_frontend_fast(st, fsd, cd, f, w, L.fe_blocks, dbg ? &dd : nullptr);
+        mark(1);
+        mark(2);
+    }
+    uint64_t n_entries = 0;
+    if (dbg) {
+        WsHeader h;
+        s = read_header(ctx, ws, &h);
+        if (s != RGS_OK) return s;
+        n_entries = std::min<uint64_t>(h.n_entries, cap);
+        if (dbg->entry_capacity < (int64_t)h.n_entries && (dbg->keys_unsorted || dbg->keys_sorted ||
+                                                           dbg->vals_unsorted || dbg->vals_sorted))
+            return fail(RGS_E_CAPACITY, "debug entry buffers hold %lld, frame has %llu",
+                        (long long)dbg->entry_capacity, (unsigned long long)h.n_entries);
+        if (dbg->keys_unsorted && n_entries) {
+            if (L.key_bytes == 8)
+                HIP_TRY(hipMemcpyAsync(dbg->keys_unsorted, w.keys_a, n_entries * 8,
+                                       hipMemcpyDeviceToDevice, st));
+            else
+                launch_widen_keys(st, static_cast<const uint32_t*>(w.keys_a), dbg->keys_unsorted, n_entries);
+        }
+        if (dbg->vals_unsorted && n_entries)
+            HIP_TRY(hipMemcpyAsync(dbg->vals_unsorted, w.vals_a, n_entries * 4, hipMemcpyDeviceToDevice, st));
+    }
+    bool in_b = false;
+    launch_sort(st, f, w, L.key_bytes, L.passes, L.sort_blocks_max, &in_b);
+    mark(3);
+    launch_ranges(st, f, w, L.key_bytes, in_b);
+    mark(4);
+    if (path == RGS_PATH_PLAIN) launch_raster_plain(st, f, cd, w, in_b, out);
+    else launch_raster_fast(st, f, cd, w, in_b, out);
+    mark(5);
+    HIP_TRY(hipGetLastError());
+
+    if (dbg) {
+        const void* ks = in_b ? w.keys_b : w.keys_a;
+        const uint32_t* vs = in_b ? w.vals_b : w.vals_a;
+        if (dbg->keys_sorted && n_entries) {
+            if (L.key_bytes == 8)
+                HIP_TRY(hipMemcpyAsync(dbg->keys_sorted, ks, n_entries * 8, hipMemcpyDeviceToDevice, st));
+            else
+                launch_widen_keys(st, static_cast<const uint32_t*>(ks), dbg->keys_sorted, n_entries);
+        }
+        if (dbg->vals_sorted && n_entries)
+            HIP_TRY(hipMemcpyAsync(dbg->vals_sorted, vs, n_entries * 4, hipMemcpyDeviceToDevice, st));
+        if (dbg->ranges)
+            HIP_TRY(hipMemcpyAsync(dbg->ranges, w.ranges, (uint64_t)p.n_tiles * 8, hipMemcpyDeviceToDevice, st));
+        if (dbg->T_final)
+            HIP_TRY(hipMemcpyAsync(dbg->T_final, w.t_final, (uint64_t)W * H * 4, hipMemcpyDeviceToDevice, st));
+        if (dbg->n_proc)
+            HIP_TRY(hipMemcpyAsync(dbg->n_proc, w.n_proc, (uint64_t)W * H * 4, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipGetLastError());
+    }
+    if (stats || dbg) {
+        WsHeader h;
+        s = read_header(ctx, ws, &h);
+        if (s != RGS_OK) return s;
+        s = header_status(h, stats, sc->n);
+        if (s != RGS_OK) return s;
+    }
+    return ok();
+}
+
+extern "C" rgs_status rgs_render(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
+                                 int32_t width, int32_t height, int32_t path, void* workspace,
+                                 uint64_t ws_bytes, float* out_chw, rgs_frame_stats* stats) {
+    return render_impl(ctx, scene, cam, width, height, path, workspace, ws_bytes, out_chw, nullptr, stats);
+}
+
+extern "C" rgs_status rgs_render_debug(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
+                                       int32_t width, int32_t height, int32_t path, void* workspace,
+                                       uint64_t ws_bytes, float* out_chw, rgs_debug_out* dbg,
+                                       rgs_frame_stats* stats) {
+    if (!dbg) return fail(RGS_E_INVALID, "rgs_render_debug: dbg is NULL");
+    return render_impl(ctx, scene, cam, width, height, path, workspace, ws_bytes, out_chw, dbg, stats);
+}
+
+extern "C" rgs_status rgs_workspace_check(rgs_ctx* ctx, const void* workspace, rgs_frame_stats* stats,
+                                          int64_t n_gaussians) {
+    if (!ctx || !workspace) return fail(RGS_E_INVALID, "ctx or workspace is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+    WsHeader h;
+    rgs_status s = read_header(ctx, workspace, &h);
+    if (s != RGS_OK) return s;
+    s = header_status(h, stats, n_gaussians);
+    return s == RGS_OK ? ok() : s;
+}
+
+extern "C" rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
+                                          int32_t width, int32_t height, const float* dL_dimg,
+                                          void* workspace, uint64_t ws_bytes, rgs_grads* grads) {
+    (void)ctx; (void)scene; (void)cam; (void)width; (void)height; (void)dL_dimg;
+    (void)workspace; (void)ws_bytes; (void)grads;
+    return fail(RGS_E_UNSUPPORTED, "rgs_render_backward is not available in this build");
+}

@@ -1,0 +1,324 @@
+// Internal definitions shared by the host library and the HIP kernels.
+//
+// Everything here is compiled with -ffp-contract=off: the key-defining
+// front-end arithmetic below must round exactly like plain IEEE float64
+// evaluated left to right, so that tile rectangles, depths and keys are
+// reproducible bit for bit by an independent float64 implementation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rgs.h"
+
+namespace rgs {
+
+constexpr int TILE = RGS_TILE;
+constexpr int TILE_PIX = TILE * TILE;
+// ln(255) rounded to float64: -ln 255 is the opacity-cull threshold of ln o and
+// the skip threshold of the folded exponent (Sec. IV-B, Eq. fast_exp_range).
+constexpr double LN255 = 5.541263545158426;
+constexpr float LN255F = 5.541263545158426f;
+constexpr double DILATION = 0.3;     // low-pass term added to the 2D covariance (3DGS)
+constexpr double J_CLAMP = 1.3;      // Jacobian clamp factor on t_x/t_z, t_y/t_z (3DGS)
+constexpr float ALPHA_MAX = 0.99f;   // Eq. opacity_clamped
+constexpr float ALPHA_MIN = 1.0f / 255.0f;
+constexpr float T_MIN = 1e-4f;       // stop blending a pixel below this transmittance
+
+constexpr int FE_BLOCK = 256;        // Gaussians per front-end block
+constexpr int SORT_THREADS = 256;    // 4 waves
+constexpr int SORT_ITEMS = 16;       // keys per thread per radix tile
+constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int MAX_PASSES = 8;
+constexpr int HIST_BLOCKS = 256;
+
+// Plain-format planes (float32, one per scalar, each n_pad long).
+enum PlainPlane { P_MX = 0, P_MY, P_MZ, P_SX, P_SY, P_SZ, P_QW, P_QX, P_QY, P_QZ, P_OPA, P_SH0,
+                  P_COUNT = P_SH0 + 48 };
+// Fast-format planes (32-bit words, one per plane, each n_pad long).
+//   F_MX..F_MZ   float32 mean
+//   F_QWX, F_QYZ FP16 pairs (w, x), (y, z) of the quaternion
+//   F_SXY, F_SZL FP16 pairs (sx, sy), (sz, ln o)
+//   F_SHQ0..11   four INT8 SH values each; value k = 4*plane + byte, k = coeff*3 + channel
+//   F_SHS0..5    FP16 pairs of the 12 SH scales, scale index = degree*3 + channel
+enum FastPlane { F_MX = 0, F_MY, F_MZ, F_QWX, F_QYZ, F_SXY, F_SZL, F_SHQ0,
+                 F_SHS0 = F_SHQ0 + 12, F_COUNT = F_SHS0 + 6 };
+
+struct CamDev {
+    double r[9];
+    double t[3];
+    double fx, fy, cx, cy;
+    double tanx, tany;
+    double zn, zf;
+    float campos[3];     // camera centre -R^T t, for the SH view direction
+    float bg[3];
+};
+
+struct FrameDev {
+    int32_t width, height;
+    int32_t tiles_x, tiles_y, n_tiles;
+    int32_t b_t, b_d;
+    int32_t passes;
+    uint32_t capacity;
+    uint32_t n_gaussians;
+};
+
+// Per visible Gaussian record read by the rasterizer (48 bytes).  The
+// projected mean is split into float hi + lo parts so that tile-local
+// coordinates keep float64 accuracy at 4K.
+struct __align__(16) Record {
+    float u_hi, u_lo, v_hi, v_lo;
+    float A, B, C, opa;       // conic; opacity (plain) or ln o (fast)
+    float r, g, b, depth;     // colour; float32 depth (diagnostics)
+};
+
+// Device-side header at offset 0 of every workspace.
+struct WsHeader {
+    uint64_t n_entries;       // entries requested by the front end
+    uint32_t n_visible;
+    uint32_t overflow;
+    uint32_t error;           // bit 0: front-end look-back gave up; bit 1: sort look-back;
+                              // bit 2: a sorted key named a tile outside the grid
+    uint32_t capacity;
+    uint32_t path;
+    uint32_t passes;
+    uint32_t fe_ticket;
+    uint32_t sort_ticket[MAX_PASSES];
+    uint32_t pad[64 - 17];
+};
+static_assert(sizeof(WsHeader) == 256, "header is one 256-byte slot");
+
+// Byte offsets of a frame's workspace regions (all 256-byte aligned).
+struct WsLayout {
+    uint64_t header, ranges, fe_state, zero_end;
+    uint64_t records, counts, rects, depths;
+    uint64_t keys_a, keys_b, vals_a, vals_b;
+    uint64_t hist, lookback;
+    uint64_t t_final, n_proc;
+    uint64_t total;
+    uint64_t capacity;
+    uint32_t key_bytes, passes, fe_blocks, sort_blocks_max;
+};
+
+// Pointers a kernel needs into the workspace.
+struct WsDev {
+    WsHeader* header;
+    uint32_t* ranges;         // [n_tiles][2]
+    uint64_t* fe_state;       // chained-scan state per front-end block
+    Record* records;          // [n]
+    uint32_t* counts;         // plain: tiles touched per Gaussian
+    uint64_t* rects;          // plain: packed x0 | x1 << 16 | y0 << 32 | y1 << 48
+    float* depths;            // plain: float32 depth per Gaussian
+    void* keys_a;
+    void* keys_b;
+    uint32_t* vals_a;
+    uint32_t* vals_b;
+    uint32_t* hist;           // [MAX_PASSES][RADIX] counts, then exclusive offsets
+    uint32_t* lookback;       // [passes][sort blocks][RADIX]
+    float* t_final;           // [H][W]
+    uint32_t* n_proc;         // [H][W]
+};
+
+struct DebugDev {
+    double* depth;
+    double* u;
+    double* v;
+    double* cov2d;
+    int32_t* rect;
+    uint8_t* visible;
+    float* color;
+};
+
+// ---------------------------------------------------------------------------
+// Front-end arithmetic (float64, evaluated exactly as written, no contraction).
+
+struct Projected {
+    double d, u, v, c00, c01, c11, det;
+    double x0, x1, y0, y1;    // inclusive tile bounds (integer valued)
+};
+
+// EWA projection, culling and tile extent of one Gaussian.  Returns false when
+// it is culled: depth outside (zn, zf], det(Sigma') <= 0, ln o < -ln 255 (fast
+// path), or an empty tile rectangle.  The evaluation order of every
+// expression is part of the definition (see the header comment).
+__host__ __device__ inline bool project_gaussian(const CamDev& c, double mx, double my, double mz,
+                                                 double qw, double qx, double qy, double qz,
+                                                 double sx, double sy, double sz, bool fast,
+                                                 double lno, double tiles_x, double tiles_y,
+                                                 Projected& o) {
+    const double* r = c.r;
+    double tx = r[0] * mx + r[1] * my + r[2] * mz + c.t[0];
+    double ty = r[3] * mx + r[4] * my + r[5] * mz + c.t[1];
+    double d = r[6] * mx + r[7] * my + r[8] * mz + c.t[2];
+    o.d = d;
+    if (!(d > c.zn && d <= c.zf)) return false;
+    if (fast && !(lno >= -LN255)) return false;
+
+    double nn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    double w = qw / nn, x = qx / nn, y = qy / nn, z = qz / nn;
+    double R00 = 1.0 - 2.0 * (y * y + z * z);
+    double R01 = 2.0 * (x * y - w * z);
+    double R02 = 2.0 * (x * z + w * y);
+    double R10 = 2.0 * (x * y + w * z);
+    double R11 = 1.0 - 2.0 * (x * x + z * z);
+    double R12 = 2.0 * (y * z - w * x);
+    double R20 = 2.0 * (x * z - w * y);
+    double R21 = 2.0 * (y * z + w * x);
+    double R22 = 1.0 - 2.0 * (x * x + y * y);
+    // M = R diag(s), Sigma = M M^T
+    double M00 = R00 * sx, M01 = R01 * sy, M02 = R02 * sz;
+    double M10 = R10 * sx, M11 = R11 * sy, M12 = R12 * sz;
+    double M20 = R20 * sx, M21 = R21 * sy, M22 = R22 * sz;
+    double S00 = M00 * M00 + M01 * M01 + M02 * M02;
+    double S01 = M00 * M10 + M01 * M11 + M02 * M12;
+    double S02 = M00 * M20 + M01 * M21 + M02 * M22;
+    double S11 = M10 * M10 + M11 * M11 + M12 * M12;
+    double S12 = M10 * M20 + M11 * M21 + M12 * M22;
+    double S22 = M20 * M20 + M21 * M21 + M22 * M22;
+
+    double limx = J_CLAMP * c.tanx;
+    double limy = J_CLAMP * c.tany;
+    double xc = fmin(limx, fmax(-limx, tx / d)) * d;
+    double yc = fmin(limy, fmax(-limy, ty / d)) * d;
+    double j00 = c.fx / d;
+    double j02 = -(c.fx * xc) / (d * d);
+    double j11 = c.fy / d;
+    double j12 = -(c.fy * yc) / (d * d);
+    // T = J R_w
+    double T00 = j00 * r[0] + j02 * r[6];
+    double T01 = j00 * r[1] + j02 * r[7];
+    double T02 = j00 * r[2] + j02 * r[8];
+    double T10 = j11 * r[3] + j12 * r[6];
+    double T11 = j11 * r[4] + j12 * r[7];
+    double T12 = j11 * r[5] + j12 * r[8];
+    // U = T Sigma, Sigma' = U T^T + 0.3 I
+    double U00 = T00 * S00 + T01 * S01 + T02 * S02;
+    double U01 = T00 * S01 + T01 * S11 + T02 * S12;
+    double U02 = T00 * S02 + T01 * S12 + T02 * S22;
+    double U10 = T10 * S00 + T11 * S01 + T12 * S02;
+    double U11 = T10 * S01 + T11 * S11 + T12 * S12;
+    double U12 = T10 * S02 + T11 * S12 + T12 * S22;
+    double c00 = U00 * T00 + U01 * T01 + U02 * T02 + DILATION;
+    double c01 = U00 * T10 + U01 * T11 + U02 * T12;
+    double c11 = U10 * T10 + U11 * T11 + U12 * T12 + DILATION;
+    o.c00 = c00;
+    o.c01 = c01;
+    o.c11 = c11;
+    double det = c00 * c11 - c01 * c01;
+    o.det = det;
+    double u = c.fx * tx / d + c.cx;
+    double v = c.fy * ty / d + c.cy;
+    o.u = u;
+    o.v = v;
+    if (!(det > 0.0)) return false;
+
+    double mid = 0.5 * (c00 + c11);
+    double lam = mid + sqrt(fmax(0.0, mid * mid - det));
+    double rad = ceil(3.0 * sqrt(lam));
+    double hx = rad, hy = rad;
+    if (fast) {
+        double tau = 2.0 * (LN255 + lno);
+        hx = fmin(rad, sqrt(tau * c00));
+        hy = fmin(rad, sqrt(tau * c11));
+    }
+    o.x0 = fmax(0.0, floor((u - hx) / 16.0));
+    o.x1 = fmin(tiles_x - 1.0, floor((u + hx) / 16.0));
+    o.y0 = fmax(0.0, floor((v - hy) / 16.0));
+    o.y1 = fmin(tiles_y - 1.0, floor((v + hy) / 16.0));
+    return o.x0 <= o.x1 && o.y0 <= o.y1;
+}
+
+// Eq. depth_quant: q = clamp(floor((d - zn) / (zf - zn) * (2^b_d - 1)), 0, 2^b_d - 1).
+__host__ __device__ inline uint32_t quantize_depth(double d, double zn, double zf, int b_d) {
+    double levels = (double)((1u << b_d) - 1u);
+    double q = floor((d - zn) / (zf - zn) * levels);
+    q = fmin(levels, fmax(0.0, q));
+    return (uint32_t)q;
+}
+
+// ---------------------------------------------------------------------------
+// Wave64 helpers.
+
+__device__ inline uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+
+__device__ inline uint64_t lanemask_lt() {
+    uint32_t l = lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <typename T>
+__device__ inline T wave_inclusive_scan(T x) {
+    uint32_t l = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T y = __shfl_up(x, off, 64);
+        if (l >= (uint32_t)off) x += y;
+    }
+    return x;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Relaxed device-scope atomics on look-back state: the value travels in the
+// same word as its flag, so no ordering with other memory is needed.
+__device__ inline uint64_t ld_state(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_state(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline uint32_t ld_state(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_state(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded waits: a look-back that polls this often without progress gives up,
+// flags the header and lets the kernel finish.
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+
+// 64-bit chained-scan state: flag in bits 63..62 (1 aggregate, 2 inclusive prefix).
+constexpr uint64_t ST_AGG = 1ull << 62;
+constexpr uint64_t ST_PRE = 2ull << 62;
+constexpr uint64_t ST_VAL = (1ull << 62) - 1;
+// 32-bit radix look-back state: flag in bits 31..30, count in bits 29..0.
+constexpr uint32_t RS_AGG = 1u << 30;
+constexpr uint32_t RS_PRE = 2u << 30;
+constexpr uint32_t RS_VAL = (1u << 30) - 1;
+
+// ---------------------------------------------------------------------------
+// Host-side launch wrappers (defined in the .hip files).
+
+struct PlainSceneDev { const float* base; uint64_t n_pad; int64_t n; };
+struct FastSceneDev { const uint32_t* base; uint64_t n_pad; int64_t n; };
+
+void launch_reset(hipStream_t s, const WsDev& ws, uint64_t zero_bytes, const FrameDev& f,
+                  uint32_t path);
+void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam,
+                             const FrameDev& f, const WsDev& ws, const DebugDev* dbg);
+void launch_duplicate_plain(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws,
+                            uint32_t fe_blocks);
+void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const CamDev& cam,
+                          const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
+                          const DebugDev* dbg);
+void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
+                 uint32_t passes, uint32_t sort_blocks_max, bool* result_in_b);
+void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
+                   bool result_in_b);
+void launch_raster_plain(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
+                         bool result_in_b, float* out);
+void launch_raster_fast(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
+                        bool result_in_b, float* out);
+void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n);
+
+}  // namespace rgs

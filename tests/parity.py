@@ -1,0 +1,106 @@
+"""Comparison of the HIP renderer with the FP64 oracle on the same seeded inputs.
+
+Bars (see the oracle's blend module for the decision bookkeeping):
+* per-Gaussian visibility, tile rectangle and float64 depth, mean and 2D
+  covariance: bit-exact;
+* duplicated entries in emission order, sorted keys and indices, tile ranges:
+  bit-exact;
+* plain image: |gpu - oracle| <= 2e-3 + slack at every pixel;
+* fast image: |gpu - oracle(bit-level exp)| <= 2e-3 + slack, and
+  |gpu - oracle(exact exp)| <= eps/(1-eps) c_max (1 - T_final) + 1e-3 + slack
+  (the per-pixel bound of the bit-level exponential, Sec. IV-B), where slack is
+  the colour at stake in skip/stop decisions that lie within the float32
+  margin of their thresholds, or that the two exponentials decide differently.
+"""
+from __future__ import annotations
+
+import importlib
+import math
+
+import numpy as np
+
+import oracle
+
+FASTEXP = importlib.import_module("oracle.fastexp")
+
+PLAIN_TOL = 2e-3
+FAST_TOL = 1e-3
+PLAIN_MARGINS = (1e-4, 0.0)      # relative alpha uncertainty of float32 + expf
+FAST_MARGINS = (2e-3, 2e-3)      # relative alpha, absolute P uncertainty of float32 folding
+
+
+def oracle_frame(scene, cam, path, tiles=None, workers=8):
+    if path == "plain":
+        arr = oracle.prepare_plain(scene)
+        return oracle.render(arr, cam, "plain", tiles=tiles, margins=PLAIN_MARGINS, workers=workers)
+    arr = oracle.prepare_fast(oracle.quantize_scene(scene))
+    return oracle.render(arr, cam, "fast", modes=("fast-def", "fast-exact"), tiles=tiles,
+                         margins=FAST_MARGINS, workers=workers)
+
+
+def compare_front_end(g, fr):
+    vis = fr.proj.visible
+    assert np.array_equal(g["visible"], vis), f"visibility differs at {np.nonzero(g['visible'] != vis)[0][:10]}"
+    assert np.array_equal(g["depth"].view(np.uint64), fr.proj.d.view(np.uint64)), "depth bits differ"
+    for k, ref in (("u", fr.proj.u), ("v", fr.proj.v)):
+        assert np.array_equal(g[k][vis].view(np.uint64), ref[vis].view(np.uint64)), f"{k} bits differ"
+    assert np.array_equal(g["cov2d"][vis].view(np.uint64), fr.proj.cov[vis].view(np.uint64)), "cov2d bits differ"
+    assert np.array_equal(g["rect"][vis].astype(np.int64), fr.proj.rect[vis]), "tile rectangles differ"
+    cerr = float(np.max(np.abs(g["color"][vis] - fr.proj.color[vis]))) if vis.any() else 0.0
+    assert cerr < 1e-5, f"SH colour differs by {cerr}"
+    return cerr
+
+
+def compare_entries(g, fr):
+    assert g["stats"]["n_entries"] == fr.keys.size, (g["stats"]["n_entries"], fr.keys.size)
+    assert np.array_equal(g["keys_unsorted"], fr.keys), "unsorted keys differ"
+    assert np.array_equal(g["vals_unsorted"].astype(np.int64), fr.entry_gauss), "unsorted indices differ"
+    assert np.array_equal(g["keys_sorted"], fr.sorted_keys), "sorted keys differ"
+    assert np.array_equal(g["vals_sorted"].astype(np.int64), fr.sorted_gauss), "sorted indices differ"
+    assert np.array_equal(g["ranges"].astype(np.int64), fr.ranges), "tile ranges differ"
+
+
+def _tile_mask(fr):
+    H, W = fr.plan.height, fr.plan.width
+    m = np.zeros((H, W), bool)
+    for t in fr.tiles:
+        tx, ty = int(t) % fr.plan.tiles_x, int(t) // fr.plan.tiles_x
+        m[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
+    return m
+
+
+def psnr(a, b, mask=None):
+    d = (a - b) if mask is None else (a - b)[:, mask]
+    mse = float(np.mean(d * d))
+    return math.inf if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+def compare_image(img, fr, path):
+    """Asserts the image bars on the oracle's blended tiles; returns a report dict."""
+    mask = _tile_mask(fr)
+    gpu = img[:, mask].astype(np.float64)
+    slack = fr.slack[mask][None]
+    rep = dict(pixels=int(mask.sum()), flagged=int(fr.flagged[mask].sum()))
+    if path == "plain":
+        ref = fr.images["plain"][:, mask]
+        err = np.abs(gpu - ref)
+        bad = err > PLAIN_TOL + slack
+        rep.update(max_err=float(err.max()), psnr=psnr(gpu, ref),
+                   max_err_unflagged=float(err[:, ~fr.flagged[mask]].max()) if (~fr.flagged[mask]).any() else 0.0)
+        assert not bad.any(), f"plain: {int(bad.sum())} values over tolerance, worst {float((err - PLAIN_TOL - slack).max())}"
+        return rep
+    ref_def = fr.images["fast-def"][:, mask]
+    ref_exact = fr.images["fast-exact"][:, mask]
+    err_def = np.abs(gpu - ref_def)
+    bad = err_def > PLAIN_TOL + slack
+    assert not bad.any(), f"fast vs bit-level-exp oracle: {int(bad.sum())} over, worst {float((err_def - PLAIN_TOL - slack).max())}"
+    eps = FASTEXP.eps_star()
+    bound = eps / (1 - eps) * fr.c_max[mask] * (1 - fr.T_final[mask])
+    allowed = bound[None] + FAST_TOL + slack + fr.mode_slack[mask][None]
+    err_ex = np.abs(gpu - ref_exact)
+    bad = err_ex > allowed
+    assert not bad.any(), f"fast vs exact oracle: {int(bad.sum())} over the bound, worst {float((err_ex - allowed).max())}"
+    rep.update(max_err_vs_def=float(err_def.max()), max_err_vs_exact=float(err_ex.max()),
+               psnr_vs_def=psnr(gpu, ref_def), psnr_vs_exact=psnr(gpu, ref_exact),
+               max_bound=float(bound.max()), mode_flagged=int((fr.mode_slack[mask] > 0).sum()))
+    return rep

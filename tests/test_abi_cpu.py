@@ -1,0 +1,137 @@
+"""The C-ABI library on the CPU: it loads, exports every declared entry point,
+and its host-only logic (frame plan, workspace sizing, compact-storage
+quantiser, argument checks) matches the oracle.  No GPU work is launched."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2608_15785_amd as rgs
+import workloads as wl
+from paper_2608_15785_amd import _binding as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "rgs.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:rgs_status|int32_t|const char\*|void)\s+(rgs_\w+)\s*\(",
+                                 text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 18
+    lib = C.CDLL(B.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert {n for n, _, _ in B.SIGNATURES} == set(names)
+    assert B.lib.rgs_abi_version() == 1
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (16, 16), (17, 1), (256, 256), (1280, 720), (1920, 1080),
+                                 (3840, 2160), (64, 64), (250, 170), (16384, 16384)])
+def test_frame_plan_matches_oracle(W, H):
+    p = rgs.frame_plan(W, H)
+    o = oracle.frame_plan(W, H)
+    assert (p["tiles_x"], p["tiles_y"], p["n_tiles"], p["b_t"], p["b_d"]) == \
+        (o.tiles_x, o.tiles_y, o.n_tiles, o.b_t, o.b_d)
+    assert p["plain_key_bits"] == o.plain_key_bits
+    assert p["plain_passes"] == -(-o.plain_key_bits // 8) and p["fast_passes"] == 4
+
+
+@pytest.mark.parametrize("W,H", [(0, 10), (10, 0), (-1, 5), (16385, 16), (16, 16385)])
+def test_frame_plan_rejects(W, H):
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.frame_plan(W, H)
+    assert e.value.status == B.RGS_E_INVALID
+
+
+def test_workspace_sizing():
+    for path in ("plain", "fast"):
+        sizes = [rgs.workspace_size(10_000, 256, 256, path, m) for m in (1, 1000, 100_000, 1_000_000)]
+        assert sizes == sorted(sizes) and sizes[0] < sizes[-1]
+        for m in (1, 4095, 4096, 4097, 123_457):
+            b = rgs.workspace_size(10_000, 256, 256, path, m)
+            assert rgs.workspace_capacity(10_000, 256, 256, path, b) >= m
+            assert rgs.workspace_capacity(10_000, 256, 256, path, b - 256) < m or m == 1
+        assert rgs.workspace_capacity(10_000, 256, 256, path, 1000) == 0
+    # the plain entry (64-bit key + index, double-buffered) costs more than the fast one
+    assert rgs.workspace_size(1, 16, 16, "plain", 1 << 20) > rgs.workspace_size(1, 16, 16, "fast", 1 << 20)
+    for bad in (0, B.MAX_ENTRIES + 1):
+        with pytest.raises(rgs.RGSError):
+            rgs.workspace_size(10, 16, 16, "fast", bad)
+
+
+def _edge_scene():
+    sc = wl.config_scene("cfg0", n=3000)
+    sh = sc.sh.copy()
+    sh[0] = 0.0                                     # all-zero SH
+    sh[1, 1:4, :] = 0.0                             # zero degree-1 blocks
+    sh[2, 4:9, 1] = 1e-6                            # subnormal FP16 scale
+    sh[3, 9:16, 2] = np.float32(127.0 * 0.25)       # exact ratios
+    sh[4, 9, 0] = 1.0
+    sh[4, 10, 0] = -1.0 / 254.0                     # q = -0.5 exactly: ties to even
+    sh[4, 11, 0] = 3.0 / 254.0                      # q = 1.5
+    scales = sc.scales.copy()
+    scales[5] = np.float32(1.0 + 2.0 ** -11)        # FP16 midpoint: ties to even
+    scales[6] = np.float32(1.0 + 3 * 2.0 ** -11)
+    scales[7] = np.float32(3e-8)                    # FP16 subnormal scale
+    opa = sc.opacity.copy()
+    opa[8] = 1.0
+    opa[9] = np.float32(1e-6)
+    return wl.Scene(sc.means, scales, sc.quats, opa, sh)
+
+
+def test_quantize_host_bit_exact_vs_oracle():
+    sc = _edge_scene()
+    q = rgs.quantize_host(sc)
+    fs = oracle.quantize_scene(sc)
+    assert np.array_equal(q["quats"], fs.quats.view(np.uint16))
+    assert np.array_equal(q["scales"], fs.scales.view(np.uint16))
+    assert np.array_equal(q["log_opacity"], fs.log_opacity.view(np.uint16))
+    assert np.array_equal(q["sh_q"], fs.sh_q)
+    assert np.array_equal(q["sh_scale"], fs.sh_scale.view(np.uint16))
+
+
+@pytest.mark.parametrize("field,index,value", [
+    ("means", (0, 1), np.nan), ("scales", (1, 0), 0.0), ("scales", (1, 2), -1.0),
+    ("quats", (2,), 0.0), ("opacity", (3,), 0.0), ("opacity", (3,), 1.5), ("sh", (4, 3, 1), np.inf),
+    ("scales", (5, 1), 1e6),
+])
+def test_quantize_host_rejects(field, index, value):
+    sc = wl.config_scene("cfg0", n=50)
+    arr = getattr(sc, field).copy()
+    arr[index] = value
+    setattr(sc, field, arr)
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.quantize_host(sc)
+    assert e.value.status == B.RGS_E_INVALID
+
+
+def test_no_device_is_reported_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.Context(0)
+    assert e.value.status == B.RGS_E_NODEVICE
+
+
+def test_backward_is_reserved():
+    status = B.lib.rgs_render_backward(None, None, None, 16, 16, None, None, 0, None)
+    assert status == B.RGS_E_UNSUPPORTED
+
+
+def test_null_arguments_are_rejected():
+    assert B.lib.rgs_frame_plan(16, 16, None) == B.RGS_E_INVALID
+    assert B.lib.rgs_scene_upload(None, None, 1, None) == B.RGS_E_INVALID
+    assert B.lib.rgs_render(None, None, None, 16, 16, 0, None, 0, None, None) == B.RGS_E_INVALID
+    assert B.lib.rgs_workspace_check(None, None, None, 0) == B.RGS_E_INVALID
+    assert B.lib.rgs_ctx_set_timing(None, 1) == B.RGS_E_INVALID

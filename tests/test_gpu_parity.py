@@ -1,0 +1,168 @@
+"""HIP renderer against the FP64 oracle through the C ABI (needs an MI355X)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from parity import compare_entries, compare_front_end, compare_image, oracle_frame
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_15785_amd as rgs
+    return rgs.Renderer(0)
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run_parity(R, scene, cam, path, tiles=None, entries=True):
+    _log(f"[parity] path={path} n={scene.n} {cam.width}x{cam.height} tiles={'all' if tiles is None else len(tiles)}")
+    ds = R.upload(scene, (path,))
+    g = R.render_debug(ds, cam, path)
+    ds.release()
+    fr = oracle_frame(scene, cam, path, tiles=tiles)
+    compare_front_end(g, fr)
+    if entries:
+        compare_entries(g, fr)
+    rep = compare_image(g["image"], fr, path)
+    rep.update(n_entries=int(g["stats"]["n_entries"]), n_visible=int(g["stats"]["n_visible"]))
+    # pair evaluations agree with the oracle's count except where a decision was flagged
+    mask = ~fr.flagged & ~(fr.mode_slack > 0) & ~np.isnan(fr.T_final)
+    assert np.array_equal(g["n_proc"][mask], fr.n_proc[mask].astype(np.uint32)), "pair counts differ"
+    _log(f"[parity] {path}: {rep}")
+    return rep
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+def test_cfg0_full(R, path):
+    run_parity(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), path)
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+@pytest.mark.parametrize("W,H", [(250, 170), (17, 33), (1, 1), (64, 16)])
+def test_ragged_sizes(R, path, W, H):
+    run_parity(R, wl.config_scene("cfg0", n=2500), wl.config_camera("cfg0", width=W, height=H), path)
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+def test_background_and_termination(R, path):
+    sc = wl.make_scene(4000, 1.0, -2.8, 0.4, 21)        # larger Gaussians: many pixels stop early
+    cam = wl.config_camera("cfg0", width=160, height=120)
+    cam.bg = np.array([0.2, 0.5, 0.7], np.float32)
+    rep = run_parity(R, sc, cam, path)
+    assert rep["n_entries"] > 0
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+def test_empty_frame(R, path):
+    import torch
+    sc = wl.config_scene("cfg0", n=500)
+    cam = wl.look_at_camera((0, 0, 30.0), (0, 0, 40.0), (0, 1, 0), 60.0, 48, 40, 1.0, 2.0,
+                            bg=(0.1, 0.2, 0.3))
+    ds = R.upload(sc, (path,))
+    img, st = R.render(ds, cam, path)
+    torch.cuda.synchronize()
+    assert st["n_entries"] == 0 and st["n_visible"] == 0
+    expect = np.broadcast_to(np.array([0.1, 0.2, 0.3], np.float32)[:, None, None], (3, 40, 48))
+    assert np.array_equal(img.cpu().numpy(), expect)
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+def test_equal_keys_keep_index_order(R, path):
+    """Many copies of a few Gaussians: long runs of equal keys must end up in index order."""
+    base = wl.config_scene("cfg0", n=40)
+    idx = np.tile(np.arange(40), 150)
+    sc = base.subset(idx)
+    run_parity(R, sc, wl.config_camera("cfg0", width=128, height=96), path)
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+def test_deterministic(R, path):
+    import torch
+    sc = wl.config_scene("cfg0")
+    cam = wl.config_camera("cfg0")
+    ds = R.upload(sc, (path,))
+    a = R.render_debug(ds, cam, path)
+    b = R.render_debug(ds, cam, path)
+    for k in ("image", "keys_sorted", "vals_sorted", "ranges", "n_proc"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+def test_capacity_overflow_is_reported(R, path):
+    import paper_2608_15785_amd as rgs
+    import torch
+    sc = wl.config_scene("cfg0")
+    cam = wl.config_camera("cfg0")
+    ds = R.upload(sc, (path,))
+    ws = rgs.new_workspace(sc.n, cam.width, cam.height, path, 1000)
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.render(R.ctx, ds, cam, path, ws, stats=True)
+    assert e.value.status == -4
+    from paper_2608_15785_amd._binding import workspace_stats
+    st = workspace_stats(R.ctx, ws, sc.n)
+    assert st["overflow"] == 1 and 1000 <= st["capacity"] < st["n_entries"]
+    # the renderer grows its workspace and the frame then matches the oracle
+    img, st = R.render(ds, cam, path)
+    assert st["overflow"] == 0
+
+
+def test_invalid_arguments(R):
+    import paper_2608_15785_amd as rgs
+    sc = wl.config_scene("cfg0", n=100)
+    ds = R.upload(sc, ("fast",))
+    cam = wl.config_camera("cfg0")
+    ws = rgs.new_workspace(sc.n, 256, 256, "plain", 10000)
+    with pytest.raises(rgs.RGSError) as e:          # plain path on a fast-only scene
+        rgs.render(R.ctx, ds, cam, "plain", ws)
+    assert e.value.status == -1
+    bad = wl.config_camera("cfg0")
+    bad.z_near, bad.z_far = 3.0, 2.0
+    with pytest.raises(rgs.RGSError):
+        rgs.render(R.ctx, ds, bad, "fast", ws)
+    bad = wl.config_camera("cfg0", width=0, height=10)
+    with pytest.raises(rgs.RGSError):
+        rgs.render(R.ctx, ds, bad, "fast", ws)
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+def test_cfg1_keys_and_sampled_tiles(R, path):
+    """1M Gaussians at 1920x1080: every key bit-exact, image on 64 sampled tiles."""
+    sc = wl.config_scene("cfg1")
+    cam = wl.config_camera("cfg1")
+    plan = oracle.frame_plan(cam.width, cam.height)
+    tiles = np.random.default_rng(7).choice(plan.n_tiles, 64, replace=False)
+    tiles = np.concatenate([tiles, [plan.n_tiles - 1]])          # the ragged corner tile
+    run_parity(R, sc, cam, path, tiles=tiles)
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+@pytest.mark.parametrize("pose", [0, 21])
+def test_cfg2_keys_and_sampled_tiles(R, path, pose):
+    """3M Gaussians at 3840x2160 on orbit poses: every key bit-exact, 48 sampled tiles."""
+    sc = _cfg2_scene()
+    cam = wl.config_camera("cfg2", pose=pose)
+    plan = oracle.frame_plan(cam.width, cam.height)
+    tiles = np.random.default_rng(pose).choice(plan.n_tiles, 48, replace=False)
+    run_parity(R, sc, cam, path, tiles=tiles)
+
+
+_CFG2 = {}
+
+
+def _cfg2_scene():
+    if "s" not in _CFG2:
+        _CFG2["s"] = wl.config_scene("cfg2")
+    return _CFG2["s"]
