@@ -1,0 +1,284 @@
+#!/usr/bin/env python3
+"""Benchmark of the tile-based 3D Gaussian Splatting forward render on one MI355X.
+
+Default workload (the N=1 line): 1,000,000 seeded Gaussians rendered at
+1920x1080 (camera at distance 25, fovx 60 deg).  A step is one frame of the
+whole hot path (front end, sort, tile ranges, rasterizer) with the scene
+already resident in HBM and the image left on the device.  `value` is the fast
+path's frames per second; the plain path's FPS, the speedup, per-frame p50/p99
+latency, per-stage times, the dominant kernel's roofline position and the
+oracle's CPU rate are reported beside it.  The 3,000,000-Gaussian 3840x2160
+64-pose orbit is measured as an extra section (--no-4k skips it).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FPS at 1080p/4K (1M/3M Gaussians) fast vs plain path; p50/p99 latency"
+
+# MI355X peaks: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 VALU
+# lane-operations per second (non-packed); HBM3E 8 TB/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+# Algorithmic VALU lane-operations per evaluated (pixel, Gaussian) pair; the
+# counts are derived in the design doc from the operations the method defines.
+OPS_PER_PAIR = {"fast": 14, "plain": 21}
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--latency-frames", type=int, default=200)
+    ap.add_argument("--orbit-rounds", type=int, default=2)
+    ap.add_argument("--no-4k", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tiles", type=int, default=2048, help="tiles the oracle blends")
+    ap.add_argument("--paths", default="fast,plain")
+    return ap.parse_args()
+
+
+def stage_bytes(path, n, n_vis, n_dup, n_tiles, passes):
+    """Algorithmic HBM bytes per frame of each memory-bound stage."""
+    if path == "fast":
+        fe = 28 * n + 72 * n_vis + 48 * n_vis + 8 * n_dup
+        dup = 0
+        kb = 4
+    else:
+        fe = 44 * n + 192 * n_vis + (48 + 8 + 4) * n_vis + 4 * n
+        dup = 4 * n + 12 * n_vis + 12 * n_dup
+        kb = 8
+    sort = (kb + passes * 2 * (kb + 4)) * n_dup
+    ranges = kb * n_dup + 8 * n_tiles
+    return dict(frontend=fe, duplicate=dup, sort=sort, ranges=ranges)
+
+
+def kernel_sha(name):
+    with open(os.path.join(ROOT, "paper_2608_15785_amd", "csrc", name), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, src):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current source of the kernel; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    for line in open(TRAFFIC_FILE):
+        line = line.strip()
+        if not line.startswith("{"):
+            continue
+        rec = json.loads(line)
+        if rec.get("kernel") == kernel and rec.get("workload") == workload and \
+                rec.get("source_sha") == kernel_sha(src):
+            return rec.get("bytes_per_launch")
+    return None
+
+
+def time_path(R, ds, cams, path, steps, warmup, lat_frames):
+    """Throughput over `steps` frames cycling through `cams`, stage times from the
+    library's HIP events over that timed region, then per-frame latency."""
+    import torch
+    W, H = cams[0].width, cams[0].height
+    need = 0
+    for cam in cams:                       # size the workspace for every pose (synchronous)
+        _, st = R.render(ds, cam, path)
+        need = max(need, st["n_entries"])
+    R.workspace(ds.n, W, H, path, int(need * 1.05) + 4096)
+    for k in range(warmup):
+        R.render(ds, cams[k % len(cams)], path, check=False)
+    torch.cuda.synchronize()
+    R.ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        R.render(ds, cams[k % len(cams)], path, check=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stage_ms, nf = R.ctx.collect_timing()
+    R.ctx.set_timing(False)
+    chk = R.check(ds, cams[(steps - 1) % len(cams)], path)
+    assert chk["overflow"] == 0 and chk["device_error"] == 0, chk
+    # per-frame latency on the stream, frames back to back
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(lat_frames)]
+    for k in range(lat_frames):
+        ev[k][0].record()
+        R.render(ds, cams[k % len(cams)], path, check=False)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    sec = (t1 - t0) / steps
+    return dict(fps=1.0 / sec, ms_per_frame=sec * 1e3,
+                stage_ms={k: v / max(nf, 1) for k, v in stage_ms.items()},
+                latency_ms=dict(p50=float(np.percentile(lat, 50)), p99=float(np.percentile(lat, 99)),
+                                mean=float(lat.mean())))
+
+
+def frame_counts(R, ds, cam, path):
+    g = R.render_debug(ds, cam, path)
+    st = g["stats"]
+    return dict(n_visible=int(st["n_visible"]), n_entries=int(st["n_entries"]),
+                pairs=int(g["n_proc"].astype(np.int64).sum()), passes=int(st["passes"]))
+
+
+def rooflines(path, counts, stage_ms, n, n_tiles):
+    by = stage_bytes(path, n, counts["n_visible"], counts["n_entries"], n_tiles, counts["passes"])
+    out = {}
+    for s, b in by.items():
+        ms = stage_ms.get(s, 0.0)
+        if b and ms > 0:
+            gbs = b / (ms * 1e-3) / 1e9
+            out[s] = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                          frac=round(gbs / HBM_PEAK_GBS, 4), bytes=int(b), ms=round(ms, 4))
+    ms = stage_ms["raster"]
+    tops = counts["pairs"] * OPS_PER_PAIR[path] / (ms * 1e-3) / 1e12
+    out["raster"] = dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 2),
+                         unit="Tops/s", frac=round(tops / VALU_PEAK_TOPS, 4), pairs=counts["pairs"],
+                         ops_per_pair=OPS_PER_PAIR[path], ms=round(ms, 4))
+    return out
+
+
+def cpu_baseline(scene, cam, n_tiles_sample):
+    """The FP64 oracle's fast path on the host cores: full front end and sort,
+    blending of a seeded sample of tiles, scaled to one frame."""
+    import oracle
+    cores = min(16, os.cpu_count() or 1)
+    arr = oracle.prepare_fast(oracle.quantize_scene(scene))
+    t = time.perf_counter()
+    fr = oracle.render(arr, cam, "fast", modes=("fast-def",), blend=False)
+    t_front = time.perf_counter() - t
+    n_t = fr.plan.n_tiles
+    k = min(n_tiles_sample, n_t)
+    tiles = np.random.default_rng(0).choice(n_t, k, replace=False)
+    t = time.perf_counter()
+    oracle.render(arr, cam, "fast", modes=("fast-def",), tiles=tiles, workers=cores)
+    t_all = time.perf_counter() - t
+    t_blend = max(t_all - t_front, 0.0)
+    frame_s = t_front + t_blend * n_t / k
+    return dict(value=round(1.0 / frame_s, 5), unit="FPS", cores=cores, kind="oracle",
+                sample=f"FP64 oracle, fast path: front end, keys and sort of all {scene.n} Gaussians "
+                       f"({t_front:.1f} s, one core) plus blending of {k} of {n_t} seeded tiles on "
+                       f"{cores} processes ({t_blend:.1f} s), scaled to the full frame "
+                       f"({frame_s:.1f} s per frame)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build renders on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import paper_2608_15785_amd as rgs
+    import workloads as wl
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU"}))
+        sys.exit(1)
+    paths = [p for p in args.paths.split(",") if p]
+    R = rgs.Renderer(0)
+
+    log("[bench] cfg1: 1,000,000 Gaussians, 1920x1080")
+    sc1 = wl.config_scene("cfg1")
+    cam1 = wl.config_camera("cfg1")
+    ds1 = R.upload(sc1)
+    plan1 = rgs.frame_plan(cam1.width, cam1.height)
+    res1 = {}
+    for path in paths:
+        r = time_path(R, ds1, [cam1], path, args.steps, args.warmup, args.latency_frames)
+        r.update(frame_counts(R, ds1, cam1, path))
+        r["roofline"] = rooflines(path, r, r["stage_ms"], sc1.n, plan1["n_tiles"])
+        res1[path] = r
+        log(f"[bench] cfg1 {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
+
+    res2 = {}
+    if not args.no_4k:
+        log("[bench] cfg2: 3,000,000 Gaussians, 3840x2160, 64-pose orbit")
+        ds1.release()
+        sc2 = wl.config_scene("cfg2")
+        cams = [wl.config_camera("cfg2", pose=k) for k in range(64)]
+        ds2 = R.upload(sc2)
+        plan2 = rgs.frame_plan(3840, 2160)
+        for path in paths:
+            r = time_path(R, ds2, cams, path, 64 * args.orbit_rounds, 64, 128)
+            r.update(frame_counts(R, ds2, cams[0], path))
+            r["roofline_pose0"] = rooflines(path, r, r["stage_ms"], sc2.n, plan2["n_tiles"])
+            res2[path] = r
+            log(f"[bench] cfg2 {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
+        ds2.release()
+
+    main_path = "fast" if "fast" in res1 else paths[0]
+    m = res1[main_path]
+    stages = {k: v for k, v in m["roofline"].items()}
+    dom = max(stages, key=lambda s: stages[s]["ms"])
+    kernel = {"raster": "k_raster_fast" if main_path == "fast" else "k_raster_plain",
+              "frontend": "k_frontend_fast" if main_path == "fast" else "k_preprocess_plain",
+              "duplicate": "k_duplicate_plain", "sort": "k_radix_pass", "ranges": "k_ranges"}[dom]
+    src = {"raster": "k_raster.hip", "frontend": "k_frontend.hip", "duplicate": "k_frontend.hip",
+           "sort": "k_sort.hip", "ranges": "k_sort.hip"}[dom]
+    rl = dict(stages[dom])
+    roofline = {"bound": rl["bound"], "achieved": rl["achieved"], "peak": rl["peak"], "unit": rl["unit"],
+                "frac": rl["frac"], "traffic": measured_traffic(kernel, "cfg1-" + main_path, src),
+                "kernel": kernel, "stage_ms": rl["ms"]}
+
+    out = {
+        "metric": METRIC,
+        "value": round(m["fps"], 2),
+        "unit": "FPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(m["ms_per_frame"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"cfg1: 1,000,000 seeded Gaussians, 1920x1080, {main_path} path "
+                               "(INT8 SH + FP16 geometry, 32-bit key, fused front end, dual-pixel, "
+                               "bit-level exp)" if main_path == "fast" else
+                               "cfg1: 1,000,000 seeded Gaussians, 1920x1080, plain path",
+                   "n_gaussians": sc1.n, "width": 1920, "height": 1080, "path": main_path},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(sc1, cam1, args.cpu_tiles)
+    out["latency_ms"] = m["latency_ms"]
+    out["paths_1080p"] = {p: {k: r[k] for k in ("fps", "ms_per_frame", "latency_ms", "stage_ms", "n_visible",
+                                                  "n_entries", "pairs", "passes", "roofline")}
+                          for p, r in res1.items()}
+    if "fast" in res1 and "plain" in res1:
+        out["speedup_fast_over_plain_1080p"] = round(res1["fast"]["fps"] / res1["plain"]["fps"], 3)
+    if res2:
+        out["paths_4k_orbit"] = {p: {k: r[k] for k in ("fps", "ms_per_frame", "latency_ms", "stage_ms",
+                                                         "n_visible", "n_entries", "pairs", "passes",
+                                                         "roofline_pose0")}
+                                 for p, r in res2.items()}
+        if "fast" in res2 and "plain" in res2:
+            out["speedup_fast_over_plain_4k"] = round(res2["fast"]["fps"] / res2["plain"]["fps"], 3)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

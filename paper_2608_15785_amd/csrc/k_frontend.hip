@@ -10,7 +10,9 @@
 // all of it in one pass over the compact attributes.  Each thread projects one
 // Gaussian and keeps its rectangle and quantised depth on chip; the block
 // computes a prefix sum of the tile counts in LDS and obtains its global
-// offset with one ticket atomic and a decoupled look-back over earlier blocks,
+// offset with one ticket atomic and a decoupled look-back over earlier blocks
+// (the visible-Gaussian count rides along in the same scan, so no counter is
+// incremented by every block),
 // which keeps allocation in Gaussian-index order (a plain atomic per block
 // would make the order, and with it the tie order of equal keys,
 // nondeterministic).  The block's entries are then written cooperatively:
@@ -139,32 +141,51 @@ void launch_reset(hipStream_t s, const WsDev& ws, uint64_t zero_bytes, const Fra
 }
 
 // ---------------------------------------------------------------------------
-// Chained scan across blocks (decoupled look-back, one wave).  Block vb
-// publishes its aggregate, then sums predecessors' aggregates until it meets
-// an inclusive prefix; blocks take vb from a ticket counter, so every block
-// waits only on blocks that are already running.
+// Chained scan across blocks (decoupled look-back).  Block vb publishes its
+// aggregate (entries, visible Gaussians), then sums predecessors' aggregates
+// until it meets an inclusive prefix.  One wave polls 64 x LB_PER_LANE
+// predecessors per round trip, nearest first.  Blocks take vb from a ticket
+// counter, so a block only ever waits on blocks that are already running.
 
-__device__ uint64_t chained_exclusive(uint64_t* states, uint32_t vb, uint64_t aggregate,
-                                      WsHeader* hdr) {
-    uint32_t lane = lane_id();
+__device__ void chained_exclusive(uint64_t* states, uint32_t vb, uint64_t agg_e, uint64_t agg_v,
+                                  WsHeader* hdr, uint64_t& ex_e, uint64_t& ex_v) {
+    const uint32_t lane = lane_id();
+    ex_e = 0;
+    ex_v = 0;
     if (vb == 0) {
-        if (lane == 0) st_state(&states[0], ST_PRE | aggregate);
-        return 0;
+        if (lane == 0) st_state(&states[0], ST_PRE | st_pack(agg_e, agg_v));
+        return;
     }
-    if (lane == 0) st_state(&states[vb], ST_AGG | aggregate);
-    uint64_t excl = 0;
+    if (lane == 0) st_state(&states[vb], ST_AGG | st_pack(agg_e, agg_v));
+    const uint64_t my_bit = 1ull << lane;
     int64_t top = (int64_t)vb - 1;
     uint32_t spins = 0;
-    uint64_t my_bit = 1ull << lane;
     while (true) {
-        int64_t idx = top - (int64_t)lane;
-        uint64_t s = idx >= 0 ? ld_state(&states[idx]) : ST_PRE;
-        uint64_t flag = s & ~ST_VAL;
-        uint64_t pre = __ballot(flag == ST_PRE);
-        uint64_t none = __ballot(flag == 0);
-        // lanes up to and including the nearest inclusive prefix (all lanes if none)
-        uint64_t upto = pre ? ((pre & (~pre + 1)) << 1) - 1 : ~0ull;
-        if (none & upto) {
+        uint64_t s[LB_PER_LANE];
+#pragma unroll
+        for (int m = 0; m < LB_PER_LANE; ++m) {
+            const int64_t idx = top - (int64_t)(lane * LB_PER_LANE + m);
+            s[m] = idx >= 0 ? ld_state(&states[idx]) : ST_PRE;    // before block 0: prefix 0
+        }
+        uint64_t le = 0, lv = 0;
+        bool has_pre = false, bad = false;
+#pragma unroll
+        for (int m = 0; m < LB_PER_LANE; ++m) {
+            if (has_pre || bad) continue;
+            const uint64_t f = s[m] & ~ST_VAL;
+            if (f == 0) {
+                bad = true;
+            } else {
+                le += st_entries(s[m]);
+                lv += st_visible(s[m]);
+                has_pre = f == ST_PRE;
+            }
+        }
+        const uint64_t pre = __ballot(has_pre);
+        const uint64_t badm = __ballot(bad);
+        // lanes up to and including the nearest one holding a prefix (all if none)
+        const uint64_t upto = pre ? ((pre & (~pre + 1)) << 1) - 1 : ~0ull;
+        if (badm & upto) {
             if (++spins > SPIN_LIMIT) {
                 if (lane == 0) atomicOr(&hdr->error, 1u);
                 break;
@@ -172,79 +193,95 @@ __device__ uint64_t chained_exclusive(uint64_t* states, uint32_t vb, uint64_t ag
             __builtin_amdgcn_s_sleep(1);
             continue;
         }
-        uint64_t v = (my_bit & upto) ? (s & ST_VAL) : 0ull;
-        excl += wave_sum(v);
+        ex_e += wave_sum((my_bit & upto) ? le : 0ull);
+        ex_v += wave_sum((my_bit & upto) ? lv : 0ull);
         if (pre) break;
-        top -= 64;
+        top -= 64 * LB_PER_LANE;
     }
-    if (lane == 0) st_state(&states[vb], ST_PRE | (excl + aggregate));
-    return excl;
+    if (lane == 0) st_state(&states[vb], ST_PRE | st_pack(ex_e + agg_e, ex_v + agg_v));
 }
 
-// Block-wide inclusive scan of one count per thread (FE_BLOCK threads), then
-// the block's global base by chained scan.  Leaves s_incl[t] = inclusive
-// prefix of thread t and returns the block total.
-__device__ inline uint32_t block_scan_and_chain(uint32_t count, uint32_t vb, WsDev& ws,
-                                                uint32_t* s_incl, uint32_t* s_wtot,
-                                                uint64_t* s_base) {
-    uint32_t lane = lane_id();
-    uint32_t wave = threadIdx.x / 64;
-    uint32_t incl = wave_inclusive_scan(count);
-    if (lane == 63) s_wtot[wave] = incl;
-    __syncthreads();
-    uint32_t total = 0, before = 0;
+// Block-wide inclusive scan of FE_ITEMS rows of per-thread counts (Gaussian
+// j = k * FE_THREADS + tid of the block sits in row k), leaving s_incl[j], then
+// the block's global base by chained scan.  Returns the block's entry total;
+// *s_base / *s_base_v receive the exclusive entry and visible counts.
+__device__ inline uint32_t block_scan_and_chain(const uint32_t (&count)[FE_ITEMS], uint32_t n_vis,
+                                                uint32_t vb, WsDev& ws, uint32_t* s_incl,
+                                                uint32_t* s_wtot, uint32_t* s_wvis, uint64_t* s_base,
+                                                uint64_t* s_base_v, uint32_t* vis_total) {
+    constexpr int WAVES = FE_THREADS / 64;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
+    const uint32_t wv = wave_sum(n_vis);
+    if (lane == 0) s_wvis[wave] = wv;
+    uint32_t carry = 0;
 #pragma unroll
-    for (int w = 0; w < FE_BLOCK / 64; ++w) {
-        uint32_t t = s_wtot[w];
-        if ((uint32_t)w < wave) before += t;
-        total += t;
+    for (int k = 0; k < FE_ITEMS; ++k) {
+        const uint32_t incl = wave_inclusive_scan(count[k]);
+        if (lane == 63) s_wtot[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            const uint32_t t = s_wtot[w];
+            if ((uint32_t)w < wave) before += t;
+            tot += t;
+        }
+        s_incl[k * FE_THREADS + threadIdx.x] = carry + before + incl;
+        carry += tot;
+        __syncthreads();
     }
-    s_incl[threadIdx.x] = incl + before;
+    uint32_t vtot = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) vtot += s_wvis[w];
+    *vis_total = vtot;
     if (wave == 0) {
-        uint64_t excl = chained_exclusive(ws.fe_state, vb, total, ws.header);
-        if (lane == 0) *s_base = excl;
+        uint64_t ex_e, ex_v;
+        chained_exclusive(ws.fe_state, vb, carry, vtot, ws.header, ex_e, ex_v);
+        if (lane == 0) {
+            *s_base = ex_e;
+            *s_base_v = ex_v;
+        }
     }
     __syncthreads();
-    return total;
+    return carry;
 }
 
-// Entry e of the block belongs to the thread t with s_incl[t-1] <= e < s_incl[t]
-// and is the (e - s_incl[t-1])-th tile of t's rectangle in row-major order.
+// Entry e of the block belongs to the Gaussian j with s_incl[j-1] <= e < s_incl[j]
+// and is the (e - s_incl[j-1])-th tile of j's rectangle in row-major order.
 template <typename KeyT, typename KeyFn>
 __device__ inline void emit_entries(uint32_t total, uint64_t base, const uint32_t* s_incl,
                                     const uint64_t* s_rect, uint32_t first_gauss, int tiles_x,
                                     uint32_t capacity, KeyT* keys, uint32_t* vals, KeyFn key_of) {
-    for (uint32_t e = threadIdx.x; e < total; e += FE_BLOCK) {
-        int lo = 0, hi = FE_BLOCK - 1;
+    for (uint32_t e = threadIdx.x; e < total; e += FE_THREADS) {
+        int lo = 0, hi = FE_TILE - 1;
         while (lo < hi) {
-            int mid = (lo + hi) >> 1;
+            const int mid = (lo + hi) >> 1;
             if (s_incl[mid] > e) hi = mid;
             else lo = mid + 1;
         }
-        uint32_t t = (uint32_t)lo;
-        uint32_t local = e - (t ? s_incl[t - 1] : 0u);
-        uint64_t rc = s_rect[t];
-        uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff;
-        uint32_t w = x1 - x0 + 1;
-        uint32_t ty = y0 + local / w;
-        uint32_t tx = x0 + local % w;
-        uint32_t tile = ty * (uint32_t)tiles_x + tx;
-        uint64_t pos = base + e;
+        const uint32_t j = (uint32_t)lo;
+        const uint32_t local = e - (j ? s_incl[j - 1] : 0u);
+        const uint64_t rc = s_rect[j];
+        const uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff;
+        const uint32_t w = x1 - x0 + 1;
+        const uint32_t ty = y0 + local / w;
+        const uint32_t tx = x0 + local % w;
+        const uint32_t tile = ty * (uint32_t)tiles_x + tx;
+        const uint64_t pos = base + e;
         if (pos < capacity) {
-            keys[pos] = key_of(tile, t);
-            vals[pos] = first_gauss + t;
+            keys[pos] = key_of(tile, j);
+            vals[pos] = first_gauss + j;
         }
     }
 }
 
 __device__ inline void finish_block(WsDev& ws, uint32_t vb, uint32_t n_blocks, uint64_t base,
-                                    uint32_t total, uint32_t capacity, uint32_t visible) {
-    uint32_t lane = lane_id();
-    uint32_t vis = wave_sum(visible);
-    if (lane == 0 && vis) atomicAdd(&ws.header->n_visible, vis);
+                                    uint64_t base_v, uint32_t total, uint32_t vis_total,
+                                    uint32_t capacity) {
     if (vb == n_blocks - 1 && threadIdx.x == 0) {
-        uint64_t n = base + total;
+        const uint64_t n = base + total;
         ws.header->n_entries = n;
+        ws.header->n_visible = (uint32_t)(base_v + vis_total);
         ws.header->overflow = n > capacity ? 1u : 0u;
     }
 }
@@ -289,8 +326,6 @@ __global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, CamD
         }
         if (DEBUG) write_debug(dbg, i, pr, vis, r, g, b);
     }
-    uint32_t vcount = wave_sum(vis ? 1u : 0u);
-    if (lane_id() == 0 && vcount) atomicAdd(&ws.header->n_visible, vcount);
 }
 
 void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam,
@@ -306,123 +341,158 @@ void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const CamDe
 // ---------------------------------------------------------------------------
 // Plain duplication: ordered allocation over the stored counts, 64-bit keys.
 
-__global__ __launch_bounds__(FE_BLOCK) void k_duplicate_plain(int64_t n, FrameDev f, WsDev ws,
-                                                              uint32_t n_blocks) {
+__global__ __launch_bounds__(FE_THREADS) void k_duplicate_plain(int64_t n, FrameDev f, WsDev ws,
+                                                                uint32_t n_blocks) {
     __shared__ uint32_t s_vb;
-    __shared__ uint32_t s_incl[FE_BLOCK];
-    __shared__ uint64_t s_rect[FE_BLOCK];
-    __shared__ uint32_t s_dbits[FE_BLOCK];
-    __shared__ uint32_t s_wtot[FE_BLOCK / 64];
-    __shared__ uint64_t s_base;
+    __shared__ uint32_t s_incl[FE_TILE];
+    __shared__ uint64_t s_rect[FE_TILE];
+    __shared__ uint32_t s_dbits[FE_TILE];
+    __shared__ uint32_t s_wtot[FE_THREADS / 64];
+    __shared__ uint32_t s_wvis[FE_THREADS / 64];
+    __shared__ uint64_t s_base, s_base_v;
     if (threadIdx.x == 0) s_vb = atomicAdd(&ws.header->fe_ticket, 1u);
     __syncthreads();
-    uint32_t vb = s_vb;
-    int64_t i = (int64_t)vb * FE_BLOCK + threadIdx.x;
-    uint32_t count = 0;
-    if (i < n) {
-        count = ws.counts[i];
-        if (count) {
-            s_rect[threadIdx.x] = ws.rects[i];
-            s_dbits[threadIdx.x] = __float_as_uint(ws.depths[i]);
+    const uint32_t vb = s_vb;
+    uint32_t count[FE_ITEMS];
+    uint32_t n_vis = 0;
+#pragma unroll
+    for (int k = 0; k < FE_ITEMS; ++k) {
+        const uint32_t j = k * FE_THREADS + threadIdx.x;
+        const int64_t i = (int64_t)vb * FE_TILE + j;
+        count[k] = 0;
+        if (i < n) {
+            count[k] = ws.counts[i];
+            if (count[k]) {
+                s_rect[j] = ws.rects[i];
+                s_dbits[j] = __float_as_uint(ws.depths[i]);
+                ++n_vis;
+            }
         }
     }
-    uint32_t total = block_scan_and_chain(count, vb, ws, s_incl, s_wtot, &s_base);
-    uint64_t base = s_base;
+    uint32_t vis_total;
+    const uint32_t total = block_scan_and_chain(count, n_vis, vb, ws, s_incl, s_wtot, s_wvis, &s_base,
+                                                &s_base_v, &vis_total);
+    const uint64_t base = s_base;
     uint64_t* keys = reinterpret_cast<uint64_t*>(ws.keys_a);
-    emit_entries<uint64_t>(total, base, s_incl, s_rect, vb * FE_BLOCK, f.tiles_x, f.capacity, keys,
-                           ws.vals_a, [&](uint32_t tile, uint32_t t) {
-                               return ((uint64_t)tile << 32) | (uint64_t)s_dbits[t];
+    emit_entries<uint64_t>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity, keys,
+                           ws.vals_a, [&](uint32_t tile, uint32_t j) {
+                               return ((uint64_t)tile << 32) | (uint64_t)s_dbits[j];
                            });
-    finish_block(ws, vb, n_blocks, base, total, f.capacity, 0u);
+    finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
 }
 
 void launch_duplicate_plain(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws,
                             uint32_t fe_blocks) {
-    hipLaunchKernelGGL(k_duplicate_plain, dim3(fe_blocks), dim3(FE_BLOCK), 0, s, n, f, ws, fe_blocks);
+    hipLaunchKernelGGL(k_duplicate_plain, dim3(fe_blocks), dim3(FE_THREADS), 0, s, n, f, ws, fe_blocks);
 }
 
 // ---------------------------------------------------------------------------
 // Fused fast front end over the compact planes: project, cull, colour, scan,
 // allocate in order and emit 32-bit (tile << b_d | q_d) keys.
 
+// Project, cull and colour Gaussian i of the compact planes.  Returns its tile
+// count (0 when culled) and leaves its rectangle and quantised depth.
 template <bool DEBUG>
-__global__ __launch_bounds__(FE_BLOCK) void k_frontend_fast(FastSceneDev sc, CamDev cam, FrameDev f,
-                                                            WsDev ws, uint32_t n_blocks,
-                                                            DebugDev dbg) {
+__device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& cam, const FrameDev& f,
+                                         WsDev& ws, const DebugDev& dbg, int64_t i, uint64_t& rect,
+                                         uint32_t& qd) {
+    const uint32_t* W = sc.base;
+    const uint64_t np = sc.n_pad;
+    const float mx = __uint_as_float(W[F_MX * np + i]);
+    const float my = __uint_as_float(W[F_MY * np + i]);
+    const float mz = __uint_as_float(W[F_MZ * np + i]);
+    const uint32_t qwx = W[F_QWX * np + i], qyz = W[F_QYZ * np + i];
+    const uint32_t sxy = W[F_SXY * np + i], szl = W[F_SZL * np + i];
+    const float lno = half_hi(szl);
+    Projected pr;
+    const bool vis = project_gaussian(cam, mx, my, mz, half_lo(qwx), half_hi(qwx), half_lo(qyz),
+                                      half_hi(qyz), half_lo(sxy), half_hi(sxy), half_lo(szl), true,
+                                      (double)lno, (double)f.tiles_x, (double)f.tiles_y, pr);
+    float r = 0.f, g = 0.f, b = 0.f;
+    uint32_t count = 0;
+    if (vis) {
+        uint32_t qw[12], sw[6];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) qw[k] = W[(F_SHQ0 + k) * np + i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sw[k] = W[(F_SHS0 + k) * np + i];
+        const ShBasis y = view_basis(mx, my, mz, cam);
+        float acc[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int deg = k == 0 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3));
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const int v = 3 * k + ch;
+                const float q = (float)(int8_t)((qw[v >> 2] >> (8 * (v & 3))) & 0xffu);
+                const int si = 3 * deg + ch;
+                const float scale = (si & 1) ? half_hi(sw[si >> 1]) : half_lo(sw[si >> 1]);
+                acc[ch] = fmaf(y.y[k], q * scale, acc[ch]);
+            }
+        }
+        r = fmaxf(acc[0], 0.f);
+        g = fmaxf(acc[1], 0.f);
+        b = fmaxf(acc[2], 0.f);
+        write_record(&ws.records[i], pr, lno, r, g, b);
+        rect = pack_rect(pr);
+        qd = quantize_depth(pr.d, cam.zn, cam.zf, f.b_d);
+        count = rect_count(rect);
+    }
+    if (DEBUG) write_debug(dbg, i, pr, vis, r, g, b);
+    return count;
+}
+
+template <bool DEBUG>
+__global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, CamDev cam, FrameDev f,
+                                                              WsDev ws, uint32_t n_blocks,
+                                                              DebugDev dbg) {
     __shared__ uint32_t s_vb;
-    __shared__ uint32_t s_incl[FE_BLOCK];
-    __shared__ uint64_t s_rect[FE_BLOCK];
-    __shared__ uint32_t s_qd[FE_BLOCK];
-    __shared__ uint32_t s_wtot[FE_BLOCK / 64];
-    __shared__ uint64_t s_base;
+    __shared__ uint32_t s_incl[FE_TILE];
+    __shared__ uint64_t s_rect[FE_TILE];
+    __shared__ uint32_t s_qd[FE_TILE];
+    __shared__ uint32_t s_wtot[FE_THREADS / 64];
+    __shared__ uint32_t s_wvis[FE_THREADS / 64];
+    __shared__ uint64_t s_base, s_base_v;
     if (threadIdx.x == 0) s_vb = atomicAdd(&ws.header->fe_ticket, 1u);
     __syncthreads();
-    uint32_t vb = s_vb;
-    int64_t i = (int64_t)vb * FE_BLOCK + threadIdx.x;
-    uint32_t count = 0;
-    bool vis = false;
-    if (i < sc.n) {
-        const uint32_t* W = sc.base;
-        const uint64_t np = sc.n_pad;
-        float mx = __uint_as_float(W[F_MX * np + i]);
-        float my = __uint_as_float(W[F_MY * np + i]);
-        float mz = __uint_as_float(W[F_MZ * np + i]);
-        uint32_t qwx = W[F_QWX * np + i], qyz = W[F_QYZ * np + i];
-        uint32_t sxy = W[F_SXY * np + i], szl = W[F_SZL * np + i];
-        float lno = half_hi(szl);
-        Projected pr;
-        vis = project_gaussian(cam, mx, my, mz, half_lo(qwx), half_hi(qwx), half_lo(qyz),
-                               half_hi(qyz), half_lo(sxy), half_hi(sxy), half_lo(szl), true,
-                               (double)lno, (double)f.tiles_x, (double)f.tiles_y, pr);
-        float r = 0.f, g = 0.f, b = 0.f;
-        if (vis) {
-            uint32_t qw[12], sw[6];
+    const uint32_t vb = s_vb;
+    uint32_t count[FE_ITEMS];
+    uint32_t n_vis = 0;
 #pragma unroll
-            for (int k = 0; k < 12; ++k) qw[k] = W[(F_SHQ0 + k) * np + i];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) sw[k] = W[(F_SHS0 + k) * np + i];
-            ShBasis y = view_basis(mx, my, mz, cam);
-            float acc[3] = {0.5f, 0.5f, 0.5f};
-#pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int deg = k == 0 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3));
-#pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    const int v = 3 * k + ch;
-                    float q = (float)(int8_t)((qw[v >> 2] >> (8 * (v & 3))) & 0xffu);
-                    const int si = 3 * deg + ch;
-                    float sc_ = (si & 1) ? half_hi(sw[si >> 1]) : half_lo(sw[si >> 1]);
-                    acc[ch] = fmaf(y.y[k], q * sc_, acc[ch]);
-                }
+    for (int k = 0; k < FE_ITEMS; ++k) {
+        const uint32_t j = k * FE_THREADS + threadIdx.x;
+        const int64_t i = (int64_t)vb * FE_TILE + j;
+        count[k] = 0;
+        if (i < sc.n) {
+            uint64_t rect = 0;
+            uint32_t qd = 0;
+            count[k] = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, qd);
+            if (count[k]) {
+                s_rect[j] = rect;
+                s_qd[j] = qd;
+                ++n_vis;
             }
-            r = fmaxf(acc[0], 0.f);
-            g = fmaxf(acc[1], 0.f);
-            b = fmaxf(acc[2], 0.f);
-            write_record(&ws.records[i], pr, lno, r, g, b);
-            uint64_t rc = pack_rect(pr);
-            s_rect[threadIdx.x] = rc;
-            s_qd[threadIdx.x] = quantize_depth(pr.d, cam.zn, cam.zf, f.b_d);
-            count = rect_count(rc);
         }
-        if (DEBUG) write_debug(dbg, i, pr, vis, r, g, b);
     }
-    uint32_t total = block_scan_and_chain(count, vb, ws, s_incl, s_wtot, &s_base);
-    uint64_t base = s_base;
+    uint32_t vis_total;
+    const uint32_t total = block_scan_and_chain(count, n_vis, vb, ws, s_incl, s_wtot, s_wvis, &s_base,
+                                                &s_base_v, &vis_total);
+    const uint64_t base = s_base;
     const int bd = f.b_d;
-    emit_entries<uint32_t>(total, base, s_incl, s_rect, vb * FE_BLOCK, f.tiles_x, f.capacity,
+    emit_entries<uint32_t>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
                            reinterpret_cast<uint32_t*>(ws.keys_a), ws.vals_a,
-                           [&](uint32_t tile, uint32_t t) { return (tile << bd) | s_qd[t]; });
-    finish_block(ws, vb, n_blocks, base, total, f.capacity, vis ? 1u : 0u);
+                           [&](uint32_t tile, uint32_t j) { return (tile << bd) | s_qd[j]; });
+    finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
 }
 
 void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const CamDev& cam,
                           const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
                           const DebugDev* dbg) {
     if (dbg)
-        hipLaunchKernelGGL(k_frontend_fast<true>, dim3(fe_blocks), dim3(FE_BLOCK), 0, s, sc, cam, f, ws,
+        hipLaunchKernelGGL(k_frontend_fast<true>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, cam, f, ws,
                            fe_blocks, *dbg);
     else
-        hipLaunchKernelGGL(k_frontend_fast<false>, dim3(fe_blocks), dim3(FE_BLOCK), 0, s, sc, cam, f,
+        hipLaunchKernelGGL(k_frontend_fast<false>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, cam, f,
                            ws, fe_blocks, DebugDev{});
 }
 

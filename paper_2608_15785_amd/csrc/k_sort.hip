@@ -2,23 +2,26 @@
 //
 // LSD radix sort with 8-bit digits over the significant bits of the key
 // (plain: 32 + b_t bits of the 64-bit key; fast: the 32-bit key, 4 passes),
-// value = Gaussian index.  The traffic model of Eq. sort_memory counts one
-// read and one write of every (key, value) entry per pass; this sort meets it
-// with one kernel per pass:
-//   * `radix_hist` reads all keys once and builds the digit histogram of every
-//     pass; `radix_scan` turns each into global digit offsets;
-//   * `radix_pass` takes a tile of 4096 entries per block (ticket-ordered
-//     block index), ranks each key among equal digits inside the tile with
-//     wave64 ballots (stable: tile order is input order), publishes the tile's
-//     digit counts and obtains each digit's offset among earlier tiles by
-//     decoupled look-back, reorders the tile in LDS by digit and writes it out,
-//     so consecutive threads store consecutive positions of a digit bucket.
+// value = Gaussian index.  Eq. sort_memory counts one read and one write of
+// every (key, value) entry per pass.  A frame's whole grid of radix tiles is
+// resident on the 256 CUs at once, so the tiles cannot pass digit offsets
+// along a look-back chain without waiting on each other; each pass is instead
+// a reduce-then-scan:
+//   * `radix_hist` (once per sort) reads all keys and builds every pass's
+//     global digit histogram, the bases of the digit buckets;
+//   * `radix_upsweep` counts each 4096-entry tile's digits (keys only);
+//   * `radix_offsets` scans, for each digit in its own workgroup, the tiles'
+//     counts into the tile's output offset inside that digit's bucket;
+//   * `radix_scatter` ranks each key among equal digits of its tile with wave64
+//     ballots (stable: tile order is input order), reorders the tile in LDS by
+//     digit and writes it out, so consecutive threads store consecutive
+//     positions of a digit bucket.
 // Ties keep input order, and the front end emits entries in Gaussian-index
 // order, so equal keys end ordered by Gaussian index.
 //
 // Grids are sized for the workspace capacity; the entry count is read from
-// the workspace header on the device, blocks beyond it return at once, so no
-// host round trip sits between the front end and the sort.
+// the workspace header on the device and tiles beyond it return at once, so
+// no host round trip sits between the front end and the sort.
 #include "rgs_internal.h"
 
 namespace rgs {
@@ -48,28 +51,34 @@ __device__ inline uint32_t block256_inclusive_scan(uint32_t x, uint32_t* s_wtot)
     return incl + before;
 }
 
+constexpr int HIST_THREADS = 1024;
+constexpr int HIST_ITEMS = 8;
+
 template <typename KeyT>
-__global__ __launch_bounds__(256) void k_radix_hist(const KeyT* __restrict__ keys, WsDev ws,
-                                                    uint32_t passes, uint32_t sort_blocks_max) {
+__global__ __launch_bounds__(HIST_THREADS) void k_radix_hist(const KeyT* __restrict__ keys, WsDev ws,
+                                                             uint32_t passes, uint32_t sort_blocks_max) {
     __shared__ uint32_t s_h[MAX_PASSES * RADIX];
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += 256) s_h[i] = 0;
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += HIST_THREADS) s_h[i] = 0;
     const uint32_t n = entry_count(ws.header);
-    // clear the look-back state of the tiles the passes will run
-    const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint32_t p = 0; p < passes; ++p) {
-        uint32_t* st = ws.lookback + (uint64_t)p * sort_blocks_max * RADIX;
-        for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < (uint64_t)nb * RADIX; i += stride)
-            st[i] = 0;
+    (void)sort_blocks_max;
+    __syncthreads();
+    const uint64_t chunk = (uint64_t)HIST_THREADS * HIST_ITEMS;
+    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk) {
+        KeyT k[HIST_ITEMS];
+#pragma unroll
+        for (int m = 0; m < HIST_ITEMS; ++m) {
+            const uint64_t idx = base + (uint64_t)m * HIST_THREADS + threadIdx.x;
+            k[m] = idx < n ? keys[idx] : (KeyT)0;
+        }
+#pragma unroll
+        for (int m = 0; m < HIST_ITEMS; ++m) {
+            if (base + (uint64_t)m * HIST_THREADS + threadIdx.x < n)
+                for (uint32_t p = 0; p < passes; ++p) atomicAdd(&s_h[p * RADIX + digit_of(k[m], 8 * p)], 1u);
+        }
     }
     __syncthreads();
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-        KeyT k = keys[i];
-        for (uint32_t p = 0; p < passes; ++p) atomicAdd(&s_h[p * RADIX + digit_of(k, 8 * p)], 1u);
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += 256) {
-        uint32_t v = s_h[i];
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += HIST_THREADS) {
+        const uint32_t v = s_h[i];
         if (v) atomicAdd(&ws.hist[i], v);
     }
 }
@@ -83,16 +92,56 @@ __global__ __launch_bounds__(256) void k_radix_scan(WsDev ws, uint32_t passes) {
     }
 }
 
+// Per-tile digit counts, digit-major: counts[d * nb_max + tile].
 template <typename KeyT>
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restrict__ kin,
-                                                             const uint32_t* __restrict__ vin,
-                                                             KeyT* __restrict__ kout,
-                                                             uint32_t* __restrict__ vout, WsDev ws,
-                                                             uint32_t pass, uint32_t shift,
-                                                             uint32_t sort_blocks_max) {
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_upsweep(const KeyT* __restrict__ kin, WsDev ws,
+                                                                uint32_t shift, uint32_t nb_max) {
+    __shared__ uint32_t s_h[RADIX];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t n = entry_count(ws.header);
+    const uint32_t tile_base = blockIdx.x * SORT_TILE;
+    if (tile_base >= n) return;
+    KeyT k[SORT_ITEMS];
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+        const uint32_t idx = tile_base + r * SORT_THREADS + threadIdx.x;
+        k[r] = idx < n ? kin[idx] : (KeyT)0;
+    }
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r)
+        if (tile_base + r * SORT_THREADS + threadIdx.x < n) atomicAdd(&s_h[digit_of(k[r], shift)], 1u);
+    __syncthreads();
+    ws.tile_counts[(uint64_t)threadIdx.x * nb_max + blockIdx.x] = s_h[threadIdx.x];
+}
+
+// Digit d (one workgroup each): exclusive scan of its per-tile counts plus the
+// digit's bucket base, in place.
+__global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t pass, uint32_t nb_max) {
+    __shared__ uint32_t s_wtot[4];
+    const uint32_t d = blockIdx.x;
+    const uint32_t n = entry_count(ws.header);
+    const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+    uint32_t* row = ws.tile_counts + (uint64_t)d * nb_max;
+    uint32_t carry = ws.hist[pass * RADIX + d];
+    for (uint32_t c = 0; c < nb; c += 256) {
+        const uint32_t i = c + threadIdx.x;
+        const uint32_t v = i < nb ? row[i] : 0u;
+        const uint32_t incl = block256_inclusive_scan(v, s_wtot);
+        if (i < nb) row[i] = carry + incl - v;
+        carry += s_wtot[0] + s_wtot[1] + s_wtot[2] + s_wtot[3];
+        __syncthreads();
+    }
+}
+
+template <typename KeyT>
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const KeyT* __restrict__ kin,
+                                                                const uint32_t* __restrict__ vin,
+                                                                KeyT* __restrict__ kout,
+                                                                uint32_t* __restrict__ vout, WsDev ws,
+                                                                uint32_t shift, uint32_t nb_max) {
     constexpr int WAVES = SORT_THREADS / 64;
     static_assert(SORT_THREADS == RADIX, "one thread per digit");
-    __shared__ uint32_t s_vb;
     __shared__ uint32_t s_whist[WAVES * RADIX];
     __shared__ uint32_t s_bstart[RADIX];
     __shared__ uint32_t s_gbase[RADIX];
@@ -101,13 +150,12 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
     __shared__ uint32_t s_vals[SORT_TILE];
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
-    if (tid == 0) s_vb = atomicAdd(&ws.header->sort_ticket[pass], 1u);
-    for (uint32_t i = tid; i < WAVES * RADIX; i += SORT_THREADS) s_whist[i] = 0;
-    __syncthreads();
-    const uint32_t vb = s_vb;
+    const uint32_t vb = blockIdx.x;
     const uint32_t n = entry_count(ws.header);
     const uint32_t tile_base = vb * SORT_TILE;
     if (tile_base >= n) return;
+    for (uint32_t i = tid; i < WAVES * RADIX; i += SORT_THREADS) s_whist[i] = 0;
+    __syncthreads();
     const uint32_t n_valid = min((uint32_t)SORT_TILE, n - tile_base);
 
     // wave w owns entries [tile_base + w*ITEMS*64, +ITEMS*64); round r, lane l
@@ -118,8 +166,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
     uint32_t rank[SORT_ITEMS];
 #pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
-        uint32_t idx = wbase + r * 64 + lane;
-        bool valid = idx < n;
+        const uint32_t idx = wbase + r * 64 + lane;
+        const bool valid = idx < n;
         k[r] = valid ? kin[idx] : (KeyT)0;
         v[r] = valid ? vin[idx] : 0u;
     }
@@ -130,81 +178,54 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
     volatile uint32_t* my_hist = s_whist + wave * RADIX;
 #pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
-        uint32_t idx = wbase + r * 64 + lane;
-        bool valid = idx < n;
-        uint32_t d = digit_of(k[r], shift);
+        const uint32_t idx = wbase + r * 64 + lane;
+        const bool valid = idx < n;
+        const uint32_t d = digit_of(k[r], shift);
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < RADIX_BITS; ++b) {
-            bool bit = (d >> b) & 1u;
-            uint64_t m = __ballot(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        uint32_t below = (uint32_t)__popcll(peers & lt);
-        uint32_t prev = valid ? my_hist[d] : 0u;
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t prev = valid ? my_hist[d] : 0u;
         rank[r] = prev + below;
         if (valid && below == 0) my_hist[d] = prev + (uint32_t)__popcll(peers);
     }
     __syncthreads();
 
-    // digit d = tid: wave offsets, tile count, look-back, global base
+    // digit d = tid: wave offsets, tile count, tile-local start, global base
     {
         const uint32_t d = tid;
         uint32_t tot = 0;
 #pragma unroll
         for (int w = 0; w < WAVES; ++w) {
-            uint32_t c = s_whist[w * RADIX + d];
+            const uint32_t c = s_whist[w * RADIX + d];
             s_whist[w * RADIX + d] = tot;
             tot += c;
         }
-        uint32_t* st = ws.lookback + ((uint64_t)pass * sort_blocks_max + vb) * RADIX;
-        st_state(&st[d], (vb == 0 ? RS_PRE : RS_AGG) | tot);
-        uint32_t incl = block256_inclusive_scan(tot, s_wtot);
+        const uint32_t incl = block256_inclusive_scan(tot, s_wtot);
         s_bstart[d] = incl - tot;
-        uint32_t excl = 0;
-        if (vb > 0) {
-            int64_t j = (int64_t)vb - 1;
-            uint32_t spins = 0;
-            const uint32_t* base = ws.lookback + (uint64_t)pass * sort_blocks_max * RADIX + d;
-            while (j >= 0) {
-                uint32_t s = ld_state(base + (uint64_t)j * RADIX);
-                uint32_t f = s & ~RS_VAL;
-                if (f == RS_PRE) {
-                    excl += s & RS_VAL;
-                    break;
-                }
-                if (f == RS_AGG) {
-                    excl += s & RS_VAL;
-                    --j;
-                    continue;
-                }
-                if (++spins > SPIN_LIMIT) {
-                    atomicOr(&ws.header->error, 2u);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            st_state(&st[d], RS_PRE | (excl + tot));
-        }
-        s_gbase[d] = ws.hist[pass * RADIX + d] + excl - (incl - tot);
+        s_gbase[d] = ws.tile_counts[(uint64_t)d * nb_max + vb] - (incl - tot);
     }
     __syncthreads();
 
 #pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
-        uint32_t idx = wbase + r * 64 + lane;
+        const uint32_t idx = wbase + r * 64 + lane;
         if (idx < n) {
-            uint32_t d = digit_of(k[r], shift);
-            uint32_t pos = s_bstart[d] + my_hist[d] + rank[r];
+            const uint32_t d = digit_of(k[r], shift);
+            const uint32_t pos = s_bstart[d] + s_whist[wave * RADIX + d] + rank[r];
             s_keys[pos] = k[r];
             s_vals[pos] = v[r];
         }
     }
     __syncthreads();
     for (uint32_t p = tid; p < n_valid; p += SORT_THREADS) {
-        KeyT kk = s_keys[p];
-        uint32_t dst = s_gbase[digit_of(kk, shift)] + p;
-        if (dst < n) {        // always true unless a look-back gave up (flagged above)
+        const KeyT kk = s_keys[p];
+        const uint32_t dst = s_gbase[digit_of(kk, shift)] + p;
+        if (dst < n) {        // always true for consistent counts; guards the bounds regardless
             kout[dst] = kk;
             vout[dst] = s_vals[p];
         }
@@ -212,18 +233,22 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
 }
 
 template <typename KeyT>
-static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, uint32_t sort_blocks_max,
+static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, uint32_t nb_max,
                        bool* result_in_b) {
     KeyT* ka = reinterpret_cast<KeyT*>(ws.keys_a);
     KeyT* kb = reinterpret_cast<KeyT*>(ws.keys_b);
-    hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(HIST_BLOCKS), dim3(256), 0, s, ka, ws, passes,
-                       sort_blocks_max);
+    hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(HIST_BLOCKS), dim3(HIST_THREADS), 0, s, ka, ws, passes,
+                       nb_max);
     hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, ws, passes);
     for (uint32_t p = 0; p < passes; ++p) {
-        bool from_a = (p % 2) == 0;
-        hipLaunchKernelGGL(k_radix_pass<KeyT>, dim3(sort_blocks_max), dim3(SORT_THREADS), 0, s,
-                           from_a ? ka : kb, from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka,
-                           from_a ? ws.vals_b : ws.vals_a, ws, p, 8 * p, sort_blocks_max);
+        const bool from_a = (p % 2) == 0;
+        const KeyT* kin = from_a ? ka : kb;
+        hipLaunchKernelGGL(k_radix_upsweep<KeyT>, dim3(nb_max), dim3(SORT_THREADS), 0, s, kin, ws, 8 * p,
+                           nb_max);
+        hipLaunchKernelGGL(k_radix_offsets, dim3(RADIX), dim3(256), 0, s, ws, p, nb_max);
+        hipLaunchKernelGGL(k_radix_scatter<KeyT>, dim3(nb_max), dim3(SORT_THREADS), 0, s, kin,
+                           from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
+                           ws, 8 * p, nb_max);
     }
     *result_in_b = (passes % 2) == 1;
 }

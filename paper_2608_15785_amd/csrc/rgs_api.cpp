@@ -128,7 +128,7 @@ static const int kDegreeStart[5] = {0, 1, 4, 9, 16};
 static rgs_status validate_desc(const rgs_scene_desc* d) {
     if (!d) return fail(RGS_E_INVALID, "scene desc is NULL");
     if (d->n < 1) return fail(RGS_E_INVALID, "scene has n = %lld < 1", (long long)d->n);
-    if (d->n > (int64_t)0x7fffffff) return fail(RGS_E_INVALID, "scene too large");
+    if (d->n > (int64_t)((1 << 30) - 1)) return fail(RGS_E_INVALID, "scene too large (n >= 2^30)");
     if (d->sh_degree != 3) return fail(RGS_E_INVALID, "sh_degree %d != 3", d->sh_degree);
     if (!d->means || !d->scales || !d->quats || !d->opacity || !d->sh)
         return fail(RGS_E_INVALID, "scene desc has a NULL array");
@@ -433,7 +433,7 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     L.capacity = capacity;
     L.key_bytes = plain ? 8 : 4;
     L.passes = plain ? (uint32_t)p.plain_passes : (uint32_t)p.fast_passes;
-    L.fe_blocks = (uint32_t)((n + FE_BLOCK - 1) / FE_BLOCK);
+    L.fe_blocks = (uint32_t)((n + FE_TILE - 1) / FE_TILE);
     L.sort_blocks_max = (uint32_t)((capacity + SORT_TILE - 1) / SORT_TILE);
     uint64_t off = 0;
     L.header = off;
@@ -464,8 +464,8 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     off = align256(off + capacity * 4);
     L.vals_b = off;
     off = align256(off + capacity * 4);
-    L.lookback = off;
-    off = align256(off + (uint64_t)L.passes * L.sort_blocks_max * RADIX * 4);
+    L.tile_counts = off;
+    off = align256(off + (uint64_t)L.sort_blocks_max * RADIX * 4);
     L.t_final = off;
     off = align256(off + (uint64_t)p.width * p.height * 4);
     L.n_proc = off;
@@ -537,7 +537,7 @@ static WsDev ws_pointers(void* base, const WsLayout& L) {
     w.vals_a = reinterpret_cast<uint32_t*>(b + L.vals_a);
     w.vals_b = reinterpret_cast<uint32_t*>(b + L.vals_b);
     w.hist = reinterpret_cast<uint32_t*>(b + L.hist);
-    w.lookback = reinterpret_cast<uint32_t*>(b + L.lookback);
+    w.tile_counts = reinterpret_cast<uint32_t*>(b + L.tile_counts);
     w.t_final = reinterpret_cast<float*>(b + L.t_final);
     w.n_proc = reinterpret_cast<uint32_t*>(b + L.n_proc);
     return w;

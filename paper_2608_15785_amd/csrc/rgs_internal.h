@@ -25,7 +25,10 @@ constexpr float ALPHA_MAX = 0.99f;   // Eq. opacity_clamped
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float T_MIN = 1e-4f;       // stop blending a pixel below this transmittance
 
-constexpr int FE_BLOCK = 256;        // Gaussians per front-end block
+constexpr int FE_THREADS = 1024;     // threads per front-end / duplication block
+constexpr int FE_ITEMS = 2;          // Gaussians per thread (block-strided)
+constexpr int FE_TILE = FE_THREADS * FE_ITEMS;   // Gaussians per block
+constexpr int LB_PER_LANE = 8;       // look-back states each lane polls per round trip
 constexpr int SORT_THREADS = 256;    // 4 waves
 constexpr int SORT_ITEMS = 16;       // keys per thread per radix tile
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
@@ -79,14 +82,13 @@ struct WsHeader {
     uint64_t n_entries;       // entries requested by the front end
     uint32_t n_visible;
     uint32_t overflow;
-    uint32_t error;           // bit 0: front-end look-back gave up; bit 1: sort look-back;
+    uint32_t error;           // bit 0: front-end look-back gave up;
                               // bit 2: a sorted key named a tile outside the grid
     uint32_t capacity;
     uint32_t path;
     uint32_t passes;
     uint32_t fe_ticket;
-    uint32_t sort_ticket[MAX_PASSES];
-    uint32_t pad[64 - 17];
+    uint32_t pad[55];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte slot");
 
@@ -95,7 +97,7 @@ struct WsLayout {
     uint64_t header, ranges, fe_state, zero_end;
     uint64_t records, counts, rects, depths;
     uint64_t keys_a, keys_b, vals_a, vals_b;
-    uint64_t hist, lookback;
+    uint64_t hist, tile_counts;
     uint64_t t_final, n_proc;
     uint64_t total;
     uint64_t capacity;
@@ -116,7 +118,7 @@ struct WsDev {
     uint32_t* vals_a;
     uint32_t* vals_b;
     uint32_t* hist;           // [MAX_PASSES][RADIX] counts, then exclusive offsets
-    uint32_t* lookback;       // [passes][sort blocks][RADIX]
+    uint32_t* tile_counts;    // [RADIX][sort tiles]: per-tile digit counts, then offsets
     float* t_final;           // [H][W]
     uint32_t* n_proc;         // [H][W]
 };
@@ -287,14 +289,16 @@ __device__ inline void st_state(uint32_t* p, uint32_t v) {
 // flags the header and lets the kernel finish.
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
 
-// 64-bit chained-scan state: flag in bits 63..62 (1 aggregate, 2 inclusive prefix).
+// 64-bit chained-scan state: flag in bits 63..62 (1 aggregate, 2 inclusive
+// prefix), entry count in bits 31..0 (saturating), visible count in 61..32.
 constexpr uint64_t ST_AGG = 1ull << 62;
 constexpr uint64_t ST_PRE = 2ull << 62;
 constexpr uint64_t ST_VAL = (1ull << 62) - 1;
-// 32-bit radix look-back state: flag in bits 31..30, count in bits 29..0.
-constexpr uint32_t RS_AGG = 1u << 30;
-constexpr uint32_t RS_PRE = 2u << 30;
-constexpr uint32_t RS_VAL = (1u << 30) - 1;
+__host__ __device__ inline uint64_t st_pack(uint64_t entries, uint64_t visible) {
+    return (entries > 0xffffffffull ? 0xffffffffull : entries) | (visible << 32);
+}
+__host__ __device__ inline uint64_t st_entries(uint64_t s) { return s & 0xffffffffull; }
+__host__ __device__ inline uint64_t st_visible(uint64_t s) { return (s >> 32) & ((1ull << 30) - 1); }
 
 // ---------------------------------------------------------------------------
 // Host-side launch wrappers (defined in the .hip files).

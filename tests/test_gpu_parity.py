@@ -132,7 +132,12 @@ def test_invalid_arguments(R):
     bad.z_near, bad.z_far = 3.0, 2.0
     with pytest.raises(rgs.RGSError):
         rgs.render(R.ctx, ds, bad, "fast", ws)
-    bad = wl.config_camera("cfg0", width=0, height=10)
+    bad = wl.config_camera("cfg0")
+    bad.width = 0
+    with pytest.raises(rgs.RGSError):
+        rgs.render(R.ctx, ds, bad, "fast", ws)
+    bad = wl.config_camera("cfg0")
+    bad.height = 20000
     with pytest.raises(rgs.RGSError):
         rgs.render(R.ctx, ds, bad, "fast", ws)
 
