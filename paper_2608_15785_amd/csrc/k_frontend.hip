@@ -63,11 +63,15 @@ __device__ inline ShBasis view_basis(float mx, float my, float mz, const CamDev&
     return sh_basis(dx * inv, dy * inv, dz * inv);
 }
 
-__device__ inline float half_lo(uint32_t w) {
-    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
-}
-__device__ inline float half_hi(uint32_t w) {
-    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+// FP16 bits of a non-negative value, rounded up (never below the value).
+__device__ inline uint32_t half_bits_up(double v) {
+    float f = (float)v;
+    if ((double)f < v) f = __uint_as_float(__float_as_uint(f) + 1u);
+    if (!(f < 65504.0f)) return 0x7c00u;                 // +inf: no culling
+    _Float16 h = (_Float16)f;
+    uint16_t b = __builtin_bit_cast(uint16_t, h);
+    if ((float)h < f) b = (uint16_t)(b + 1u);
+    return b;
 }
 
 __device__ inline uint64_t pack_rect(const Projected& p) {
@@ -81,11 +85,11 @@ __device__ inline uint32_t rect_count(uint64_t rc) {
 }
 
 __device__ inline void write_record(Record* rec, const Projected& p, float opa, float r, float g,
-                                    float b) {
+                                    float b, uint32_t extra) {
     float uh = (float)p.u, vh = (float)p.v;
     float4 a = make_float4(uh, (float)(p.u - (double)uh), vh, (float)(p.v - (double)vh));
     float4 m = make_float4((float)(p.c11 / p.det), (float)(-p.c01 / p.det), (float)(p.c00 / p.det), opa);
-    float4 c = make_float4(r, g, b, (float)p.d);
+    float4 c = make_float4(r, g, b, __uint_as_float(extra));
     float4* dst = reinterpret_cast<float4*>(rec);
     dst[0] = a;
     dst[1] = m;
@@ -316,7 +320,7 @@ __global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, CamD
             r = fmaxf(acc[0], 0.f);
             g = fmaxf(acc[1], 0.f);
             b = fmaxf(acc[2], 0.f);
-            write_record(&ws.records[i], pr, P[P_OPA * np + i], r, g, b);
+            write_record(&ws.records[i], pr, P[P_OPA * np + i], r, g, b, __float_as_uint((float)pr.d));
             uint64_t rc = pack_rect(pr);
             ws.rects[i] = rc;
             ws.depths[i] = (float)pr.d;
@@ -433,7 +437,7 @@ __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& c
         r = fmaxf(acc[0], 0.f);
         g = fmaxf(acc[1], 0.f);
         b = fmaxf(acc[2], 0.f);
-        write_record(&ws.records[i], pr, lno, r, g, b);
+        write_record(&ws.records[i], pr, lno, r, g, b, half_bits_up(pr.ax) | (half_bits_up(pr.ay) << 16));
         rect = pack_rect(pr);
         qd = quantize_depth(pr.d, cam.zn, cam.zf, f.b_d);
         count = rect_count(rect);

@@ -127,41 +127,30 @@ void launch_raster_plain(hipStream_t s, const FrameDev& f, const CamDev& cam, co
 
 // ---------------------------------------------------------------------------
 
-constexpr int FAST_THREADS = 128;
-
-struct PixelState {
-    float T, r, g, b;
-    bool done;
-    uint32_t stop_at;
-};
-
-__device__ inline void blend_fast(PixelState& s, float P, float cr, float cg, float cb, uint32_t at) {
-    if (!s.done && P >= -LN255F) {
-        const float alpha = fminf(ALPHA_MAX, fast_exp(P));
-        const float Tn = fmaf(-alpha, s.T, s.T);
-        if (Tn < T_MIN) {
-            s.done = true;
-            s.stop_at = at;
-        } else {
-            const float w = alpha * s.T;
-            s.r = fmaf(w, cr, s.r);
-            s.g = fmaf(w, cg, s.g);
-            s.b = fmaf(w, cb, s.b);
-            s.T = Tn;
-        }
-    }
-}
+constexpr int FAST_THREADS = 128;    // 2 waves: wave w owns tile rows 8w .. 8w+7
+constexpr int FAST_BATCH = FAST_THREADS;
+constexpr int LIST_UNROLL = 4;
+constexpr int LIST_CAP = FAST_BATCH + LIST_UNROLL;
+constexpr int ALPHA_MAX_BITS = 0x3f7d70a4;   // bit pattern of 0.99f
+// Margin added to the alpha-ellipse half-extents before culling a Gaussian for
+// a wave: float32 rounding of the folded exponent near the 1/255 threshold
+// must never hide a pair that the exact test would keep.
+constexpr float BOX_MARGIN_REL = 1.0e-3f;
+constexpr float BOX_MARGIN_ABS = 0.05f;
 
 __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev cam, WsDev ws,
                                                               const uint32_t* __restrict__ vals,
                                                               float* __restrict__ out) {
-    __shared__ float4 s_a[FAST_THREADS];   // C1, C2, C3, C4
-    __shared__ float4 s_b[FAST_THREADS];   // C5, C6, r, g
-    __shared__ float s_c[FAST_THREADS];    // b
+    // per-wave lists of folded Gaussians, in depth order
+    __shared__ float4 s_a[2][LIST_CAP];   // C1, C2, C3, C4
+    __shared__ float4 s_b[2][LIST_CAP];   // C5, C6, r, g
+    __shared__ float2 s_c[2][LIST_CAP];   // b, list position (as float bits)
+    __shared__ uint32_t s_cnt[2][2];      // [wave of the staging thread][list]
     const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)f.n_tiles);
     if (tile >= (uint32_t)f.n_tiles) return;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
     const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / 64, lane = tid % 64;
     const uint32_t lx = tid % TILE, ly = 2 * (tid / TILE);
     const uint32_t px = tx * TILE + lx, py = ty * TILE + ly;
     const bool in0 = px < (uint32_t)f.width && py < (uint32_t)f.height;
@@ -172,11 +161,18 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev
     const float x = (float)lx - 7.5f, y = (float)ly - 7.5f;
     const float x2 = x * x, xy = x * y, y2 = y * y, y21 = fmaf(2.0f, y, 1.0f);
 
-    PixelState p0{1.0f, 0.0f, 0.0f, 0.0f, !in0, 0xffffffffu};
-    PixelState p1{1.0f, 0.0f, 0.0f, 0.0f, !in1, 0xffffffffu};
-    for (uint32_t b0 = start; b0 < end; b0 += FAST_THREADS) {
-        if (__syncthreads_count(!(p0.done && p1.done)) == 0) break;
-        const uint32_t idx = b0 + tid;
+    float T0 = 1.0f, r0 = 0.0f, g0 = 0.0f, b0 = 0.0f;
+    float T1 = 1.0f, r1 = 0.0f, g1 = 0.0f, b1 = 0.0f;
+    bool live0 = in0, live1 = in1;
+    uint32_t stop0 = 0xffffffffu, stop1 = 0xffffffffu;
+
+    for (uint32_t base = start; base < end; base += FAST_BATCH) {
+        if (__syncthreads_count(live0 || live1) == 0) break;
+        // ---- stage: fold, cull against both half-tiles, compact per wave ----
+        const uint32_t idx = base + tid;
+        bool hit0 = false, hit1 = false;
+        float4 ca = make_float4(0.f, 0.f, 0.f, 0.f), cbv = make_float4(0.f, 0.f, 0.f, 0.f);
+        float cb = 0.f;
         if (idx < end) {
             const uint32_t g = vals[idx];
             const Record rec = ws.records[g < f.n_gaussians ? g : 0u];
@@ -184,40 +180,112 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev
             const float v = (rec.v_hi - oy) + rec.v_lo;
             const float A = rec.A, B = rec.B, C = rec.C;
             const float C0 = fmaf(A * u, u, fmaf(2.0f * B * u, v, C * v * v));
-            s_a[tid] = make_float4(-0.5f * A, -B, -0.5f * C, fmaf(A, u, B * v));
-            s_b[tid] = make_float4(fmaf(C, v, B * u), fmaf(-0.5f, C0, rec.opa), rec.r, rec.g);
-            s_c[tid] = rec.b;
+            ca = make_float4(-0.5f * A, -B, -0.5f * C, fmaf(A, u, B * v));
+            cbv = make_float4(fmaf(C, v, B * u), fmaf(-0.5f, C0, rec.opa), rec.r, rec.g);
+            cb = rec.b;
+            // the box |x - u| <= hx, |y - v| <= hy holds every pixel with
+            // P >= -ln 255 (half-extents from the front end, rounded up, then
+            // widened); a half-tile outside it has no pair that passes the skip
+            // test.  Comparisons are phrased so that a NaN keeps the Gaussian.
+            const float hx = fmaf(half_lo(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
+            const float hy = fmaf(half_hi(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
+            const bool x_out = u - hx > 7.5f || u + hx < -7.5f;
+            hit0 = !(x_out || v - hy > -0.5f || v + hy < -7.5f);
+            hit1 = !(x_out || v - hy > 7.5f || v + hy < 0.5f);
+        }
+        const uint64_t m0 = __ballot(hit0), m1 = __ballot(hit1);
+        const uint64_t lt = lanemask_lt();
+        if (lane == 0) {
+            s_cnt[wave][0] = (uint32_t)__popcll(m0);
+            s_cnt[wave][1] = (uint32_t)__popcll(m1);
         }
         __syncthreads();
-        const uint32_t cnt = min((uint32_t)FAST_THREADS, end - b0);
-        for (uint32_t j = 0; j < cnt; ++j) {
-            if (p0.done && p1.done) break;
-            const float4 a = s_a[j];
-            const float4 m = s_b[j];
-            const float P0 = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(m.x, y, m.y)))));
-            const float P1 = P0 + fmaf(a.y, x, fmaf(a.z, y21, m.x));
-            const float cb = s_c[j];
-            blend_fast(p0, P0, m.z, m.w, cb, b0 + j);
-            blend_fast(p1, P1, m.z, m.w, cb, b0 + j);
+        const uint32_t off0 = wave ? s_cnt[0][0] : 0u, off1 = wave ? s_cnt[0][1] : 0u;
+        const float posf = __uint_as_float(idx);
+        if (hit0) {
+            const uint32_t p = off0 + (uint32_t)__popcll(m0 & lt);
+            s_a[0][p] = ca;
+            s_b[0][p] = cbv;
+            s_c[0][p] = make_float2(cb, posf);
+        }
+        if (hit1) {
+            const uint32_t p = off1 + (uint32_t)__popcll(m1 & lt);
+            s_a[1][p] = ca;
+            s_b[1][p] = cbv;
+            s_c[1][p] = make_float2(cb, posf);
+        }
+        const uint32_t n0 = s_cnt[0][0] + s_cnt[1][0], n1 = s_cnt[0][1] + s_cnt[1][1];
+        // inert padding up to a multiple of the unroll: P = -1e30 is always skipped
+        if (tid < 2 * LIST_UNROLL) {
+            const uint32_t w = tid / LIST_UNROLL, k = tid % LIST_UNROLL;
+            const uint32_t p = (w ? n1 : n0) + k;
+            s_a[w][p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_b[w][p] = make_float4(0.f, -1.0e30f, 0.f, 0.f);
+            s_c[w][p] = make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+
+        // ---- blend this wave's list ----
+        const uint32_t n = wave ? n1 : n0;
+        const float4* __restrict__ la = s_a[wave];
+        const float4* __restrict__ lb = s_b[wave];
+        const float2* __restrict__ lc = s_c[wave];
+        if (__ballot(live0 || live1) != 0) {
+            for (uint32_t k0 = 0; k0 < n; k0 += LIST_UNROLL) {
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) {
+                    const float4 a = la[k0 + u];
+                    const float4 m = lb[k0 + u];
+                    const float2 c = lc[k0 + u];
+                    const float P0 = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(m.x, y, m.y)))));
+                    const float P1 = P0 + fmaf(a.y, x, fmaf(a.z, y21, m.x));
+                    const int I0 = min((int)fmaf(P0, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
+                    const int I1 = min((int)fmaf(P1, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
+                    const float al0 = (live0 && P0 >= -LN255F) ? __int_as_float(I0) : 0.0f;
+                    const float al1 = (live1 && P1 >= -LN255F) ? __int_as_float(I1) : 0.0f;
+                    const float w0 = al0 * T0, w1 = al1 * T1;
+                    float Tn0 = T0 - w0, Tn1 = T1 - w1;
+                    float nr0 = fmaf(w0, m.z, r0), ng0 = fmaf(w0, m.w, g0), nb0 = fmaf(w0, c.x, b0);
+                    float nr1 = fmaf(w1, m.z, r1), ng1 = fmaf(w1, m.w, g1), nb1 = fmaf(w1, c.x, b1);
+                    const bool s0 = Tn0 < T_MIN, s1 = Tn1 < T_MIN;
+                    if (__ballot(s0 || s1) != 0) {
+                        // a pixel reached the stop: that pair is not blended
+                        const uint32_t at = __float_as_uint(c.y);
+                        if (s0) {
+                            live0 = false;
+                            stop0 = at;
+                            Tn0 = T0; nr0 = r0; ng0 = g0; nb0 = b0;
+                        }
+                        if (s1) {
+                            live1 = false;
+                            stop1 = at;
+                            Tn1 = T1; nr1 = r1; ng1 = g1; nb1 = b1;
+                        }
+                    }
+                    T0 = Tn0; r0 = nr0; g0 = ng0; b0 = nb0;
+                    T1 = Tn1; r1 = nr1; g1 = ng1; b1 = nb1;
+                }
+                if (__ballot(live0 || live1) == 0) break;
+            }
         }
         __syncthreads();
     }
     const uint64_t plane = (uint64_t)f.width * f.height;
     if (in0) {
         const uint64_t o = (uint64_t)py * f.width + px;
-        out[o] = fmaf(p0.T, cam.bg[0], p0.r);
-        out[plane + o] = fmaf(p0.T, cam.bg[1], p0.g);
-        out[2 * plane + o] = fmaf(p0.T, cam.bg[2], p0.b);
-        ws.t_final[o] = p0.T;
-        ws.n_proc[o] = p0.stop_at != 0xffffffffu ? p0.stop_at - start + 1 : end - start;
+        out[o] = fmaf(T0, cam.bg[0], r0);
+        out[plane + o] = fmaf(T0, cam.bg[1], g0);
+        out[2 * plane + o] = fmaf(T0, cam.bg[2], b0);
+        ws.t_final[o] = T0;
+        ws.n_proc[o] = stop0 != 0xffffffffu ? stop0 - start + 1 : end - start;
     }
     if (in1) {
         const uint64_t o = (uint64_t)(py + 1) * f.width + px;
-        out[o] = fmaf(p1.T, cam.bg[0], p1.r);
-        out[plane + o] = fmaf(p1.T, cam.bg[1], p1.g);
-        out[2 * plane + o] = fmaf(p1.T, cam.bg[2], p1.b);
-        ws.t_final[o] = p1.T;
-        ws.n_proc[o] = p1.stop_at != 0xffffffffu ? p1.stop_at - start + 1 : end - start;
+        out[o] = fmaf(T1, cam.bg[0], r1);
+        out[plane + o] = fmaf(T1, cam.bg[1], g1);
+        out[2 * plane + o] = fmaf(T1, cam.bg[2], b1);
+        ws.t_final[o] = T1;
+        ws.n_proc[o] = stop1 != 0xffffffffu ? stop1 - start + 1 : end - start;
     }
 }
 

@@ -74,8 +74,17 @@ struct FrameDev {
 struct __align__(16) Record {
     float u_hi, u_lo, v_hi, v_lo;
     float A, B, C, opa;       // conic; opacity (plain) or ln o (fast)
-    float r, g, b, depth;     // colour; float32 depth (diagnostics)
+    float r, g, b;            // colour
+    uint32_t extra;           // plain: float32 depth bits; fast: FP16 pair (hx, hy) of the
+                              // alpha-ellipse box half-extents, rounded up
 };
+
+__host__ __device__ inline float half_lo(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w & 0xffffu));
+}
+__host__ __device__ inline float half_hi(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(w >> 16));
+}
 
 // Device-side header at offset 0 of every workspace.
 struct WsHeader {
@@ -138,6 +147,7 @@ struct DebugDev {
 
 struct Projected {
     double d, u, v, c00, c01, c11, det;
+    double ax, ay;            // fast path: half-extents of the ellipse where P >= -ln 255
     double x0, x1, y0, y1;    // inclusive tile bounds (integer valued)
 };
 
@@ -222,8 +232,10 @@ __host__ __device__ inline bool project_gaussian(const CamDev& c, double mx, dou
     double hx = rad, hy = rad;
     if (fast) {
         double tau = 2.0 * (LN255 + lno);
-        hx = fmin(rad, sqrt(tau * c00));
-        hy = fmin(rad, sqrt(tau * c11));
+        o.ax = sqrt(tau * c00);
+        o.ay = sqrt(tau * c11);
+        hx = fmin(rad, o.ax);
+        hy = fmin(rad, o.ay);
     }
     o.x0 = fmax(0.0, floor((u - hx) / 16.0));
     o.x1 = fmin(tiles_x - 1.0, floor((u + hx) / 16.0));
