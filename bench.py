@@ -33,8 +33,9 @@ METRIC = "FPS at 1080p/4K (1M/3M Gaussians) fast vs plain path; p50/p99 latency"
 # lane-operations per second (non-packed); HBM3E 8 TB/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
-# Algorithmic VALU lane-operations per evaluated (pixel, Gaussian) pair; the
-# counts are derived in the design doc from the operations the method defines.
+# Algorithmic VALU lane-operations per blended (pixel, Gaussian) pair -- a pair
+# past the skip test that the method must composite; the counts are derived in
+# the design doc from the operations the method defines.
 OPS_PER_PAIR = {"fast": 14, "plain": 21}
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
@@ -55,6 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=2048, help="tiles the oracle blends")
     ap.add_argument("--paths", default="fast,plain")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device copies of MIB MiB (scale reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -68,7 +71,7 @@ def stage_bytes(path, n, n_vis, n_dup, n_tiles, passes):
         fe = 44 * n + 192 * n_vis + (48 + 8 + 4) * n_vis + 4 * n
         dup = 4 * n + 12 * n_vis + 12 * n_dup
         kb = 8
-    sort = (kb + passes * 2 * (kb + 4)) * n_dup
+    sort = passes * 2 * (kb + 4) * n_dup          # Eq. sort_memory: read + write per pass
     ranges = kb * n_dup + 8 * n_tiles
     return dict(frontend=fe, duplicate=dup, sort=sort, ranges=ranges)
 
@@ -138,7 +141,8 @@ def frame_counts(R, ds, cam, path):
     g = R.render_debug(ds, cam, path)
     st = g["stats"]
     return dict(n_visible=int(st["n_visible"]), n_entries=int(st["n_entries"]),
-                pairs=int(g["n_proc"].astype(np.int64).sum()), passes=int(st["passes"]))
+                pairs_visited=int(g["n_proc"].astype(np.int64).sum()),
+                pairs=int(g["n_blend"].astype(np.int64).sum()), passes=int(st["passes"]))
 
 
 def rooflines(path, counts, stage_ms, n, n_tiles):
@@ -153,8 +157,9 @@ def rooflines(path, counts, stage_ms, n, n_tiles):
     ms = stage_ms["raster"]
     tops = counts["pairs"] * OPS_PER_PAIR[path] / (ms * 1e-3) / 1e12
     out["raster"] = dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 2),
-                         unit="Tops/s", frac=round(tops / VALU_PEAK_TOPS, 4), pairs=counts["pairs"],
-                         ops_per_pair=OPS_PER_PAIR[path], ms=round(ms, 4))
+                         unit="Tops/s", frac=round(tops / VALU_PEAK_TOPS, 4), pairs_blended=counts["pairs"],
+                         pairs_visited=counts["pairs_visited"], ops_per_pair=OPS_PER_PAIR[path],
+                         ms=round(ms, 4))
     return out
 
 
@@ -195,6 +200,15 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 5}))
+        return
     paths = [p for p in args.paths.split(",") if p]
     R = rgs.Renderer(0)
 
@@ -266,14 +280,14 @@ def main():
         out["cpu_baseline"] = cpu_baseline(sc1, cam1, args.cpu_tiles)
     out["latency_ms"] = m["latency_ms"]
     out["paths_1080p"] = {p: {k: r[k] for k in ("fps", "ms_per_frame", "latency_ms", "stage_ms", "n_visible",
-                                                  "n_entries", "pairs", "passes", "roofline")}
+                                                  "n_entries", "pairs", "pairs_visited", "passes", "roofline")}
                           for p, r in res1.items()}
     if "fast" in res1 and "plain" in res1:
         out["speedup_fast_over_plain_1080p"] = round(res1["fast"]["fps"] / res1["plain"]["fps"], 3)
     if res2:
         out["paths_4k_orbit"] = {p: {k: r[k] for k in ("fps", "ms_per_frame", "latency_ms", "stage_ms",
-                                                         "n_visible", "n_entries", "pairs", "passes",
-                                                         "roofline_pose0")}
+                                                         "n_visible", "n_entries", "pairs", "pairs_visited",
+                                                         "passes", "roofline_pose0")}
                                  for p, r in res2.items()}
         if "fast" in res2 and "plain" in res2:
             out["speedup_fast_over_plain_4k"] = round(res2["fast"]["fps"] / res2["plain"]["fps"], 3)

@@ -253,7 +253,9 @@ rgs_status rgs_workspace_check(rgs_ctx* ctx, const void* workspace, rgs_frame_st
  *   entries [entry_capacity]: keys in emission order and sorted (uint64; the
  *                      fast path's 32-bit keys zero-extended), Gaussian index
  *                      per entry (uint32)
- *   ranges [n_tiles][2] (uint32 start, end); T_final, n_proc [H][W]
+ *   ranges [n_tiles][2] (uint32 start, end); per pixel [H][W]: T_final, n_proc
+ *   (list entries visited, the stopping one included) and n_blend (pairs
+ *   blended: past the skip test and not stopped)
  * RGS_E_CAPACITY if entry_capacity is smaller than the frame's entry count.
  */
 typedef struct {
@@ -272,6 +274,7 @@ typedef struct {
     uint32_t* ranges;
     float* T_final;
     uint32_t* n_proc;
+    uint32_t* n_blend;
 } rgs_debug_out;
 
 rgs_status rgs_render_debug(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,

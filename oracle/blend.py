@@ -54,6 +54,7 @@ class BlendResult:
     color: list          # per mode: [3, npix] float64 (C + T bg)
     T: list              # per mode: [npix] final transmittance
     n_proc: list         # per mode: [npix] pairs visited (the stopping pair included)
+    n_blend: list        # per mode: [npix] pairs blended (past the skip test, not the stopping one)
     c_max: np.ndarray    # [npix]
     slack: np.ndarray    # [npix] decision slack of the primary mode (colour units)
     flagged: np.ndarray  # [npix] bool, a decision of the primary mode was within margin
@@ -90,6 +91,7 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
     C = [np.zeros((3, n)) for _ in range(k)]
     done = [np.zeros(n, bool) for _ in range(k)]
     n_proc = [np.zeros(n, np.int64) for _ in range(k)]
+    n_blend = [np.zeros(n, np.int64) for _ in range(k)]
     c_max = np.zeros(n)
     slack_units = np.zeros(n)
     flagged = np.zeros(n, bool)
@@ -119,6 +121,7 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
             stop = blend & (Tn < T_MIN)
             done[m] |= stop
             blend &= ~stop
+            n_blend[m] += blend
             C[m] += np.where(blend, a * T[m], 0.0)[None, :] * col[:, None]
             T[m] = np.where(blend, Tn, T[m])
             if m == 0:
@@ -157,6 +160,6 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
 
     bg = np.asarray(bg, np.float64)
     colors = [C[m] + T[m][None, :] * bg[:, None] for m in range(k)]
-    return BlendResult(color=colors, T=T, n_proc=n_proc, c_max=c_max,
+    return BlendResult(color=colors, T=T, n_proc=n_proc, n_blend=n_blend, c_max=c_max,
                        slack=slack_units * c_max, flagged=flagged,
                        mode_slack=mode_slack_T * c_max)

@@ -50,6 +50,7 @@ class OracleFrame:
     images: dict = field(default_factory=dict)   # mode -> [3, H, W] (NaN outside blended tiles)
     T_final: np.ndarray | None = None            # primary mode, [H, W]
     n_proc: np.ndarray | None = None             # primary mode, [H, W]
+    n_blend: np.ndarray | None = None            # primary mode, [H, W]
     c_max: np.ndarray | None = None
     slack: np.ndarray | None = None
     flagged: np.ndarray | None = None
@@ -118,6 +119,7 @@ def render(arrays: dict, cam, path: str = "plain", modes=None, tiles=None, margi
         frame.images[m] = np.full((3, H, W), np.nan)
     frame.T_final = np.full((H, W), np.nan)
     frame.n_proc = np.zeros((H, W), np.int64)
+    frame.n_blend = np.zeros((H, W), np.int64)
     frame.c_max = np.zeros((H, W))
     frame.slack = np.zeros((H, W))
     frame.flagged = np.zeros((H, W), bool)
@@ -139,6 +141,7 @@ def render(arrays: dict, cam, path: str = "plain", modes=None, tiles=None, margi
             frame.images[m][:, Y, X] = r.color[mi]
         frame.T_final[Y, X] = r.T[0]
         frame.n_proc[Y, X] = r.n_proc[0]
+        frame.n_blend[Y, X] = r.n_blend[0]
         frame.c_max[Y, X] = r.c_max
         frame.slack[Y, X] = r.slack
         frame.flagged[Y, X] = r.flagged

@@ -80,7 +80,7 @@ class DebugOut(C.Structure):
                 ("keys_unsorted", C.c_void_p), ("vals_unsorted", C.c_void_p),
                 ("keys_sorted", C.c_void_p), ("vals_sorted", C.c_void_p),
                 ("entry_capacity", C.c_int64), ("ranges", C.c_void_p), ("T_final", C.c_void_p),
-                ("n_proc", C.c_void_p)]
+                ("n_proc", C.c_void_p), ("n_blend", C.c_void_p)]
 
 
 class Grads(C.Structure):
@@ -339,11 +339,12 @@ def render_debug(ctx: Context, scene: DeviceScene, cam, path: str, workspace, en
         ranges=torch.zeros((frame_plan(W, H)["n_tiles"], 2), dtype=torch.int32, device=dev),
         T_final=torch.zeros((H, W), dtype=torch.float32, device=dev),
         n_proc=torch.zeros((H, W), dtype=torch.int32, device=dev),
+        n_blend=torch.zeros((H, W), dtype=torch.int32, device=dev),
     )
     image = torch.zeros((3, H, W), dtype=torch.float32, device=dev)
     dbg = DebugOut(*(_ptr(t[k]) for k in ("depth", "u", "v", "cov2d", "rect", "visible", "color",
                                           "keys_unsorted", "vals_unsorted", "keys_sorted", "vals_sorted")),
-                   entry_capacity, *(_ptr(t[k]) for k in ("ranges", "T_final", "n_proc")))
+                   entry_capacity, *(_ptr(t[k]) for k in ("ranges", "T_final", "n_proc", "n_blend")))
     cc = camera_struct(cam)
     st = FrameStats()
     _check(lib.rgs_render_debug(ctx.handle, scene.handle, C.byref(cc), W, H, PATHS[path],
@@ -358,6 +359,7 @@ def render_debug(ctx: Context, scene: DeviceScene, cam, path: str, workspace, en
         out[k] = out[k][:m].view(np.uint32)
     out["ranges"] = out["ranges"].view(np.uint32)
     out["n_proc"] = out["n_proc"].view(np.uint32)
+    out["n_blend"] = out["n_blend"].view(np.uint32)
     out["visible"] = out["visible"].astype(bool)
     out["image"] = image.cpu().numpy()
     out["stats"] = st.as_dict()

@@ -53,6 +53,7 @@ __device__ inline float fast_exp(float P) {
 
 // ---------------------------------------------------------------------------
 
+template <bool COUNT>
 __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, CamDev cam, WsDev ws,
                                                       const uint32_t* __restrict__ vals,
                                                       float* __restrict__ out) {
@@ -73,6 +74,7 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, CamDev cam, Ws
     float T = 1.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
     bool done = !inside;
     uint32_t stop_at = 0xffffffffu;
+    uint32_t n_blend = 0;
     for (uint32_t b0 = start; b0 < end; b0 += 256) {
         if (__syncthreads_count(!done) == 0) break;
         const uint32_t idx = b0 + tid;
@@ -104,6 +106,7 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, CamDev cam, Ws
                 cg = fmaf(w, m.w, cg);
                 cb = fmaf(w, s_c[j], cb);
                 T = Tn;
+                if (COUNT) ++n_blend;
             }
         }
         __syncthreads();
@@ -116,13 +119,18 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, CamDev cam, Ws
         out[2 * plane + o] = fmaf(T, cam.bg[2], cb);
         ws.t_final[o] = T;
         ws.n_proc[o] = stop_at != 0xffffffffu ? stop_at - start + 1 : end - start;
+        if (COUNT) ws.n_blend[o] = n_blend;
     }
 }
 
 void launch_raster_plain(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
-                         bool result_in_b, float* out) {
-    hipLaunchKernelGGL(k_raster_plain, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, cam, ws,
-                       result_in_b ? ws.vals_b : ws.vals_a, out);
+                         bool result_in_b, float* out, bool count) {
+    if (count)
+        hipLaunchKernelGGL(k_raster_plain<true>, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, cam, ws,
+                           result_in_b ? ws.vals_b : ws.vals_a, out);
+    else
+        hipLaunchKernelGGL(k_raster_plain<false>, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, cam, ws,
+                           result_in_b ? ws.vals_b : ws.vals_a, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -138,6 +146,7 @@ constexpr int ALPHA_MAX_BITS = 0x3f7d70a4;   // bit pattern of 0.99f
 constexpr float BOX_MARGIN_REL = 1.0e-3f;
 constexpr float BOX_MARGIN_ABS = 0.05f;
 
+template <bool COUNT>
 __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev cam, WsDev ws,
                                                               const uint32_t* __restrict__ vals,
                                                               float* __restrict__ out) {
@@ -165,6 +174,7 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev
     float T1 = 1.0f, r1 = 0.0f, g1 = 0.0f, b1 = 0.0f;
     bool live0 = in0, live1 = in1;
     uint32_t stop0 = 0xffffffffu, stop1 = 0xffffffffu;
+    uint32_t nbl0 = 0, nbl1 = 0;
 
     for (uint32_t base = start; base < end; base += FAST_BATCH) {
         if (__syncthreads_count(live0 || live1) == 0) break;
@@ -248,6 +258,10 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev
                     float nr0 = fmaf(w0, m.z, r0), ng0 = fmaf(w0, m.w, g0), nb0 = fmaf(w0, c.x, b0);
                     float nr1 = fmaf(w1, m.z, r1), ng1 = fmaf(w1, m.w, g1), nb1 = fmaf(w1, c.x, b1);
                     const bool s0 = Tn0 < T_MIN, s1 = Tn1 < T_MIN;
+                    if (COUNT) {
+                        nbl0 += (al0 > 0.0f && !s0) ? 1u : 0u;
+                        nbl1 += (al1 > 0.0f && !s1) ? 1u : 0u;
+                    }
                     if (__ballot(s0 || s1) != 0) {
                         // a pixel reached the stop: that pair is not blended
                         const uint32_t at = __float_as_uint(c.y);
@@ -278,6 +292,7 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev
         out[2 * plane + o] = fmaf(T0, cam.bg[2], b0);
         ws.t_final[o] = T0;
         ws.n_proc[o] = stop0 != 0xffffffffu ? stop0 - start + 1 : end - start;
+        if (COUNT) ws.n_blend[o] = nbl0;
     }
     if (in1) {
         const uint64_t o = (uint64_t)(py + 1) * f.width + px;
@@ -286,13 +301,18 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev
         out[2 * plane + o] = fmaf(T1, cam.bg[2], b1);
         ws.t_final[o] = T1;
         ws.n_proc[o] = stop1 != 0xffffffffu ? stop1 - start + 1 : end - start;
+        if (COUNT) ws.n_blend[o] = nbl1;
     }
 }
 
 void launch_raster_fast(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
-                        bool result_in_b, float* out) {
-    hipLaunchKernelGGL(k_raster_fast, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, cam, ws,
-                       result_in_b ? ws.vals_b : ws.vals_a, out);
+                        bool result_in_b, float* out, bool count) {
+    if (count)
+        hipLaunchKernelGGL(k_raster_fast<true>, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, cam,
+                           ws, result_in_b ? ws.vals_b : ws.vals_a, out);
+    else
+        hipLaunchKernelGGL(k_raster_fast<false>, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, cam,
+                           ws, result_in_b ? ws.vals_b : ws.vals_a, out);
 }
 
 }  // namespace rgs

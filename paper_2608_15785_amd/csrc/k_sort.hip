@@ -7,15 +7,15 @@
 // resident on the 256 CUs at once, so the tiles cannot pass digit offsets
 // along a look-back chain without waiting on each other; each pass is instead
 // a reduce-then-scan:
-//   * `radix_hist` (once per sort) reads all keys and builds every pass's
-//     global digit histogram, the bases of the digit buckets;
-//   * `radix_upsweep` counts each 4096-entry tile's digits (keys only);
+//   * `radix_upsweep` counts each 2048-entry tile's digits (keys only);
 //   * `radix_offsets` scans, for each digit in its own workgroup, the tiles'
-//     counts into the tile's output offset inside that digit's bucket;
-//   * `radix_scatter` ranks each key among equal digits of its tile with wave64
-//     ballots (stable: tile order is input order), reorders the tile in LDS by
-//     digit and writes it out, so consecutive threads store consecutive
-//     positions of a digit bucket.
+//     counts into the tile's offset inside that digit's bucket, and records
+//     the bucket's size;
+//   * `radix_scatter` turns the 256 bucket sizes into bucket bases (one block
+//     scan), ranks each key among equal digits of its tile with wave64 ballots
+//     (stable: tile order is input order), reorders the tile in LDS by digit
+//     and writes it out, so consecutive threads store consecutive positions of
+//     a digit bucket.
 // Ties keep input order, and the front end emits entries in Gaussian-index
 // order, so equal keys end ordered by Gaussian index.
 //
@@ -51,47 +51,6 @@ __device__ inline uint32_t block256_inclusive_scan(uint32_t x, uint32_t* s_wtot)
     return incl + before;
 }
 
-constexpr int HIST_THREADS = 1024;
-constexpr int HIST_ITEMS = 8;
-
-template <typename KeyT>
-__global__ __launch_bounds__(HIST_THREADS) void k_radix_hist(const KeyT* __restrict__ keys, WsDev ws,
-                                                             uint32_t passes, uint32_t sort_blocks_max) {
-    __shared__ uint32_t s_h[MAX_PASSES * RADIX];
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += HIST_THREADS) s_h[i] = 0;
-    const uint32_t n = entry_count(ws.header);
-    (void)sort_blocks_max;
-    __syncthreads();
-    const uint64_t chunk = (uint64_t)HIST_THREADS * HIST_ITEMS;
-    for (uint64_t base = (uint64_t)blockIdx.x * chunk; base < n; base += (uint64_t)gridDim.x * chunk) {
-        KeyT k[HIST_ITEMS];
-#pragma unroll
-        for (int m = 0; m < HIST_ITEMS; ++m) {
-            const uint64_t idx = base + (uint64_t)m * HIST_THREADS + threadIdx.x;
-            k[m] = idx < n ? keys[idx] : (KeyT)0;
-        }
-#pragma unroll
-        for (int m = 0; m < HIST_ITEMS; ++m) {
-            if (base + (uint64_t)m * HIST_THREADS + threadIdx.x < n)
-                for (uint32_t p = 0; p < passes; ++p) atomicAdd(&s_h[p * RADIX + digit_of(k[m], 8 * p)], 1u);
-        }
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += HIST_THREADS) {
-        const uint32_t v = s_h[i];
-        if (v) atomicAdd(&ws.hist[i], v);
-    }
-}
-
-__global__ __launch_bounds__(256) void k_radix_scan(WsDev ws, uint32_t passes) {
-    __shared__ uint32_t s_wtot[4];
-    for (uint32_t p = 0; p < passes; ++p) {
-        uint32_t v = ws.hist[p * RADIX + threadIdx.x];
-        uint32_t incl = block256_inclusive_scan(v, s_wtot);
-        ws.hist[p * RADIX + threadIdx.x] = incl - v;
-    }
-}
-
 // Per-tile digit counts, digit-major: counts[d * nb_max + tile].
 template <typename KeyT>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_upsweep(const KeyT* __restrict__ kin, WsDev ws,
@@ -115,15 +74,15 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_upsweep(const KeyT* __re
     ws.tile_counts[(uint64_t)threadIdx.x * nb_max + blockIdx.x] = s_h[threadIdx.x];
 }
 
-// Digit d (one workgroup each): exclusive scan of its per-tile counts plus the
-// digit's bucket base, in place.
-__global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t pass, uint32_t nb_max) {
+// Digit d (one workgroup each): exclusive scan of its per-tile counts, in
+// place, and the size of the digit's bucket.
+__global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t nb_max) {
     __shared__ uint32_t s_wtot[4];
     const uint32_t d = blockIdx.x;
     const uint32_t n = entry_count(ws.header);
     const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
     uint32_t* row = ws.tile_counts + (uint64_t)d * nb_max;
-    uint32_t carry = ws.hist[pass * RADIX + d];
+    uint32_t carry = 0;
     for (uint32_t c = 0; c < nb; c += 256) {
         const uint32_t i = c + threadIdx.x;
         const uint32_t v = i < nb ? row[i] : 0u;
@@ -132,6 +91,7 @@ __global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t pass, 
         carry += s_wtot[0] + s_wtot[1] + s_wtot[2] + s_wtot[3];
         __syncthreads();
     }
+    if (threadIdx.x == 0) ws.hist[d] = carry;
 }
 
 template <typename KeyT>
@@ -207,7 +167,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const KeyT* __re
         }
         const uint32_t incl = block256_inclusive_scan(tot, s_wtot);
         s_bstart[d] = incl - tot;
-        s_gbase[d] = ws.tile_counts[(uint64_t)d * nb_max + vb] - (incl - tot);
+        const uint32_t bucket = ws.hist[d];
+        const uint32_t bincl = block256_inclusive_scan(bucket, s_wtot);
+        s_gbase[d] = (bincl - bucket) + ws.tile_counts[(uint64_t)d * nb_max + vb] - (incl - tot);
     }
     __syncthreads();
 
@@ -237,15 +199,12 @@ static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, uint32_t
                        bool* result_in_b) {
     KeyT* ka = reinterpret_cast<KeyT*>(ws.keys_a);
     KeyT* kb = reinterpret_cast<KeyT*>(ws.keys_b);
-    hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3(HIST_BLOCKS), dim3(HIST_THREADS), 0, s, ka, ws, passes,
-                       nb_max);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(256), 0, s, ws, passes);
     for (uint32_t p = 0; p < passes; ++p) {
         const bool from_a = (p % 2) == 0;
         const KeyT* kin = from_a ? ka : kb;
         hipLaunchKernelGGL(k_radix_upsweep<KeyT>, dim3(nb_max), dim3(SORT_THREADS), 0, s, kin, ws, 8 * p,
                            nb_max);
-        hipLaunchKernelGGL(k_radix_offsets, dim3(RADIX), dim3(256), 0, s, ws, p, nb_max);
+        hipLaunchKernelGGL(k_radix_offsets, dim3(RADIX), dim3(256), 0, s, ws, nb_max);
         hipLaunchKernelGGL(k_radix_scatter<KeyT>, dim3(nb_max), dim3(SORT_THREADS), 0, s, kin,
                            from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
                            ws, 8 * p, nb_max);

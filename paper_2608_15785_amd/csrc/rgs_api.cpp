@@ -470,6 +470,8 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     off = align256(off + (uint64_t)p.width * p.height * 4);
     L.n_proc = off;
     off = align256(off + (uint64_t)p.width * p.height * 4);
+    L.n_blend = off;
+    off = align256(off + (uint64_t)p.width * p.height * 4);
     L.total = off;
 }
 
@@ -540,6 +542,7 @@ static WsDev ws_pointers(void* base, const WsLayout& L) {
     w.tile_counts = reinterpret_cast<uint32_t*>(b + L.tile_counts);
     w.t_final = reinterpret_cast<float*>(b + L.t_final);
     w.n_proc = reinterpret_cast<uint32_t*>(b + L.n_proc);
+    w.n_blend = reinterpret_cast<uint32_t*>(b + L.n_blend);
     return w;
 }
 
@@ -708,8 +711,8 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
     mark(3);
     launch_ranges(st, f, w, L.key_bytes, in_b);
     mark(4);
-    if (path == RGS_PATH_PLAIN) launch_raster_plain(st, f, cd, w, in_b, out);
-    else launch_raster_fast(st, f, cd, w, in_b, out);
+    if (path == RGS_PATH_PLAIN) launch_raster_plain(st, f, cd, w, in_b, out, dbg != nullptr);
+    else launch_raster_fast(st, f, cd, w, in_b, out, dbg != nullptr);
     mark(5);
     HIP_TRY(hipGetLastError());
 
@@ -730,6 +733,8 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
             HIP_TRY(hipMemcpyAsync(dbg->T_final, w.t_final, (uint64_t)W * H * 4, hipMemcpyDeviceToDevice, st));
         if (dbg->n_proc)
             HIP_TRY(hipMemcpyAsync(dbg->n_proc, w.n_proc, (uint64_t)W * H * 4, hipMemcpyDeviceToDevice, st));
+        if (dbg->n_blend)
+            HIP_TRY(hipMemcpyAsync(dbg->n_blend, w.n_blend, (uint64_t)W * H * 4, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipGetLastError());
     }
     if (stats || dbg) {

@@ -30,12 +30,11 @@ constexpr int FE_ITEMS = 2;          // Gaussians per thread (block-strided)
 constexpr int FE_TILE = FE_THREADS * FE_ITEMS;   // Gaussians per block
 constexpr int LB_PER_LANE = 8;       // look-back states each lane polls per round trip
 constexpr int SORT_THREADS = 256;    // 4 waves
-constexpr int SORT_ITEMS = 16;       // keys per thread per radix tile
+constexpr int SORT_ITEMS = 8;        // keys per thread per radix tile
 constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
-constexpr int HIST_BLOCKS = 256;
 
 // Plain-format planes (float32, one per scalar, each n_pad long).
 enum PlainPlane { P_MX = 0, P_MY, P_MZ, P_SX, P_SY, P_SZ, P_QW, P_QX, P_QY, P_QZ, P_OPA, P_SH0,
@@ -107,7 +106,7 @@ struct WsLayout {
     uint64_t records, counts, rects, depths;
     uint64_t keys_a, keys_b, vals_a, vals_b;
     uint64_t hist, tile_counts;
-    uint64_t t_final, n_proc;
+    uint64_t t_final, n_proc, n_blend;
     uint64_t total;
     uint64_t capacity;
     uint32_t key_bytes, passes, fe_blocks, sort_blocks_max;
@@ -126,10 +125,11 @@ struct WsDev {
     void* keys_b;
     uint32_t* vals_a;
     uint32_t* vals_b;
-    uint32_t* hist;           // [MAX_PASSES][RADIX] counts, then exclusive offsets
+    uint32_t* hist;           // [RADIX] digit bucket sizes of the current radix pass
     uint32_t* tile_counts;    // [RADIX][sort tiles]: per-tile digit counts, then offsets
     float* t_final;           // [H][W]
-    uint32_t* n_proc;         // [H][W]
+    uint32_t* n_proc;         // [H][W] list entries visited per pixel
+    uint32_t* n_blend;        // [H][W] pairs blended per pixel (written by counting renders)
 };
 
 struct DebugDev {
@@ -332,9 +332,9 @@ void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key
 void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                    bool result_in_b);
 void launch_raster_plain(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
-                         bool result_in_b, float* out);
+                         bool result_in_b, float* out, bool count);
 void launch_raster_fast(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
-                        bool result_in_b, float* out);
+                        bool result_in_b, float* out, bool count);
 void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n);
 
 }  // namespace rgs

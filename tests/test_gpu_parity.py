@@ -41,6 +41,7 @@ def run_parity(R, scene, cam, path, tiles=None, entries=True):
     # pair evaluations agree with the oracle's count except where a decision was flagged
     mask = ~fr.flagged & ~(fr.mode_slack > 0) & ~np.isnan(fr.T_final)
     assert np.array_equal(g["n_proc"][mask], fr.n_proc[mask].astype(np.uint32)), "pair counts differ"
+    assert np.array_equal(g["n_blend"][mask], fr.n_blend[mask].astype(np.uint32)), "blended counts differ"
     _log(f"[parity] {path}: {rep}")
     return rep
 

@@ -1,0 +1,87 @@
+"""The oracle's decision-margin bookkeeping (CPU only).
+
+Slack loosens the image tolerance only at pixels whose skip or stop decision
+lies within the float32 margin of its threshold, by the colour that decision
+can move; these tests build single-pixel sequences with known alphas.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import oracle
+
+X = np.zeros(1)
+Y = np.zeros(1)
+
+
+def seq(alphas, colors, lno=False):
+    """Gaussians on one pixel at offsets d_k from it with conic I, so alpha_k = o_k exp(-d_k^2/2)."""
+    k = len(alphas)
+    u = np.zeros(k)
+    v = np.zeros(k)
+    conic = np.tile([1.0, 0.0, 1.0], (k, 1))
+    o = np.asarray(alphas, np.float64)           # d = 0: alpha = o exactly
+    opa = np.log(o) if lno else o
+    col = np.tile(np.asarray(colors, np.float64)[:, None], (1, 3))
+    return u, v, conic, opa, col
+
+
+def test_no_flags_far_from_thresholds():
+    u, v, c, o, col = seq([0.5, 0.3, 0.2], [0.4, 0.9, 0.1])
+    r = oracle.blend_tile(np.arange(3), X, Y, u, v, c, o, col, margins=(1e-4, 0.0))
+    assert not r.flagged[0] and r.slack[0] == 0.0
+    expect = 0.4 * 0.5 + 0.9 * 0.3 * 0.5 + 0.1 * 0.2 * 0.5 * 0.7
+    assert abs(r.color[0][0, 0] - expect) < 1e-15
+
+
+def test_skip_within_margin_is_flagged_with_its_contribution():
+    a = (1.0 / 255.0) * (1.0 + 5e-5)              # passes, but within 1e-4 of the threshold
+    u, v, c, o, col = seq([0.5, a], [0.2, 1.5])
+    r = oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, margins=(1e-4, 0.0))
+    assert r.flagged[0]
+    T_hi = 1.0 - 0.5 * (1 - 1e-4)                  # upper bound of T after the first pair
+    assert math.isclose(r.slack[0], a * (1 + 1e-4) * T_hi * 1.5, rel_tol=1e-9)
+    # outside the margin nothing is flagged
+    u, v, c, o, col = seq([0.5, (1.0 / 255.0) * 1.01], [0.2, 1.5])
+    r = oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, margins=(1e-4, 0.0))
+    assert not r.flagged[0]
+
+
+def test_stop_within_margin_is_flagged_with_remaining_colour():
+    # T after the first two pairs is 0.02 * 0.01; a third pair of alpha 0.5 takes it to
+    # 1e-4 * (1 + 1e-5): just above the stop threshold, within the margin
+    a3 = 1.0 - 1e-4 * (1 + 1e-5) / (0.02 * 0.01)
+    u, v, c, o, col = seq([0.98, 0.99, a3, 0.3], [0.5, 0.5, 0.8, 1.2])
+    r = oracle.blend_tile(np.arange(4), X, Y, u, v, c, o, col, margins=(1e-4, 0.0))
+    assert r.flagged[0]
+    T_before = 0.02 * 0.01
+    assert r.slack[0] >= T_before * 1.2 * 0.99
+    # the same sequence with a clear stop is not flagged and stops at the third pair
+    u, v, c, o, col = seq([0.98, 0.99, 0.9, 0.3], [0.5, 0.5, 0.8, 1.2])
+    r = oracle.blend_tile(np.arange(4), X, Y, u, v, c, o, col, margins=(1e-4, 0.0))
+    assert not r.flagged[0] and r.n_proc[0][0] == 3
+
+
+def test_exact_and_bit_level_stops_that_differ_give_mode_slack():
+    # bit-level exp underestimates alpha by up to 3 %, so T can stay above 1e-4 where the
+    # exact alpha takes it below
+    P = [math.log(0.9), math.log(0.9), math.log(0.9), math.log(0.92), math.log(0.5)]
+    u, v, c, o, col = seq(np.exp(P), [0.3, 0.4, 0.5, 0.6, 0.9], lno=True)
+    r = oracle.blend_tile(np.arange(5), X, Y, u, v, c, o, col, modes=("fast-def", "fast-exact"),
+                          margins=(2e-3, 2e-3))
+    stops = [int(r.n_proc[m][0]) for m in range(2)]
+    T_def = float(r.T[0][0])
+    if stops[0] != stops[1]:
+        assert r.mode_slack[0] > 0
+    else:
+        assert r.mode_slack[0] == 0
+    assert 0.0 <= T_def <= 1.0
+
+
+def test_fast_skip_margin_on_P():
+    P = [math.log(0.6), -math.log(255.0) + 1e-3]     # second pair within 2e-3 of the threshold
+    u, v, c, o, col = seq(np.exp(P), [0.3, 2.0], lno=True)
+    r = oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, modes=("fast-def",), margins=(2e-3, 2e-3))
+    assert r.flagged[0] and r.slack[0] > 0
