@@ -98,8 +98,11 @@ def measured_traffic(kernel, workload, src):
 
 
 def time_path(R, ds, cams, path, steps, warmup, lat_frames):
-    """Throughput over `steps` frames cycling through `cams`, stage times from the
-    library's HIP events over that timed region, then per-frame latency."""
+    """Throughput over `steps` frames cycling through `cams` (nothing but the
+    frames on the stream), then the same number of frames with the library's
+    per-stage HIP events on its stream (each recorded event idles the GPU for a
+    few microseconds, so they stay out of the throughput loop), then per-frame
+    latency between events bracketing back-to-back frames."""
     import torch
     W, H = cams[0].width, cams[0].height
     need = 0
@@ -110,18 +113,18 @@ def time_path(R, ds, cams, path, steps, warmup, lat_frames):
     for k in range(warmup):
         R.render(ds, cams[k % len(cams)], path, check=False)
     torch.cuda.synchronize()
-    R.ctx.set_timing(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
         R.render(ds, cams[k % len(cams)], path, check=False)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stage_ms, nf = R.ctx.collect_timing()
-    R.ctx.set_timing(False)
     chk = R.check(ds, cams[(steps - 1) % len(cams)], path)
     assert chk["overflow"] == 0 and chk["device_error"] == 0, chk
-    # per-frame latency on the stream, frames back to back
+    R.ctx.set_timing(True)
+    for k in range(steps):
+        R.render(ds, cams[k % len(cams)], path, check=False)
+    stage_ms, nf = R.ctx.collect_timing()
+    R.ctx.set_timing(False)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(lat_frames)]
     for k in range(lat_frames):

@@ -249,10 +249,12 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev
                     const float2 c = lc[k0 + u];
                     const float P0 = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(m.x, y, m.y)))));
                     const float P1 = P0 + fmaf(a.y, x, fmaf(a.z, y21, m.x));
+                    const bool pass0 = live0 && P0 >= -LN255F;
+                    const bool pass1 = live1 && P1 >= -LN255F;
                     const int I0 = min((int)fmaf(P0, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
                     const int I1 = min((int)fmaf(P1, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
-                    const float al0 = (live0 && P0 >= -LN255F) ? __int_as_float(I0) : 0.0f;
-                    const float al1 = (live1 && P1 >= -LN255F) ? __int_as_float(I1) : 0.0f;
+                    const float al0 = pass0 ? __int_as_float(I0) : 0.0f;
+                    const float al1 = pass1 ? __int_as_float(I1) : 0.0f;
                     const float w0 = al0 * T0, w1 = al1 * T1;
                     float Tn0 = T0 - w0, Tn1 = T1 - w1;
                     float nr0 = fmaf(w0, m.z, r0), ng0 = fmaf(w0, m.w, g0), nb0 = fmaf(w0, c.x, b0);

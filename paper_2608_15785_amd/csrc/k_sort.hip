@@ -75,7 +75,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_upsweep(const KeyT* __re
 }
 
 // Digit d (one workgroup each): exclusive scan of its per-tile counts, in
-// place, and the size of the digit's bucket.
+// place, and the size of the digit's bucket.  Each thread scans a contiguous
+// chunk of the row in registers; one block scan joins the chunks.
+constexpr int OFFSETS_CHUNK = 16;
+
 __global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t nb_max) {
     __shared__ uint32_t s_wtot[4];
     const uint32_t d = blockIdx.x;
@@ -83,11 +86,22 @@ __global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t nb_max
     const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
     uint32_t* row = ws.tile_counts + (uint64_t)d * nb_max;
     uint32_t carry = 0;
-    for (uint32_t c = 0; c < nb; c += 256) {
-        const uint32_t i = c + threadIdx.x;
-        const uint32_t v = i < nb ? row[i] : 0u;
-        const uint32_t incl = block256_inclusive_scan(v, s_wtot);
-        if (i < nb) row[i] = carry + incl - v;
+    for (uint32_t c0 = 0; c0 < nb; c0 += 256 * OFFSETS_CHUNK) {
+        const uint32_t b = c0 + threadIdx.x * OFFSETS_CHUNK;
+        uint32_t v[OFFSETS_CHUNK];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int k = 0; k < OFFSETS_CHUNK; ++k) {
+            v[k] = b + k < nb ? row[b + k] : 0u;
+            sum += v[k];
+        }
+        const uint32_t incl = block256_inclusive_scan(sum, s_wtot);
+        uint32_t run = carry + incl - sum;
+#pragma unroll
+        for (int k = 0; k < OFFSETS_CHUNK; ++k) {
+            if (b + k < nb) row[b + k] = run;
+            run += v[k];
+        }
         carry += s_wtot[0] + s_wtot[1] + s_wtot[2] + s_wtot[3];
         __syncthreads();
     }
@@ -117,6 +131,10 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const KeyT* __re
     for (uint32_t i = tid; i < WAVES * RADIX; i += SORT_THREADS) s_whist[i] = 0;
     __syncthreads();
     const uint32_t n_valid = min((uint32_t)SORT_TILE, n - tile_base);
+    // this tile's offset inside digit tid's bucket and the bucket's size do not
+    // depend on the keys: start both loads before the keys'
+    const uint32_t tile_off = ws.tile_counts[(uint64_t)tid * nb_max + vb];
+    const uint32_t bucket = ws.hist[tid];
 
     // wave w owns entries [tile_base + w*ITEMS*64, +ITEMS*64); round r, lane l
     // holds entry tile_base + w*ITEMS*64 + r*64 + l
@@ -167,9 +185,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const KeyT* __re
         }
         const uint32_t incl = block256_inclusive_scan(tot, s_wtot);
         s_bstart[d] = incl - tot;
-        const uint32_t bucket = ws.hist[d];
         const uint32_t bincl = block256_inclusive_scan(bucket, s_wtot);
-        s_gbase[d] = (bincl - bucket) + ws.tile_counts[(uint64_t)d * nb_max + vb] - (incl - tot);
+        s_gbase[d] = (bincl - bucket) + tile_off - (incl - tot);
     }
     __syncthreads();
 
