@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=2048, help="tiles the oracle blends")
     ap.add_argument("--paths", default="fast,plain")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=1.5, help="schedule length per arrival rate")
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (scale reference for HBM counters)")
     return ap.parse_args()
@@ -190,6 +193,75 @@ def cpu_baseline(scene, cam, n_tiles_sample):
                        f"({frame_s:.1f} s per frame)")
 
 
+def serving_section(rgs, wl, torch, dev_scenes, args):
+    """Poisson request schedules at 200/500/1000 req/s over the two resident scenes,
+    resolutions 50% 720p / 35% 1080p / 15% 4K, fast path through graph replays."""
+    res_list = [(1280, 720), (1920, 1080), (3840, 2160)]
+    ring = {wh: [torch.empty((3, wh[1], wh[0]), dtype=torch.float32, device="cuda") for _ in range(8)]
+            for wh in res_list}
+    torch.cuda.synchronize()
+
+    def schedule(rate, n, seed, burst_all=False):
+        arr, res, sc, pose = wl.poisson_requests(rate, n, seed=seed)
+        arr = np.zeros(n) if burst_all else arr - arr[0]
+        reqs = []
+        for i in range(n):
+            wh = (int(res[i][0]), int(res[i][1]))
+            cam = wl.serving_camera(int(sc[i]), int(pose[i]), *wh)
+            reqs.append((dev_scenes[int(sc[i])], cam, "fast", float(arr[i]), ring[wh][i % 8]))
+        return reqs
+
+    def summarise(resp, st, n):
+        lat = np.array([r["latency"] for r in resp if r["status"] == 0]) * 1e3
+        ok = int(np.sum([r["status"] == 0 for r in resp]))
+        return {"requests": n, "ok": ok, "retried": int(sum(r["retried"] for r in resp)),
+                "fps": round(ok / st["wall"], 1) if st["wall"] > 0 else None,
+                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                               "p99": round(float(np.percentile(lat, 99)), 4),
+                               "mean": round(float(lat.mean()), 4)},
+                "max_in_flight": st["max_in_flight"], "mean_in_flight": round(st["mean_in_flight"], 3),
+                "ws_gib_peak": round(st["ws_bytes_peak"] / 2**30, 2), "n_evicted": st["n_evicted"]}
+
+    budget = 32 << 30
+    out = {"n_streams": args.serve_streams, "mem_budget_gib": budget >> 30, "graphs": True,
+           "mix": "50% 1280x720, 35% 1920x1080, 15% 3840x2160; scenes 1M / 3M equally; random orbit pose"}
+    srv = rgs.Server(0, n_streams=args.serve_streams, mem_budget=budget, use_graphs=True,
+                     entries_per_gaussian=6.0)
+    # warm-up: every class once per slot, so workspaces and graphs exist before timing
+    warm = []
+    for s_idx in range(2):
+        for wh in res_list:
+            for k in range(args.serve_streams):
+                cam = wl.serving_camera(s_idx, 5 * k, *wh)
+                warm.append((dev_scenes[s_idx], cam, "fast", 0.0, ring[wh][k]))
+    _, st = srv.serve(warm)
+    srv.serve(warm)
+    out["warmup"] = {"requests": len(warm), "graphs_captured": st["n_captured"],
+                     "ws_gib": round(st["ws_bytes_held"] / 2**30, 2)}
+    rates = {}
+    for rate in (200, 500, 1000):
+        n = max(50, int(rate * args.serve_seconds))
+        resp, st = srv.serve(schedule(rate, n, 3))
+        rates[str(rate)] = summarise(resp, st, n)
+        log(f"[bench] serving {rate} req/s: {rates[str(rate)]}")
+    out["rates"] = rates
+    n_sat = 600
+    resp, st = srv.serve(schedule(1000, n_sat, 7, burst_all=True))
+    out["saturation"] = summarise(resp, st, n_sat)
+    log(f"[bench] serving saturation: {out['saturation']}")
+    srv.close()
+    for label, streams, graphs in (("saturation_direct_launch", args.serve_streams, False),
+                                   ("saturation_one_stream", 1, True)):
+        s2 = rgs.Server(0, n_streams=streams, mem_budget=budget, use_graphs=graphs, entries_per_gaussian=6.0)
+        s2.serve(warm)
+        resp, st = s2.serve(schedule(1000, n_sat, 7, burst_all=True))
+        out[label] = summarise(resp, st, n_sat)
+        log(f"[bench] serving {label}: {out[label]}")
+        s2.close()
+    del ring
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -242,6 +314,22 @@ def main():
             r["roofline_pose0"] = rooflines(path, r, r["stage_ms"], sc2.n, plan2["n_tiles"])
             res2[path] = r
             log(f"[bench] cfg2 {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
+        if args.no_serving:
+            ds2.release()
+
+    serving = None
+    if not args.no_serving:
+        log("[bench] serving: 1M and 3M scenes resident, Poisson arrivals")
+        if args.no_4k:
+            sc2 = wl.config_scene("cfg2")
+            ds2 = R.upload(sc2, ("fast",))
+        ds1b = R.upload(sc1, ("fast",))
+        try:
+            serving = serving_section(rgs, wl, torch, [ds1b, ds2], args)
+        except rgs.RGSError as e:
+            serving = {"error": str(e)}
+            log(f"[bench] serving failed: {e}")
+        ds1b.release()
         ds2.release()
 
     main_path = "fast" if "fast" in res1 else paths[0]
@@ -294,6 +382,8 @@ def main():
                                  for p, r in res2.items()}
         if "fast" in res2 and "plain" in res2:
             out["speedup_fast_over_plain_4k"] = round(res2["fast"]["fps"] / res2["plain"]["fps"], 3)
+    if serving is not None:
+        out["serving"] = serving
     print(json.dumps(out), flush=True)
 
 

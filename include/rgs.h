@@ -283,6 +283,95 @@ rgs_status rgs_render_debug(rgs_ctx* ctx, const rgs_scene* scene, const rgs_came
                             rgs_debug_out* dbg, rgs_frame_stats* stats);
 
 /* ---------------------------------------------------------------------------
+ * Request server: continuous batching of view requests over resident scenes.
+ * The paper renders one view at a time; this runtime serves many, and every
+ * image it returns is the one rgs_render computes for the same request, bit
+ * for bit.
+ *
+ * A request is admitted, in arrival order, as soon as (a) one of n_streams
+ * frame slots is free and (b) a workspace of its (scene, width, height, path)
+ * class is idle or can be allocated within mem_budget bytes (idle workspaces
+ * of other classes are released, least recently used first, to make room).
+ * Frames of different slots overlap on the device.  A request waits behind an
+ * earlier one that cannot be admitted yet.
+ *
+ * With use_graphs = 1 every workspace carries a HIP graph of its whole frame
+ * (reset, front end, sort, ranges, raster, status export) captured once with
+ * the workspace's capacity; a request replays it after its camera and output
+ * pointer are written into the argument block of the graph's reset kernel.
+ * With use_graphs = 0 the kernels are launched per request.  A frame whose
+ * entries exceed its workspace is rendered again, uncaptured, in a workspace
+ * sized for it, and later workspaces of its class are allocated larger.
+ *
+ * Requests' device pointers (scenes, outputs) must stay valid, and outputs
+ * untouched by other work, until rgs_serve returns.  rgs_serve synchronises:
+ * it returns when every admitted frame has finished.  One thread at a time
+ * may use a server.
+ */
+typedef struct rgs_server rgs_server;
+
+typedef struct {
+    int32_t device;
+    int32_t n_streams;            /* frame slots, 1..16                                      */
+    uint64_t mem_budget;          /* bytes of workspace the server may hold at once (> 0)   */
+    int32_t use_graphs;           /* 1: replay captured frame graphs; 0: per-request launches */
+    int32_t reserved;
+    double entries_per_gaussian;  /* first workspace size of a class, entries per Gaussian
+                                     (0: 4)                                                   */
+} rgs_server_config;
+
+typedef struct {
+    const rgs_scene* scene;       /* resident scene on the server's device                  */
+    rgs_camera camera;
+    int32_t width, height;
+    int32_t path;                 /* RGS_PATH_PLAIN or RGS_PATH_FAST                         */
+    int32_t reserved;
+    double arrival;               /* seconds after the schedule starts, non-decreasing, >= 0 */
+    float* out_chw;               /* device [3][height][width], caller-owned                 */
+} rgs_request;
+
+typedef struct {
+    rgs_status status;            /* RGS_OK, or why this request failed (RGS_E_OOM: its
+                                     workspace alone exceeds the budget)                      */
+    int32_t slot;                 /* frame slot that ran it (-1 if none)                      */
+    int32_t graph;                /* 1 if the frame was a graph replay                        */
+    int32_t retried;              /* 1 if it was rendered again after running out of entries */
+    double t_admit;               /* host clock, s after start, when its work was enqueued     */
+    double t_done;                /* device clock, s after start, when its image was complete  */
+    double latency;               /* t_done - arrival                                          */
+    int64_t n_entries;            /* duplicated (key, index) entries of the frame              */
+} rgs_response;
+
+typedef struct {
+    double wall;                  /* s from start until the last image was complete          */
+    uint64_t ws_bytes_held;       /* workspace bytes held when rgs_serve returned             */
+    uint64_t ws_bytes_peak;       /* most workspace bytes held at once during the call        */
+    int32_t n_workspaces;         /* workspaces held when rgs_serve returned                  */
+    int32_t n_captured;           /* graphs captured during the call                          */
+    int32_t n_evicted;            /* idle workspaces released to make room                    */
+    int32_t max_in_flight;        /* most frames admitted and unfinished at once              */
+    double mean_in_flight;        /* sum over requests of (t_done - t_admit) / wall           */
+    double reserved;
+} rgs_server_stats;
+
+/* Creates the slots' streams (default priority, non-blocking) and events.
+ * Errors: INVALID (NULL, device out of range, n_streams outside 1..16,
+ * mem_budget 0, negative entries_per_gaussian), NODEVICE, HIP. */
+rgs_status rgs_server_create(const rgs_server_config* cfg, rgs_server** out);
+/* Waits for the slots' streams, then frees workspaces, graphs, streams. */
+void rgs_server_destroy(rgs_server* server);
+/* Runs the schedule reqs[0..n) in real time (request i becomes eligible at
+ * reqs[i].arrival seconds after the call starts) and fills resp[0..n).
+ * Returns RGS_OK when the schedule ran, even if single requests failed (see
+ * resp[i].status); INVALID (nothing ran) if any request is malformed: NULL
+ * scene or output, a scene of another device or without the path's format,
+ * a bad size, camera or path, arrivals not finite, negative or decreasing;
+ * HIP if the runtime failed (every admitted frame has finished or been
+ * abandoned by then).  stats may be NULL. */
+rgs_status rgs_serve(rgs_server* server, const rgs_request* reqs, int64_t n, rgs_response* resp,
+                     rgs_server_stats* stats);
+
+/* ---------------------------------------------------------------------------
  * Gradients of a loss with respect to the activated scene parameters
  * (means, scales, quats, opacity, sh) given dL/d(image).  Not part of the
  * paper, which renders only (Sec. V names training as future work).

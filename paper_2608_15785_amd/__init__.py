@@ -4,11 +4,11 @@ The render runs in the HIP kernels of ``librgs.so`` (C ABI in include/rgs.h);
 this package is its binding.  Importing it fails if the library has not been
 built: there is no CPU path.
 """
-from ._binding import (FMT_FAST, FMT_PLAIN, PATHS, RGSError, Context, DeviceScene, camera_struct,
+from ._binding import (FMT_FAST, FMT_PLAIN, PATHS, RGSError, Context, DeviceScene, Server, camera_struct,
                        frame_plan, lib, new_workspace, quantize_host, render, render_debug,
                        workspace_capacity, workspace_check, workspace_size)
 from .renderer import Renderer
 
-__all__ = ["FMT_FAST", "FMT_PLAIN", "PATHS", "RGSError", "Context", "DeviceScene", "camera_struct",
+__all__ = ["FMT_FAST", "FMT_PLAIN", "PATHS", "RGSError", "Context", "DeviceScene", "Server", "camera_struct",
            "frame_plan", "lib", "new_workspace", "quantize_host", "render", "render_debug",
            "workspace_capacity", "workspace_check", "workspace_size", "Renderer"]

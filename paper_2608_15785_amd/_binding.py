@@ -88,6 +88,29 @@ class Grads(C.Structure):
                 ("d_opacity", C.c_void_p), ("d_sh", C.c_void_p)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("device", C.c_int32), ("n_streams", C.c_int32), ("mem_budget", C.c_uint64),
+                ("use_graphs", C.c_int32), ("reserved", C.c_int32), ("entries_per_gaussian", C.c_double)]
+
+
+class Request(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("camera", CameraC), ("width", C.c_int32), ("height", C.c_int32),
+                ("path", C.c_int32), ("reserved", C.c_int32), ("arrival", C.c_double),
+                ("out_chw", C.c_void_p)]
+
+
+class Response(C.Structure):
+    _fields_ = [("status", C.c_int32), ("slot", C.c_int32), ("graph", C.c_int32), ("retried", C.c_int32),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("latency", C.c_double),
+                ("n_entries", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("wall", C.c_double), ("ws_bytes_held", C.c_uint64), ("ws_bytes_peak", C.c_uint64),
+                ("n_workspaces", C.c_int32), ("n_captured", C.c_int32), ("n_evicted", C.c_int32),
+                ("max_in_flight", C.c_int32), ("mean_in_flight", C.c_double), ("reserved", C.c_double)]
+
+
 # (name, restype, argtypes) of every entry point of rgs.h
 SIGNATURES = [
     ("rgs_abi_version", C.c_int32, []),
@@ -114,6 +137,10 @@ SIGNATURES = [
     ("rgs_render_debug", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(CameraC), C.c_int32, C.c_int32,
                                      C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(DebugOut),
                                      C.POINTER(FrameStats)]),
+    ("rgs_server_create", C.c_int32, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
+    ("rgs_server_destroy", None, [C.c_void_p]),
+    ("rgs_serve", C.c_int32, [C.c_void_p, C.POINTER(Request), C.c_int64, C.POINTER(Response),
+                              C.POINTER(ServerStats)]),
     ("rgs_render_backward", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(CameraC), C.c_int32, C.c_int32,
                                         C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Grads)]),
 ]
@@ -301,6 +328,50 @@ def render(ctx: Context, scene: DeviceScene, cam, path: str, workspace, out=None
                           workspace.numel(), out.data_ptr(), C.byref(st) if st is not None else None),
            "rgs_render")
     return out, (st.as_dict() if st is not None else None)
+
+
+class Server:
+    """Continuous-batching request server over resident scenes (``rgs_serve``)."""
+
+    def __init__(self, device: int = 0, n_streams: int = 4, mem_budget: int = 8 << 30,
+                 use_graphs: bool = True, entries_per_gaussian: float = 0.0):
+        cfg = ServerConfig(device=device, n_streams=n_streams, mem_budget=int(mem_budget),
+                           use_graphs=1 if use_graphs else 0, reserved=0,
+                           entries_per_gaussian=float(entries_per_gaussian))
+        h = C.c_void_p()
+        _check(lib.rgs_server_create(C.byref(cfg), C.byref(h)), "rgs_server_create")
+        self.handle = h.value
+
+    def serve(self, requests):
+        """Run a schedule.  ``requests``: sequence of (DeviceScene, camera, path, arrival_s, out) with
+        ``out`` a device tensor [3, H, W]; returns (list of response dicts, stats dict)."""
+        n = len(requests)
+        reqs = (Request * max(n, 1))()
+        for i, (scene, cam, path, arrival, out) in enumerate(requests):
+            r = reqs[i]
+            r.scene = scene.handle
+            r.camera = camera_struct(cam)
+            r.width, r.height = int(cam.width), int(cam.height)
+            r.path = PATHS[path]
+            r.reserved = 0
+            r.arrival = float(arrival)
+            r.out_chw = out.data_ptr()
+        resp = (Response * max(n, 1))()
+        st = ServerStats()
+        _check(lib.rgs_serve(self.handle, reqs, n, resp, C.byref(st)), "rgs_serve")
+        rows = [{k: getattr(resp[i], k) for k, _ in Response._fields_} for i in range(n)]
+        return rows, {k: getattr(st, k) for k, _ in ServerStats._fields_ if k != "reserved"}
+
+    def close(self):
+        if self.handle:
+            lib.rgs_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def workspace_stats(ctx: Context, workspace, n: int = 0) -> dict:

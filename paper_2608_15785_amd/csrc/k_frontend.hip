@@ -121,27 +121,59 @@ __device__ inline void write_debug(const DebugDev& dbg, int64_t i, const Project
 }
 
 // ---------------------------------------------------------------------------
-// Frame reset: zero the header, the tile ranges and the front-end scan state.
+// Frame reset: copy the frame's parameters into the workspace, zero the
+// header, the tile ranges, the front-end scan state and the digit buckets.
 
-__global__ void k_reset(uint32_t* base, uint64_t n_words, uint32_t capacity, uint32_t path,
-                        uint32_t passes) {
-    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += stride) {
+__global__ void k_reset(ResetArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.dst = a.prm;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_words; i += stride) {
         uint32_t v = 0;
-        if (i == offsetof(WsHeader, capacity) / 4) v = capacity;
-        if (i == offsetof(WsHeader, path) / 4) v = path;
-        if (i == offsetof(WsHeader, passes) / 4) v = passes;
-        base[i] = v;
+        if (i == offsetof(WsHeader, capacity) / 4) v = a.capacity;
+        if (i == offsetof(WsHeader, path) / 4) v = a.path;
+        if (i == offsetof(WsHeader, passes) / 4) v = a.passes;
+        a.base[i] = v;
     }
 }
 
-void launch_reset(hipStream_t s, const WsDev& ws, uint64_t zero_bytes, const FrameDev& f,
-                  uint32_t path) {
-    uint64_t words = zero_bytes / 4;
-    uint32_t blocks = (uint32_t)((words + 255) / 256);
+ResetArgs reset_args(const WsDev& ws, uint64_t zero_bytes, const FrameDev& f, uint32_t path,
+                     const FrameParams& prm) {
+    ResetArgs a{};
+    a.base = reinterpret_cast<uint32_t*>(ws.header);
+    a.n_words = zero_bytes / 4;
+    a.capacity = f.capacity;
+    a.path = path;
+    a.passes = (uint32_t)f.passes;
+    a.dst = const_cast<FrameParams*>(ws.params);
+    a.prm = prm;
+    return a;
+}
+
+void launch_reset(hipStream_t s, const ResetArgs& a) {
+    uint32_t blocks = (uint32_t)((a.n_words + 255) / 256);
     if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, s, reinterpret_cast<uint32_t*>(ws.header),
-                       words, f.capacity, path, (uint32_t)f.passes);
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_reset, dim3(blocks), dim3(256), 0, s, a);
+}
+
+const void* reset_kernel() { return reinterpret_cast<const void*>(&k_reset); }
+
+// Copy the frame's outcome from the header to host-visible memory.
+__global__ void k_export_status(const WsHeader* h, const FrameParams* prm, FrameStatus* dst) {
+    if (threadIdx.x == 0) {
+        FrameStatus st;
+        st.n_entries = h->n_entries;
+        st.n_visible = h->n_visible;
+        st.overflow = h->overflow;
+        st.error = h->error;
+        st.done = 1;
+        st.out = reinterpret_cast<uint64_t>(prm->out);
+        *dst = st;
+    }
+}
+
+void launch_export_status(hipStream_t s, const WsDev& ws, FrameStatus* dst) {
+    hipLaunchKernelGGL(k_export_status, dim3(1), dim3(64), 0, s, ws.header, ws.params, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -294,8 +326,9 @@ __device__ inline void finish_block(WsDev& ws, uint32_t vb, uint32_t n_blocks, u
 // Plain preprocess: one thread per Gaussian over the FP32 planes.
 
 template <bool DEBUG>
-__global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, CamDev cam, FrameDev f,
-                                                          WsDev ws, DebugDev dbg) {
+__global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, FrameDev f, WsDev ws,
+                                                          DebugDev dbg) {
+    const CamDev cam = ws.params->cam;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool in = i < sc.n;
     bool vis = false;
@@ -332,13 +365,13 @@ __global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, CamD
     }
 }
 
-void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam,
-                             const FrameDev& f, const WsDev& ws, const DebugDev* dbg) {
+void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const FrameDev& f,
+                             const WsDev& ws, const DebugDev* dbg) {
     uint32_t blocks = (uint32_t)((sc.n + 255) / 256);
     if (dbg)
-        hipLaunchKernelGGL(k_preprocess_plain<true>, dim3(blocks), dim3(256), 0, s, sc, cam, f, ws, *dbg);
+        hipLaunchKernelGGL(k_preprocess_plain<true>, dim3(blocks), dim3(256), 0, s, sc, f, ws, *dbg);
     else
-        hipLaunchKernelGGL(k_preprocess_plain<false>, dim3(blocks), dim3(256), 0, s, sc, cam, f, ws,
+        hipLaunchKernelGGL(k_preprocess_plain<false>, dim3(blocks), dim3(256), 0, s, sc, f, ws,
                            DebugDev{});
 }
 
@@ -447,9 +480,9 @@ __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& c
 }
 
 template <bool DEBUG>
-__global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, CamDev cam, FrameDev f,
-                                                              WsDev ws, uint32_t n_blocks,
-                                                              DebugDev dbg) {
+__global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, FrameDev f, WsDev ws,
+                                                              uint32_t n_blocks, DebugDev dbg) {
+    const CamDev cam = ws.params->cam;
     __shared__ uint32_t s_vb;
     __shared__ uint32_t s_incl[FE_TILE];
     __shared__ uint64_t s_rect[FE_TILE];
@@ -489,15 +522,14 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, C
     finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
 }
 
-void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const CamDev& cam,
-                          const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
-                          const DebugDev* dbg) {
+void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
+                          uint32_t fe_blocks, const DebugDev* dbg) {
     if (dbg)
-        hipLaunchKernelGGL(k_frontend_fast<true>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, cam, f, ws,
+        hipLaunchKernelGGL(k_frontend_fast<true>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, f, ws,
                            fe_blocks, *dbg);
     else
-        hipLaunchKernelGGL(k_frontend_fast<false>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, cam, f,
-                           ws, fe_blocks, DebugDev{});
+        hipLaunchKernelGGL(k_frontend_fast<false>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, f, ws,
+                           fe_blocks, DebugDev{});
 }
 
 __global__ void k_widen_keys(const uint32_t* in, uint64_t* out, uint64_t n) {

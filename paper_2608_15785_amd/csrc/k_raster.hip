@@ -54,9 +54,8 @@ __device__ inline float fast_exp(float P) {
 // ---------------------------------------------------------------------------
 
 template <bool COUNT>
-__global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, CamDev cam, WsDev ws,
-                                                      const uint32_t* __restrict__ vals,
-                                                      float* __restrict__ out) {
+__global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
+                                                      const uint32_t* __restrict__ vals) {
     __shared__ float4 s_a[256];   // u, v (tile-local), A, B
     __shared__ float4 s_b[256];   // C, opacity, r, g
     __shared__ float s_c[256];    // b
@@ -114,23 +113,24 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, CamDev cam, Ws
     if (inside) {
         const uint64_t plane = (uint64_t)f.width * f.height;
         const uint64_t o = (uint64_t)py * f.width + px;
-        out[o] = fmaf(T, cam.bg[0], cr);
-        out[plane + o] = fmaf(T, cam.bg[1], cg);
-        out[2 * plane + o] = fmaf(T, cam.bg[2], cb);
+        float* __restrict__ out = ws.params->out;
+        const float bg0 = ws.params->cam.bg[0], bg1 = ws.params->cam.bg[1], bg2 = ws.params->cam.bg[2];
+        out[o] = fmaf(T, bg0, cr);
+        out[plane + o] = fmaf(T, bg1, cg);
+        out[2 * plane + o] = fmaf(T, bg2, cb);
         ws.t_final[o] = T;
         ws.n_proc[o] = stop_at != 0xffffffffu ? stop_at - start + 1 : end - start;
         if (COUNT) ws.n_blend[o] = n_blend;
     }
 }
 
-void launch_raster_plain(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
-                         bool result_in_b, float* out, bool count) {
+void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
+                         bool count) {
+    const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
     if (count)
-        hipLaunchKernelGGL(k_raster_plain<true>, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, cam, ws,
-                           result_in_b ? ws.vals_b : ws.vals_a, out);
+        hipLaunchKernelGGL(k_raster_plain<true>, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, ws, vals);
     else
-        hipLaunchKernelGGL(k_raster_plain<false>, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, cam, ws,
-                           result_in_b ? ws.vals_b : ws.vals_a, out);
+        hipLaunchKernelGGL(k_raster_plain<false>, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, ws, vals);
 }
 
 // ---------------------------------------------------------------------------
@@ -147,9 +147,8 @@ constexpr float BOX_MARGIN_REL = 1.0e-3f;
 constexpr float BOX_MARGIN_ABS = 0.05f;
 
 template <bool COUNT>
-__global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev cam, WsDev ws,
-                                                              const uint32_t* __restrict__ vals,
-                                                              float* __restrict__ out) {
+__global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev ws,
+                                                              const uint32_t* __restrict__ vals) {
     // per-wave lists of folded Gaussians, in depth order
     __shared__ float4 s_a[2][LIST_CAP];   // C1, C2, C3, C4
     __shared__ float4 s_b[2][LIST_CAP];   // C5, C6, r, g
@@ -287,34 +286,37 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, CamDev
         __syncthreads();
     }
     const uint64_t plane = (uint64_t)f.width * f.height;
+    float* __restrict__ out = ws.params->out;
+    const float bg0 = ws.params->cam.bg[0], bg1 = ws.params->cam.bg[1], bg2 = ws.params->cam.bg[2];
     if (in0) {
         const uint64_t o = (uint64_t)py * f.width + px;
-        out[o] = fmaf(T0, cam.bg[0], r0);
-        out[plane + o] = fmaf(T0, cam.bg[1], g0);
-        out[2 * plane + o] = fmaf(T0, cam.bg[2], b0);
+        out[o] = fmaf(T0, bg0, r0);
+        out[plane + o] = fmaf(T0, bg1, g0);
+        out[2 * plane + o] = fmaf(T0, bg2, b0);
         ws.t_final[o] = T0;
         ws.n_proc[o] = stop0 != 0xffffffffu ? stop0 - start + 1 : end - start;
         if (COUNT) ws.n_blend[o] = nbl0;
     }
     if (in1) {
         const uint64_t o = (uint64_t)(py + 1) * f.width + px;
-        out[o] = fmaf(T1, cam.bg[0], r1);
-        out[plane + o] = fmaf(T1, cam.bg[1], g1);
-        out[2 * plane + o] = fmaf(T1, cam.bg[2], b1);
+        out[o] = fmaf(T1, bg0, r1);
+        out[plane + o] = fmaf(T1, bg1, g1);
+        out[2 * plane + o] = fmaf(T1, bg2, b1);
         ws.t_final[o] = T1;
         ws.n_proc[o] = stop1 != 0xffffffffu ? stop1 - start + 1 : end - start;
         if (COUNT) ws.n_blend[o] = nbl1;
     }
 }
 
-void launch_raster_fast(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
-                        bool result_in_b, float* out, bool count) {
+void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
+                        bool count) {
+    const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
     if (count)
-        hipLaunchKernelGGL(k_raster_fast<true>, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, cam,
-                           ws, result_in_b ? ws.vals_b : ws.vals_a, out);
+        hipLaunchKernelGGL(k_raster_fast<true>, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
+                           vals);
     else
-        hipLaunchKernelGGL(k_raster_fast<false>, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, cam,
-                           ws, result_in_b ? ws.vals_b : ws.vals_a, out);
+        hipLaunchKernelGGL(k_raster_fast<false>, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
+                           vals);
 }
 
 }  // namespace rgs

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "rgs.h"
+#include "rgs_host.h"
 #include "rgs_internal.h"
 
 using namespace rgs;
@@ -20,7 +21,7 @@ using namespace rgs;
 
 static thread_local std::string g_last_error;
 
-static rgs_status fail(rgs_status s, const char* fmt, ...) {
+rgs_status rgs::fail(rgs_status s, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -30,18 +31,10 @@ static rgs_status fail(rgs_status s, const char* fmt, ...) {
     return s;
 }
 
-static rgs_status ok() {
+rgs_status rgs::ok() {
     g_last_error.clear();
     return RGS_OK;
 }
-
-#define HIP_TRY(expr)                                                                       \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess)                                                               \
-            return fail(e_ == hipErrorOutOfMemory ? RGS_E_OOM : RGS_E_HIP, "%s: %s", #expr, \
-                        hipGetErrorString(e_));                                             \
-    } while (0)
 
 extern "C" int32_t rgs_abi_version(void) { return RGS_ABI_VERSION; }
 
@@ -445,6 +438,8 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     L.hist = off;
     off = align256(off + (uint64_t)MAX_PASSES * RADIX * 4);
     L.zero_end = off;
+    L.params = off;                  // written by the reset kernel, outside the zeroed span
+    off = align256(off + sizeof(FrameParams));
     L.records = off;
     off = align256(off + (uint64_t)n * sizeof(Record));
     L.counts = L.rects = L.depths = 0;
@@ -527,6 +522,7 @@ extern "C" rgs_status rgs_workspace_capacity(int64_t n, int32_t width, int32_t h
 static WsDev ws_pointers(void* base, const WsLayout& L) {
     char* b = static_cast<char*>(base);
     WsDev w;
+    w.params = reinterpret_cast<const FrameParams*>(b + L.params);
     w.header = reinterpret_cast<WsHeader*>(b + L.header);
     w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
     w.fe_state = reinterpret_cast<uint64_t*>(b + L.fe_state);
@@ -549,7 +545,7 @@ static WsDev ws_pointers(void* base, const WsLayout& L) {
 // ---------------------------------------------------------------------------
 // Render
 
-static rgs_status check_camera(const rgs_camera* c) {
+rgs_status rgs::check_camera(const rgs_camera* c) {
     if (!c) return fail(RGS_E_INVALID, "camera is NULL");
     const double* all[] = {c->R, c->t};
     for (int k = 0; k < 9; ++k)
@@ -615,32 +611,38 @@ static rgs_status header_status(const WsHeader& h, rgs_frame_stats* st, int64_t 
     return RGS_OK;
 }
 
-static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camera* cam, int32_t W,
-                              int32_t H, int32_t path, void* ws, uint64_t ws_bytes, float* out,
-                              rgs_debug_out* dbg, rgs_frame_stats* stats) {
-    if (!ctx || !sc) return fail(RGS_E_INVALID, "ctx or scene is NULL");
+FrameParams rgs::frame_params(const rgs_camera* c, float* out) {
+    FrameParams p;
+    p.cam = cam_dev(c);
+    p.out = out;
+    return p;
+}
+
+int rgs::scene_device(const rgs_scene* sc) { return sc->device; }
+
+rgs_status rgs::prepare_frame(const rgs_scene* sc, int32_t W, int32_t H, int32_t path, void* ws,
+                              uint64_t ws_bytes, FrameLaunch* fl) {
+    if (!sc) return fail(RGS_E_INVALID, "scene is NULL");
     rgs_status s = check_path(path);
     if (s != RGS_OK) return s;
     if (path == RGS_PATH_PLAIN && !(sc->formats & RGS_FMT_PLAIN))
         return fail(RGS_E_INVALID, "scene was uploaded without the plain format");
     if (path == RGS_PATH_FAST && !(sc->formats & RGS_FMT_FAST))
         return fail(RGS_E_INVALID, "scene was uploaded without the fast format");
-    s = check_camera(cam);
+    s = rgs_frame_plan(W, H, &fl->plan);
     if (s != RGS_OK) return s;
-    rgs_plan p;
-    s = rgs_frame_plan(W, H, &p);
-    if (s != RGS_OK) return s;
-    if (!ws || !out) return fail(RGS_E_INVALID, "workspace or output is NULL");
+    if (!ws) return fail(RGS_E_INVALID, "workspace is NULL");
     if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
         return fail(RGS_E_INVALID, "workspace must be 256-byte aligned");
+    const rgs_plan& p = fl->plan;
     uint64_t cap = capacity_for(sc->n, p, path, ws_bytes);
     if (cap == 0) return fail(RGS_E_INVALID, "workspace of %llu bytes is too small", (unsigned long long)ws_bytes);
-    WsLayout L;
-    make_layout(sc->n, p, path, cap, L);
-    HIP_TRY(hipSetDevice(ctx->device));
-
-    WsDev w = ws_pointers(ws, L);
-    FrameDev f;
+    fl->device = sc->device;
+    fl->n = sc->n;
+    fl->path = path;
+    make_layout(sc->n, p, path, cap, fl->L);
+    fl->w = ws_pointers(ws, fl->L);
+    FrameDev& f = fl->f;
     f.width = W;
     f.height = H;
     f.tiles_x = p.tiles_x;
@@ -648,10 +650,109 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
     f.n_tiles = p.n_tiles;
     f.b_t = p.b_t;
     f.b_d = p.b_d;
-    f.passes = (int32_t)L.passes;
+    f.passes = (int32_t)fl->L.passes;
     f.capacity = (uint32_t)cap;
     f.n_gaussians = (uint32_t)sc->n;
-    CamDev cd = cam_dev(cam);
+    fl->plain = PlainSceneDev{sc->plain, sc->n_pad, sc->n};
+    fl->fast = FastSceneDev{sc->fast, sc->n_pad, sc->n};
+    return RGS_OK;
+}
+
+rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const FrameParams& prm,
+                              const DebugDev* dbg, bool count, FrameStatus* status,
+                              const FrameHooks* hooks, bool* result_in_b) {
+    auto mark = [&](int k) {
+        if (hooks && hooks->mark) hooks->mark(hooks->user, k);
+    };
+    const WsDev& w = fl.w;
+    mark(0);
+    launch_reset(st, reset_args(w, fl.L.zero_end, fl.f, (uint32_t)fl.path, prm));
+    if (fl.path == RGS_PATH_PLAIN) {
+        launch_preprocess_plain(st, fl.plain, fl.f, w, dbg);
+        mark(1);
+        launch_duplicate_plain(st, fl.n, fl.f, w, fl.L.fe_blocks);
+        mark(2);
+    } else {
+        launch_frontend_fast(st, fl.fast, fl.f, w, fl.L.fe_blocks, dbg);
+        mark(1);
+        mark(2);
+    }
+    if (hooks && hooks->after_front) {
+        rgs_status s = hooks->after_front(hooks->user);
+        if (s != RGS_OK) return s;
+    }
+    bool in_b = false;
+    launch_sort(st, fl.f, w, fl.L.key_bytes, fl.L.passes, fl.L.sort_blocks_max, &in_b);
+    mark(3);
+    launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
+    mark(4);
+    if (fl.path == RGS_PATH_PLAIN) launch_raster_plain(st, fl.f, w, in_b, count);
+    else launch_raster_fast(st, fl.f, w, in_b, count);
+    mark(5);
+    if (status) launch_export_status(st, w, status);
+    if (result_in_b) *result_in_b = in_b;
+    HIP_TRY(hipGetLastError());
+    return RGS_OK;
+}
+
+namespace {
+
+// Instrumentation of a render call: stage events and, for debug renders, the
+// copies of the unsorted entries once the front end has finished.
+struct RenderHooks {
+    rgs_ctx* ctx;
+    FrameEvents* fe;
+    rgs_debug_out* dbg;
+    const FrameLaunch* fl;
+    void* ws;
+    uint64_t n_entries;
+};
+
+void hook_mark(void* user, int k) {
+    RenderHooks* h = static_cast<RenderHooks*>(user);
+    if (h->fe) (void)hipEventRecord(h->fe->ev[k], h->ctx->stream);
+}
+
+rgs_status hook_after_front(void* user) {
+    RenderHooks* h = static_cast<RenderHooks*>(user);
+    rgs_debug_out* dbg = h->dbg;
+    if (!dbg) return RGS_OK;
+    hipStream_t st = h->ctx->stream;
+    const WsDev& w = h->fl->w;
+    WsHeader hd;
+    rgs_status s = read_header(h->ctx, h->ws, &hd);
+    if (s != RGS_OK) return s;
+    h->n_entries = std::min<uint64_t>(hd.n_entries, h->fl->L.capacity);
+    if (dbg->entry_capacity < (int64_t)hd.n_entries &&
+        (dbg->keys_unsorted || dbg->keys_sorted || dbg->vals_unsorted || dbg->vals_sorted))
+        return fail(RGS_E_CAPACITY, "debug entry buffers hold %lld, frame has %llu",
+                    (long long)dbg->entry_capacity, (unsigned long long)hd.n_entries);
+    const uint64_t n = h->n_entries;
+    if (dbg->keys_unsorted && n) {
+        if (h->fl->L.key_bytes == 8)
+            HIP_TRY(hipMemcpyAsync(dbg->keys_unsorted, w.keys_a, n * 8, hipMemcpyDeviceToDevice, st));
+        else
+            launch_widen_keys(st, static_cast<const uint32_t*>(w.keys_a), dbg->keys_unsorted, n);
+    }
+    if (dbg->vals_unsorted && n)
+        HIP_TRY(hipMemcpyAsync(dbg->vals_unsorted, w.vals_a, n * 4, hipMemcpyDeviceToDevice, st));
+    return RGS_OK;
+}
+
+}  // namespace
+
+static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camera* cam, int32_t W,
+                              int32_t H, int32_t path, void* ws, uint64_t ws_bytes, float* out,
+                              rgs_debug_out* dbg, rgs_frame_stats* stats) {
+    if (!ctx || !sc) return fail(RGS_E_INVALID, "ctx or scene is NULL");
+    FrameLaunch fl;
+    rgs_status s = prepare_frame(sc, W, H, path, ws, ws_bytes, &fl);
+    if (s != RGS_OK) return s;
+    s = check_camera(cam);
+    if (s != RGS_OK) return s;
+    if (!out) return fail(RGS_E_INVALID, "output is NULL");
+    HIP_TRY(hipSetDevice(ctx->device));
+
     DebugDev dd{};
     if (dbg) {
         dd.depth = dbg->depth;
@@ -663,64 +764,24 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
         dd.color = dbg->color;
     }
     hipStream_t st = ctx->stream;
-    FrameEvents* fe = nullptr;
+    RenderHooks rh{ctx, nullptr, dbg, &fl, ws, 0};
     if (ctx->timing) {
-        s = next_events(ctx, &fe);
+        s = next_events(ctx, &rh.fe);
         if (s != RGS_OK) return s;
     }
-    auto mark = [&](int k) {
-        if (fe) (void)hipEventRecord(fe->ev[k], st);
-    };
-
-    mark(0);
-    launch_reset(st, w, L.zero_end, f, (uint32_t)path);
-    if (path == RGS_PATH_PLAIN) {
-        PlainSceneDev psd{sc->plain, sc->n_pad, sc->n};
-        launch_preprocess_plain(st, psd, cd, f, w, dbg ? &dd : nullptr);
-        mark(1);
-        launch_duplicate_plain(st, sc->n, f, w, L.fe_blocks);
-        mark(2);
-    } else {
-        FastSceneDev fsd{sc->fast, sc->n_pad, sc->n};
-        launch_frontend_fast(st, fsd, cd, f, w, L.fe_blocks, dbg ? &dd : nullptr);
-        mark(1);
-        mark(2);
-    }
-    uint64_t n_entries = 0;
-    if (dbg) {
-        WsHeader h;
-        s = read_header(ctx, ws, &h);
-        if (s != RGS_OK) return s;
-        n_entries = std::min<uint64_t>(h.n_entries, cap);
-        if (dbg->entry_capacity < (int64_t)h.n_entries && (dbg->keys_unsorted || dbg->keys_sorted ||
-                                                           dbg->vals_unsorted || dbg->vals_sorted))
-            return fail(RGS_E_CAPACITY, "debug entry buffers hold %lld, frame has %llu",
-                        (long long)dbg->entry_capacity, (unsigned long long)h.n_entries);
-        if (dbg->keys_unsorted && n_entries) {
-            if (L.key_bytes == 8)
-                HIP_TRY(hipMemcpyAsync(dbg->keys_unsorted, w.keys_a, n_entries * 8,
-                                       hipMemcpyDeviceToDevice, st));
-            else
-                launch_widen_keys(st, static_cast<const uint32_t*>(w.keys_a), dbg->keys_unsorted, n_entries);
-        }
-        if (dbg->vals_unsorted && n_entries)
-            HIP_TRY(hipMemcpyAsync(dbg->vals_unsorted, w.vals_a, n_entries * 4, hipMemcpyDeviceToDevice, st));
-    }
+    FrameHooks hooks{hook_mark, hook_after_front, &rh};
     bool in_b = false;
-    launch_sort(st, f, w, L.key_bytes, L.passes, L.sort_blocks_max, &in_b);
-    mark(3);
-    launch_ranges(st, f, w, L.key_bytes, in_b);
-    mark(4);
-    if (path == RGS_PATH_PLAIN) launch_raster_plain(st, f, cd, w, in_b, out, dbg != nullptr);
-    else launch_raster_fast(st, f, cd, w, in_b, out, dbg != nullptr);
-    mark(5);
-    HIP_TRY(hipGetLastError());
+    s = enqueue_frame(st, fl, frame_params(cam, out), dbg ? &dd : nullptr, dbg != nullptr, nullptr,
+                      (rh.fe || dbg) ? &hooks : nullptr, &in_b);
+    if (s != RGS_OK) return s;
 
     if (dbg) {
+        const WsDev& w = fl.w;
+        const uint64_t n_entries = rh.n_entries;
         const void* ks = in_b ? w.keys_b : w.keys_a;
         const uint32_t* vs = in_b ? w.vals_b : w.vals_a;
         if (dbg->keys_sorted && n_entries) {
-            if (L.key_bytes == 8)
+            if (fl.L.key_bytes == 8)
                 HIP_TRY(hipMemcpyAsync(dbg->keys_sorted, ks, n_entries * 8, hipMemcpyDeviceToDevice, st));
             else
                 launch_widen_keys(st, static_cast<const uint32_t*>(ks), dbg->keys_sorted, n_entries);
@@ -728,7 +789,8 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
         if (dbg->vals_sorted && n_entries)
             HIP_TRY(hipMemcpyAsync(dbg->vals_sorted, vs, n_entries * 4, hipMemcpyDeviceToDevice, st));
         if (dbg->ranges)
-            HIP_TRY(hipMemcpyAsync(dbg->ranges, w.ranges, (uint64_t)p.n_tiles * 8, hipMemcpyDeviceToDevice, st));
+            HIP_TRY(hipMemcpyAsync(dbg->ranges, w.ranges, (uint64_t)fl.plan.n_tiles * 8,
+                                   hipMemcpyDeviceToDevice, st));
         if (dbg->T_final)
             HIP_TRY(hipMemcpyAsync(dbg->T_final, w.t_final, (uint64_t)W * H * 4, hipMemcpyDeviceToDevice, st));
         if (dbg->n_proc)

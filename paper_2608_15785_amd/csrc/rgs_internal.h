@@ -58,6 +58,17 @@ struct CamDev {
     float bg[3];
 };
 
+// What changes from one frame to the next at a fixed scene, resolution and
+// workspace: the camera and the output image.  The reset kernel copies it into
+// the workspace and every later kernel of the frame reads it from there, so a
+// captured frame is replayed for another request by changing the reset
+// kernel's argument block alone.
+struct FrameParams {
+    CamDev cam;
+    float* out;          // [3][H][W]
+};
+static_assert(sizeof(FrameParams) <= 256, "frame parameters fit one 256-byte slot");
+
 struct FrameDev {
     int32_t width, height;
     int32_t tiles_x, tiles_y, n_tiles;
@@ -102,6 +113,7 @@ static_assert(sizeof(WsHeader) == 256, "header is one 256-byte slot");
 
 // Byte offsets of a frame's workspace regions (all 256-byte aligned).
 struct WsLayout {
+    uint64_t params;
     uint64_t header, ranges, fe_state, zero_end;
     uint64_t records, counts, rects, depths;
     uint64_t keys_a, keys_b, vals_a, vals_b;
@@ -114,6 +126,7 @@ struct WsLayout {
 
 // Pointers a kernel needs into the workspace.
 struct WsDev {
+    const FrameParams* params;
     WsHeader* header;
     uint32_t* ranges;         // [n_tiles][2]
     uint64_t* fe_state;       // chained-scan state per front-end block
@@ -318,23 +331,44 @@ __host__ __device__ inline uint64_t st_visible(uint64_t s) { return (s >> 32) & 
 struct PlainSceneDev { const float* base; uint64_t n_pad; int64_t n; };
 struct FastSceneDev { const uint32_t* base; uint64_t n_pad; int64_t n; };
 
-void launch_reset(hipStream_t s, const WsDev& ws, uint64_t zero_bytes, const FrameDev& f,
-                  uint32_t path);
-void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam,
-                             const FrameDev& f, const WsDev& ws, const DebugDev* dbg);
+// Arguments of the reset kernel: the span it zeroes (header, tile ranges,
+// scan state, digit buckets), the header fields it sets, and the frame's
+// parameters with their place in the workspace.
+struct ResetArgs {
+    uint32_t* base;
+    uint64_t n_words;
+    uint32_t capacity, path, passes, pad;
+    FrameParams* dst;
+    FrameParams prm;
+};
+
+// A frame's outcome as the host sees it after the frame: written by the last
+// kernel of a frame into host-visible memory when the caller asks for it.
+struct FrameStatus {
+    uint64_t n_entries;
+    uint32_t n_visible, overflow, error, done;
+    uint64_t out;        // output address the frame used (checks replayed parameters)
+};
+
+ResetArgs reset_args(const WsDev& ws, uint64_t zero_bytes, const FrameDev& f, uint32_t path,
+                     const FrameParams& prm);
+void launch_reset(hipStream_t s, const ResetArgs& a);
+const void* reset_kernel();          // host handle of the reset kernel (graph node lookup)
+void launch_export_status(hipStream_t s, const WsDev& ws, FrameStatus* dst);
+void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const FrameDev& f,
+                             const WsDev& ws, const DebugDev* dbg);
 void launch_duplicate_plain(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws,
                             uint32_t fe_blocks);
-void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const CamDev& cam,
-                          const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
-                          const DebugDev* dbg);
+void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
+                          uint32_t fe_blocks, const DebugDev* dbg);
 void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                  uint32_t passes, uint32_t sort_blocks_max, bool* result_in_b);
 void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                    bool result_in_b);
-void launch_raster_plain(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
-                         bool result_in_b, float* out, bool count);
-void launch_raster_fast(hipStream_t s, const FrameDev& f, const CamDev& cam, const WsDev& ws,
-                        bool result_in_b, float* out, bool count);
+void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
+                         bool count);
+void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
+                        bool count);
 void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n);
 
 }  // namespace rgs

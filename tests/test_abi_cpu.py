@@ -135,3 +135,53 @@ def test_null_arguments_are_rejected():
     assert B.lib.rgs_render(None, None, None, 16, 16, 0, None, 0, None, None) == B.RGS_E_INVALID
     assert B.lib.rgs_workspace_check(None, None, None, 0) == B.RGS_E_INVALID
     assert B.lib.rgs_ctx_set_timing(None, 1) == B.RGS_E_INVALID
+
+
+def test_server_config_is_validated_before_device_use():
+    def create(**kw):
+        cfg = B.ServerConfig(device=0, n_streams=4, mem_budget=1 << 30, use_graphs=1, reserved=0,
+                             entries_per_gaussian=0.0)
+        for k, v in kw.items():
+            setattr(cfg, k, v)
+        h = C.c_void_p()
+        return B.lib.rgs_server_create(C.byref(cfg), C.byref(h))
+
+    assert create(n_streams=0) == B.RGS_E_INVALID
+    assert create(n_streams=17) == B.RGS_E_INVALID
+    assert create(mem_budget=0) == B.RGS_E_INVALID
+    assert create(entries_per_gaussian=-1.0) == B.RGS_E_INVALID
+    assert create(entries_per_gaussian=float("nan")) == B.RGS_E_INVALID
+    assert B.lib.rgs_server_create(None, None) == B.RGS_E_INVALID
+    import torch
+    if not torch.cuda.is_available():
+        assert create() == B.RGS_E_NODEVICE
+    assert B.lib.rgs_serve(None, None, 0, None, None) == B.RGS_E_INVALID
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the ABI structs have the C compiler's sizes and offsets."""
+    structs = {"rgs_camera": B.CameraC, "rgs_frame_stats": B.FrameStats, "rgs_debug_out": B.DebugOut,
+               "rgs_plan": B.Plan, "rgs_scene_desc": B.SceneDesc, "rgs_fast_host": B.FastHost,
+               "rgs_grads": B.Grads, "rgs_server_config": B.ServerConfig, "rgs_request": B.Request,
+               "rgs_response": B.Response, "rgs_server_stats": B.ServerStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "rgs.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for ln in out:
+        if ln:
+            s, f, v = ln.split()
+            got[(s, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -36,7 +36,7 @@ import numpy as np
 
 __all__ = [
     "Scene", "Camera", "make_scene", "look_at_camera", "orbit_camera",
-    "config_scene", "config_camera", "SCENE_CONFIGS", "CAMERA_CONFIGS",
+    "config_scene", "config_camera", "SCENE_CONFIGS", "CAMERA_CONFIGS", "SERVING_ORBITS", "serving_camera",
     "poisson_requests", "perturbed_means",
 ]
 
@@ -202,6 +202,21 @@ def poisson_requests(rate_hz: float, n_requests: int, seed: int = 3):
     scene = rng.integers(0, 2, size=n_requests)
     pose = rng.integers(0, 64, size=n_requests)
     return arrivals, res, scene, pose
+
+
+# Orbits of the two resident scenes of the serving workload: the 1M scene is
+# viewed from its single-frame distance, the 3M scene from its 64-pose orbit.
+SERVING_ORBITS = (
+    dict(scene="cfg1", orbit_radius=25.0, elevation=20.0, n_poses=64, fovx=60.0, half_extent=10.0),
+    dict(scene="cfg2", orbit_radius=40.0, elevation=20.0, n_poses=64, fovx=50.0, half_extent=20.0),
+)
+
+
+def serving_camera(scene_index: int, pose: int, width: int, height: int) -> Camera:
+    """Camera of a serving request: orbit pose ``pose`` of resident scene ``scene_index``."""
+    o = SERVING_ORBITS[scene_index]
+    return orbit_camera(pose, o["n_poses"], o["orbit_radius"], o["elevation"], o["fovx"], width, height,
+                        o["half_extent"])
 
 
 def perturbed_means(scene: Scene, sigma: float = 0.01, seed: int = 4) -> np.ndarray:
