@@ -372,19 +372,65 @@ rgs_status rgs_serve(rgs_server* server, const rgs_request* reqs, int64_t n, rgs
                      rgs_server_stats* stats);
 
 /* ---------------------------------------------------------------------------
- * Gradients of a loss with respect to the activated scene parameters
- * (means, scales, quats, opacity, sh) given dL/d(image).  Not part of the
- * paper, which renders only (Sec. V names training as future work).
- * Reserved: returns RGS_E_UNSUPPORTED in this build.
+ * Differentiation of the plain path.  The paper renders only and names
+ * training pipelines as the renderer's next use (Sec. V); these calls
+ * differentiate the plain image definition (Sec. II-A, III-D; Eqs.
+ * alpha_computation, power, opacity_clamped) with every discrete decision of
+ * the forward pass held fixed (culling, tile membership, depth order, the
+ * 1/255 skip test, the 1e-4 stop test, the 0.99 alpha clamp, the EWA
+ * Jacobian clamp and the clamp of each colour channel at 0).
  */
+
+/* Activated parameters in device memory, laid out as [n][...] rows (the
+ * layout of contiguous torch tensors). */
 typedef struct {
-    float* d_means;   /* device [n][3]     */
-    float* d_scales;  /* device [n][3]     */
-    float* d_quats;   /* device [n][4]     */
-    float* d_opacity; /* device [n]        */
-    float* d_sh;      /* device [n][16][3] */
+    int64_t n;
+    const float* means;   /* device [n][3]                       */
+    const float* scales;  /* device [n][3], > 0                  */
+    const float* quats;   /* device [n][4] (w, x, y, z), nonzero */
+    const float* opacity; /* device [n], in (0, 1]               */
+    const float* sh;      /* device [n][16][3]                   */
+} rgs_device_params;
+
+/* Overwrites the plain-format attributes of an uploaded scene with params
+ * (enqueued on the context's stream; values are not checked: NaN or
+ * out-of-range values propagate into the image).  The fast format, if the
+ * scene has one, is left as it was.  Errors: INVALID (NULL, n differs from the
+ * scene's, scene without the plain format). */
+rgs_status rgs_scene_update_plain(rgs_ctx* ctx, rgs_scene* scene, const rgs_device_params* params);
+
+typedef struct {
+    float* d_means;     /* device [n][3]                                           */
+    float* d_scales;    /* device [n][3]                                           */
+    float* d_quats;     /* device [n][4], w.r.t. the quaternion as given            */
+    float* d_opacity;   /* device [n]                                               */
+    float* d_sh;        /* device [n][16][3]                                        */
+    float* d_screen;    /* device [n][9] or NULL: dL/d(u, v, A, B, C, o, r, g, b),
+                           the image-space quantities of each Gaussian               */
+    void* scratch;      /* device, 256-byte aligned, rgs_backward_scratch_size bytes */
+    uint64_t scratch_bytes;
 } rgs_grads;
 
+/* Scratch bytes rgs_render_backward needs for a plain workspace of ws_bytes
+ * (one 48-byte partial per duplicated entry the workspace can hold).
+ * Host-only arithmetic. */
+rgs_status rgs_backward_scratch_size(int64_t n, int32_t width, int32_t height, uint64_t ws_bytes,
+                                     uint64_t* bytes);
+
+/* Gradients of a loss L with respect to the activated parameters of the
+ * scene, given dL_dimg = dL/d(image) (device [3][H][W]).  workspace must hold
+ * the last plain-path rgs_render of this scene with this camera and size, and
+ * nothing may have rendered into it since.  Per tile, the pixels' pairs are
+ * walked back to front from the last blended one; transmittance is recovered
+ * from the stored final T by division instead of being stored per pair.  Each
+ * tile writes one partial per sorted entry (no atomics); one thread per
+ * Gaussian then gathers its entries (one per covered tile) and applies the
+ * chain rule through projection and SH in double precision.  Enqueued on the
+ * context's stream after one synchronous read of the workspace header.
+ * Errors: INVALID (NULL, bad size, a workspace whose last frame was not a
+ * plain render of this scene, scratch too small); CAPACITY (that frame
+ * overflowed its workspace); DEVICE (that frame reported an internal
+ * failure). */
 rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
                                int32_t width, int32_t height, const float* dL_dimg,
                                void* workspace, uint64_t ws_bytes, rgs_grads* grads);

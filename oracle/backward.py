@@ -56,15 +56,30 @@ class TileAdjoint:
     abs_sum: np.ndarray    # [n_entries, 9] the same sums of absolute values (conditioning)
     flagged: np.ndarray    # [npix] bool: a decision lies within the margin of its threshold
     entry_flagged: np.ndarray  # [n_entries] bool: blended, or near a decision, at a flagged pixel
+    near: list             # (pixel, entry, kind) of every decision within its margin
+    terms: np.ndarray      # [n_entries, 9, npix] the per-pixel terms
 
 
-def blend_tile_adjoint(gauss_ids, X, Y, u, v, conic, opa, color, bg, dC, margin=1e-4) -> TileAdjoint:
+# Relative margins within which a decision counts as uncertain for a float32
+# implementation: alpha carries about 2e-6 relative error (exponent error of a
+# few 1e-7 times |p| <= 6), so the skip and clamp tests get 1e-5; T carries the
+# error of every (1 - alpha) factor, amplified up to 100x when alpha is near
+# 0.99, so the stop test gets 1e-3.
+DECISION_MARGINS = (1e-5, 1e-3, 1e-5)      # skip, stop, clamp
+
+
+def blend_tile_adjoint(gauss_ids, X, Y, u, v, conic, opa, color, bg, dC, margins=DECISION_MARGINS,
+                       force=None, flip=None) -> TileAdjoint:
     """dL/d(image-space quantities) of the Gaussians ``gauss_ids`` (sorted) of one tile.
 
     ``dC`` is dL/d(pixel colour), [3, npix], for pixels at X, Y.  A pixel is
-    flagged when one of its skip, stop or clamp decisions lies within relative
-    ``margin`` of its threshold.
+    flagged when one of its skip, stop or clamp decisions lies within the
+    relative ``margins`` of its threshold, or when ``force`` [npix] says so.
+    ``flip`` = (entry, kind) takes that entry's "skip", "stop" or "clamp"
+    decision the other way at every pixel (used one pixel at a time).
     """
+    m_skip, m_stop, m_clamp = margins
+    near_list = []
     X = np.asarray(X, np.float64)
     Y = np.asarray(Y, np.float64)
     ids = np.asarray(gauss_ids, np.int64)
@@ -90,25 +105,41 @@ def blend_tile_adjoint(gauss_ids, X, Y, u, v, conic, opa, color, bg, dC, margin=
         raw = opa[g] * e
         a = np.minimum(ALPHA_MAX, raw)
         active = ~done
-        passes = active & (raw >= ALPHA_MIN)
+        pass_test = raw >= ALPHA_MIN
+        clamp_test = raw > ALPHA_MAX
+        if flip is not None and flip[0] == j and flip[1] == "clamp":
+            clamp_test = ~clamp_test
+            a = np.where(clamp_test, ALPHA_MAX, raw)
+        if flip is not None and flip[0] == j and flip[1] == "skip":
+            pass_test = ~pass_test
+        passes = active & pass_test
         Tn = T * (1.0 - a)
-        stop = passes & (Tn < T_MIN)
+        stop_test = Tn < T_MIN
+        if flip is not None and flip[0] == j and flip[1] == "stop":
+            stop_test = ~stop_test
+        stop = passes & stop_test
         blend = passes & ~stop
-        nr = active & (np.abs(raw - ALPHA_MIN) <= margin * ALPHA_MIN)
-        nr |= passes & (np.abs(Tn - T_MIN) <= margin * T_MIN)
-        nr |= passes & (np.abs(raw - ALPHA_MAX) <= margin * ALPHA_MAX)
+        n_skip = active & (np.abs(raw - ALPHA_MIN) <= m_skip * ALPHA_MIN)
+        n_stop = passes & (np.abs(Tn - T_MIN) <= m_stop * T_MIN)
+        n_clamp = passes & (np.abs(raw - ALPHA_MAX) <= m_clamp * ALPHA_MAX)
+        for kind, mask in (("skip", n_skip), ("stop", n_stop), ("clamp", n_clamp)):
+            for px in np.nonzero(mask)[0]:
+                near_list.append((int(px), j, kind))
+        nr = n_skip | n_stop | n_clamp
         near[j] = nr
         flagged |= nr
         alpha[j] = np.where(blend, a, 0.0)
         ep[j] = e
         T_before[j] = T
         blended[j] = blend
-        clamped[j] = blend & (raw > ALPHA_MAX)
+        clamped[j] = blend & clamp_test
         dxs[j] = dx
         dys[j] = dy
         T = np.where(blend, Tn, T)
         done |= stop
     T_final = T
+    if force is not None:
+        flagged |= force
     col = color[ids]                                   # [k, 3]
     contrib = alpha[:, None, :] * T_before[:, None, :] * col[:, :, None]      # [k, 3, n]
     # S_j = sum of contributions behind j
@@ -138,7 +169,7 @@ def blend_tile_adjoint(gauss_ids, X, Y, u, v, conic, opa, color, bg, dC, margin=
     # pair blended there is affected
     entry_flagged = ((blended | near) & flagged[None, :]).any(axis=1)
     return TileAdjoint(grad=terms.sum(axis=2), abs_sum=np.abs(terms).sum(axis=2), flagged=flagged,
-                       entry_flagged=entry_flagged)
+                       entry_flagged=entry_flagged, near=near_list, terms=terms)
 
 
 def sh_basis_jacobian(dirs: np.ndarray) -> np.ndarray:
@@ -242,9 +273,11 @@ def project_adjoint(arrays: dict, cam, visible: np.ndarray, screen_grad: np.ndar
     tw = np.asarray(cam.t, np.float64)
     fx, fy = cam.fx, cam.fy
 
-    # forward quantities
-    t = mu @ Rw.T + tw[None, :]
-    tx, ty, d = t[:, 0], t[:, 1], t[:, 2]
+    # forward quantities (the forward pass's expression order)
+    mx, my, mz = mu[:, 0], mu[:, 1], mu[:, 2]
+    tx = Rw[0, 0] * mx + Rw[0, 1] * my + Rw[0, 2] * mz + tw[0]
+    ty = Rw[1, 0] * mx + Rw[1, 1] * my + Rw[1, 2] * mz + tw[1]
+    d = Rw[2, 0] * mx + Rw[2, 1] * my + Rw[2, 2] * mz + tw[2]
     nq = np.linalg.norm(q, axis=1)
     qn = q / nq[:, None]
     R = quat_to_rotation(qn)
@@ -333,47 +366,81 @@ class RenderAdjoint:
     image: np.ndarray          # forward image [3, H, W] (NaN outside the tiles)
     screen: np.ndarray         # [n, 9] dL/d(u, v, A, B, C, o, r, g, b)
     screen_abs: np.ndarray     # [n, 9] sums of absolute per-pixel terms
+    slack: np.ndarray          # [n, 9] how far decisions near their thresholds can move screen
     params: ProjectAdjoint
     touched: np.ndarray        # [n] bool: blended at some pixel of the tiles
-    flagged: np.ndarray        # [n] bool: blended at a flagged pixel, or flagged in the front end
+    flagged: np.ndarray        # [n] bool: slack above 1e-3 of screen_abs, or flagged in the front end
     pixel_flagged: np.ndarray  # [H, W] bool
+    n_proc: np.ndarray         # [H, W] the oracle's pairs visited per pixel
+    n_blend: np.ndarray        # [H, W] the oracle's pairs blended per pixel
+    unexplained: int           # pixels whose given decisions differ with no decision near its threshold
 
 
-def render_adjoint(arrays: dict, cam, dL_dimg: np.ndarray, tiles=None, margin=1e-4) -> RenderAdjoint:
+def render_adjoint(arrays: dict, cam, dL_dimg: np.ndarray, tiles=None, margins=DECISION_MARGINS,
+                   decisions=None) -> RenderAdjoint:
     """Gradients of L with dL/d(image) = ``dL_dimg`` [3, H, W] for the plain path.
 
     With ``tiles`` given, only those tiles' pixels are differentiated (the
-    caller's dL/d(image) must vanish elsewhere).
+    caller's dL/d(image) must vanish elsewhere).  ``decisions`` = (n_proc,
+    n_blend) [H, W] of another implementation's forward pass flags the pixels
+    where its pairs visited or blended differ from the oracle's.
+
+    Slack: at each pixel with a decision within its margin, the pixel is
+    differentiated again with that decision taken the other way, one decision
+    at a time, and the absolute changes of every Gaussian's terms are summed.
     """
     fr = render(arrays, cam, "plain", tiles=tiles)
+    force = None
+    if decisions is not None:
+        force = (np.asarray(decisions[0]) != fr.n_proc) | (np.asarray(decisions[1]) != fr.n_blend)
     plan = fr.plan
     n = arrays["means"].shape[0]
     screen = np.zeros((n, 9))
     screen_abs = np.zeros((n, 9))
+    slack = np.zeros((n, 9))
     touched = np.zeros(n, bool)
-    flagged = np.zeros(n, bool)
+    loose = np.zeros(n, bool)
     pix_flag = np.zeros((cam.height, cam.width), bool)
+    unexplained = 0
     proj = fr.proj
     bg = np.asarray(cam.bg, np.float64)
+    opa = arrays["opacity"]
     for t in fr.tiles:
         a, b = fr.ranges[t]
         if b <= a:
             continue
         X, Y = _tile_pixels(int(t), plan)
+        Xf, Yf = X.astype(np.float64), Y.astype(np.float64)
         ids = fr.sorted_gauss[a:b]
         dC = dL_dimg[:, Y, X].astype(np.float64)
-        ta = blend_tile_adjoint(ids, X.astype(np.float64), Y.astype(np.float64), proj.u, proj.v,
-                                proj.conic, arrays["opacity"], proj.color, bg, dC, margin)
+        fpx = None if force is None else force[Y, X]
+        ta = blend_tile_adjoint(ids, Xf, Yf, proj.u, proj.v, proj.conic, opa, proj.color, bg, dC, margins, fpx)
         np.add.at(screen, ids, ta.grad)
         np.add.at(screen_abs, ids, ta.abs_sum)
         hit = ta.abs_sum.sum(axis=1) > 0
         touched[ids[hit]] = True
         pix_flag[Y, X] = ta.flagged
-        flagged[ids[ta.entry_flagged]] = True
-    pa = project_adjoint(arrays, cam, proj.visible, screen, margin)
-    flagged |= pa.flagged & touched
-    return RenderAdjoint(image=fr.image, screen=screen, screen_abs=screen_abs, params=pa, touched=touched,
-                         flagged=flagged, pixel_flagged=pix_flag)
+        by_pixel = {}
+        for px, j, kind in ta.near:
+            by_pixel.setdefault(px, []).append((j, kind))
+        if fpx is not None:
+            for px in np.nonzero(fpx)[0]:
+                if int(px) not in by_pixel:
+                    unexplained += 1
+                    loose[ids[np.abs(ta.terms[:, :, px]).sum(axis=1) > 0]] = True
+        for px, flips in by_pixel.items():
+            base = ta.terms[:, :, px]
+            dev = np.zeros_like(base)
+            for j, kind in flips:
+                alt = blend_tile_adjoint(ids, Xf[px:px + 1], Yf[px:px + 1], proj.u, proj.v, proj.conic, opa,
+                                         proj.color, bg, dC[:, px:px + 1], margins, None, flip=(j, kind))
+                dev += np.abs(alt.terms[:, :, 0] - base)
+            np.add.at(slack, ids, dev)
+    pa = project_adjoint(arrays, cam, proj.visible, screen)
+    flagged = loose | (pa.flagged & touched) | np.any(slack > 1e-3 * screen_abs, axis=1)
+    return RenderAdjoint(image=fr.image, screen=screen, screen_abs=screen_abs, slack=slack, params=pa,
+                         touched=touched, flagged=flagged, pixel_flagged=pix_flag, n_proc=fr.n_proc,
+                         n_blend=fr.n_blend, unexplained=unexplained)
 
 
 def linear_loss(image: np.ndarray, w: np.ndarray) -> float:

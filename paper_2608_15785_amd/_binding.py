@@ -85,7 +85,13 @@ class DebugOut(C.Structure):
 
 class Grads(C.Structure):
     _fields_ = [("d_means", C.c_void_p), ("d_scales", C.c_void_p), ("d_quats", C.c_void_p),
-                ("d_opacity", C.c_void_p), ("d_sh", C.c_void_p)]
+                ("d_opacity", C.c_void_p), ("d_sh", C.c_void_p), ("d_screen", C.c_void_p),
+                ("scratch", C.c_void_p), ("scratch_bytes", C.c_uint64)]
+
+
+class DeviceParams(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity", C.c_void_p), ("sh", C.c_void_p)]
 
 
 class ServerConfig(C.Structure):
@@ -141,6 +147,9 @@ SIGNATURES = [
     ("rgs_server_destroy", None, [C.c_void_p]),
     ("rgs_serve", C.c_int32, [C.c_void_p, C.POINTER(Request), C.c_int64, C.POINTER(Response),
                               C.POINTER(ServerStats)]),
+    ("rgs_scene_update_plain", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(DeviceParams)]),
+    ("rgs_backward_scratch_size", C.c_int32, [C.c_int64, C.c_int32, C.c_int32, C.c_uint64,
+                                              C.POINTER(C.c_uint64)]),
     ("rgs_render_backward", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(CameraC), C.c_int32, C.c_int32,
                                         C.c_void_p, C.c_void_p, C.c_uint64, C.POINTER(Grads)]),
 ]
@@ -429,7 +438,9 @@ def render_debug(ctx: Context, scene: DeviceScene, cam, path: str, workspace, en
     for k in ("vals_unsorted", "vals_sorted"):
         out[k] = out[k][:m].view(np.uint32)
     out["ranges"] = out["ranges"].view(np.uint32)
-    out["n_proc"] = out["n_proc"].view(np.uint32)
+    word = out["n_proc"].view(np.uint32)
+    out["n_proc"] = word & np.uint32(0x7FFFFFFF)          # pairs visited
+    out["stopped"] = (word >> np.uint32(31)).astype(bool)  # blending stopped at the last of them
     out["n_blend"] = out["n_blend"].view(np.uint32)
     out["visible"] = out["visible"].astype(bool)
     out["image"] = image.cpu().numpy()
@@ -437,5 +448,50 @@ def render_debug(ctx: Context, scene: DeviceScene, cam, path: str, workspace, en
     return out
 
 
-def render_backward(*args, **kwargs):
-    raise RGSError(RGS_E_UNSUPPORTED, "rgs_render_backward is not available in this build")
+def scene_update_plain(ctx: Context, scene: DeviceScene, means, scales, quats, opacity, sh):
+    """Overwrite the plain attributes of ``scene`` from contiguous float32 device tensors."""
+    for t in (means, scales, quats, opacity, sh):
+        if not (t.is_contiguous() and t.dtype == _torch().float32 and t.is_cuda):
+            raise ValueError("parameters must be contiguous float32 device tensors")
+    p = DeviceParams(n=int(means.shape[0]), means=means.data_ptr(), scales=scales.data_ptr(),
+                     quats=quats.data_ptr(), opacity=opacity.data_ptr(), sh=sh.data_ptr())
+    _check(lib.rgs_scene_update_plain(ctx.handle, scene.handle, C.byref(p)), "rgs_scene_update_plain")
+
+
+def backward_scratch_size(n: int, width: int, height: int, ws_bytes: int) -> int:
+    b = C.c_uint64()
+    _check(lib.rgs_backward_scratch_size(n, width, height, ws_bytes, C.byref(b)), "rgs_backward_scratch_size")
+    return int(b.value)
+
+
+def render_backward(ctx: Context, scene: DeviceScene, cam, workspace, dL_dimg, scratch=None,
+                    screen: bool = False) -> dict:
+    """Gradients w.r.t. the activated plain parameters after a plain render into ``workspace``.
+
+    Returns float32 device tensors means [n,3], scales [n,3], quats [n,4], opacity [n], sh [n,16,3]
+    (and screen [n,9] = dL/d(u, v, A, B, C, o, r, g, b) when ``screen``)."""
+    torch = _torch()
+    n = scene.n
+    W, H = int(cam.width), int(cam.height)
+    dev = workspace.device
+    need = backward_scratch_size(n, W, H, workspace.numel())
+    if scratch is None or scratch.numel() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    g = dict(means=torch.empty((n, 3), dtype=torch.float32, device=dev),
+             scales=torch.empty((n, 3), dtype=torch.float32, device=dev),
+             quats=torch.empty((n, 4), dtype=torch.float32, device=dev),
+             opacity=torch.empty((n,), dtype=torch.float32, device=dev),
+             sh=torch.empty((n, 16, 3), dtype=torch.float32, device=dev))
+    if screen:
+        g["screen"] = torch.empty((n, 9), dtype=torch.float32, device=dev)
+    dimg = dL_dimg.contiguous()
+    if dimg.shape != (3, H, W) or dimg.dtype != torch.float32:
+        raise ValueError("dL_dimg must be float32 [3, H, W]")
+    gr = Grads(d_means=g["means"].data_ptr(), d_scales=g["scales"].data_ptr(), d_quats=g["quats"].data_ptr(),
+               d_opacity=g["opacity"].data_ptr(), d_sh=g["sh"].data_ptr(),
+               d_screen=g["screen"].data_ptr() if screen else None, scratch=scratch.data_ptr(),
+               scratch_bytes=scratch.numel())
+    cc = camera_struct(cam)
+    _check(lib.rgs_render_backward(ctx.handle, scene.handle, C.byref(cc), W, H, dimg.data_ptr(),
+                                   workspace.data_ptr(), workspace.numel(), C.byref(gr)), "rgs_render_backward")
+    return g

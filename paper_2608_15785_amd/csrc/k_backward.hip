@@ -1,0 +1,468 @@
+// Reverse mode of the plain render (differentiation of Sec. II-A / III-D's
+// image definition with its discrete decisions held fixed), and the device
+// update of plain attributes that a training step needs.
+//
+// raster_backward: one workgroup per 16x16 tile, one pixel per thread, the
+// tile's sorted list walked back to front in batches staged in LDS.  A pixel
+// starts after its last blended pair (the forward pass left its final T, the
+// number of pairs it visited and whether it stopped); T before each blended
+// pair is recovered as T_after / (1 - alpha), and the colour accumulated behind
+// the pair, S, is carried along, so that
+//   dC/dc_j = alpha_j T_j,   dC/dalpha_j = c_j T_j - (S_j + T_final bg) / (1 - alpha_j).
+// The nine image-space derivatives of a pair (u, v, A, B, C, o, r, g, b) are
+// summed over the wave with DPP adds, the four waves' sums meet in LDS, and
+// each sorted entry receives one 48-byte partial: no atomics.
+//
+// grad_gaussian: one thread per Gaussian gathers the partials of its entries
+// (one per tile of its rectangle; a binary search on (key, index) in the
+// tile's run finds each) and applies the chain rule through the EWA
+// projection and the SH colour in double precision.
+#include "rgs_internal.h"
+
+namespace rgs {
+
+__device__ inline uint32_t bwd_xcd_tile(uint32_t block, uint32_t n_tiles) {
+    const uint32_t per = (n_tiles + 7u) / 8u;
+    return (block % 8u) * per + block / 8u;
+}
+
+static uint32_t bwd_xcd_grid(uint32_t n_tiles) { return 8u * ((n_tiles + 7u) / 8u); }
+
+// ---------------------------------------------------------------------------
+// Plain attributes from [n][...] rows.
+
+__global__ __launch_bounds__(256) void k_update_plain(float* __restrict__ planes, uint64_t n_pad, int64_t n,
+                                                      const float* __restrict__ means,
+                                                      const float* __restrict__ scales,
+                                                      const float* __restrict__ quats,
+                                                      const float* __restrict__ opacity,
+                                                      const float* __restrict__ sh) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) planes[(P_MX + k) * n_pad + i] = means[3 * i + k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) planes[(P_SX + k) * n_pad + i] = scales[3 * i + k];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) planes[(P_QW + k) * n_pad + i] = quats[4 * i + k];
+    planes[P_OPA * n_pad + i] = opacity[i];
+#pragma unroll 8
+    for (int k = 0; k < 48; ++k) planes[(P_SH0 + k) * n_pad + i] = sh[48 * i + k];
+}
+
+void launch_update_plain(hipStream_t s, float* planes, uint64_t n_pad, int64_t n, const float* means,
+                         const float* scales, const float* quats, const float* opacity, const float* sh) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_update_plain, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, planes, n_pad, n,
+                       means, scales, quats, opacity, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Sum over the 64 lanes of a wave, valid in lane 63: two quad permutations,
+// two row shifts, then the row broadcasts 15 and 31 (each a DPP-modified add).
+
+template <int CTRL, int ROW_MASK>
+__device__ inline float dpp_moved(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+__device__ inline float wave_sum_last(float v) {
+    v += dpp_moved<0xb1, 0xf>(v);     // quad_perm [1,0,3,2]
+    v += dpp_moved<0x4e, 0xf>(v);     // quad_perm [2,3,0,1]
+    v += dpp_moved<0x114, 0xf>(v);    // row_shr:4
+    v += dpp_moved<0x118, 0xf>(v);    // row_shr:8
+    v += dpp_moved<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_moved<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+constexpr int BWD_THREADS = 256;
+
+__global__ __launch_bounds__(BWD_THREADS) void k_raster_backward(FrameDev f, WsDev ws,
+                                                                 const uint32_t* __restrict__ vals,
+                                                                 const float* __restrict__ dimg,
+                                                                 float4* __restrict__ partial) {
+    __shared__ float4 s_a[BWD_THREADS];          // u, v (tile-local), A, B
+    __shared__ float4 s_b[BWD_THREADS];          // C, o, r, g
+    __shared__ float s_c[BWD_THREADS];           // b
+    __shared__ float s_acc[4][9][BWD_THREADS];   // per-wave sums of the nine derivatives
+    __shared__ uint32_t s_last;
+    const uint32_t tile = bwd_xcd_tile(blockIdx.x, (uint32_t)f.n_tiles);
+    if (tile >= (uint32_t)f.n_tiles) return;
+    const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    const uint32_t lx = tid % TILE, ly = tid / TILE;
+    const uint32_t px = tx * TILE + lx, py = ty * TILE + ly;
+    const bool inside = px < (uint32_t)f.width && py < (uint32_t)f.height;
+    const uint32_t start = ws.ranges[2 * tile], end = ws.ranges[2 * tile + 1];
+    const float ox = (float)(tx * TILE), oy = (float)(ty * TILE);
+    const float x = (float)lx, y = (float)ly;
+    const uint64_t plane = (uint64_t)f.width * f.height;
+
+    float T = 1.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f;
+    uint32_t last = start;                       // pairs [start, last) may have been blended
+    if (inside) {
+        const uint64_t o = (uint64_t)py * f.width + px;
+        T = ws.t_final[o];
+        const uint32_t word = ws.n_proc[o];
+        last = start + (word & ~N_PROC_STOPPED) - ((word & N_PROC_STOPPED) ? 1u : 0u);
+        d0 = dimg[o];
+        d1 = dimg[plane + o];
+        d2 = dimg[2 * plane + o];
+    }
+    const float fb0 = T * ws.params->cam.bg[0];
+    const float fb1 = T * ws.params->cam.bg[1];
+    const float fb2 = T * ws.params->cam.bg[2];
+    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+
+    if (tid == 0) s_last = start;
+    __syncthreads();
+    if (last > start) atomicMax(&s_last, last);
+    __syncthreads();
+    const uint32_t block_last = s_last;
+
+    for (uint32_t b_end = block_last; b_end > start;) {
+        const uint32_t b0 = b_end - start > (uint32_t)BWD_THREADS ? b_end - BWD_THREADS : start;
+        const uint32_t cnt = b_end - b0;
+        __syncthreads();                         // the previous batch is fully read
+        if (tid < cnt) {
+            const uint32_t g = vals[b0 + tid];
+            const Record rec = ws.records[g < f.n_gaussians ? g : 0u];
+            s_a[tid] = make_float4((rec.u_hi - ox) + rec.u_lo, (rec.v_hi - oy) + rec.v_lo, rec.A, rec.B);
+            s_b[tid] = make_float4(rec.C, rec.opa, rec.r, rec.g);
+            s_c[tid] = rec.b;
+        }
+#pragma unroll
+        for (int w = 0; w < 4; ++w)
+#pragma unroll
+            for (int c = 0; c < 9; ++c) s_acc[w][c][tid] = 0.0f;
+        __syncthreads();
+        for (int j = (int)cnt - 1; j >= 0; --j) {
+            const bool act = b0 + (uint32_t)j < last;
+            if (__ballot(act) == 0) continue;
+            float g[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) g[c] = 0.0f;
+            bool blended = false;
+            if (act) {
+                const float4 a = s_a[j];
+                const float4 m = s_b[j];
+                const float dx = x - a.x, dy = y - a.y;
+                const float p = fmaf(-0.5f, fmaf(a.z * dx, dx, m.x * dy * dy), -a.w * dx * dy);
+                const float e = expf(p);
+                const float raw = m.y * e;
+                const float alpha = fminf(ALPHA_MAX, raw);
+                if (alpha >= ALPHA_MIN) {
+                    blended = true;
+                    const float inv = 1.0f / (1.0f - alpha);
+                    const float Tb = T * inv;
+                    const float w = alpha * Tb;
+                    const float cb = s_c[j];
+                    g[6] = w * d0;
+                    g[7] = w * d1;
+                    g[8] = w * d2;
+                    const float dA = d0 * (m.z * Tb - (S0 + fb0) * inv) + d1 * (m.w * Tb - (S1 + fb1) * inv) +
+                                     d2 * (cb * Tb - (S2 + fb2) * inv);
+                    S0 = fmaf(m.z, w, S0);
+                    S1 = fmaf(m.w, w, S1);
+                    S2 = fmaf(cb, w, S2);
+                    T = Tb;
+                    const float dRaw = raw <= ALPHA_MAX ? dA : 0.0f;   // a clamped alpha is constant
+                    g[5] = dRaw * e;
+                    const float dP = dRaw * raw;
+                    g[0] = dP * fmaf(a.z, dx, a.w * dy);               // dp/du = A dx + B dy
+                    g[1] = dP * fmaf(m.x, dy, a.w * dx);               // dp/dv = C dy + B dx
+                    g[2] = -0.5f * dP * dx * dx;
+                    g[3] = -dP * dx * dy;
+                    g[4] = -0.5f * dP * dy * dy;
+                }
+            }
+            if (__ballot(blended) != 0) {
+#pragma unroll
+                for (int c = 0; c < 9; ++c) {
+                    const float s = __builtin_amdgcn_readlane(__float_as_int(wave_sum_last(g[c])), 63);
+                    if (lane == 0) s_acc[wave][c][j] = __int_as_float(s);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < cnt) {
+            float r[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) r[c] = (s_acc[0][c][tid] + s_acc[1][c][tid]) + (s_acc[2][c][tid] + s_acc[3][c][tid]);
+            float4* dst = partial + 3ull * (b0 + tid);
+            dst[0] = make_float4(r[0], r[1], r[2], r[3]);
+            dst[1] = make_float4(r[4], r[5], r[6], r[7]);
+            dst[2] = make_float4(r[8], 0.0f, 0.0f, 0.0f);
+        }
+        b_end = b0;
+    }
+    // entries no pixel of the tile blended
+    for (uint32_t idx = block_last + tid; idx < end; idx += BWD_THREADS) {
+        float4* dst = partial + 3ull * idx;
+        dst[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        dst[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        dst[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
+                            const float* dimg, float4* partial) {
+    hipLaunchKernelGGL(k_raster_backward, dim3(bwd_xcd_grid(f.n_tiles)), dim3(BWD_THREADS), 0, s, f, ws,
+                       result_in_b ? ws.vals_b : ws.vals_a, dimg, partial);
+}
+
+// ---------------------------------------------------------------------------
+// Per-Gaussian gather and chain rule.
+
+// sum_k gY_k dY_k/d(x, y, z) for the degree-3 basis written as polynomials in
+// (x, y, z) (the forward basis, in double).
+__device__ inline void sh_basis_backward(double x, double y, double z, const double* gY, double& gx,
+                                         double& gy, double& gz) {
+    const double pi = 3.14159265358979323846;
+    const double c1 = sqrt(3.0 / (4.0 * pi));
+    const double c2a = 0.5 * sqrt(15.0 / pi), c2b = 0.25 * sqrt(5.0 / pi), c2c = 0.25 * sqrt(15.0 / pi);
+    const double c3a = 0.25 * sqrt(35.0 / (2.0 * pi)), c3b = 0.5 * sqrt(105.0 / pi);
+    const double c3c = 0.25 * sqrt(21.0 / (2.0 * pi)), c3d = 0.25 * sqrt(7.0 / pi);
+    const double c3e = 0.25 * sqrt(105.0 / pi);
+    const double xx = x * x, yy = y * y, zz = z * z;
+    gx = -c1 * gY[3] + c2a * y * gY[4] - 2.0 * c2b * x * gY[6] - c2a * z * gY[7] + 2.0 * c2c * x * gY[8] -
+         c3a * 6.0 * x * y * gY[9] + c3b * y * z * gY[10] + c3c * 2.0 * x * y * gY[11] -
+         c3d * 6.0 * x * z * gY[12] - c3c * (4.0 * zz - 3.0 * xx - yy) * gY[13] + c3e * 2.0 * x * z * gY[14] -
+         c3a * (3.0 * xx - 3.0 * yy) * gY[15];
+    gy = -c1 * gY[1] + c2a * x * gY[4] - c2a * z * gY[5] - 2.0 * c2b * y * gY[6] - 2.0 * c2c * y * gY[8] -
+         c3a * (3.0 * xx - 3.0 * yy) * gY[9] + c3b * x * z * gY[10] - c3c * (4.0 * zz - xx - 3.0 * yy) * gY[11] -
+         c3d * 6.0 * y * z * gY[12] + c3c * 2.0 * x * y * gY[13] - c3e * 2.0 * y * z * gY[14] +
+         c3a * 6.0 * x * y * gY[15];
+    gz = c1 * gY[2] - c2a * y * gY[5] + 4.0 * c2b * z * gY[6] - c2a * x * gY[7] + c3b * x * y * gY[10] -
+         c3c * 8.0 * y * z * gY[11] + c3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * gY[12] - c3c * 8.0 * x * z * gY[13] +
+         c3e * (xx - yy) * gY[14];
+}
+
+__device__ inline void sh_basis_double(double x, double y, double z, double* Y) {
+    const double pi = 3.14159265358979323846;
+    const double c1 = sqrt(3.0 / (4.0 * pi));
+    const double c2a = 0.5 * sqrt(15.0 / pi), c2b = 0.25 * sqrt(5.0 / pi), c2c = 0.25 * sqrt(15.0 / pi);
+    const double c3a = 0.25 * sqrt(35.0 / (2.0 * pi)), c3b = 0.5 * sqrt(105.0 / pi);
+    const double c3c = 0.25 * sqrt(21.0 / (2.0 * pi)), c3d = 0.25 * sqrt(7.0 / pi);
+    const double c3e = 0.25 * sqrt(105.0 / pi);
+    const double xx = x * x, yy = y * y, zz = z * z;
+    Y[0] = 0.5 / sqrt(pi);
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    Y[4] = c2a * x * y;
+    Y[5] = -c2a * y * z;
+    Y[6] = c2b * (2.0 * zz - xx - yy);
+    Y[7] = -c2a * x * z;
+    Y[8] = c2c * (xx - yy);
+    Y[9] = -c3a * y * (3.0 * xx - yy);
+    Y[10] = c3b * x * y * z;
+    Y[11] = -c3c * y * (4.0 * zz - xx - yy);
+    Y[12] = c3d * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+    Y[13] = -c3c * x * (4.0 * zz - xx - yy);
+    Y[14] = c3e * z * (xx - yy);
+    Y[15] = -c3a * x * (xx - 3.0 * yy);
+}
+
+__global__ __launch_bounds__(128) void k_grad_gaussian(PlainSceneDev sc, CamDev cam, FrameDev f, WsDev ws,
+                                                       const uint64_t* __restrict__ keys,
+                                                       const uint32_t* __restrict__ vals,
+                                                       const float4* __restrict__ partial, GradOut go) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.n) return;
+    const uint32_t count = ws.counts[i];
+    double gs[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) gs[c] = 0.0;
+    if (count) {
+        const uint64_t rc = ws.rects[i];
+        const uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff, y1 = rc >> 48;
+        const uint64_t klo = __float_as_uint(ws.depths[i]);
+        float acc[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
+        for (uint32_t ty = y0; ty <= y1; ++ty) {
+            for (uint32_t tx = x0; tx <= x1; ++tx) {
+                const uint32_t tile = ty * (uint32_t)f.tiles_x + tx;
+                const uint64_t key = ((uint64_t)tile << 32) | klo;
+                uint32_t lo = ws.ranges[2 * tile], hi = ws.ranges[2 * tile + 1];
+                while (lo < hi) {                    // first entry not below (key, i)
+                    const uint32_t mid = lo + (hi - lo) / 2;
+                    const uint64_t k = keys[mid];
+                    if (k < key || (k == key && vals[mid] < (uint32_t)i)) lo = mid + 1;
+                    else hi = mid;
+                }
+                if (lo >= ws.ranges[2 * tile + 1] || keys[lo] != key || vals[lo] != (uint32_t)i) {
+                    atomicOr(&ws.header->error, 8u);
+                    continue;
+                }
+                const float4 p0 = partial[3ull * lo], p1 = partial[3ull * lo + 1], p2 = partial[3ull * lo + 2];
+                acc[0] += p0.x; acc[1] += p0.y; acc[2] += p0.z; acc[3] += p0.w;
+                acc[4] += p1.x; acc[5] += p1.y; acc[6] += p1.z; acc[7] += p1.w;
+                acc[8] += p2.x;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 9; ++c) gs[c] = acc[c];
+    }
+    if (go.screen) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) go.screen[9 * i + c] = (float)gs[c];
+    }
+    float* dm = go.means + 3 * i;
+    float* ds = go.scales + 3 * i;
+    float* dq = go.quats + 4 * i;
+    float* dsh = go.sh + 48 * i;
+    if (!count) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dm[k] = 0.0f, ds[k] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dq[k] = 0.0f;
+        go.opacity[i] = 0.0f;
+        for (int k = 0; k < 48; ++k) dsh[k] = 0.0f;
+        return;
+    }
+    const float* P = sc.base;
+    const uint64_t np = sc.n_pad;
+    const double mx = P[P_MX * np + i], my = P[P_MY * np + i], mz = P[P_MZ * np + i];
+    const double s[3] = {P[P_SX * np + i], P[P_SY * np + i], P[P_SZ * np + i]};
+    const double qw0 = P[P_QW * np + i], qx0 = P[P_QX * np + i], qy0 = P[P_QY * np + i], qz0 = P[P_QZ * np + i];
+    const double* r = cam.r;
+    const double g_u = gs[0], g_v = gs[1], g_A = gs[2], g_B = gs[3], g_C = gs[4];
+
+    // forward quantities (the forward pass's expressions)
+    const double tx = r[0] * mx + r[1] * my + r[2] * mz + cam.t[0];
+    const double ty = r[3] * mx + r[4] * my + r[5] * mz + cam.t[1];
+    const double d = r[6] * mx + r[7] * my + r[8] * mz + cam.t[2];
+    const double nq = sqrt(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
+    const double w = qw0 / nq, x = qx0 / nq, y = qy0 / nq, z = qz0 / nq;
+    double R[3][3];
+    R[0][0] = 1.0 - 2.0 * (y * y + z * z);
+    R[0][1] = 2.0 * (x * y - w * z);
+    R[0][2] = 2.0 * (x * z + w * y);
+    R[1][0] = 2.0 * (x * y + w * z);
+    R[1][1] = 1.0 - 2.0 * (x * x + z * z);
+    R[1][2] = 2.0 * (y * z - w * x);
+    R[2][0] = 2.0 * (x * z - w * y);
+    R[2][1] = 2.0 * (y * z + w * x);
+    R[2][2] = 1.0 - 2.0 * (x * x + y * y);
+    double M[3][3], S[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) M[a][k] = R[a][k] * s[k];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) S[a][b] = M[a][0] * M[b][0] + M[a][1] * M[b][1] + M[a][2] * M[b][2];
+    const double limx = J_CLAMP * cam.tanx, limy = J_CLAMP * cam.tany;
+    const double rx = tx / d, ry = ty / d;
+    const bool inx = rx > -limx && rx < limx, iny = ry > -limy && ry < limy;
+    const double xc = fmin(limx, fmax(-limx, rx)) * d;
+    const double yc = fmin(limy, fmax(-limy, ry)) * d;
+    const double dd = d * d;
+    const double j00 = cam.fx / d, j02 = -(cam.fx * xc) / dd;
+    const double j11 = cam.fy / d, j12 = -(cam.fy * yc) / dd;
+    double T0[3], T1[3];
+    for (int k = 0; k < 3; ++k) {
+        T0[k] = j00 * r[k] + j02 * r[6 + k];
+        T1[k] = j11 * r[3 + k] + j12 * r[6 + k];
+    }
+    double ST0[3], ST1[3];
+    for (int a = 0; a < 3; ++a) {
+        ST0[a] = S[a][0] * T0[0] + S[a][1] * T0[1] + S[a][2] * T0[2];
+        ST1[a] = S[a][0] * T1[0] + S[a][1] * T1[1] + S[a][2] * T1[2];
+    }
+    const double c00 = T0[0] * ST0[0] + T0[1] * ST0[1] + T0[2] * ST0[2] + DILATION;
+    const double c01 = T0[0] * ST1[0] + T0[1] * ST1[1] + T0[2] * ST1[2];
+    const double c11 = T1[0] * ST1[0] + T1[1] * ST1[1] + T1[2] * ST1[2] + DILATION;
+    const double det = c00 * c11 - c01 * c01;
+    const double id = 1.0 / det, id2 = id * id;
+
+    // conic (A, B, C) = (c11, -c01, c00) / det  ->  Sigma' entries
+    const double g00 = g_A * (-c11 * c11 * id2) + g_B * (c01 * c11 * id2) + g_C * (id - c00 * c11 * id2);
+    const double g11 = g_A * (id - c11 * c00 * id2) + g_B * (c01 * c00 * id2) + g_C * (-c00 * c00 * id2);
+    const double g01 = g_A * (2.0 * c01 * c11 * id2) + g_B * (-id - 2.0 * c01 * c01 * id2) +
+                       g_C * (2.0 * c00 * c01 * id2);
+    // Sigma' = T Sigma T^T
+    double gT0[3], gT1[3];
+    for (int a = 0; a < 3; ++a) {
+        gT0[a] = 2.0 * g00 * ST0[a] + g01 * ST1[a];
+        gT1[a] = 2.0 * g11 * ST1[a] + g01 * ST0[a];
+    }
+    // symmetrised dL/dSigma: GS + GS^T with GS = g00 T0 T0^T + g01 T0 T1^T + g11 T1 T1^T
+    double GSs[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            GSs[a][b] = 2.0 * g00 * T0[a] * T0[b] + g01 * (T0[a] * T1[b] + T0[b] * T1[a]) +
+                        2.0 * g11 * T1[a] * T1[b];
+    // T = J R_w
+    const double g_j00 = gT0[0] * r[0] + gT0[1] * r[1] + gT0[2] * r[2];
+    const double g_j02 = gT0[0] * r[6] + gT0[1] * r[7] + gT0[2] * r[8];
+    const double g_j11 = gT1[0] * r[3] + gT1[1] * r[4] + gT1[2] * r[5];
+    const double g_j12 = gT1[0] * r[6] + gT1[1] * r[7] + gT1[2] * r[8];
+    // J and (u, v) -> camera-space t
+    const double g_tx = g_u * cam.fx / d + (inx ? g_j02 * (-cam.fx / dd) : 0.0);
+    const double g_ty = g_v * cam.fy / d + (iny ? g_j12 * (-cam.fy / dd) : 0.0);
+    const double sgx = rx > 0.0 ? 1.0 : -1.0, sgy = ry > 0.0 ? 1.0 : -1.0;
+    const double g_d = g_u * (-cam.fx * tx / dd) + g_v * (-cam.fy * ty / dd) + g_j00 * (-cam.fx / dd) +
+                       g_j11 * (-cam.fy / dd) +
+                       g_j02 * (inx ? 2.0 * cam.fx * tx / (dd * d) : cam.fx * sgx * limx / dd) +
+                       g_j12 * (iny ? 2.0 * cam.fy * ty / (dd * d) : cam.fy * sgy * limy / dd);
+    double gmu[3];
+    for (int k = 0; k < 3; ++k) gmu[k] = r[k] * g_tx + r[3 + k] * g_ty + r[6 + k] * g_d;
+    // Sigma = M M^T, M = R diag(s)
+    double gM[3][3], gR[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) gM[a][k] = GSs[a][0] * M[0][k] + GSs[a][1] * M[1][k] + GSs[a][2] * M[2][k];
+    for (int k = 0; k < 3; ++k) ds[k] = (float)(gM[0][k] * R[0][k] + gM[1][k] * R[1][k] + gM[2][k] * R[2][k]);
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < 3; ++k) gR[a][k] = gM[a][k] * s[k];
+    // rotation of the unit quaternion (w, x, y, z)
+    const double gw = 2.0 * (-z * gR[0][1] + y * gR[0][2] + z * gR[1][0] - x * gR[1][2] - y * gR[2][0] + x * gR[2][1]);
+    const double gx = 2.0 * (y * gR[0][1] + z * gR[0][2] + y * gR[1][0] - 2.0 * x * gR[1][1] - w * gR[1][2] +
+                             z * gR[2][0] + w * gR[2][1] - 2.0 * x * gR[2][2]);
+    const double gy = 2.0 * (-2.0 * y * gR[0][0] + x * gR[0][1] + w * gR[0][2] + x * gR[1][0] + z * gR[1][2] -
+                             w * gR[2][0] + z * gR[2][1] - 2.0 * y * gR[2][2]);
+    const double gz = 2.0 * (-2.0 * z * gR[0][0] - w * gR[0][1] + x * gR[0][2] + w * gR[1][0] - 2.0 * z * gR[1][1] +
+                             y * gR[1][2] + x * gR[2][0] + y * gR[2][1]);
+    const double qdot = w * gw + x * gx + y * gy + z * gz;
+    dq[0] = (float)((gw - w * qdot) / nq);
+    dq[1] = (float)((gx - x * qdot) / nq);
+    dq[2] = (float)((gy - y * qdot) / nq);
+    dq[3] = (float)((gz - z * qdot) / nq);
+    go.opacity[i] = (float)gs[5];
+
+    // colour: a channel clamped at 0 in the forward pass has no gradient
+    const Record rec = ws.records[i];
+    const double ga[3] = {rec.r > 0.0f ? gs[6] : 0.0, rec.g > 0.0f ? gs[7] : 0.0, rec.b > 0.0f ? gs[8] : 0.0};
+    double cp[3];
+    for (int k = 0; k < 3; ++k) cp[k] = -(r[k] * cam.t[0] + r[3 + k] * cam.t[1] + r[6 + k] * cam.t[2]);
+    const double vx = mx - cp[0], vy = my - cp[1], vz = mz - cp[2];
+    const double vlen = sqrt(vx * vx + vy * vy + vz * vz);
+    const double ux = vx / vlen, uy = vy / vlen, uz = vz / vlen;
+    double Y[16], gY[16];
+    sh_basis_double(ux, uy, uz, Y);
+    for (int k = 0; k < 16; ++k) {
+        double acc = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            dsh[3 * k + c] = (float)(Y[k] * ga[c]);
+            acc += (double)P[(P_SH0 + 3 * k + c) * np + i] * ga[c];
+        }
+        gY[k] = acc;
+    }
+    double gdx, gdy, gdz;
+    sh_basis_backward(ux, uy, uz, gY, gdx, gdy, gdz);
+    const double dot = ux * gdx + uy * gdy + uz * gdz;
+    gmu[0] += (gdx - ux * dot) / vlen;
+    gmu[1] += (gdy - uy * dot) / vlen;
+    gmu[2] += (gdz - uz * dot) / vlen;
+    for (int k = 0; k < 3; ++k) dm[k] = (float)gmu[k];
+}
+
+void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const FrameDev& f,
+                          const WsDev& ws, bool result_in_b, const float4* partial, const GradOut& go) {
+    if (sc.n <= 0) return;
+    hipLaunchKernelGGL(k_grad_gaussian, dim3((uint32_t)((sc.n + 127) / 128)), dim3(128), 0, s, sc, cam, f, ws,
+                       static_cast<const uint64_t*>(result_in_b ? ws.keys_b : ws.keys_a),
+                       result_in_b ? ws.vals_b : ws.vals_a, partial, go);
+}
+
+}  // namespace rgs

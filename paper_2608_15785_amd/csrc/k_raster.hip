@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
         out[plane + o] = fmaf(T, bg1, cg);
         out[2 * plane + o] = fmaf(T, bg2, cb);
         ws.t_final[o] = T;
-        ws.n_proc[o] = stop_at != 0xffffffffu ? stop_at - start + 1 : end - start;
+        ws.n_proc[o] = stop_at != 0xffffffffu ? (stop_at - start + 1) | N_PROC_STOPPED : end - start;
         if (COUNT) ws.n_blend[o] = n_blend;
     }
 }
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
         out[plane + o] = fmaf(T0, bg1, g0);
         out[2 * plane + o] = fmaf(T0, bg2, b0);
         ws.t_final[o] = T0;
-        ws.n_proc[o] = stop0 != 0xffffffffu ? stop0 - start + 1 : end - start;
+        ws.n_proc[o] = stop0 != 0xffffffffu ? (stop0 - start + 1) | N_PROC_STOPPED : end - start;
         if (COUNT) ws.n_blend[o] = nbl0;
     }
     if (in1) {
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
         out[plane + o] = fmaf(T1, bg1, g1);
         out[2 * plane + o] = fmaf(T1, bg2, b1);
         ws.t_final[o] = T1;
-        ws.n_proc[o] = stop1 != 0xffffffffu ? stop1 - start + 1 : end - start;
+        ws.n_proc[o] = stop1 != 0xffffffffu ? (stop1 - start + 1) | N_PROC_STOPPED : end - start;
         if (COUNT) ws.n_blend[o] = nbl1;
     }
 }

@@ -834,10 +834,65 @@ extern "C" rgs_status rgs_workspace_check(rgs_ctx* ctx, const void* workspace, r
     return s == RGS_OK ? ok() : s;
 }
 
+extern "C" rgs_status rgs_scene_update_plain(rgs_ctx* ctx, rgs_scene* sc, const rgs_device_params* p) {
+    if (!ctx || !sc || !p) return fail(RGS_E_INVALID, "rgs_scene_update_plain: NULL argument");
+    if (!(sc->formats & RGS_FMT_PLAIN)) return fail(RGS_E_INVALID, "scene has no plain format");
+    if (p->n != sc->n)
+        return fail(RGS_E_INVALID, "params hold %lld Gaussians, the scene %lld", (long long)p->n, (long long)sc->n);
+    if (!p->means || !p->scales || !p->quats || !p->opacity || !p->sh)
+        return fail(RGS_E_INVALID, "rgs_scene_update_plain: NULL parameter pointer");
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_update_plain(ctx->stream, sc->plain, sc->n_pad, sc->n, p->means, p->scales, p->quats, p->opacity,
+                        p->sh);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
+static constexpr uint64_t PARTIAL_BYTES = 48;   // three float4 per sorted entry
+
+extern "C" rgs_status rgs_backward_scratch_size(int64_t n, int32_t width, int32_t height, uint64_t ws_bytes,
+                                                uint64_t* bytes) {
+    if (!bytes) return fail(RGS_E_INVALID, "bytes is NULL");
+    if (n < 1 || n > RGS_MAX_ENTRIES) return fail(RGS_E_INVALID, "n = %lld out of range", (long long)n);
+    rgs_plan p;
+    rgs_status s = rgs_frame_plan(width, height, &p);
+    if (s != RGS_OK) return s;
+    const uint64_t cap = capacity_for(n, p, RGS_PATH_PLAIN, ws_bytes);
+    if (cap == 0) return fail(RGS_E_INVALID, "workspace of %llu bytes is too small", (unsigned long long)ws_bytes);
+    *bytes = align256(cap * PARTIAL_BYTES);
+    return ok();
+}
+
 extern "C" rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
                                           int32_t width, int32_t height, const float* dL_dimg,
                                           void* workspace, uint64_t ws_bytes, rgs_grads* grads) {
-    (void)ctx; (void)scene; (void)cam; (void)width; (void)height; (void)dL_dimg;
-    (void)workspace; (void)ws_bytes; (void)grads;
-    return fail(RGS_E_UNSUPPORTED, "rgs_render_backward is not available in this build");
+    if (!ctx || !scene || !grads || !dL_dimg) return fail(RGS_E_INVALID, "rgs_render_backward: NULL argument");
+    if (!grads->d_means || !grads->d_scales || !grads->d_quats || !grads->d_opacity || !grads->d_sh ||
+        !grads->scratch)
+        return fail(RGS_E_INVALID, "rgs_render_backward: NULL gradient or scratch pointer");
+    if (reinterpret_cast<uintptr_t>(grads->scratch) % 256 != 0)
+        return fail(RGS_E_INVALID, "scratch must be 256-byte aligned");
+    FrameLaunch fl;
+    rgs_status s = prepare_frame(scene, width, height, RGS_PATH_PLAIN, workspace, ws_bytes, &fl);
+    if (s != RGS_OK) return s;
+    s = check_camera(cam);
+    if (s != RGS_OK) return s;
+    if (grads->scratch_bytes < fl.L.capacity * PARTIAL_BYTES)
+        return fail(RGS_E_INVALID, "scratch of %llu bytes, need %llu", (unsigned long long)grads->scratch_bytes,
+                    (unsigned long long)(fl.L.capacity * PARTIAL_BYTES));
+    HIP_TRY(hipSetDevice(ctx->device));
+    WsHeader h;
+    s = read_header(ctx, workspace, &h);
+    if (s != RGS_OK) return s;
+    if (h.path != (uint32_t)RGS_PATH_PLAIN || h.capacity != fl.f.capacity || h.passes != fl.L.passes)
+        return fail(RGS_E_INVALID, "the workspace does not hold a plain render of this size");
+    s = header_status(h, nullptr, scene->n);
+    if (s != RGS_OK) return s;
+    const bool in_b = (fl.L.passes % 2) == 1;
+    float4* partial = static_cast<float4*>(grads->scratch);
+    launch_raster_backward(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial);
+    GradOut go{grads->d_means, grads->d_scales, grads->d_quats, grads->d_opacity, grads->d_sh, grads->d_screen};
+    launch_grad_gaussian(ctx->stream, fl.plain, cam_dev(cam), fl.f, fl.w, in_b, partial, go);
+    HIP_TRY(hipGetLastError());
+    return ok();
 }

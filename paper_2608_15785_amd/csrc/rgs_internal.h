@@ -371,4 +371,25 @@ void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool 
                         bool count);
 void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n);
 
+// The n_proc word of a pixel: pairs visited, with this bit set when blending
+// stopped at the last of them (that pair was not blended).
+constexpr uint32_t N_PROC_STOPPED = 0x80000000u;
+
+// Gradient outputs of the backward pass, [n][...] rows; screen may be NULL.
+struct GradOut {
+    float* means;
+    float* scales;
+    float* quats;
+    float* opacity;
+    float* sh;
+    float* screen;
+};
+
+void launch_update_plain(hipStream_t s, float* planes, uint64_t n_pad, int64_t n, const float* means,
+                         const float* scales, const float* quats, const float* opacity, const float* sh);
+void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
+                            const float* dimg, float4* partial);
+void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const FrameDev& f,
+                          const WsDev& ws, bool result_in_b, const float4* partial, const GradOut& go);
+
 }  // namespace rgs

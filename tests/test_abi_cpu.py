@@ -124,9 +124,16 @@ def test_no_device_is_reported_cleanly():
     assert e.value.status == B.RGS_E_NODEVICE
 
 
-def test_backward_is_reserved():
-    status = B.lib.rgs_render_backward(None, None, None, 16, 16, None, None, 0, None)
-    assert status == B.RGS_E_UNSUPPORTED
+def test_backward_host_checks_and_scratch_size():
+    assert B.lib.rgs_render_backward(None, None, None, 16, 16, None, None, 0, None) == B.RGS_E_INVALID
+    assert B.lib.rgs_scene_update_plain(None, None, None) == B.RGS_E_INVALID
+    for n, W, H in [(10000, 256, 256), (1000000, 1920, 1080), (5, 17, 33)]:
+        ws = rgs.workspace_size(n, W, H, "plain", 4 * n + 65536)
+        cap = rgs.workspace_capacity(n, W, H, "plain", ws)
+        got = rgs.backward_scratch_size(n, W, H, ws)
+        assert got == (cap * 48 + 255) // 256 * 256
+    with pytest.raises(rgs.RGSError):
+        rgs.backward_scratch_size(100, 64, 64, 1024)          # workspace too small for any entry
 
 
 def test_null_arguments_are_rejected():

@@ -1,0 +1,223 @@
+"""Backward pass of the plain render through the C ABI against the FP64 oracle
+adjoint (needs an MI355X).
+
+The oracle's adjoint is pinned to finite differences of its forward render on
+the CPU.  Here the GPU's gradients (image-space per Gaussian, then the
+activated parameters) are compared with it Gaussian by Gaussian.
+
+Tolerances.  Each image-space derivative of a Gaussian is a sum of per-pixel
+terms computed in float32 with transmittance recovered by division; its error
+is bounded by 1e-3 of the sum of the terms' magnitudes (the oracle reports that
+sum).  Where a skip, stop or clamp decision lies near its threshold, float32
+and float64 may take it differently; the oracle differentiates those pixels
+again with the decision flipped and adds the change of every Gaussian's terms
+as slack.  Every Gaussian the loss reaches is checked to that bound.  The
+parameter gradients are the double-precision chain rule applied to those
+sums; they are checked, for the Gaussians whose slack is below 1e-3 of their
+terms, to 2e-3 of the largest gradient of their kind plus 2e-3 of themselves.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from oracle import backward as OB
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_15785_amd as rgs
+    return rgs.Renderer(0)
+
+
+def gpu_backward(R, scene, cam, dimg):
+    import torch
+    import paper_2608_15785_amd as rgs
+    ds = R.upload(scene, ("plain",))
+    dbg = R.render_debug(ds, cam, "plain")        # the frame, with its per-pixel decisions
+    ws = R.workspace(scene.n, cam.width, cam.height, "plain")
+    g = rgs.render_backward(R.ctx, ds, cam, ws, torch.from_numpy(dimg).cuda(), screen=True)
+    torch.cuda.synchronize()
+    chk = rgs.workspace_check(R.ctx, ws, scene.n)
+    assert chk["device_error"] == 0, chk
+    out = {k: v.cpu().numpy().astype(np.float64) for k, v in g.items()}
+    out["image"] = dbg["image"]
+    out["decisions"] = (dbg["n_proc"].astype(np.int64), dbg["n_blend"].astype(np.int64))
+    ds.release()
+    return out
+
+
+def compare(g, adj, n_expect_min=1):
+    touched = adj.touched
+    strict = touched & ~adj.flagged
+    _log(f"[bwd] flagged pixels {int(adj.pixel_flagged.sum())}, touched {int(touched.sum())}, "
+         f"strict {int(strict.sum())}, with slack {int(adj.flagged.sum())}")
+    assert adj.unexplained == 0, "GPU decisions differ where no decision is near its threshold"
+    assert strict.sum() >= n_expect_min
+    assert adj.flagged.sum() <= 0.1 * max(1, touched.sum()), "too many near-threshold decisions"
+    # untouched Gaussians: exactly zero
+    for k in ("means", "scales", "quats", "opacity", "sh", "screen"):
+        assert np.all(g[k][~touched] == 0.0), k
+    # image-space sums, every touched Gaussian
+    err = np.abs(g["screen"][touched] - adj.screen[touched])
+    bound = 1e-3 * adj.screen_abs[touched] + adj.slack[touched] + 1e-7
+    worst = float(np.max(err / bound)) if err.size else 0.0
+    _log(f"[bwd] screen: worst err/bound {worst:.3g}")
+    assert np.all(err <= bound), np.unravel_index(np.argmax(err / bound), err.shape)
+    # parameter gradients
+    p = adj.params
+    ref = dict(means=p.means, scales=p.scales, quats=p.quats, opacity=p.opacity, sh=p.sh)
+    for k, o in ref.items():
+        gv = g[k][strict]
+        ov = o[strict]
+        scale = np.max(np.abs(ov)) if ov.size else 0.0
+        e = np.abs(gv - ov)
+        tol = 2e-3 * scale + 2e-3 * np.abs(ov)
+        rel = float(np.linalg.norm(gv - ov) / max(np.linalg.norm(ov), 1e-30))
+        _log(f"[bwd] {k}: max err {float(e.max()):.3g} (scale {scale:.3g}), rel L2 {rel:.3g}")
+        assert np.all(e <= tol + 1e-12), (k, float(e.max()))
+        assert rel < 1e-3, (k, rel)
+
+
+@pytest.mark.parametrize("W,H", [(128, 96), (120, 88)])
+def test_small_scene_all_tiles(R, W, H):
+    sc = wl.make_scene(3000, 1.0, -3.0, 0.5, 31)
+    cam = wl.config_camera("cfg0", width=W, height=H)
+    cam.bg = np.array([0.1, 0.2, 0.3], np.float32)
+    rng = np.random.Generator(np.random.PCG64(41))
+    dimg = rng.normal(0.0, 1.0, (3, H, W)).astype(np.float32)
+    _log(f"[bwd] small scene n={sc.n} {W}x{H}")
+    g = gpu_backward(R, sc, cam, dimg)
+    adj = OB.render_adjoint(oracle.prepare_plain(sc), cam, dimg.astype(np.float64), decisions=g["decisions"])
+    compare(g, adj, n_expect_min=1000)
+
+
+def test_deterministic(R):
+    sc = wl.make_scene(2000, 1.0, -3.0, 0.5, 32)
+    cam = wl.config_camera("cfg0", width=96, height=80)
+    dimg = np.random.Generator(np.random.PCG64(3)).normal(0, 1, (3, 80, 96)).astype(np.float32)
+    a = gpu_backward(R, sc, cam, dimg)
+    b = gpu_backward(R, sc, cam, dimg)
+    for k in ("means", "scales", "quats", "opacity", "sh", "screen"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.abs(a["screen"]).sum() > 0
+
+
+def test_cfg4_l1_loss_sampled_tiles(R):
+    """1M Gaussians at 1080p; L1 loss against a render of the same scene with
+    means perturbed by N(0, 0.01); dL/d(image) kept on 40 sampled tiles so that
+    the oracle differentiates exactly the same loss."""
+    import torch
+    sc = wl.config_scene("cfg1")
+    cam = wl.config_camera("cfg1")
+    H, W = cam.height, cam.width
+    target_scene = wl.Scene(means=wl.perturbed_means(sc), scales=sc.scales, quats=sc.quats,
+                            opacity=sc.opacity, sh=sc.sh)
+    dt = R.upload(target_scene, ("plain",))
+    target, _ = R.render(dt, cam, "plain")
+    torch.cuda.synchronize()
+    target = target.cpu().numpy()
+    dt.release()
+    ds = R.upload(sc, ("plain",))
+    img, _ = R.render(ds, cam, "plain")
+    torch.cuda.synchronize()
+    img = img.cpu().numpy()
+    ds.release()
+    plan = oracle.frame_plan(W, H)
+    rng = np.random.Generator(np.random.PCG64(4))
+    tiles = np.sort(rng.choice(plan.n_tiles, 40, replace=False))
+    mask = np.zeros((H, W), bool)
+    for t in tiles:
+        tx, ty = t % plan.tiles_x, t // plan.tiles_x
+        mask[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
+    dimg = (np.sign(img - target) / img.size * mask[None]).astype(np.float32)
+    _log(f"[bwd] cfg4: L1 loss {np.abs(img - target).mean():.6g}, {len(tiles)} tiles")
+    g = gpu_backward(R, sc, cam, dimg)
+    assert np.array_equal(g["image"], img)
+    adj = OB.render_adjoint(oracle.prepare_plain(sc), cam, dimg.astype(np.float64), tiles=tiles,
+                            decisions=g["decisions"])
+    compare(g, adj, n_expect_min=2000)
+
+
+def test_autograd_function_chains_activations(R):
+    import torch
+    from paper_2608_15785_amd.autograd import GaussianRasterizer
+    import paper_2608_15785_amd as rgs
+    sc = wl.make_scene(1500, 1.0, -3.0, 0.5, 33)
+    cam = wl.config_camera("cfg0", width=64, height=64)
+    dev = "cuda:0"
+    means = torch.tensor(sc.means, device=dev, requires_grad=True)
+    log_scales = torch.tensor(np.log(sc.scales.astype(np.float64)).astype(np.float32), device=dev,
+                              requires_grad=True)
+    quats = torch.tensor(sc.quats, device=dev, requires_grad=True)
+    o = np.clip(sc.opacity.astype(np.float64), 1e-6, 1 - 1e-6)
+    logits = torch.tensor(np.log(o / (1 - o)).astype(np.float32), device=dev, requires_grad=True)
+    sh = torch.tensor(sc.sh, device=dev, requires_grad=True)
+    rast = GaussianRasterizer(R)
+    target = torch.zeros((3, 64, 64), device=dev)
+    scales, opac = torch.exp(log_scales), torch.sigmoid(logits)
+    img = rast(means, scales, quats, opac, sh, cam)
+    loss = (img - target).abs().mean()
+    loss.backward()
+    # the same gradients straight from the C ABI, chained by hand
+    dimg = torch.sign(img.detach() - target) / img.numel()
+    ws = rast.workspace(cam)
+    g = rgs.render_backward(R.ctx, rast.scene, cam, ws, dimg)
+    torch.cuda.synchronize()
+    assert torch.equal(means.grad, g["means"])
+    assert torch.equal(quats.grad, g["quats"])
+    assert torch.equal(sh.grad, g["sh"])
+    assert torch.allclose(log_scales.grad, g["scales"] * scales.detach(), rtol=1e-6, atol=0)
+    assert torch.allclose(logits.grad, g["opacity"] * opac.detach() * (1 - opac.detach()), rtol=1e-6, atol=0)
+    # a small step against the gradient lowers the loss
+    with torch.no_grad():
+        for p in (means, log_scales, quats, logits, sh):
+            p -= 1e-3 * p.grad / (p.grad.abs().max() + 1e-30)
+        img2 = rast(means, torch.exp(log_scales), quats, torch.sigmoid(logits), sh, cam)
+        assert (img2 - target).abs().mean() < loss
+
+
+def test_backward_refuses_a_fast_frame_and_small_scratch(R):
+    import torch
+    import paper_2608_15785_amd as rgs
+    from paper_2608_15785_amd import _binding as B
+    sc = wl.make_scene(500, 1.0, -3.0, 0.5, 34)
+    cam = wl.config_camera("cfg0", width=48, height=32)
+    ds = R.upload(sc)
+    dimg = torch.zeros((3, 32, 48), device="cuda:0")
+    R.render(ds, cam, "fast")
+    ws_fast = R.workspace(sc.n, 48, 32, "fast")
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.render_backward(R.ctx, ds, cam, ws_fast, dimg)
+    assert e.value.status == B.RGS_E_INVALID
+    R.render(ds, cam, "plain")
+    ws = R.workspace(sc.n, 48, 32, "plain")
+    tiny = torch.empty(256, dtype=torch.uint8, device="cuda:0")
+    need = rgs.backward_scratch_size(sc.n, 48, 32, ws.numel())
+    assert need > 256
+    with pytest.raises(rgs.RGSError) as e:
+        g = rgs.render_backward(R.ctx, ds, cam, ws, dimg, scratch=None)
+        # a scratch buffer that is too small is replaced by the binding; call the ABI directly
+        gr = B.Grads(d_means=g["means"].data_ptr(), d_scales=g["scales"].data_ptr(),
+                     d_quats=g["quats"].data_ptr(), d_opacity=g["opacity"].data_ptr(), d_sh=g["sh"].data_ptr(),
+                     d_screen=None, scratch=tiny.data_ptr(), scratch_bytes=256)
+        cc = B.camera_struct(cam)
+        B._check(B.lib.rgs_render_backward(R.ctx.handle, ds.handle, B.C.byref(cc), 48, 32, dimg.data_ptr(),
+                                           ws.data_ptr(), ws.numel(), B.C.byref(gr)), "rgs_render_backward")
+    assert e.value.status == B.RGS_E_INVALID
+    torch.cuda.synchronize()
+    ds.release()
