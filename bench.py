@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # past the skip test that the method must composite; the counts are derived in
 # the design doc from the operations the method defines.
 OPS_PER_PAIR = {"fast": 14, "plain": 21}
+# ... and per blended pair of the backward pass (recomputed alpha, recovered T,
+# the nine derivatives and the running colour behind the pair).
+OPS_PER_PAIR_BACKWARD = 45
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
 
@@ -57,6 +60,8 @@ def parse():
     ap.add_argument("--cpu-tiles", type=int, default=2048, help="tiles the oracle blends")
     ap.add_argument("--paths", default="fast,plain")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--backward-steps", type=int, default=50)
     ap.add_argument("--serve-seconds", type=float, default=1.5, help="schedule length per arrival rate")
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -262,6 +267,82 @@ def serving_section(rgs, wl, torch, dev_scenes, args):
     return out
 
 
+def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup):
+    """One training step at 1M Gaussians, 1920x1080: write the parameters into the
+    device scene, render the plain path, L1 loss gradient against a render of the
+    scene with means perturbed by N(0, 0.01), backward to the activated parameters."""
+    from paper_2608_15785_amd import _binding as B
+    W, H = cam.width, cam.height
+    dev = "cuda"
+    tgt_scene = wl.Scene(means=wl.perturbed_means(sc), scales=sc.scales, quats=sc.quats, opacity=sc.opacity,
+                         sh=sc.sh)
+    dt = R.upload(tgt_scene, ("plain",))
+    target, _ = R.render(dt, cam, "plain")
+    target = target.clone()
+    dt.release()
+    ds = R.upload(sc, ("plain",))
+    params = [torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
+              for a in (sc.means, sc.scales, sc.quats, sc.opacity, sc.sh)]
+    _, st = R.render(ds, cam, "plain")
+    ws = R.workspace(sc.n, W, H, "plain", int(st["n_entries"] * 1.05) + 4096)
+    out = torch.empty((3, H, W), dtype=torch.float32, device=dev)
+    scratch = torch.empty(rgs.backward_scratch_size(sc.n, W, H, ws.numel()), dtype=torch.uint8, device=dev)
+    inv_n = 1.0 / out.numel()
+    ev = {k: torch.cuda.Event(enable_timing=True) for k in ("a", "b", "c", "d", "e")}
+
+    def step(timed=False):
+        if timed:
+            ev["a"].record()
+        rgs.scene_update_plain(R.ctx, ds, *params)
+        if timed:
+            ev["b"].record()
+        B.render(R.ctx, ds, cam, "plain", ws, out)
+        if timed:
+            ev["c"].record()
+        dimg = torch.sign(out - target) * inv_n
+        if timed:
+            ev["d"].record()
+        g = rgs.render_backward(R.ctx, ds, cam, ws, dimg, scratch=scratch)
+        if timed:
+            ev["e"].record()
+        return g
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    chk = rgs.workspace_check(R.ctx, ws, sc.n)
+    assert chk["overflow"] == 0 and chk["device_error"] == 0, chk
+    parts = {"update": 0.0, "forward": 0.0, "loss_grad": 0.0, "backward": 0.0}
+    for _ in range(steps):
+        step(timed=True)
+        torch.cuda.synchronize()
+        parts["update"] += ev["a"].elapsed_time(ev["b"])
+        parts["forward"] += ev["b"].elapsed_time(ev["c"])
+        parts["loss_grad"] += ev["c"].elapsed_time(ev["d"])
+        parts["backward"] += ev["d"].elapsed_time(ev["e"])
+    parts = {k: round(v / steps, 4) for k, v in parts.items()}
+    dbg = R.render_debug(ds, cam, "plain")
+    pairs = int(dbg["n_blend"].astype(np.int64).sum())
+    loss = float((out - target).abs().mean())
+    ds.release()
+    bwd_s = parts["backward"] * 1e-3
+    achieved = pairs * OPS_PER_PAIR_BACKWARD / bwd_s / 1e12
+    return {"workload": "cfg4: 1,000,000 Gaussians, 1920x1080, plain path, L1 loss against a render with "
+                        "means + N(0, 0.01)",
+            "steps": steps, "ms_per_step": round((t1 - t0) / steps * 1e3, 4),
+            "steps_per_s": round(steps / (t1 - t0), 2), "stage_ms": parts, "l1_loss": loss,
+            "pairs_blended": pairs,
+            "roofline_backward": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+                                  "unit": "T lane-op/s", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+                                  "ops_per_pair": OPS_PER_PAIR_BACKWARD,
+                                  "note": "whole backward call (both kernels and the header read)"}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -299,6 +380,12 @@ def main():
         r["roofline"] = rooflines(path, r, r["stage_ms"], sc1.n, plan1["n_tiles"])
         res1[path] = r
         log(f"[bench] cfg1 {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
+
+    diff = None
+    if not args.no_backward:
+        log("[bench] differentiation: forward + backward, 1M Gaussians at 1080p")
+        diff = differentiation_section(rgs, wl, torch, R, sc1, cam1, args.backward_steps, 5)
+        log(f"[bench] differentiation: {diff['ms_per_step']} ms/step, stages {diff['stage_ms']}")
 
     res2 = {}
     if not args.no_4k:
@@ -384,6 +471,8 @@ def main():
             out["speedup_fast_over_plain_4k"] = round(res2["fast"]["fps"] / res2["plain"]["fps"], 3)
     if serving is not None:
         out["serving"] = serving
+    if diff is not None:
+        out["differentiation"] = diff
     print(json.dumps(out), flush=True)
 
 

@@ -156,6 +156,11 @@ SIGNATURES = [
 
 
 def _load():
+    # torch bundles its own HIP and HSA runtimes.  Loaded first, they are the
+    # process's only ones: librgs.so's libamdhip64.so.7 then resolves to torch's
+    # copy.  Loaded after the library, they would come in as a second pair of
+    # runtimes beside /opt/rocm's, and the second cannot open the device.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(the renderer has no fallback path)")

@@ -2,21 +2,23 @@
 // image definition with its discrete decisions held fixed), and the device
 // update of plain attributes that a training step needs.
 //
-// raster_backward: one workgroup per 16x16 tile, one pixel per thread, the
-// tile's sorted list walked back to front in batches staged in LDS.  A pixel
+// raster_backward: one wave per 16x16 tile, four pixels per lane, the tile's
+// sorted list walked back to front in batches staged in LDS.  A pixel
 // starts after its last blended pair (the forward pass left its final T, the
 // number of pairs it visited and whether it stopped); T before each blended
 // pair is recovered as T_after / (1 - alpha), and the colour accumulated behind
 // the pair, S, is carried along, so that
 //   dC/dc_j = alpha_j T_j,   dC/dalpha_j = c_j T_j - (S_j + T_final bg) / (1 - alpha_j).
 // The nine image-space derivatives of a pair (u, v, A, B, C, o, r, g, b) are
-// summed over the wave with DPP adds, the four waves' sums meet in LDS, and
-// each sorted entry receives one 48-byte partial: no atomics.
+// summed over a lane's four pixels, then over the wave with DPP adds, and each
+// entry receives one 48-byte partial at its position in emission order: no
+// atomics.  Ordered allocation emitted a Gaussian's entries contiguously,
+// one per tile of its rectangle in row-major order, from the offset the
+// duplication kernel recorded, so that position is known from the tile.
 //
-// grad_gaussian: one thread per Gaussian gathers the partials of its entries
-// (one per tile of its rectangle; a binary search on (key, index) in the
-// tile's run finds each) and applies the chain rule through the EWA
-// projection and the SH colour in double precision.
+// grad_gaussian: one thread per Gaussian sums its contiguous partials and
+// applies the chain rule through the EWA projection and the SH colour in
+// double precision; the SH gradients leave through LDS in coalesced rows.
 #include "rgs_internal.h"
 
 namespace rgs {
@@ -76,130 +78,171 @@ __device__ inline float wave_sum_last(float v) {
     return v;
 }
 
-constexpr int BWD_THREADS = 256;
+// Position, in emission order, of Gaussian g's entry for tile (tx, ty).
+__device__ inline uint64_t emission_pos(const WsDev& ws, uint32_t g, uint32_t tx, uint32_t ty) {
+    const uint64_t rc = ws.rects[g];
+    const uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff;
+    return (uint64_t)ws.offsets[g] + (uint64_t)(ty - y0) * (x1 - x0 + 1) + (tx - x0);
+}
 
-__global__ __launch_bounds__(BWD_THREADS) void k_raster_backward(FrameDev f, WsDev ws,
-                                                                 const uint32_t* __restrict__ vals,
-                                                                 const float* __restrict__ dimg,
-                                                                 float4* __restrict__ partial) {
-    __shared__ float4 s_a[BWD_THREADS];          // u, v (tile-local), A, B
-    __shared__ float4 s_b[BWD_THREADS];          // C, o, r, g
-    __shared__ float s_c[BWD_THREADS];           // b
-    __shared__ float s_acc[4][9][BWD_THREADS];   // per-wave sums of the nine derivatives
-    __shared__ uint32_t s_last;
+// One wave per tile; lane l owns the pixels (l % 16, l / 16 + 4 k), k = 0..3,
+// and adds its four pixels' terms before the wave reduction of an entry.
+constexpr int BWD_LANES = 64;
+constexpr int BWD_PIX = 4;
+constexpr int BWD_BATCH = 64;
+
+// Row bands k (tile rows 4k .. 4k+3) that can hold a pixel with alpha >= 1/255
+// for a Gaussian at tile-local (u, v) with conic (A, B, C) and opacity o: the
+// ellipse A dx^2 + 2 B dx dy + C dy^2 <= 2 ln(255 o) spans |dy| <= sqrt(tau A / det).
+// The half-height is widened by 1e-3 of itself plus 0.05 pixel, far beyond the
+// float32 rounding of the exponent, so no blended pair falls outside.
+__device__ inline uint32_t band_mask(float v, float A, float B, float C, float o) {
+    const float tau = 2.0f * logf(255.0f * o);
+    if (!(tau > 0.0f)) return 0u;                      // alpha < 1/255 everywhere
+    const float det = A * C - B * B;
+    if (!(det > 0.0f)) return 0xfu;
+    const float hy = sqrtf(tau * A / det) * 1.001f + 0.05f;
+    if (!(hy < 1e30f)) return 0xfu;
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < BWD_PIX; ++k)
+        if (v - hy <= (float)(4 * k + 3) && v + hy >= (float)(4 * k)) m |= 1u << k;
+    return m;
+}
+
+__global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev ws,
+                                                               const uint32_t* __restrict__ vals,
+                                                               const float* __restrict__ dimg,
+                                                               float4* __restrict__ partial) {
+    __shared__ float4 s_a[BWD_BATCH];          // u, v (tile-local), A, B
+    __shared__ float4 s_b[BWD_BATCH];          // C, o, r, g
+    __shared__ float s_c[BWD_BATCH];           // b
+    __shared__ uint32_t s_band[BWD_BATCH];     // row bands the entry can reach
+    __shared__ float s_acc[9][BWD_BATCH];      // the entry sums of the batch
     const uint32_t tile = bwd_xcd_tile(blockIdx.x, (uint32_t)f.n_tiles);
     if (tile >= (uint32_t)f.n_tiles) return;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    const uint32_t lx = tid % TILE, ly = tid / TILE;
-    const uint32_t px = tx * TILE + lx, py = ty * TILE + ly;
-    const bool inside = px < (uint32_t)f.width && py < (uint32_t)f.height;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t lx = lane % TILE, ly0 = lane / TILE;
+    const uint32_t px = tx * TILE + lx;
     const uint32_t start = ws.ranges[2 * tile], end = ws.ranges[2 * tile + 1];
     const float ox = (float)(tx * TILE), oy = (float)(ty * TILE);
-    const float x = (float)lx, y = (float)ly;
+    const float x = (float)lx;
     const uint64_t plane = (uint64_t)f.width * f.height;
+    const float bg0 = ws.params->cam.bg[0], bg1 = ws.params->cam.bg[1], bg2 = ws.params->cam.bg[2];
 
-    float T = 1.0f, d0 = 0.0f, d1 = 0.0f, d2 = 0.0f;
-    uint32_t last = start;                       // pairs [start, last) may have been blended
-    if (inside) {
-        const uint64_t o = (uint64_t)py * f.width + px;
-        T = ws.t_final[o];
-        const uint32_t word = ws.n_proc[o];
-        last = start + (word & ~N_PROC_STOPPED) - ((word & N_PROC_STOPPED) ? 1u : 0u);
-        d0 = dimg[o];
-        d1 = dimg[plane + o];
-        d2 = dimg[2 * plane + o];
+    float T[BWD_PIX], fb[BWD_PIX][3], d[BWD_PIX][3], S[BWD_PIX][3];
+    uint32_t last[BWD_PIX];                    // pairs [start, last) may have been blended
+    uint32_t lane_last = start;
+#pragma unroll
+    for (int k = 0; k < BWD_PIX; ++k) {
+        const uint32_t py = ty * TILE + ly0 + 4 * k;
+        T[k] = 1.0f;
+        last[k] = start;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[k][c] = 0.0f, S[k][c] = 0.0f;
+        if (px < (uint32_t)f.width && py < (uint32_t)f.height) {
+            const uint64_t o = (uint64_t)py * f.width + px;
+            T[k] = ws.t_final[o];
+            const uint32_t word = ws.n_proc[o];
+            last[k] = start + (word & ~N_PROC_STOPPED) - ((word & N_PROC_STOPPED) ? 1u : 0u);
+            d[k][0] = dimg[o];
+            d[k][1] = dimg[plane + o];
+            d[k][2] = dimg[2 * plane + o];
+        }
+        fb[k][0] = T[k] * bg0;
+        fb[k][1] = T[k] * bg1;
+        fb[k][2] = T[k] * bg2;
+        lane_last = max(lane_last, last[k]);
     }
-    const float fb0 = T * ws.params->cam.bg[0];
-    const float fb1 = T * ws.params->cam.bg[1];
-    const float fb2 = T * ws.params->cam.bg[2];
-    float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f;
+    uint32_t wave_last = lane_last;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) wave_last = max(wave_last, (uint32_t)__shfl_xor((int)wave_last, off));
 
-    if (tid == 0) s_last = start;
-    __syncthreads();
-    if (last > start) atomicMax(&s_last, last);
-    __syncthreads();
-    const uint32_t block_last = s_last;
-
-    for (uint32_t b_end = block_last; b_end > start;) {
-        const uint32_t b0 = b_end - start > (uint32_t)BWD_THREADS ? b_end - BWD_THREADS : start;
+    for (uint32_t b_end = wave_last; b_end > start;) {
+        const uint32_t b0 = b_end - start > (uint32_t)BWD_BATCH ? b_end - BWD_BATCH : start;
         const uint32_t cnt = b_end - b0;
         __syncthreads();                         // the previous batch is fully read
-        if (tid < cnt) {
-            const uint32_t g = vals[b0 + tid];
-            const Record rec = ws.records[g < f.n_gaussians ? g : 0u];
-            s_a[tid] = make_float4((rec.u_hi - ox) + rec.u_lo, (rec.v_hi - oy) + rec.v_lo, rec.A, rec.B);
-            s_b[tid] = make_float4(rec.C, rec.opa, rec.r, rec.g);
-            s_c[tid] = rec.b;
+        uint64_t my_pos = 0;
+        if (lane < cnt) {
+            const uint32_t g0 = vals[b0 + lane];
+            const uint32_t g = g0 < f.n_gaussians ? g0 : 0u;
+            const Record rec = ws.records[g];
+            s_a[lane] = make_float4((rec.u_hi - ox) + rec.u_lo, (rec.v_hi - oy) + rec.v_lo, rec.A, rec.B);
+            s_b[lane] = make_float4(rec.C, rec.opa, rec.r, rec.g);
+            s_c[lane] = rec.b;
+            s_band[lane] = band_mask((rec.v_hi - oy) + rec.v_lo, rec.A, rec.B, rec.C, rec.opa);
+            my_pos = emission_pos(ws, g, tx, ty);
         }
 #pragma unroll
-        for (int w = 0; w < 4; ++w)
-#pragma unroll
-            for (int c = 0; c < 9; ++c) s_acc[w][c][tid] = 0.0f;
+        for (int c = 0; c < 9; ++c) s_acc[c][lane] = 0.0f;
         __syncthreads();
         for (int j = (int)cnt - 1; j >= 0; --j) {
-            const bool act = b0 + (uint32_t)j < last;
-            if (__ballot(act) == 0) continue;
+            const uint32_t idx = b0 + (uint32_t)j;
+            if (__ballot(idx < lane_last) == 0) continue;
+            const float4 a = s_a[j];
+            const float4 m = s_b[j];
+            const float cb = s_c[j];
+            const uint32_t band = s_band[j];
             float g[9];
 #pragma unroll
             for (int c = 0; c < 9; ++c) g[c] = 0.0f;
-            bool blended = false;
-            if (act) {
-                const float4 a = s_a[j];
-                const float4 m = s_b[j];
-                const float dx = x - a.x, dy = y - a.y;
-                const float p = fmaf(-0.5f, fmaf(a.z * dx, dx, m.x * dy * dy), -a.w * dx * dy);
-                const float e = expf(p);
-                const float raw = m.y * e;
-                const float alpha = fminf(ALPHA_MAX, raw);
-                if (alpha >= ALPHA_MIN) {
-                    blended = true;
-                    const float inv = 1.0f / (1.0f - alpha);
-                    const float Tb = T * inv;
-                    const float w = alpha * Tb;
-                    const float cb = s_c[j];
-                    g[6] = w * d0;
-                    g[7] = w * d1;
-                    g[8] = w * d2;
-                    const float dA = d0 * (m.z * Tb - (S0 + fb0) * inv) + d1 * (m.w * Tb - (S1 + fb1) * inv) +
-                                     d2 * (cb * Tb - (S2 + fb2) * inv);
-                    S0 = fmaf(m.z, w, S0);
-                    S1 = fmaf(m.w, w, S1);
-                    S2 = fmaf(cb, w, S2);
-                    T = Tb;
-                    const float dRaw = raw <= ALPHA_MAX ? dA : 0.0f;   // a clamped alpha is constant
-                    g[5] = dRaw * e;
-                    const float dP = dRaw * raw;
-                    g[0] = dP * fmaf(a.z, dx, a.w * dy);               // dp/du = A dx + B dy
-                    g[1] = dP * fmaf(m.x, dy, a.w * dx);               // dp/dv = C dy + B dx
-                    g[2] = -0.5f * dP * dx * dx;
-                    g[3] = -dP * dx * dy;
-                    g[4] = -0.5f * dP * dy * dy;
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < BWD_PIX; ++k) {
+                if (((band >> k) & 1u) && idx < last[k]) {
+                    const float dx = x - a.x, dy = (float)(ly0 + 4 * k) - a.y;
+                    const float p = fmaf(-0.5f, fmaf(a.z * dx, dx, m.x * dy * dy), -a.w * dx * dy);
+                    const float e = expf(p);
+                    const float raw = m.y * e;
+                    const float alpha = fminf(ALPHA_MAX, raw);
+                    if (alpha >= ALPHA_MIN) {
+                        any = true;
+                        const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+                        const float Tb = T[k] * inv;
+                        const float w = alpha * Tb;
+                        g[6] = fmaf(w, d[k][0], g[6]);
+                        g[7] = fmaf(w, d[k][1], g[7]);
+                        g[8] = fmaf(w, d[k][2], g[8]);
+                        const float dA = d[k][0] * (m.z * Tb - (S[k][0] + fb[k][0]) * inv) +
+                                         d[k][1] * (m.w * Tb - (S[k][1] + fb[k][1]) * inv) +
+                                         d[k][2] * (cb * Tb - (S[k][2] + fb[k][2]) * inv);
+                        S[k][0] = fmaf(m.z, w, S[k][0]);
+                        S[k][1] = fmaf(m.w, w, S[k][1]);
+                        S[k][2] = fmaf(cb, w, S[k][2]);
+                        T[k] = Tb;
+                        const float dRaw = raw <= ALPHA_MAX ? dA : 0.0f;   // a clamped alpha is constant
+                        g[5] = fmaf(dRaw, e, g[5]);
+                        const float dP = dRaw * raw;
+                        g[0] = fmaf(dP, fmaf(a.z, dx, a.w * dy), g[0]);    // dp/du = A dx + B dy
+                        g[1] = fmaf(dP, fmaf(m.x, dy, a.w * dx), g[1]);    // dp/dv = C dy + B dx
+                        g[2] = fmaf(-0.5f * dP, dx * dx, g[2]);
+                        g[3] = fmaf(-dP, dx * dy, g[3]);
+                        g[4] = fmaf(-0.5f * dP, dy * dy, g[4]);
+                    }
                 }
             }
-            if (__ballot(blended) != 0) {
+            if (__ballot(any) != 0) {
 #pragma unroll
                 for (int c = 0; c < 9; ++c) {
-                    const float s = __builtin_amdgcn_readlane(__float_as_int(wave_sum_last(g[c])), 63);
-                    if (lane == 0) s_acc[wave][c][j] = __int_as_float(s);
+                    const float sum = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_last(g[c])), 63));
+                    if (lane == 0) s_acc[c][j] = sum;
                 }
             }
         }
         __syncthreads();
-        if (tid < cnt) {
-            float r[9];
-#pragma unroll
-            for (int c = 0; c < 9; ++c) r[c] = (s_acc[0][c][tid] + s_acc[1][c][tid]) + (s_acc[2][c][tid] + s_acc[3][c][tid]);
-            float4* dst = partial + 3ull * (b0 + tid);
-            dst[0] = make_float4(r[0], r[1], r[2], r[3]);
-            dst[1] = make_float4(r[4], r[5], r[6], r[7]);
-            dst[2] = make_float4(r[8], 0.0f, 0.0f, 0.0f);
+        if (lane < cnt) {
+            float4* dst = partial + 3ull * my_pos;
+            dst[0] = make_float4(s_acc[0][lane], s_acc[1][lane], s_acc[2][lane], s_acc[3][lane]);
+            dst[1] = make_float4(s_acc[4][lane], s_acc[5][lane], s_acc[6][lane], s_acc[7][lane]);
+            dst[2] = make_float4(s_acc[8][lane], 0.0f, 0.0f, 0.0f);
         }
         b_end = b0;
     }
-    // entries no pixel of the tile blended
-    for (uint32_t idx = block_last + tid; idx < end; idx += BWD_THREADS) {
-        float4* dst = partial + 3ull * idx;
+    // entries no pixel of the tile reached
+    for (uint32_t idx = wave_last + lane; idx < end; idx += BWD_LANES) {
+        const uint32_t g = vals[idx];
+        float4* dst = partial + 3ull * emission_pos(ws, g < f.n_gaussians ? g : 0u, tx, ty);
         dst[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         dst[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         dst[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -208,7 +251,7 @@ __global__ __launch_bounds__(BWD_THREADS) void k_raster_backward(FrameDev f, WsD
 
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
                             const float* dimg, float4* partial) {
-    hipLaunchKernelGGL(k_raster_backward, dim3(bwd_xcd_grid(f.n_tiles)), dim3(BWD_THREADS), 0, s, f, ws,
+    hipLaunchKernelGGL(k_raster_backward, dim3(bwd_xcd_grid(f.n_tiles)), dim3(BWD_LANES), 0, s, f, ws,
                        result_in_b ? ws.vals_b : ws.vals_a, dimg, partial);
 }
 
@@ -265,43 +308,27 @@ __device__ inline void sh_basis_double(double x, double y, double z, double* Y) 
     Y[15] = -c3a * x * (xx - 3.0 * yy);
 }
 
-__global__ __launch_bounds__(128) void k_grad_gaussian(PlainSceneDev sc, CamDev cam, FrameDev f, WsDev ws,
-                                                       const uint64_t* __restrict__ keys,
-                                                       const uint32_t* __restrict__ vals,
-                                                       const float4* __restrict__ partial, GradOut go) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= sc.n) return;
+constexpr int GRAD_THREADS = 128;
+
+// Gradients of Gaussian i: sum of its partials, then the chain rule.  The SH
+// gradients go to dsh (48 floats, LDS), the rest straight to global memory.
+__device__ inline void grad_one(const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
+                                const float4* __restrict__ partial, const GradOut& go, int64_t i,
+                                float* dsh) {
     const uint32_t count = ws.counts[i];
     double gs[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) gs[c] = 0.0;
     if (count) {
-        const uint64_t rc = ws.rects[i];
-        const uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff, y1 = rc >> 48;
-        const uint64_t klo = __float_as_uint(ws.depths[i]);
+        const float4* pp = partial + 3ull * ws.offsets[i];
         float acc[9];
 #pragma unroll
         for (int c = 0; c < 9; ++c) acc[c] = 0.0f;
-        for (uint32_t ty = y0; ty <= y1; ++ty) {
-            for (uint32_t tx = x0; tx <= x1; ++tx) {
-                const uint32_t tile = ty * (uint32_t)f.tiles_x + tx;
-                const uint64_t key = ((uint64_t)tile << 32) | klo;
-                uint32_t lo = ws.ranges[2 * tile], hi = ws.ranges[2 * tile + 1];
-                while (lo < hi) {                    // first entry not below (key, i)
-                    const uint32_t mid = lo + (hi - lo) / 2;
-                    const uint64_t k = keys[mid];
-                    if (k < key || (k == key && vals[mid] < (uint32_t)i)) lo = mid + 1;
-                    else hi = mid;
-                }
-                if (lo >= ws.ranges[2 * tile + 1] || keys[lo] != key || vals[lo] != (uint32_t)i) {
-                    atomicOr(&ws.header->error, 8u);
-                    continue;
-                }
-                const float4 p0 = partial[3ull * lo], p1 = partial[3ull * lo + 1], p2 = partial[3ull * lo + 2];
-                acc[0] += p0.x; acc[1] += p0.y; acc[2] += p0.z; acc[3] += p0.w;
-                acc[4] += p1.x; acc[5] += p1.y; acc[6] += p1.z; acc[7] += p1.w;
-                acc[8] += p2.x;
-            }
+        for (uint32_t q = 0; q < count; ++q, pp += 3) {
+            const float4 p0 = pp[0], p1 = pp[1], p2 = pp[2];
+            acc[0] += p0.x; acc[1] += p0.y; acc[2] += p0.z; acc[3] += p0.w;
+            acc[4] += p1.x; acc[5] += p1.y; acc[6] += p1.z; acc[7] += p1.w;
+            acc[8] += p2.x;
         }
 #pragma unroll
         for (int c = 0; c < 9; ++c) gs[c] = acc[c];
@@ -313,7 +340,6 @@ __global__ __launch_bounds__(128) void k_grad_gaussian(PlainSceneDev sc, CamDev 
     float* dm = go.means + 3 * i;
     float* ds = go.scales + 3 * i;
     float* dq = go.quats + 4 * i;
-    float* dsh = go.sh + 48 * i;
     if (!count) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) dm[k] = 0.0f, ds[k] = 0.0f;
@@ -457,12 +483,24 @@ __global__ __launch_bounds__(128) void k_grad_gaussian(PlainSceneDev sc, CamDev 
     for (int k = 0; k < 3; ++k) dm[k] = (float)gmu[k];
 }
 
-void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const FrameDev& f,
-                          const WsDev& ws, bool result_in_b, const float4* partial, const GradOut& go) {
+__global__ __launch_bounds__(GRAD_THREADS) void k_grad_gaussian(PlainSceneDev sc, CamDev cam, WsDev ws,
+                                                                const float4* __restrict__ partial,
+                                                                GradOut go) {
+    __shared__ float s_sh[GRAD_THREADS * 48];
+    const int64_t first = (int64_t)blockIdx.x * GRAD_THREADS;
+    const int64_t i = first + threadIdx.x;
+    if (i < sc.n) grad_one(sc, cam, ws, partial, go, i, s_sh + 48 * threadIdx.x);
+    __syncthreads();
+    const int64_t rows = sc.n - first < GRAD_THREADS ? sc.n - first : GRAD_THREADS;
+    float* dst = go.sh + 48 * first;
+    for (int64_t k = threadIdx.x; k < rows * 48; k += GRAD_THREADS) dst[k] = s_sh[k];
+}
+
+void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
+                          const float4* partial, const GradOut& go) {
     if (sc.n <= 0) return;
-    hipLaunchKernelGGL(k_grad_gaussian, dim3((uint32_t)((sc.n + 127) / 128)), dim3(128), 0, s, sc, cam, f, ws,
-                       static_cast<const uint64_t*>(result_in_b ? ws.keys_b : ws.keys_a),
-                       result_in_b ? ws.vals_b : ws.vals_a, partial, go);
+    hipLaunchKernelGGL(k_grad_gaussian, dim3((uint32_t)((sc.n + GRAD_THREADS - 1) / GRAD_THREADS)),
+                       dim3(GRAD_THREADS), 0, s, sc, cam, ws, partial, go);
 }
 
 }  // namespace rgs

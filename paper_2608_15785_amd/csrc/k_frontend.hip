@@ -410,6 +410,14 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate_plain(int64_t n, Frame
     const uint32_t total = block_scan_and_chain(count, n_vis, vb, ws, s_incl, s_wtot, s_wvis, &s_base,
                                                 &s_base_v, &vis_total);
     const uint64_t base = s_base;
+    // where each Gaussian's entries start in emission order (the backward pass
+    // gathers a Gaussian's per-entry partials from there)
+#pragma unroll
+    for (int k = 0; k < FE_ITEMS; ++k) {
+        const uint32_t j = k * FE_THREADS + threadIdx.x;
+        const int64_t i = (int64_t)vb * FE_TILE + j;
+        if (i < n && count[k]) ws.offsets[i] = (uint32_t)(base + (j ? s_incl[j - 1] : 0u));
+    }
     uint64_t* keys = reinterpret_cast<uint64_t*>(ws.keys_a);
     emit_entries<uint64_t>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity, keys,
                            ws.vals_a, [&](uint32_t tile, uint32_t j) {

@@ -442,13 +442,15 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     off = align256(off + sizeof(FrameParams));
     L.records = off;
     off = align256(off + (uint64_t)n * sizeof(Record));
-    L.counts = L.rects = L.depths = 0;
+    L.counts = L.rects = L.depths = L.offsets = 0;
     if (plain) {
         L.counts = off;
         off = align256(off + (uint64_t)n * 4);
         L.rects = off;
         off = align256(off + (uint64_t)n * 8);
         L.depths = off;
+        off = align256(off + (uint64_t)n * 4);
+        L.offsets = off;
         off = align256(off + (uint64_t)n * 4);
     }
     L.keys_a = off;
@@ -530,6 +532,7 @@ static WsDev ws_pointers(void* base, const WsLayout& L) {
     w.counts = L.counts ? reinterpret_cast<uint32_t*>(b + L.counts) : nullptr;
     w.rects = L.rects ? reinterpret_cast<uint64_t*>(b + L.rects) : nullptr;
     w.depths = L.depths ? reinterpret_cast<float*>(b + L.depths) : nullptr;
+    w.offsets = L.offsets ? reinterpret_cast<uint32_t*>(b + L.offsets) : nullptr;
     w.keys_a = b + L.keys_a;
     w.keys_b = b + L.keys_b;
     w.vals_a = reinterpret_cast<uint32_t*>(b + L.vals_a);
@@ -892,7 +895,7 @@ extern "C" rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, 
     float4* partial = static_cast<float4*>(grads->scratch);
     launch_raster_backward(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial);
     GradOut go{grads->d_means, grads->d_scales, grads->d_quats, grads->d_opacity, grads->d_sh, grads->d_screen};
-    launch_grad_gaussian(ctx->stream, fl.plain, cam_dev(cam), fl.f, fl.w, in_b, partial, go);
+    launch_grad_gaussian(ctx->stream, fl.plain, cam_dev(cam), fl.w, partial, go);
     HIP_TRY(hipGetLastError());
     return ok();
 }

@@ -115,7 +115,7 @@ static_assert(sizeof(WsHeader) == 256, "header is one 256-byte slot");
 struct WsLayout {
     uint64_t params;
     uint64_t header, ranges, fe_state, zero_end;
-    uint64_t records, counts, rects, depths;
+    uint64_t records, counts, rects, depths, offsets;
     uint64_t keys_a, keys_b, vals_a, vals_b;
     uint64_t hist, tile_counts;
     uint64_t t_final, n_proc, n_blend;
@@ -134,6 +134,7 @@ struct WsDev {
     uint32_t* counts;         // plain: tiles touched per Gaussian
     uint64_t* rects;          // plain: packed x0 | x1 << 16 | y0 << 32 | y1 << 48
     float* depths;            // plain: float32 depth per Gaussian
+    uint32_t* offsets;        // plain: position of the Gaussian's first entry in emission order
     void* keys_a;
     void* keys_b;
     uint32_t* vals_a;
@@ -389,7 +390,7 @@ void launch_update_plain(hipStream_t s, float* planes, uint64_t n_pad, int64_t n
                          const float* scales, const float* quats, const float* opacity, const float* sh);
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
                             const float* dimg, float4* partial);
-void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const FrameDev& f,
-                          const WsDev& ws, bool result_in_b, const float4* partial, const GradOut& go);
+void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
+                          const float4* partial, const GradOut& go);
 
 }  // namespace rgs
