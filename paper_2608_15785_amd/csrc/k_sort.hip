@@ -7,7 +7,8 @@
 // resident on the 256 CUs at once, so the tiles cannot pass digit offsets
 // along a look-back chain without waiting on each other; each pass is instead
 // a reduce-then-scan:
-//   * `radix_upsweep` counts each 2048-entry tile's digits (keys only);
+//   * `radix_upsweep` counts each radix tile's digits (keys only; 4096-entry
+//     tiles for 32-bit keys, 2048 for 64-bit keys);
 //   * `radix_offsets` scans, for each digit in its own workgroup, the tiles'
 //     counts into the tile's offset inside that digit's bucket, and records
 //     the bucket's size;
@@ -59,6 +60,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_upsweep(const KeyT* __re
     s_h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t n = entry_count(ws.header);
+    constexpr int SORT_ITEMS = SortTile<KeyT>::ITEMS;
+    constexpr int SORT_TILE = SortTile<KeyT>::SIZE;
     const uint32_t tile_base = blockIdx.x * SORT_TILE;
     if (tile_base >= n) return;
     KeyT k[SORT_ITEMS];
@@ -79,11 +82,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_upsweep(const KeyT* __re
 // chunk of the row in registers; one block scan joins the chunks.
 constexpr int OFFSETS_CHUNK = 16;
 
-__global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t nb_max) {
+__global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t nb_max, uint32_t tile_size) {
     __shared__ uint32_t s_wtot[4];
     const uint32_t d = blockIdx.x;
     const uint32_t n = entry_count(ws.header);
-    const uint32_t nb = (n + SORT_TILE - 1) / SORT_TILE;
+    const uint32_t nb = (n + tile_size - 1) / tile_size;
     uint32_t* row = ws.tile_counts + (uint64_t)d * nb_max;
     uint32_t carry = 0;
     for (uint32_t c0 = 0; c0 < nb; c0 += 256 * OFFSETS_CHUNK) {
@@ -115,6 +118,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const KeyT* __re
                                                                 uint32_t* __restrict__ vout, WsDev ws,
                                                                 uint32_t shift, uint32_t nb_max) {
     constexpr int WAVES = SORT_THREADS / 64;
+    constexpr int SORT_ITEMS = SortTile<KeyT>::ITEMS;
+    constexpr int SORT_TILE = SortTile<KeyT>::SIZE;
     static_assert(SORT_THREADS == RADIX, "one thread per digit");
     __shared__ uint32_t s_whist[WAVES * RADIX];
     __shared__ uint32_t s_bstart[RADIX];
@@ -221,7 +226,8 @@ static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, uint32_t
         const KeyT* kin = from_a ? ka : kb;
         hipLaunchKernelGGL(k_radix_upsweep<KeyT>, dim3(nb_max), dim3(SORT_THREADS), 0, s, kin, ws, 8 * p,
                            nb_max);
-        hipLaunchKernelGGL(k_radix_offsets, dim3(RADIX), dim3(256), 0, s, ws, nb_max);
+        hipLaunchKernelGGL(k_radix_offsets, dim3(RADIX), dim3(256), 0, s, ws, nb_max,
+                           (uint32_t)SortTile<KeyT>::SIZE);
         hipLaunchKernelGGL(k_radix_scatter<KeyT>, dim3(nb_max), dim3(SORT_THREADS), 0, s, kin,
                            from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
                            ws, 8 * p, nb_max);

@@ -427,7 +427,8 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     L.key_bytes = plain ? 8 : 4;
     L.passes = plain ? (uint32_t)p.plain_passes : (uint32_t)p.fast_passes;
     L.fe_blocks = (uint32_t)((n + FE_TILE - 1) / FE_TILE);
-    L.sort_blocks_max = (uint32_t)((capacity + SORT_TILE - 1) / SORT_TILE);
+    const uint64_t st = sort_tile_size(L.key_bytes);
+    L.sort_blocks_max = (uint32_t)((capacity + st - 1) / st);
     uint64_t off = 0;
     L.header = off;
     off = align256(off + sizeof(WsHeader));

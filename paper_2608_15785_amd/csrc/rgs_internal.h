@@ -30,8 +30,16 @@ constexpr int FE_ITEMS = 2;          // Gaussians per thread (block-strided)
 constexpr int FE_TILE = FE_THREADS * FE_ITEMS;   // Gaussians per block
 constexpr int LB_PER_LANE = 8;       // look-back states each lane polls per round trip
 constexpr int SORT_THREADS = 256;    // 4 waves
-constexpr int SORT_ITEMS = 8;        // keys per thread per radix tile
-constexpr int SORT_TILE = SORT_THREADS * SORT_ITEMS;
+// Keys per thread of a radix tile: 16 for 32-bit keys (4096-key tiles), 8 for
+// 64-bit keys (2048-key tiles, which keep the scatter's LDS at 24 KB).
+template <typename KeyT>
+struct SortTile {
+    static constexpr int ITEMS = sizeof(KeyT) == 8 ? 8 : 16;
+    static constexpr int SIZE = SORT_THREADS * ITEMS;
+};
+inline uint32_t sort_tile_size(uint32_t key_bytes) {
+    return key_bytes == 8 ? (uint32_t)SortTile<uint64_t>::SIZE : (uint32_t)SortTile<uint32_t>::SIZE;
+}
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
