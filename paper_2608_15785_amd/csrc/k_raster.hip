@@ -26,7 +26,13 @@
 //   * the range-aware bit-level exponential (Eq. fma_exp): for P in
 //     [-ln 255, 0] the bits of exp(P) are built as the integer
 //     floor(P 2^23 log2 e + 2^23 (127 - sigma)), sigma = 0.045677, one FMA and
-//     one float-to-int conversion.  The skip test is made on P itself.
+//     one float-to-int conversion.  The skip test is made on P itself;
+//   * per-wave culled lists: while a batch is staged, each Gaussian is tested
+//     against the two 16x8 half-tiles of the two waves, first with the box of
+//     its alpha >= 1/255 ellipse, then with the ellipse itself (the least value
+//     of its quadratic form over the half-tile), both widened far beyond the
+//     float32 error of P; each wave blends only its survivors, in depth order.
+//     A culled pair would have failed the skip test, so no result changes.
 //
 // Tiles are mapped to workgroups so that each of the 8 XCDs (workgroups are
 // dispatched to them round-robin) works through one contiguous band of tile
@@ -145,6 +151,30 @@ constexpr int ALPHA_MAX_BITS = 0x3f7d70a4;   // bit pattern of 0.99f
 // must never hide a pair that the exact test would keep.
 constexpr float BOX_MARGIN_REL = 1.0e-3f;
 constexpr float BOX_MARGIN_ABS = 0.05f;
+// The same safety margin on the quadratic form q = A dx^2 + 2 B dx dy + C dy^2
+// (P = ln o - q / 2): a half-tile is kept when min q <= tau (1 + 1e-3) + 0.02.
+constexpr float Q_MARGIN_REL = 1.0e-3f;
+constexpr float Q_MARGIN_ABS = 0.02f;
+
+// Smallest q over the rectangle [-7.5, 7.5] x [y0, y1] (tile-centre
+// coordinates) for a Gaussian at (u, v) with a positive-definite conic: 0 when
+// the mean is inside, else the least of the four edge minima (on an edge q is
+// a parabola in the free coordinate, minimised at a clamped closed form).
+__device__ inline float conic_rect_min(float u, float v, float A, float B, float C, float iA, float iC,
+                                       float y0, float y1) {
+    if (u >= -7.5f && u <= 7.5f && v >= y0 && v <= y1) return 0.0f;
+    float best = 3.0e38f;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float dx = (e ? 7.5f : -7.5f) - u;                 // vertical edge x = -7.5 or 7.5
+        const float dy = fminf(y1, fmaxf(y0, fmaf(-B * dx, iC, v))) - v;
+        best = fminf(best, fmaf(A * dx, dx, fmaf(2.0f * B * dx, dy, C * dy * dy)));
+        const float ey = (e ? y1 : y0) - v;                       // horizontal edge y = y0 or y1
+        const float ex = fminf(7.5f, fmaxf(-7.5f, fmaf(-B * ey, iA, u))) - u;
+        best = fminf(best, fmaf(A * ex, ex, fmaf(2.0f * B * ex, ey, C * ey * ey)));
+    }
+    return best;
+}
 
 template <bool COUNT>
 __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev ws,
@@ -201,6 +231,12 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
             const bool x_out = u - hx > 7.5f || u + hx < -7.5f;
             hit0 = !(x_out || v - hy > -0.5f || v + hy < -7.5f);
             hit1 = !(x_out || v - hy > 7.5f || v + hy < 0.5f);
+            // then the ellipse itself: the half-tile must hold a point with
+            // q <= tau = 2 (ln 255 + ln o), up to the margin
+            const float qlim = fmaf(2.0f * (LN255F + rec.opa), 1.0f + Q_MARGIN_REL, Q_MARGIN_ABS);
+            const float iA = 1.0f / A, iC = 1.0f / C;
+            if (hit0) hit0 = !(conic_rect_min(u, v, A, B, C, iA, iC, -7.5f, -0.5f) > qlim);
+            if (hit1) hit1 = !(conic_rect_min(u, v, A, B, C, iA, iC, 0.5f, 7.5f) > qlim);
         }
         const uint64_t m0 = __ballot(hit0), m1 = __ballot(hit1);
         const uint64_t lt = lanemask_lt();
