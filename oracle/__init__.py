@@ -32,7 +32,7 @@ from .project import Projection, project, sh_basis, LN255
 from .tiles import duplicate, sort_entries, tile_ranges, plain_keys, fast_keys
 from .fastexp import fast_exp, fast_exp_rel_error, SIGMA
 from .blend import blend_tile, BlendResult
-from .render import OracleFrame, render, prepare_plain, prepare_fast
+from .render import OracleFrame, render, prepare_plain, prepare_fast, prepare_fast_ablated
 
 __all__ = [
     "TILE", "FramePlan", "frame_plan", "key_bits",
@@ -41,5 +41,5 @@ __all__ = [
     "duplicate", "sort_entries", "tile_ranges", "plain_keys", "fast_keys",
     "fast_exp", "fast_exp_rel_error", "SIGMA",
     "blend_tile", "BlendResult",
-    "OracleFrame", "render", "prepare_plain", "prepare_fast",
+    "OracleFrame", "render", "prepare_plain", "prepare_fast", "prepare_fast_ablated",
 ]

@@ -204,11 +204,13 @@ def sh_color(means, sh, cam) -> np.ndarray:
     return np.maximum(rgb, 0.0)
 
 
-def project(arrays: dict, cam, plan: FramePlan, fast: bool) -> Projection:
+def project(arrays: dict, cam, plan: FramePlan, fast: bool, alpha_extent: bool = True) -> Projection:
     """The whole per-Gaussian front end for the plain (fast=False) or fast path.
 
     ``arrays`` holds float64 means [n,3], quats [n,4], scales [n,3], sh
     [n,16,3] and either ``opacity`` [n] (plain) or ``log_opacity`` [n] (fast).
+    ``alpha_extent=False`` drops the fast path's opacity cull and alpha-ellipse
+    extent and keeps the 3-sigma square (the ablation of that step).
     """
     means, quats, scales = arrays["means"], arrays["quats"], arrays["scales"]
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
@@ -219,7 +221,7 @@ def project(arrays: dict, cam, plan: FramePlan, fast: bool) -> Projection:
         lam = mid + np.sqrt(np.maximum(0.0, mid * mid - det))
         r = np.ceil(3.0 * np.sqrt(lam))
         visible = (d > cam.z_near) & (d <= cam.z_far) & (det > 0.0)
-        if fast:
+        if fast and alpha_extent:
             lno = arrays["log_opacity"]
             visible &= lno >= -LN255
             tau = 2.0 * (LN255 + lno)

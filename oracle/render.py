@@ -34,6 +34,22 @@ def prepare_fast(fs: FastScene) -> dict:
     return dequantize_scene(fs)
 
 
+def prepare_fast_ablated(scene, fs: FastScene, int8_sh: bool = True, fp16_geometry: bool = True) -> dict:
+    """float64 view of the fast path's inputs with a compact-storage step
+    ablated (Sec. IV-A, "Compact Attribute Storage"): FP32 SH instead of the
+    INT8 ones, and/or FP32 rotation and scale with ln o taken in float64 and
+    rounded to float32, instead of their FP16 forms."""
+    arr = dequantize_scene(fs)
+    if not int8_sh:
+        arr["sh"] = np.asarray(scene.sh, np.float64)
+    if not fp16_geometry:
+        arr["quats"] = np.asarray(scene.quats, np.float64)
+        arr["scales"] = np.asarray(scene.scales, np.float64)
+        lno = np.log(np.asarray(scene.opacity, np.float64)).astype(np.float32)
+        arr["log_opacity"] = lno.astype(np.float64)
+    return arr
+
+
 @dataclass
 class OracleFrame:
     plan: FramePlan
@@ -60,9 +76,11 @@ class OracleFrame:
     def image(self) -> np.ndarray:
         return self.images[self.modes[0]]
 
+    key64: bool = False          # the fast path keyed like the plain one (ablation)
+
     @property
     def key_shift(self) -> int:
-        return 32 if self.path == "plain" else self.plan.b_d
+        return 32 if (self.path == "plain" or self.key64) else self.plan.b_d
 
 
 _SHARED: dict = {}
@@ -90,27 +108,34 @@ def _blend_tiles(tiles):
 
 
 def render(arrays: dict, cam, path: str = "plain", modes=None, tiles=None, margins=None,
-           workers: int = 1, blend: bool = True) -> OracleFrame:
-    """Render one frame.  ``tiles`` restricts blending to a subset of tiles."""
+           workers: int = 1, blend: bool = True, alpha_extent: bool = True,
+           key64: bool = False) -> OracleFrame:
+    """Render one frame.  ``tiles`` restricts blending to a subset of tiles.
+
+    For the fast path, ``alpha_extent=False`` keeps the 3-sigma tile extent
+    and ``key64=True`` sorts on the plain path's (tile, float32 depth) key:
+    the ablations of the opacity-culling step and of the 32-bit key.
+    """
     if path not in ("plain", "fast"):
         raise ValueError(path)
     fast = path == "fast"
     if modes is None:
         modes = ("fast-def", "fast-exact") if fast else ("plain",)
     plan = frame_plan(cam.width, cam.height)
-    proj = project(arrays, cam, plan, fast)
+    proj = project(arrays, cam, plan, fast, alpha_extent)
     eg, et = duplicate(proj.rect, proj.visible, plan)
     d = proj.d[eg]
-    keys = fast_keys(et, d, cam.z_near, cam.z_far, plan) if fast else plain_keys(et, d)
+    key32 = fast and not key64
+    keys = fast_keys(et, d, cam.z_near, cam.z_far, plan) if key32 else plain_keys(et, d)
     sk, sg = sort_entries(keys, eg)
-    shift = plan.b_d if fast else 32
+    shift = plan.b_d if key32 else 32
     ranges = tile_ranges(sk, shift, plan.n_tiles)
     if tiles is None:
         tiles = np.arange(plan.n_tiles)
     tiles = np.asarray(tiles, np.int64)
     frame = OracleFrame(plan=plan, path=path, modes=tuple(modes), proj=proj, entry_gauss=eg,
                         entry_tile=et, keys=keys, sorted_keys=sk, sorted_gauss=sg, ranges=ranges,
-                        tiles=tiles)
+                        tiles=tiles, key64=fast and key64)
     if not blend:
         return frame
 

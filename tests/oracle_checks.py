@@ -236,18 +236,22 @@ def fp16_round_exact(x: float) -> float:
     return sign * float(val)
 
 
-def brute_force_image(arrays, cam, path, mode):
+def brute_force_image(arrays, cam, path, mode, key64=False, alpha_extent=True):
     """Per-pixel reference: every visible Gaussian whose tile rectangle holds the
     pixel's tile, ordered by (depth key, index), blended with a scalar loop.
 
     No duplication, sort or tile ranges; the projection is the oracle's.
-    Also asserts the blending invariants along the way.
+    Also asserts the blending invariants along the way.  ``key64`` orders the
+    fast path by float32 depth; ``alpha_extent`` selects its tile extent.
     """
     fast = path == "fast"
     plan = oracle.frame_plan(cam.width, cam.height)
-    pr = oracle.project(arrays, cam, plan, fast)
+    pr = oracle.project(arrays, cam, plan, fast, alpha_extent)
     vis = np.nonzero(pr.visible)[0]
-    if fast:
+    if fast and key64:
+        dk = [int(np.float32(pr.d[g]).view(np.uint32)) for g in vis]
+        opa = arrays["log_opacity"]
+    elif fast:
         lv = (1 << plan.b_d) - 1
         dk = [min(max(math.floor((pr.d[g] - cam.z_near) / (cam.z_far - cam.z_near) * lv), 0), lv)
               for g in vis]
@@ -298,16 +302,16 @@ def brute_force_image(arrays, cam, path, mode):
     return img
 
 
-def check_brute_force(path="plain", seed=5, n=40, W=45, H=37):
+def check_brute_force(path="plain", seed=5, n=40, W=45, H=37, key64=False, alpha_extent=True):
     sc = wl.make_scene(n, 1.0, -2.5, 0.4, seed)
     cam = wl.look_at_camera((0.0, 0.0, -3.0), (0, 0, 0), (0, 1, 0), 60.0, W, H, 1.268, 4.732)
     if path == "fast":
         arr = oracle.prepare_fast(oracle.quantize_scene(sc))
         mode = "fast-def"
-        fr = oracle.render(arr, cam, "fast", modes=(mode,))
+        fr = oracle.render(arr, cam, "fast", modes=(mode,), key64=key64, alpha_extent=alpha_extent)
     else:
         arr = oracle.prepare_plain(sc)
         mode = "plain"
         fr = oracle.render(arr, cam, "plain")
-    ref = brute_force_image(arr, cam, path, mode)
+    ref = brute_force_image(arr, cam, path, mode, key64, alpha_extent)
     return float(np.max(np.abs(fr.image - ref)))

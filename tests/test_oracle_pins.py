@@ -107,6 +107,44 @@ def test_tiled_equals_brute_force(path, seed):
     assert check_brute_force(path=path, seed=seed) < 1e-12
 
 
+@pytest.mark.parametrize("key64,alpha_extent", [(True, True), (False, False), (True, False)])
+def test_fast_ablations_equal_brute_force(key64, alpha_extent):
+    """The fast path keyed on float32 depth, or with the 3-sigma extent, still
+    equals per-pixel blending in (key, index) order over the same rectangles."""
+    for seed in (5, 11):
+        assert check_brute_force("fast", seed, key64=key64, alpha_extent=alpha_extent) < 1e-12
+
+
+def test_alpha_extent_changes_entries_not_the_image():
+    """Sec. IV-A's opacity cull and alpha-ellipse extent only drop pairs whose
+    P is below -ln 255, which the skip test rejects: the image is the same bit
+    for bit, with fewer entries."""
+    sc = wl.make_scene(3000, 1.0, -3.0, 0.5, 17)
+    cam = wl.config_camera("cfg0", width=96, height=80)
+    arr = oracle.prepare_fast(oracle.quantize_scene(sc))
+    a = oracle.render(arr, cam, "fast")
+    b = oracle.render(arr, cam, "fast", alpha_extent=False)
+    assert b.keys.size > a.keys.size
+    for m in a.modes:
+        assert np.array_equal(a.images[m], b.images[m])
+    assert np.array_equal(a.n_blend, b.n_blend)
+
+
+def test_ablated_storage_reads_the_fp32_scene():
+    sc = wl.make_scene(500, 1.0, -3.0, 0.5, 19)
+    fs = oracle.quantize_scene(sc)
+    full = oracle.prepare_fast_ablated(sc, fs, int8_sh=False, fp16_geometry=False)
+    assert np.array_equal(full["sh"], sc.sh.astype(np.float64))
+    assert np.array_equal(full["quats"], sc.quats.astype(np.float64))
+    assert np.array_equal(full["means"], sc.means.astype(np.float64))
+    lno = full["log_opacity"]
+    assert np.all(np.abs(np.exp(lno) - sc.opacity) <= 2e-7 * sc.opacity)
+    assert np.array_equal(lno, lno.astype(np.float32).astype(np.float64))
+    only_sh = oracle.prepare_fast_ablated(sc, fs, int8_sh=False)
+    dq = oracle.prepare_fast(fs)
+    assert np.array_equal(only_sh["quats"], dq["quats"]) and np.array_equal(only_sh["sh"], full["sh"])
+
+
 def test_empty_frame():
     sc = wl.make_scene(20, 1.0, -3.0, 0.3, 3)
     cam = wl.look_at_camera((0, 0, 30.0), (0, 0, 40.0), (0, 1, 0), 60.0, 40, 40, 1.0, 2.0)
