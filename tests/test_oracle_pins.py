@@ -138,7 +138,9 @@ def test_ablated_storage_reads_the_fp32_scene():
     assert np.array_equal(full["quats"], sc.quats.astype(np.float64))
     assert np.array_equal(full["means"], sc.means.astype(np.float64))
     lno = full["log_opacity"]
-    assert np.all(np.abs(np.exp(lno) - sc.opacity) <= 2e-7 * sc.opacity)
+    # float32 rounding moves ln o by at most half an ulp, 2^-24 |ln o|, which is
+    # the relative change of o
+    assert np.all(np.abs(np.exp(lno) - sc.opacity) <= (2.0 ** -24 * np.abs(lno) + 1e-12) * 1.001 * sc.opacity)
     assert np.array_equal(lno, lno.astype(np.float32).astype(np.float64))
     only_sh = oracle.prepare_fast_ablated(sc, fs, int8_sh=False)
     dq = oracle.prepare_fast(fs)
