@@ -425,7 +425,7 @@ def main():
     dom = max(stages, key=lambda s: stages[s]["ms"])
     kernel = {"raster": "k_raster_fast" if main_path == "fast" else "k_raster_plain",
               "frontend": "k_frontend_fast" if main_path == "fast" else "k_preprocess_plain",
-              "duplicate": "k_duplicate_plain", "sort": "k_radix_pass", "ranges": "k_ranges"}[dom]
+              "duplicate": "k_duplicate", "sort": "k_radix_pass", "ranges": "k_ranges"}[dom]
     src = {"raster": "k_raster.hip", "frontend": "k_frontend.hip", "duplicate": "k_frontend.hip",
            "sort": "k_sort.hip", "ranges": "k_sort.hip"}[dom]
     rl = dict(stages[dom])

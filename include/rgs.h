@@ -56,11 +56,26 @@ typedef int32_t rgs_status;
 
 #define RGS_ABI_VERSION 1
 
-#define RGS_FMT_PLAIN 1u      /* FP32 structure-of-arrays, 236 bytes per Gaussian          */
+#define RGS_FMT_PLAIN 1u      /* FP32 structure-of-arrays, 240 bytes per Gaussian (the
+                                 plain path reads 236 of them; ln o is kept for ablations)   */
 #define RGS_FMT_FAST  2u      /* compact structure-of-arrays, 100 bytes per Gaussian       */
 
 #define RGS_PATH_PLAIN 0
 #define RGS_PATH_FAST  1
+
+/* Ablations of the fast path: each bit, OR-ed into a `path` argument together
+ * with RGS_PATH_FAST, removes one of the paper's optimisations (Sec. IV) and
+ * keeps the rest, for the per-step study of what each contributes.  The image
+ * definition of every combination is the oracle's fast path with the matching
+ * step removed. */
+#define RGS_ABLATE_FASTEXP   (1 << 8)   /* alpha = min(0.99, exp(P)) instead of Eq. fma_exp        */
+#define RGS_ABLATE_DUALPIXEL (1 << 9)   /* one pixel per thread instead of Eq. dual_pixel          */
+#define RGS_ABLATE_FUSION    (1 << 10)  /* separate preprocess and duplication kernels             */
+#define RGS_ABLATE_EXTENT    (1 << 11)  /* 3-sigma tile extent, no opacity cull                     */
+#define RGS_ABLATE_KEY32     (1 << 12)  /* 64-bit (tile | FP32 depth) key of the plain path        */
+#define RGS_ABLATE_INT8_SH   (1 << 13)  /* FP32 SH from the plain format (the scene needs both)    */
+#define RGS_ABLATE_FP16_GEOM (1 << 14)  /* FP32 rotation, scale and ln o from the plain format     */
+#define RGS_ABLATE_MASK      (0x7f << 8)
 
 #define RGS_TILE 16
 #define RGS_MAX_DIM 16384     /* largest accepted image width or height                    */

@@ -28,7 +28,26 @@ FMT_PLAIN = 1
 FMT_FAST = 2
 PATH_PLAIN = 0
 PATH_FAST = 1
-PATHS = {"plain": PATH_PLAIN, "fast": PATH_FAST}
+# Ablations of the fast path (rgs.h, RGS_ABLATE_*): a path string
+# "fast/no-<name>[/no-<name>...]" removes the named steps.
+ABLATIONS = {"fastexp": 1 << 8, "dualpixel": 1 << 9, "fusion": 1 << 10, "extent": 1 << 11,
+             "key32": 1 << 12, "int8sh": 1 << 13, "fp16geom": 1 << 14}
+
+
+class _Paths(dict):
+    """"plain", "fast", or "fast/no-<ablation>/..." -> the C path argument."""
+
+    def __missing__(self, key):
+        parts = str(key).split("/")
+        if parts[0] != "fast" or len(parts) < 2 or not all(p.startswith("no-") for p in parts[1:]):
+            raise KeyError(key)
+        code = PATH_FAST
+        for p in parts[1:]:
+            code |= ABLATIONS[p[3:]]
+        return code
+
+
+PATHS = _Paths({"plain": PATH_PLAIN, "fast": PATH_FAST})
 N_STAGES = 5
 STAGE_NAMES = ("frontend", "duplicate", "sort", "ranges", "raster")
 MAX_ENTRIES = (1 << 30) - 1

@@ -48,6 +48,7 @@ __global__ __launch_bounds__(256) void k_update_plain(float* __restrict__ planes
 #pragma unroll
     for (int k = 0; k < 4; ++k) planes[(P_QW + k) * n_pad + i] = quats[4 * i + k];
     planes[P_OPA * n_pad + i] = opacity[i];
+    planes[P_LNO * n_pad + i] = (float)log((double)opacity[i]);
 #pragma unroll 8
     for (int k = 0; k < 48; ++k) planes[(P_SH0 + k) * n_pad + i] = sh[48 * i + k];
 }

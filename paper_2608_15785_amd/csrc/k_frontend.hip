@@ -376,10 +376,14 @@ void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const Frame
 }
 
 // ---------------------------------------------------------------------------
-// Plain duplication: ordered allocation over the stored counts, 64-bit keys.
+// Duplication over the stored counts (the plain path, and the fast path with
+// fusion ablated): ordered allocation, then (tile << shift | low bits) keys,
+// where the low bits are the float32 depth (shift 32) or the quantised depth
+// (shift b_d) kept as a word in `depths`.
 
-__global__ __launch_bounds__(FE_THREADS) void k_duplicate_plain(int64_t n, FrameDev f, WsDev ws,
-                                                                uint32_t n_blocks) {
+template <typename KeyT>
+__global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f, WsDev ws, uint32_t n_blocks,
+                                                          uint32_t shift) {
     __shared__ uint32_t s_vb;
     __shared__ uint32_t s_incl[FE_TILE];
     __shared__ uint64_t s_rect[FE_TILE];
@@ -418,17 +422,20 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate_plain(int64_t n, Frame
         const int64_t i = (int64_t)vb * FE_TILE + j;
         if (i < n && count[k]) ws.offsets[i] = (uint32_t)(base + (j ? s_incl[j - 1] : 0u));
     }
-    uint64_t* keys = reinterpret_cast<uint64_t*>(ws.keys_a);
-    emit_entries<uint64_t>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity, keys,
-                           ws.vals_a, [&](uint32_t tile, uint32_t j) {
-                               return ((uint64_t)tile << 32) | (uint64_t)s_dbits[j];
-                           });
+    emit_entries<KeyT>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
+                       reinterpret_cast<KeyT*>(ws.keys_a), ws.vals_a,
+                       [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_dbits[j]; });
     finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
 }
 
-void launch_duplicate_plain(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws,
-                            uint32_t fe_blocks) {
-    hipLaunchKernelGGL(k_duplicate_plain, dim3(fe_blocks), dim3(FE_THREADS), 0, s, n, f, ws, fe_blocks);
+void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
+                      uint32_t key_bytes) {
+    if (key_bytes == 8)
+        hipLaunchKernelGGL(k_duplicate<uint64_t>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, n, f, ws, fe_blocks,
+                           32u);
+    else
+        hipLaunchKernelGGL(k_duplicate<uint32_t>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, n, f, ws, fe_blocks,
+                           (uint32_t)f.b_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -436,43 +443,63 @@ void launch_duplicate_plain(hipStream_t s, int64_t n, const FrameDev& f, const W
 // allocate in order and emit 32-bit (tile << b_d | q_d) keys.
 
 // Project, cull and colour Gaussian i of the compact planes.  Returns its tile
-// count (0 when culled) and leaves its rectangle and quantised depth.
+// count (0 when culled) and leaves its rectangle and the low part of its key
+// (the quantised depth; the float32 depth bits when the 32-bit key is
+// ablated).  `opts` holds the ablation bits the generic instances honour; the
+// production instance passes 0 and the compiler drops every ablation branch.
 template <bool DEBUG>
 __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& cam, const FrameDev& f,
                                          WsDev& ws, const DebugDev& dbg, int64_t i, uint64_t& rect,
-                                         uint32_t& qd) {
+                                         uint32_t& klo, uint32_t opts) {
     const uint32_t* W = sc.base;
     const uint64_t np = sc.n_pad;
     const float mx = __uint_as_float(W[F_MX * np + i]);
     const float my = __uint_as_float(W[F_MY * np + i]);
     const float mz = __uint_as_float(W[F_MZ * np + i]);
-    const uint32_t qwx = W[F_QWX * np + i], qyz = W[F_QYZ * np + i];
-    const uint32_t sxy = W[F_SXY * np + i], szl = W[F_SZL * np + i];
-    const float lno = half_hi(szl);
+    float qw, qx, qy, qz, sx, sy, sz, lno;
+    if (opts & OPT_FP16_GEOM) {
+        const float* P = sc.plain;
+        qw = P[P_QW * np + i]; qx = P[P_QX * np + i]; qy = P[P_QY * np + i]; qz = P[P_QZ * np + i];
+        sx = P[P_SX * np + i]; sy = P[P_SY * np + i]; sz = P[P_SZ * np + i];
+        lno = P[P_LNO * np + i];
+    } else {
+        const uint32_t qwx = W[F_QWX * np + i], qyz = W[F_QYZ * np + i];
+        const uint32_t sxy = W[F_SXY * np + i], szl = W[F_SZL * np + i];
+        qw = half_lo(qwx); qx = half_hi(qwx); qy = half_lo(qyz); qz = half_hi(qyz);
+        sx = half_lo(sxy); sy = half_hi(sxy); sz = half_lo(szl);
+        lno = half_hi(szl);
+    }
     Projected pr;
-    const bool vis = project_gaussian(cam, mx, my, mz, half_lo(qwx), half_hi(qwx), half_lo(qyz),
-                                      half_hi(qyz), half_lo(sxy), half_hi(sxy), half_lo(szl), true,
-                                      (double)lno, (double)f.tiles_x, (double)f.tiles_y, pr);
+    const bool vis = project_gaussian(cam, mx, my, mz, qw, qx, qy, qz, sx, sy, sz, true, (double)lno,
+                                      (double)f.tiles_x, (double)f.tiles_y, pr, !(opts & OPT_EXTENT));
     float r = 0.f, g = 0.f, b = 0.f;
     uint32_t count = 0;
     if (vis) {
-        uint32_t qw[12], sw[6];
-#pragma unroll
-        for (int k = 0; k < 12; ++k) qw[k] = W[(F_SHQ0 + k) * np + i];
-#pragma unroll
-        for (int k = 0; k < 6; ++k) sw[k] = W[(F_SHS0 + k) * np + i];
         const ShBasis y = view_basis(mx, my, mz, cam);
         float acc[3] = {0.5f, 0.5f, 0.5f};
+        if (opts & OPT_INT8_SH) {
+            const float* P = sc.plain;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int deg = k == 0 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3));
+            for (int k = 0; k < 16; ++k)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const int v = 3 * k + ch;
-                const float q = (float)(int8_t)((qw[v >> 2] >> (8 * (v & 3))) & 0xffu);
-                const int si = 3 * deg + ch;
-                const float scale = (si & 1) ? half_hi(sw[si >> 1]) : half_lo(sw[si >> 1]);
-                acc[ch] = fmaf(y.y[k], q * scale, acc[ch]);
+                for (int ch = 0; ch < 3; ++ch) acc[ch] = fmaf(y.y[k], P[(P_SH0 + 3 * k + ch) * np + i], acc[ch]);
+        } else {
+            uint32_t qwd[12], sw[6];
+#pragma unroll
+            for (int k = 0; k < 12; ++k) qwd[k] = W[(F_SHQ0 + k) * np + i];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sw[k] = W[(F_SHS0 + k) * np + i];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int deg = k == 0 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3));
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    const int v = 3 * k + ch;
+                    const float q = (float)(int8_t)((qwd[v >> 2] >> (8 * (v & 3))) & 0xffu);
+                    const int si = 3 * deg + ch;
+                    const float scale = (si & 1) ? half_hi(sw[si >> 1]) : half_lo(sw[si >> 1]);
+                    acc[ch] = fmaf(y.y[k], q * scale, acc[ch]);
+                }
             }
         }
         r = fmaxf(acc[0], 0.f);
@@ -480,17 +507,23 @@ __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& c
         b = fmaxf(acc[2], 0.f);
         write_record(&ws.records[i], pr, lno, r, g, b, half_bits_up(pr.ax) | (half_bits_up(pr.ay) << 16));
         rect = pack_rect(pr);
-        qd = quantize_depth(pr.d, cam.zn, cam.zf, f.b_d);
+        klo = (opts & OPT_KEY32) ? __float_as_uint((float)pr.d) : quantize_depth(pr.d, cam.zn, cam.zf, f.b_d);
         count = rect_count(rect);
     }
     if (DEBUG) write_debug(dbg, i, pr, vis, r, g, b);
     return count;
 }
 
-template <bool DEBUG>
+// The fused front end: project, cull, colour, scan, allocate in order, emit.
+// KeyT is uint32_t for (tile << b_d | q_d) keys and uint64_t for the plain
+// path's (tile << 32 | float32 depth bits) keys (the key ablation); GENERIC
+// instances honour the ablation bits in `opts`, the production one ignores it.
+template <bool DEBUG, bool GENERIC, typename KeyT>
 __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, FrameDev f, WsDev ws,
-                                                              uint32_t n_blocks, DebugDev dbg) {
+                                                              uint32_t n_blocks, DebugDev dbg,
+                                                              uint32_t opts_arg) {
     const CamDev cam = ws.params->cam;
+    const uint32_t opts = GENERIC ? opts_arg : 0u;
     __shared__ uint32_t s_vb;
     __shared__ uint32_t s_incl[FE_TILE];
     __shared__ uint64_t s_rect[FE_TILE];
@@ -510,11 +543,11 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
         count[k] = 0;
         if (i < sc.n) {
             uint64_t rect = 0;
-            uint32_t qd = 0;
-            count[k] = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, qd);
+            uint32_t klo = 0;
+            count[k] = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, klo, opts);
             if (count[k]) {
                 s_rect[j] = rect;
-                s_qd[j] = qd;
+                s_qd[j] = klo;
                 ++n_vis;
             }
         }
@@ -523,21 +556,60 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
     const uint32_t total = block_scan_and_chain(count, n_vis, vb, ws, s_incl, s_wtot, s_wvis, &s_base,
                                                 &s_base_v, &vis_total);
     const uint64_t base = s_base;
-    const int bd = f.b_d;
-    emit_entries<uint32_t>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
-                           reinterpret_cast<uint32_t*>(ws.keys_a), ws.vals_a,
-                           [&](uint32_t tile, uint32_t j) { return (tile << bd) | s_qd[j]; });
+    const uint32_t shift = sizeof(KeyT) == 8 ? 32u : (uint32_t)f.b_d;
+    emit_entries<KeyT>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
+                       reinterpret_cast<KeyT*>(ws.keys_a), ws.vals_a,
+                       [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_qd[j]; });
     finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
 }
 
+template <bool DEBUG, bool GENERIC, typename KeyT>
+static void launch_fe(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
+                      uint32_t fe_blocks, const DebugDev* dbg, uint32_t opts) {
+    hipLaunchKernelGGL((k_frontend_fast<DEBUG, GENERIC, KeyT>), dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, f,
+                       ws, fe_blocks, dbg ? *dbg : DebugDev{}, opts);
+}
+
 void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
-                          uint32_t fe_blocks, const DebugDev* dbg) {
+                          uint32_t fe_blocks, const DebugDev* dbg, uint32_t opts) {
+    const bool key64 = (opts & OPT_KEY32) != 0;
+    if (opts == 0) {
+        if (dbg) launch_fe<true, false, uint32_t>(s, sc, f, ws, fe_blocks, dbg, 0);
+        else launch_fe<false, false, uint32_t>(s, sc, f, ws, fe_blocks, dbg, 0);
+    } else if (key64) {
+        if (dbg) launch_fe<true, true, uint64_t>(s, sc, f, ws, fe_blocks, dbg, opts);
+        else launch_fe<false, true, uint64_t>(s, sc, f, ws, fe_blocks, dbg, opts);
+    } else {
+        if (dbg) launch_fe<true, true, uint32_t>(s, sc, f, ws, fe_blocks, dbg, opts);
+        else launch_fe<false, true, uint32_t>(s, sc, f, ws, fe_blocks, dbg, opts);
+    }
+}
+
+// Fusion ablated: the fast preprocess alone, one thread per Gaussian, leaving
+// counts, rectangles and the low key part for the duplication kernel.
+template <bool DEBUG>
+__global__ __launch_bounds__(256) void k_preprocess_fast(FastSceneDev sc, FrameDev f, WsDev ws, DebugDev dbg,
+                                                         uint32_t opts) {
+    const CamDev cam = ws.params->cam;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= sc.n) return;
+    uint64_t rect = 0;
+    uint32_t klo = 0;
+    const uint32_t count = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, klo, opts);
+    ws.counts[i] = count;
+    if (count) {
+        ws.rects[i] = rect;
+        ws.depths[i] = __uint_as_float(klo);
+    }
+}
+
+void launch_preprocess_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
+                            const DebugDev* dbg, uint32_t opts) {
+    const uint32_t blocks = (uint32_t)((sc.n + 255) / 256);
     if (dbg)
-        hipLaunchKernelGGL(k_frontend_fast<true>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, f, ws,
-                           fe_blocks, *dbg);
+        hipLaunchKernelGGL(k_preprocess_fast<true>, dim3(blocks), dim3(256), 0, s, sc, f, ws, *dbg, opts);
     else
-        hipLaunchKernelGGL(k_frontend_fast<false>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, f, ws,
-                           fe_blocks, DebugDev{});
+        hipLaunchKernelGGL(k_preprocess_fast<false>, dim3(blocks), dim3(256), 0, s, sc, f, ws, DebugDev{}, opts);
 }
 
 __global__ void k_widen_keys(const uint32_t* in, uint64_t* out, uint64_t n) {

@@ -152,7 +152,7 @@ constexpr int ALPHA_MAX_BITS = 0x3f7d70a4;   // bit pattern of 0.99f
 constexpr float BOX_MARGIN_REL = 1.0e-3f;
 constexpr float BOX_MARGIN_ABS = 0.05f;
 // The same safety margin on the quadratic form q = A dx^2 + 2 B dx dy + C dy^2
-// (P = ln o - q / 2): a half-tile is kept when min q <= tau (1 + 1e-3) + 0.02.
+// (P = ln o - q / 2): a band is kept when min q <= tau (1 + 1e-3) + 0.02.
 constexpr float Q_MARGIN_REL = 1.0e-3f;
 constexpr float Q_MARGIN_ABS = 0.02f;
 
@@ -176,7 +176,7 @@ __device__ inline float conic_rect_min(float u, float v, float A, float B, float
     return best;
 }
 
-template <bool COUNT>
+template <bool COUNT, bool EXACT>
 __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev ws,
                                                               const uint32_t* __restrict__ vals) {
     // per-wave lists of folded Gaussians, in depth order
@@ -286,10 +286,16 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
                     const float P1 = P0 + fmaf(a.y, x, fmaf(a.z, y21, m.x));
                     const bool pass0 = live0 && P0 >= -LN255F;
                     const bool pass1 = live1 && P1 >= -LN255F;
-                    const int I0 = min((int)fmaf(P0, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
-                    const int I1 = min((int)fmaf(P1, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
-                    const float al0 = pass0 ? __int_as_float(I0) : 0.0f;
-                    const float al1 = pass1 ? __int_as_float(I1) : 0.0f;
+                    float al0, al1;
+                    if (EXACT) {          // the exponential's ablation: alpha = min(0.99, exp(P))
+                        al0 = pass0 ? fminf(ALPHA_MAX, expf(P0)) : 0.0f;
+                        al1 = pass1 ? fminf(ALPHA_MAX, expf(P1)) : 0.0f;
+                    } else {
+                        const int I0 = min((int)fmaf(P0, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
+                        const int I1 = min((int)fmaf(P1, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
+                        al0 = pass0 ? __int_as_float(I0) : 0.0f;
+                        al1 = pass1 ? __int_as_float(I1) : 0.0f;
+                    }
                     const float w0 = al0 * T0, w1 = al1 * T1;
                     float Tn0 = T0 - w0, Tn1 = T1 - w1;
                     float nr0 = fmaf(w0, m.z, r0), ng0 = fmaf(w0, m.w, g0), nb0 = fmaf(w0, c.x, b0);
@@ -344,15 +350,238 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
     }
 }
 
-void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                        bool count) {
-    const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
+// The dual-pixel ablation of the fast rasterizer: one pixel per thread, 256
+// threads in four waves of 16x4 rows, each wave with its own culled list;
+// written for any PIX, instantiated with PIX = 1 only (the production kernel
+// above is the tuned PIX = 2 case).  EXACT as above.
+template <bool COUNT, bool EXACT, int PIX>
+__global__ __launch_bounds__(256 / PIX) void k_raster_fast_px(FrameDev f, WsDev ws,
+                                                           const uint32_t* __restrict__ vals) {
+    constexpr int THREADS = 256 / PIX;
+    constexpr int WAVES = THREADS / 64;
+    constexpr int BATCH = THREADS;
+    constexpr int CAP = BATCH + LIST_UNROLL;
+    constexpr int ROWS = TILE / WAVES;             // rows per wave
+    __shared__ float4 s_a[WAVES][CAP];             // C1, C2, C3, C4
+    __shared__ float4 s_b[WAVES][CAP];             // C5, C6, r, g
+    __shared__ float2 s_c[WAVES][CAP];             // b, list position (as float bits)
+    __shared__ uint32_t s_cnt[WAVES][WAVES];       // [wave of the staging thread][list]
+    const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)f.n_tiles);
+    if (tile >= (uint32_t)f.n_tiles) return;
+    const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / 64, lane = tid % 64;
+    const uint32_t lx = tid % TILE, ly = PIX * (tid / TILE);
+    const uint32_t px = tx * TILE + lx, py = ty * TILE + ly;
+    const bool in0 = px < (uint32_t)f.width && py < (uint32_t)f.height;
+    const bool in1 = PIX == 2 && px < (uint32_t)f.width && py + 1 < (uint32_t)f.height;
+    const uint32_t start = ws.ranges[2 * tile], end = ws.ranges[2 * tile + 1];
+    // tile-centre coordinates
+    const float ox = (float)(tx * TILE) + 7.5f, oy = (float)(ty * TILE) + 7.5f;
+    const float x = (float)lx - 7.5f, y = (float)ly - 7.5f;
+    const float x2 = x * x, xy = x * y, y2 = y * y, y21 = fmaf(2.0f, y, 1.0f);
+
+    float T0 = 1.0f, r0 = 0.0f, g0 = 0.0f, b0 = 0.0f;
+    float T1 = 1.0f, r1 = 0.0f, g1 = 0.0f, b1 = 0.0f;
+    bool live0 = in0, live1 = in1;
+    uint32_t stop0 = 0xffffffffu, stop1 = 0xffffffffu;
+    uint32_t nbl0 = 0, nbl1 = 0;
+
+    for (uint32_t base = start; base < end; base += BATCH) {
+        if (__syncthreads_count(live0 || live1) == 0) break;
+        // ---- stage: fold, cull against the waves' bands, compact per wave ----
+        const uint32_t idx = base + tid;
+        bool hit[WAVES];
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) hit[w] = false;
+        float4 ca = make_float4(0.f, 0.f, 0.f, 0.f), cbv = make_float4(0.f, 0.f, 0.f, 0.f);
+        float cb = 0.f;
+        if (idx < end) {
+            const uint32_t g = vals[idx];
+            const Record rec = ws.records[g < f.n_gaussians ? g : 0u];
+            const float u = (rec.u_hi - ox) + rec.u_lo;
+            const float v = (rec.v_hi - oy) + rec.v_lo;
+            const float A = rec.A, B = rec.B, C = rec.C;
+            const float C0 = fmaf(A * u, u, fmaf(2.0f * B * u, v, C * v * v));
+            ca = make_float4(-0.5f * A, -B, -0.5f * C, fmaf(A, u, B * v));
+            cbv = make_float4(fmaf(C, v, B * u), fmaf(-0.5f, C0, rec.opa), rec.r, rec.g);
+            cb = rec.b;
+            // the box |x - u| <= hx, |y - v| <= hy holds every pixel with
+            // P >= -ln 255 (half-extents from the front end, rounded up, then
+            // widened); a band outside it has no pair that passes the skip
+            // test; then the ellipse itself: the band must hold a point with
+            // q <= tau = 2 (ln 255 + ln o), up to the margin.  Comparisons are
+            // phrased so that a NaN keeps the Gaussian.
+            const float hx = fmaf(half_lo(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
+            const float hy = fmaf(half_hi(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
+            const bool x_out = u - hx > 7.5f || u + hx < -7.5f;
+            const float qlim = fmaf(2.0f * (LN255F + rec.opa), 1.0f + Q_MARGIN_REL, Q_MARGIN_ABS);
+            const float iA = 1.0f / A, iC = 1.0f / C;
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const float y0 = (float)(w * ROWS) - 7.5f, y1 = (float)(w * ROWS + ROWS - 1) - 7.5f;
+                hit[w] = !(x_out || v - hy > y1 || v + hy < y0);
+                if (hit[w]) hit[w] = !(conic_rect_min(u, v, A, B, C, iA, iC, y0, y1) > qlim);
+            }
+        }
+        uint64_t mk[WAVES];
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) mk[w] = __ballot(hit[w]);
+        const uint64_t lt = lanemask_lt();
+        if (lane == 0) {
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) s_cnt[wave][w] = (uint32_t)__popcll(mk[w]);
+        }
+        __syncthreads();
+        const float posf = __uint_as_float(idx);
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            if (hit[w]) {
+                uint32_t p = (uint32_t)__popcll(mk[w] & lt);
+                for (uint32_t sw = 0; sw < wave; ++sw) p += s_cnt[sw][w];
+                s_a[w][p] = ca;
+                s_b[w][p] = cbv;
+                s_c[w][p] = make_float2(cb, posf);
+            }
+        }
+        uint32_t nl[WAVES];
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            nl[w] = 0;
+#pragma unroll
+            for (int sw = 0; sw < WAVES; ++sw) nl[w] += s_cnt[sw][w];
+        }
+        // inert padding up to a multiple of the unroll: P = -1e30 is always skipped
+        if (tid < WAVES * LIST_UNROLL) {
+            const uint32_t w = tid / LIST_UNROLL, k = tid % LIST_UNROLL;
+            const uint32_t p = nl[w] + k;
+            s_a[w][p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_b[w][p] = make_float4(0.f, -1.0e30f, 0.f, 0.f);
+            s_c[w][p] = make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+
+        // ---- blend this wave's list ----
+        const uint32_t n = nl[wave];
+        const float4* __restrict__ la = s_a[wave];
+        const float4* __restrict__ lb = s_b[wave];
+        const float2* __restrict__ lc = s_c[wave];
+        if (__ballot(live0 || live1) != 0) {
+            for (uint32_t k0 = 0; k0 < n; k0 += LIST_UNROLL) {
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) {
+                    const float4 a = la[k0 + u];
+                    const float4 m = lb[k0 + u];
+                    const float2 c = lc[k0 + u];
+                    const float P0 = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(m.x, y, m.y)))));
+                    const bool pass0 = live0 && P0 >= -LN255F;
+                    float al0;
+                    if (EXACT) {
+                        al0 = pass0 ? fminf(ALPHA_MAX, expf(P0)) : 0.0f;
+                    } else {
+                        const int I0 = min((int)fmaf(P0, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
+                        al0 = pass0 ? __int_as_float(I0) : 0.0f;
+                    }
+                    const float w0 = al0 * T0;
+                    float Tn0 = T0 - w0;
+                    float nr0 = fmaf(w0, m.z, r0), ng0 = fmaf(w0, m.w, g0), nb0 = fmaf(w0, c.x, b0);
+                    const bool s0 = Tn0 < T_MIN;
+                    float al1 = 0.0f, w1 = 0.0f, Tn1 = T1, nr1 = r1, ng1 = g1, nb1 = b1;
+                    bool s1 = false;
+                    if (PIX == 2) {
+                        const float P1 = P0 + fmaf(a.y, x, fmaf(a.z, y21, m.x));
+                        const bool pass1 = live1 && P1 >= -LN255F;
+                        if (EXACT) {
+                            al1 = pass1 ? fminf(ALPHA_MAX, expf(P1)) : 0.0f;
+                        } else {
+                            const int I1 = min((int)fmaf(P1, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
+                            al1 = pass1 ? __int_as_float(I1) : 0.0f;
+                        }
+                        w1 = al1 * T1;
+                        Tn1 = T1 - w1;
+                        nr1 = fmaf(w1, m.z, r1); ng1 = fmaf(w1, m.w, g1); nb1 = fmaf(w1, c.x, b1);
+                        s1 = Tn1 < T_MIN;
+                    }
+                    if (COUNT) {
+                        nbl0 += (al0 > 0.0f && !s0) ? 1u : 0u;
+                        if (PIX == 2) nbl1 += (al1 > 0.0f && !s1) ? 1u : 0u;
+                    }
+                    if (__ballot(s0 || s1) != 0) {
+                        // a pixel reached the stop: that pair is not blended
+                        const uint32_t at = __float_as_uint(c.y);
+                        if (s0) {
+                            live0 = false;
+                            stop0 = at;
+                            Tn0 = T0; nr0 = r0; ng0 = g0; nb0 = b0;
+                        }
+                        if (PIX == 2 && s1) {
+                            live1 = false;
+                            stop1 = at;
+                            Tn1 = T1; nr1 = r1; ng1 = g1; nb1 = b1;
+                        }
+                    }
+                    T0 = Tn0; r0 = nr0; g0 = ng0; b0 = nb0;
+                    if (PIX == 2) {
+                        T1 = Tn1; r1 = nr1; g1 = ng1; b1 = nb1;
+                    }
+                }
+                if (__ballot(live0 || live1) == 0) break;
+            }
+        }
+        __syncthreads();
+    }
+    const uint64_t plane = (uint64_t)f.width * f.height;
+    float* __restrict__ out = ws.params->out;
+    const float bg0 = ws.params->cam.bg[0], bg1 = ws.params->cam.bg[1], bg2 = ws.params->cam.bg[2];
+    if (in0) {
+        const uint64_t o = (uint64_t)py * f.width + px;
+        out[o] = fmaf(T0, bg0, r0);
+        out[plane + o] = fmaf(T0, bg1, g0);
+        out[2 * plane + o] = fmaf(T0, bg2, b0);
+        ws.t_final[o] = T0;
+        ws.n_proc[o] = stop0 != 0xffffffffu ? (stop0 - start + 1) | N_PROC_STOPPED : end - start;
+        if (COUNT) ws.n_blend[o] = nbl0;
+    }
+    if (in1) {
+        const uint64_t o = (uint64_t)(py + 1) * f.width + px;
+        out[o] = fmaf(T1, bg0, r1);
+        out[plane + o] = fmaf(T1, bg1, g1);
+        out[2 * plane + o] = fmaf(T1, bg2, b1);
+        ws.t_final[o] = T1;
+        ws.n_proc[o] = stop1 != 0xffffffffu ? (stop1 - start + 1) | N_PROC_STOPPED : end - start;
+        if (COUNT) ws.n_blend[o] = nbl1;
+    }
+}
+
+template <bool EXACT>
+static void launch_fast_dual(hipStream_t s, const FrameDev& f, const WsDev& ws, const uint32_t* vals, bool count) {
     if (count)
-        hipLaunchKernelGGL(k_raster_fast<true>, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
+        hipLaunchKernelGGL((k_raster_fast<true, EXACT>), dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
                            vals);
     else
-        hipLaunchKernelGGL(k_raster_fast<false>, dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
+        hipLaunchKernelGGL((k_raster_fast<false, EXACT>), dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
                            vals);
+}
+
+template <bool EXACT>
+static void launch_fast_single(hipStream_t s, const FrameDev& f, const WsDev& ws, const uint32_t* vals,
+                               bool count) {
+    if (count)
+        hipLaunchKernelGGL((k_raster_fast_px<true, EXACT, 1>), dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, ws,
+                           vals);
+    else
+        hipLaunchKernelGGL((k_raster_fast_px<false, EXACT, 1>), dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, ws,
+                           vals);
+}
+
+void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count,
+                        uint32_t opts) {
+    const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
+    const bool exact = (opts & OPT_FASTEXP) != 0, single = (opts & OPT_DUALPIXEL) != 0;
+    if (!exact && !single) launch_fast_dual<false>(s, f, ws, vals, count);
+    else if (exact && !single) launch_fast_dual<true>(s, f, ws, vals, count);
+    else if (!exact && single) launch_fast_single<false>(s, f, ws, vals, count);
+    else launch_fast_single<true>(s, f, ws, vals, count);
 }
 
 }  // namespace rgs

@@ -341,6 +341,7 @@ extern "C" rgs_status rgs_scene_upload(rgs_ctx* ctx, const rgs_scene_desc* d, ui
             for (int k = 0; k < 3; ++k) h[(P_SX + k) * np + i] = d->scales[3 * i + k];
             for (int k = 0; k < 4; ++k) h[(P_QW + k) * np + i] = d->quats[4 * i + k];
             h[P_OPA * np + i] = d->opacity[i];
+            h[P_LNO * np + i] = (float)std::log((double)d->opacity[i]);
             for (int k = 0; k < 48; ++k) h[(P_SH0 + k) * np + i] = d->sh[48 * i + k];
         }
         size_t bytes = h.size() * sizeof(float);
@@ -421,11 +422,17 @@ extern "C" rgs_status rgs_scene_info(const rgs_scene* sc, int64_t* n, uint32_t* 
 
 static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 
+// The base path (RGS_PATH_PLAIN / RGS_PATH_FAST) and the ablation bits of a
+// path argument.
+static int32_t path_base(int32_t path) { return path & 0xff; }
+static uint32_t path_opts(int32_t path) { return ((uint32_t)path & RGS_ABLATE_MASK) >> 8; }
+
 static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t capacity, WsLayout& L) {
-    const bool plain = path == RGS_PATH_PLAIN;
+    const bool plain = path_base(path) == RGS_PATH_PLAIN;
+    const uint32_t opts = path_opts(path);
     L.capacity = capacity;
-    L.key_bytes = plain ? 8 : 4;
-    L.passes = plain ? (uint32_t)p.plain_passes : (uint32_t)p.fast_passes;
+    L.key_bytes = (plain || (opts & OPT_KEY32)) ? 8 : 4;
+    L.passes = L.key_bytes == 8 ? (uint32_t)p.plain_passes : (uint32_t)p.fast_passes;
     L.fe_blocks = (uint32_t)((n + FE_TILE - 1) / FE_TILE);
     const uint64_t st = sort_tile_size(L.key_bytes);
     L.sort_blocks_max = (uint32_t)((capacity + st - 1) / st);
@@ -444,7 +451,7 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     L.records = off;
     off = align256(off + (uint64_t)n * sizeof(Record));
     L.counts = L.rects = L.depths = L.offsets = 0;
-    if (plain) {
+    if (plain || (opts & OPT_FUSION)) {
         L.counts = off;
         off = align256(off + (uint64_t)n * 4);
         L.rects = off;
@@ -474,8 +481,11 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
 }
 
 static rgs_status check_path(int32_t path) {
-    if (path != RGS_PATH_PLAIN && path != RGS_PATH_FAST)
-        return fail(RGS_E_INVALID, "path %d is neither RGS_PATH_PLAIN nor RGS_PATH_FAST", path);
+    const int32_t base = path_base(path);
+    if ((base != RGS_PATH_PLAIN && base != RGS_PATH_FAST) || (path & ~(0xff | RGS_ABLATE_MASK)))
+        return fail(RGS_E_INVALID, "path 0x%x is neither RGS_PATH_PLAIN nor RGS_PATH_FAST with ablation bits", path);
+    if (base == RGS_PATH_PLAIN && path_opts(path))
+        return fail(RGS_E_INVALID, "ablation bits apply to the fast path only");
     return RGS_OK;
 }
 
@@ -629,10 +639,14 @@ rgs_status rgs::prepare_frame(const rgs_scene* sc, int32_t W, int32_t H, int32_t
     if (!sc) return fail(RGS_E_INVALID, "scene is NULL");
     rgs_status s = check_path(path);
     if (s != RGS_OK) return s;
-    if (path == RGS_PATH_PLAIN && !(sc->formats & RGS_FMT_PLAIN))
+    const int32_t base = path_base(path);
+    const uint32_t opts = path_opts(path);
+    if (base == RGS_PATH_PLAIN && !(sc->formats & RGS_FMT_PLAIN))
         return fail(RGS_E_INVALID, "scene was uploaded without the plain format");
-    if (path == RGS_PATH_FAST && !(sc->formats & RGS_FMT_FAST))
+    if (base == RGS_PATH_FAST && !(sc->formats & RGS_FMT_FAST))
         return fail(RGS_E_INVALID, "scene was uploaded without the fast format");
+    if ((opts & (OPT_INT8_SH | OPT_FP16_GEOM)) && !(sc->formats & RGS_FMT_PLAIN))
+        return fail(RGS_E_INVALID, "the storage ablations read the plain format, which the scene lacks");
     s = rgs_frame_plan(W, H, &fl->plan);
     if (s != RGS_OK) return s;
     if (!ws) return fail(RGS_E_INVALID, "workspace is NULL");
@@ -643,7 +657,9 @@ rgs_status rgs::prepare_frame(const rgs_scene* sc, int32_t W, int32_t H, int32_t
     if (cap == 0) return fail(RGS_E_INVALID, "workspace of %llu bytes is too small", (unsigned long long)ws_bytes);
     fl->device = sc->device;
     fl->n = sc->n;
-    fl->path = path;
+    fl->path = base;
+    fl->opts = opts;
+    fl->path_word = (uint32_t)path;
     make_layout(sc->n, p, path, cap, fl->L);
     fl->w = ws_pointers(ws, fl->L);
     FrameDev& f = fl->f;
@@ -658,7 +674,7 @@ rgs_status rgs::prepare_frame(const rgs_scene* sc, int32_t W, int32_t H, int32_t
     f.capacity = (uint32_t)cap;
     f.n_gaussians = (uint32_t)sc->n;
     fl->plain = PlainSceneDev{sc->plain, sc->n_pad, sc->n};
-    fl->fast = FastSceneDev{sc->fast, sc->n_pad, sc->n};
+    fl->fast = FastSceneDev{sc->fast, sc->n_pad, sc->n, sc->plain};
     return RGS_OK;
 }
 
@@ -670,14 +686,19 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
     };
     const WsDev& w = fl.w;
     mark(0);
-    launch_reset(st, reset_args(w, fl.L.zero_end, fl.f, (uint32_t)fl.path, prm));
+    launch_reset(st, reset_args(w, fl.L.zero_end, fl.f, fl.path_word, prm));
     if (fl.path == RGS_PATH_PLAIN) {
         launch_preprocess_plain(st, fl.plain, fl.f, w, dbg);
         mark(1);
-        launch_duplicate_plain(st, fl.n, fl.f, w, fl.L.fe_blocks);
+        launch_duplicate(st, fl.n, fl.f, w, fl.L.fe_blocks, fl.L.key_bytes);
+        mark(2);
+    } else if (fl.opts & OPT_FUSION) {
+        launch_preprocess_fast(st, fl.fast, fl.f, w, dbg, fl.opts);
+        mark(1);
+        launch_duplicate(st, fl.n, fl.f, w, fl.L.fe_blocks, fl.L.key_bytes);
         mark(2);
     } else {
-        launch_frontend_fast(st, fl.fast, fl.f, w, fl.L.fe_blocks, dbg);
+        launch_frontend_fast(st, fl.fast, fl.f, w, fl.L.fe_blocks, dbg, fl.opts);
         mark(1);
         mark(2);
     }
@@ -691,7 +712,7 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
     launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
     mark(4);
     if (fl.path == RGS_PATH_PLAIN) launch_raster_plain(st, fl.f, w, in_b, count);
-    else launch_raster_fast(st, fl.f, w, in_b, count);
+    else launch_raster_fast(st, fl.f, w, in_b, count, fl.opts);
     mark(5);
     if (status) launch_export_status(st, w, status);
     if (result_in_b) *result_in_b = in_b;

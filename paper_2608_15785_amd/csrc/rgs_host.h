@@ -27,7 +27,9 @@ rgs_status ok();
 struct FrameLaunch {
     int device;
     int64_t n;
-    int32_t path;
+    int32_t path;        // RGS_PATH_PLAIN or RGS_PATH_FAST
+    uint32_t opts;       // ablation bits of the fast path (OPT_*)
+    uint32_t path_word;  // the path argument as given, kept in the workspace header
     rgs_plan plan;
     WsLayout L;
     WsDev w;

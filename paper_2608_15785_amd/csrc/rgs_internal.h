@@ -45,8 +45,14 @@ constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
 
 // Plain-format planes (float32, one per scalar, each n_pad long).
+// P_LNO holds ln o rounded to float32 (computed in double on the host); only
+// the fast path's FP16-geometry ablation reads it.
 enum PlainPlane { P_MX = 0, P_MY, P_MZ, P_SX, P_SY, P_SZ, P_QW, P_QX, P_QY, P_QZ, P_OPA, P_SH0,
-                  P_COUNT = P_SH0 + 48 };
+                  P_LNO = P_SH0 + 48, P_COUNT };
+
+// Fast-path ablation bits (the path argument's bits 8..14, shifted down).
+constexpr uint32_t OPT_FASTEXP = 1u, OPT_DUALPIXEL = 2u, OPT_FUSION = 4u, OPT_EXTENT = 8u, OPT_KEY32 = 16u,
+                   OPT_INT8_SH = 32u, OPT_FP16_GEOM = 64u;
 // Fast-format planes (32-bit words, one per plane, each n_pad long).
 //   F_MX..F_MZ   float32 mean
 //   F_QWX, F_QYZ FP16 pairs (w, x), (y, z) of the quaternion
@@ -181,14 +187,14 @@ __host__ __device__ inline bool project_gaussian(const CamDev& c, double mx, dou
                                                  double qw, double qx, double qy, double qz,
                                                  double sx, double sy, double sz, bool fast,
                                                  double lno, double tiles_x, double tiles_y,
-                                                 Projected& o) {
+                                                 Projected& o, bool alpha_extent = true) {
     const double* r = c.r;
     double tx = r[0] * mx + r[1] * my + r[2] * mz + c.t[0];
     double ty = r[3] * mx + r[4] * my + r[5] * mz + c.t[1];
     double d = r[6] * mx + r[7] * my + r[8] * mz + c.t[2];
     o.d = d;
     if (!(d > c.zn && d <= c.zf)) return false;
-    if (fast && !(lno >= -LN255)) return false;
+    if (fast && alpha_extent && !(lno >= -LN255)) return false;
 
     double nn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
     double w = qw / nn, x = qx / nn, y = qy / nn, z = qz / nn;
@@ -256,8 +262,10 @@ __host__ __device__ inline bool project_gaussian(const CamDev& c, double mx, dou
         double tau = 2.0 * (LN255 + lno);
         o.ax = sqrt(tau * c00);
         o.ay = sqrt(tau * c11);
-        hx = fmin(rad, o.ax);
-        hy = fmin(rad, o.ay);
+        if (alpha_extent) {
+            hx = fmin(rad, o.ax);
+            hy = fmin(rad, o.ay);
+        }
     }
     o.x0 = fmax(0.0, floor((u - hx) / 16.0));
     o.x1 = fmin(tiles_x - 1.0, floor((u + hx) / 16.0));
@@ -338,7 +346,7 @@ __host__ __device__ inline uint64_t st_visible(uint64_t s) { return (s >> 32) & 
 // Host-side launch wrappers (defined in the .hip files).
 
 struct PlainSceneDev { const float* base; uint64_t n_pad; int64_t n; };
-struct FastSceneDev { const uint32_t* base; uint64_t n_pad; int64_t n; };
+struct FastSceneDev { const uint32_t* base; uint64_t n_pad; int64_t n; const float* plain; };
 
 // Arguments of the reset kernel: the span it zeroes (header, tile ranges,
 // scan state, digit buckets), the header fields it sets, and the frame's
@@ -366,18 +374,20 @@ const void* reset_kernel();          // host handle of the reset kernel (graph n
 void launch_export_status(hipStream_t s, const WsDev& ws, FrameStatus* dst);
 void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const FrameDev& f,
                              const WsDev& ws, const DebugDev* dbg);
-void launch_duplicate_plain(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws,
-                            uint32_t fe_blocks);
+void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
+                      uint32_t key_bytes);
 void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
-                          uint32_t fe_blocks, const DebugDev* dbg);
+                          uint32_t fe_blocks, const DebugDev* dbg, uint32_t opts);
+void launch_preprocess_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
+                            const DebugDev* dbg, uint32_t opts);
 void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                  uint32_t passes, uint32_t sort_blocks_max, bool* result_in_b);
 void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                    bool result_in_b);
 void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
                          bool count);
-void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                        bool count);
+void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count,
+                        uint32_t opts);
 void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n);
 
 // The n_proc word of a pixel: pairs visited, with this bit set when blending

@@ -218,7 +218,7 @@ rgs_status launch(rgs_server* s, Slot& slot, Workspace* w, const rgs_request& r)
     w->status->done = 0;
     const FrameParams prm = frame_params(&r.camera, r.out_chw);
     if (w->exec) {
-        ResetArgs ra = reset_args(w->fl.w, w->fl.L.zero_end, w->fl.f, (uint32_t)w->fl.path, prm);
+        ResetArgs ra = reset_args(w->fl.w, w->fl.L.zero_end, w->fl.f, w->fl.path_word, prm);
         void* args[] = {&ra};
         hipKernelNodeParams np = w->reset_params;
         np.kernelParams = args;
@@ -278,12 +278,15 @@ rgs_status check_request(const rgs_server* s, const rgs_request& r, double prev_
     if (!r.out_chw) return fail(RGS_E_INVALID, "request output is NULL");
     if (!(std::isfinite(r.arrival) && r.arrival >= prev_arrival))
         return fail(RGS_E_INVALID, "arrivals must be finite, >= 0 and non-decreasing");
-    if (r.path != RGS_PATH_PLAIN && r.path != RGS_PATH_FAST) return fail(RGS_E_INVALID, "bad path %d", r.path);
+    const int32_t base = r.path & 0xff;
+    if ((base != RGS_PATH_PLAIN && base != RGS_PATH_FAST) || (r.path & ~(0xff | RGS_ABLATE_MASK)) ||
+        (base == RGS_PATH_PLAIN && (r.path & RGS_ABLATE_MASK)))
+        return fail(RGS_E_INVALID, "bad path 0x%x", r.path);
     int64_t n = 0;
     uint32_t formats = 0;
     uint64_t bytes = 0;
     rgs_scene_info(r.scene, &n, &formats, &bytes);
-    if (!(formats & (r.path == RGS_PATH_PLAIN ? RGS_FMT_PLAIN : RGS_FMT_FAST)))
+    if (!(formats & (base == RGS_PATH_PLAIN ? RGS_FMT_PLAIN : RGS_FMT_FAST)))
         return fail(RGS_E_INVALID, "request scene lacks the format of its path");
     rgs_plan p;
     rgs_status e = rgs_frame_plan(r.width, r.height, &p);
