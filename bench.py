@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--paths", default="fast,plain")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
+    ap.add_argument("--no-ablation", action="store_true")
+    ap.add_argument("--ablation-steps", type=int, default=100)
     ap.add_argument("--backward-steps", type=int, default=50)
     ap.add_argument("--serve-seconds", type=float, default=1.5, help="schedule length per arrival rate")
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -267,6 +269,29 @@ def serving_section(rgs, wl, torch, dev_scenes, args):
     return out
 
 
+ABLATIONS = ["fastexp", "dualpixel", "fusion", "extent", "key32", "int8sh", "fp16geom"]
+
+
+def ablation_section(R, ds, cam, steps):
+    """The fast path with each of Sec. IV's optimisations removed in turn (and
+    all of them), on the 1M/1080p workload: FPS, stage times, entries, passes."""
+    out = {}
+    paths = ["fast"] + ["fast/no-" + a for a in ABLATIONS] + ["fast/" + "/".join("no-" + a for a in ABLATIONS),
+                                                              "plain"]
+    for path in paths:
+        r = time_path(R, ds, [cam], path, steps, 10, 20)
+        c = frame_counts(R, ds, cam, path)
+        name = "all" if path.count("/") > 1 else path.replace("fast/no-", "no-")
+        out[name] = {"fps": round(r["fps"], 1), "ms_per_frame": round(r["ms_per_frame"], 4),
+                     "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
+                     "n_entries": c["n_entries"], "passes": c["passes"], "pairs_visited": c["pairs_visited"]}
+        log(f"[bench] ablation {path}: {out[name]['fps']} FPS, stages {out[name]['stage_ms']}")
+    base = out["fast"]["fps"]
+    for k, v in out.items():
+        v["fps_vs_fast"] = round(v["fps"] / base, 3)
+    return out
+
+
 def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup):
     """One training step at 1M Gaussians, 1920x1080: write the parameters into the
     device scene, render the plain path, L1 loss gradient against a render of the
@@ -381,6 +406,11 @@ def main():
         res1[path] = r
         log(f"[bench] cfg1 {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
 
+    ablation = None
+    if not args.no_ablation and "fast" in paths:
+        log("[bench] ablation: the fast path without each optimisation, 1M Gaussians at 1080p")
+        ablation = ablation_section(R, ds1, cam1, args.ablation_steps)
+
     diff = None
     if not args.no_backward:
         log("[bench] differentiation: forward + backward, 1M Gaussians at 1080p")
@@ -473,6 +503,8 @@ def main():
         out["serving"] = serving
     if diff is not None:
         out["differentiation"] = diff
+    if ablation is not None:
+        out["ablation_1080p"] = ablation
     print(json.dumps(out), flush=True)
 
 
