@@ -284,10 +284,17 @@ __device__ inline uint32_t block_scan_and_chain(const uint32_t (&count)[FE_ITEMS
 
 // Entry e of the block belongs to the Gaussian j with s_incl[j-1] <= e < s_incl[j]
 // and is the (e - s_incl[j-1])-th tile of j's rectangle in row-major order.
+// Each stored key also counts its digits of radix passes p_first..passes-1
+// into the block's LDS histogram s_h[pass][digit] (the passes before p_first
+// read only the depth bits, which all entries of a Gaussian share: those are
+// counted once per Gaussian by count_depth_digits).  A wave whose stored keys
+// all share a digit adds it once (the high digits of neighbouring entries are
+// often equal, and LDS atomics on one address serialise).
 template <typename KeyT, typename KeyFn>
 __device__ inline void emit_entries(uint32_t total, uint64_t base, const uint32_t* s_incl,
                                     const uint64_t* s_rect, uint32_t first_gauss, int tiles_x,
-                                    uint32_t capacity, KeyT* keys, uint32_t* vals, KeyFn key_of) {
+                                    uint32_t capacity, KeyT* keys, uint32_t* vals, KeyFn key_of,
+                                    uint32_t* s_h, uint32_t p_first, uint32_t passes) {
     for (uint32_t e = threadIdx.x; e < total; e += FE_THREADS) {
         int lo = 0, hi = FE_TILE - 1;
         while (lo < hi) {
@@ -304,10 +311,83 @@ __device__ inline void emit_entries(uint32_t total, uint64_t base, const uint32_
         const uint32_t tx = x0 + local % w;
         const uint32_t tile = ty * (uint32_t)tiles_x + tx;
         const uint64_t pos = base + e;
-        if (pos < capacity) {
-            keys[pos] = key_of(tile, j);
+        const bool stored = pos < capacity;
+        const KeyT key = key_of(tile, j);
+        if (stored) {
+            keys[pos] = key;
             vals[pos] = first_gauss + j;
         }
+        const uint64_t active = __ballot(true);
+        const bool all_stored = __ballot(stored) == active;
+        for (uint32_t p = p_first; p < passes; ++p) {
+            const uint32_t dg = (uint32_t)(key >> (RADIX_BITS * p)) & (RADIX - 1);
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+            if (all_stored && __ballot(dg == d0) == active) {
+                if (lane_id() == (uint32_t)__builtin_ctzll(active))
+                    atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(active));
+            } else if (stored) {
+                atomicAdd(&s_h[p * RADIX + dg], 1u);
+            }
+        }
+    }
+}
+
+// The radix sort's inputs that the front end prepares alongside the keys:
+// digit counts (the block's LDS histogram added into histogram copy
+// vb % HIST_COPIES) and zeroed look-back words of the first pass for every
+// radix tile that starts inside this block's entries.  Call after the emission
+// and a barrier.
+template <typename KeyT>
+__device__ inline void prepare_sort(WsDev& ws, const uint32_t* s_h, uint32_t passes, uint32_t vb, uint64_t base,
+                                    uint32_t total) {
+    uint32_t* copy = ws.hist + (uint64_t)(vb % HIST_COPIES) * MAX_PASSES * RADIX;
+    for (uint32_t i = threadIdx.x; i < passes * RADIX; i += FE_THREADS) {
+        const uint32_t c = s_h[i];
+        if (c) atomicAdd(&copy[i], c);
+    }
+    constexpr uint64_t SIZE = SortTile<KeyT>::SIZE;
+    const uint64_t t0 = (base + SIZE - 1) / SIZE;
+    uint64_t t1 = (base + total + SIZE - 1) / SIZE;
+    if (t1 > ws.sort_rows) t1 = ws.sort_rows;
+    uint32_t* tiles = sort_state_tiles(ws, 0);
+    uint32_t* groups = sort_state_groups(ws, 0);
+    for (uint64_t t = t0; t < t1; ++t) {
+        for (uint32_t i = threadIdx.x; i < RADIX; i += FE_THREADS) {
+            st_state(&tiles[t * RADIX + i], 0u);
+            if (t % SORT_GROUP == 0) st_state(&groups[(t / SORT_GROUP) * RADIX + i], 0u);
+        }
+    }
+}
+
+__device__ inline void zero_hist(uint32_t* s_h) {
+    for (uint32_t i = threadIdx.x; i < MAX_PASSES * RADIX; i += FE_THREADS) s_h[i] = 0;
+}
+
+// Radix passes whose digit lies wholly below bit `shift` of the key (the depth
+// bits) come first; their digits are the same for all entries of a Gaussian.
+__device__ inline uint32_t depth_only_passes(uint32_t shift, uint32_t passes) {
+    const uint32_t p = shift / RADIX_BITS;
+    return p < passes ? p : passes;
+}
+
+// The entries of a block's Gaussian j share its depth bits low[j]: add the
+// digits of the depth-only passes once per Gaussian, weighted by how many of
+// its entries fit in the workspace (entries at or past `capacity` are not
+// stored, and the sort counts only stored keys).
+__device__ inline void count_depth_digits(uint32_t* s_h, const uint32_t (&count)[FE_ITEMS], const uint32_t* low,
+                                          const uint32_t* s_incl, uint64_t base, uint32_t capacity,
+                                          uint32_t p_depth) {
+    if (p_depth == 0) return;
+#pragma unroll
+    for (int k = 0; k < FE_ITEMS; ++k) {
+        const uint32_t j = k * FE_THREADS + threadIdx.x;
+        if (!count[k]) continue;
+        const uint64_t start = base + (j ? s_incl[j - 1] : 0u);
+        const uint64_t room = start < capacity ? capacity - start : 0u;
+        const uint32_t stored = room < count[k] ? (uint32_t)room : count[k];
+        if (!stored) continue;
+        for (uint32_t p = 0; p < p_depth; ++p)
+            atomicAdd(&s_h[p * RADIX + ((low[j] >> (RADIX_BITS * p)) & (RADIX - 1))], stored);
     }
 }
 
@@ -391,9 +471,12 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
     __shared__ uint32_t s_wtot[FE_THREADS / 64];
     __shared__ uint32_t s_wvis[FE_THREADS / 64];
     __shared__ uint64_t s_base, s_base_v;
+    __shared__ uint32_t s_h[MAX_PASSES * RADIX];
     if (threadIdx.x == 0) s_vb = atomicAdd(&ws.header->fe_ticket, 1u);
+    zero_hist(s_h);
     __syncthreads();
     const uint32_t vb = s_vb;
+    const uint32_t p_depth = depth_only_passes(shift, (uint32_t)f.passes);
     uint32_t count[FE_ITEMS];
     uint32_t n_vis = 0;
 #pragma unroll
@@ -422,9 +505,13 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
         const int64_t i = (int64_t)vb * FE_TILE + j;
         if (i < n && count[k]) ws.offsets[i] = (uint32_t)(base + (j ? s_incl[j - 1] : 0u));
     }
+    count_depth_digits(s_h, count, s_dbits, s_incl, base, f.capacity, p_depth);
     emit_entries<KeyT>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
                        reinterpret_cast<KeyT*>(ws.keys_a), ws.vals_a,
-                       [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_dbits[j]; });
+                       [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_dbits[j]; },
+                       s_h, p_depth, (uint32_t)f.passes);
+    __syncthreads();
+    prepare_sort<KeyT>(ws, s_h, (uint32_t)f.passes, vb, base, total);
     finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
 }
 
@@ -531,9 +618,13 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
     __shared__ uint32_t s_wtot[FE_THREADS / 64];
     __shared__ uint32_t s_wvis[FE_THREADS / 64];
     __shared__ uint64_t s_base, s_base_v;
+    __shared__ uint32_t s_h[MAX_PASSES * RADIX];
     if (threadIdx.x == 0) s_vb = atomicAdd(&ws.header->fe_ticket, 1u);
+    zero_hist(s_h);
     __syncthreads();
     const uint32_t vb = s_vb;
+    const uint32_t shift = sizeof(KeyT) == 8 ? 32u : (uint32_t)f.b_d;
+    const uint32_t p_depth = depth_only_passes(shift, (uint32_t)f.passes);
     uint32_t count[FE_ITEMS];
     uint32_t n_vis = 0;
 #pragma unroll
@@ -556,10 +647,13 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
     const uint32_t total = block_scan_and_chain(count, n_vis, vb, ws, s_incl, s_wtot, s_wvis, &s_base,
                                                 &s_base_v, &vis_total);
     const uint64_t base = s_base;
-    const uint32_t shift = sizeof(KeyT) == 8 ? 32u : (uint32_t)f.b_d;
+    count_depth_digits(s_h, count, s_qd, s_incl, base, f.capacity, p_depth);
     emit_entries<KeyT>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
                        reinterpret_cast<KeyT*>(ws.keys_a), ws.vals_a,
-                       [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_qd[j]; });
+                       [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_qd[j]; },
+                       s_h, p_depth, (uint32_t)f.passes);
+    __syncthreads();
+    prepare_sort<KeyT>(ws, s_h, (uint32_t)f.passes, vb, base, total);
     finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
 }
 

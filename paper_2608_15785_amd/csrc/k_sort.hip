@@ -3,20 +3,26 @@
 // LSD radix sort with 8-bit digits over the significant bits of the key
 // (plain: 32 + b_t bits of the 64-bit key; fast: the 32-bit key, 4 passes),
 // value = Gaussian index.  Eq. sort_memory counts one read and one write of
-// every (key, value) entry per pass.  A frame's whole grid of radix tiles is
-// resident on the 256 CUs at once, so the tiles cannot pass digit offsets
-// along a look-back chain without waiting on each other; each pass is instead
-// a reduce-then-scan:
-//   * `radix_upsweep` counts each radix tile's digits (keys only; 4096-entry
-//     tiles for 32-bit keys, 2048 for 64-bit keys);
-//   * `radix_offsets` scans, for each digit in its own workgroup, the tiles'
-//     counts into the tile's offset inside that digit's bucket, and records
-//     the bucket's size;
-//   * `radix_scatter` turns the 256 bucket sizes into bucket bases (one block
-//     scan), ranks each key among equal digits of its tile with wave64 ballots
-//     (stable: tile order is input order), reorders the tile in LDS by digit
-//     and writes it out, so consecutive threads store consecutive positions of
-//     a digit bucket.
+// every (key, value) entry per pass.
+//
+// The kernel that writes the keys (the front end) also counts every pass's
+// digits into the workspace histogram and clears the first pass's look-back
+// words; each pass is then one kernel over radix tiles of 4096 keys:
+//   * a tile takes its index from a ticket counter, loads its keys, ranks each
+//     key among equal digits of the tile with wave64 ballots (stable: tile
+//     order is input order) and publishes its 256 digit counts;
+//   * it then sums the counts of the tiles before it: the earlier tiles of its
+//     group of SORT_GROUP, and one published total per earlier group (the last
+//     tile of a group publishes the group's total).  A frame's tiles are all
+//     resident at once and publish at about the same time; this two-level sum
+//     keeps every tile's wait at two round trips instead of a chain through all
+//     its predecessors;
+//   * it reorders the tile in LDS by digit and writes it out, so consecutive
+//     threads store consecutive positions of a digit bucket.
+// A tile only waits on tiles with smaller tickets, which are already running,
+// so the passes cannot deadlock however many tiles are resident.  The two sets
+// of look-back words alternate between passes: a pass clears its tile's words
+// of the set the next pass uses.
 // Ties keep input order, and the front end emits entries in Gaussian-index
 // order, so equal keys end ordered by Gaussian index.
 //
@@ -38,165 +44,179 @@ __device__ inline uint32_t entry_count(const WsHeader* h) {
     return (uint32_t)(n < cap ? n : cap);
 }
 
-// Inclusive scan over a 256-thread block (one value per thread).
-__device__ inline uint32_t block256_inclusive_scan(uint32_t x, uint32_t* s_wtot) {
-    uint32_t lane = lane_id(), wave = threadIdx.x / 64;
-    uint32_t incl = wave_inclusive_scan(x);
-    if (lane == 63) s_wtot[wave] = incl;
+constexpr uint32_t SORT_READY = 0x80000000u;   // look-back word: published
+constexpr int SORT_WAVES = SORT_THREADS / 64;
+constexpr uint32_t SORT_SPLIT = SORT_THREADS / RADIX;   // threads per digit in the look-back
+static_assert(SORT_THREADS % RADIX == 0 && SORT_THREADS >= RADIX, "whole digit rows per block");
+
+// Exclusive scan of one value per digit (threads 0..RADIX-1; other threads
+// pass anything and get an unspecified result).  Every thread of the block
+// must call it: it holds two barriers.
+__device__ inline uint32_t digit_exclusive_scan(uint32_t x, uint32_t* s_wtot) {
+    const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
+    const uint32_t incl = wave_inclusive_scan(x);
+    if (lane == 63 && wave < RADIX / 64) s_wtot[wave] = incl;
     __syncthreads();
     uint32_t before = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w)
+    for (int w = 0; w < RADIX / 64; ++w)
         if ((uint32_t)w < wave) before += s_wtot[w];
     __syncthreads();
-    return incl + before;
+    return incl - x + before;
 }
 
-// Per-tile digit counts, digit-major: counts[d * nb_max + tile].
-template <typename KeyT>
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_upsweep(const KeyT* __restrict__ kin, WsDev ws,
-                                                                uint32_t shift, uint32_t nb_max) {
-    __shared__ uint32_t s_h[RADIX];
-    s_h[threadIdx.x] = 0;
-    __syncthreads();
-    const uint32_t n = entry_count(ws.header);
-    constexpr int SORT_ITEMS = SortTile<KeyT>::ITEMS;
-    constexpr int SORT_TILE = SortTile<KeyT>::SIZE;
-    const uint32_t tile_base = blockIdx.x * SORT_TILE;
-    if (tile_base >= n) return;
-    KeyT k[SORT_ITEMS];
+// Sum over rows r0 + s, r0 + s + SORT_SPLIT, ... < r1 of column d of a
+// look-back table, waiting for each word's ready flag (bounded: on giving up
+// the header's error bit 3 is set and the word counts as zero).
+__device__ inline uint32_t lookback_sum(const uint32_t* tab, uint32_t r0, uint32_t r1, uint32_t s, uint32_t d,
+                                        WsHeader* hdr) {
+    constexpr int BATCH = 16;
+    uint32_t sum = 0;
+    for (uint32_t r = r0 + s; r < r1; r += BATCH * SORT_SPLIT) {
+        uint32_t v[BATCH];
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-        const uint32_t idx = tile_base + r * SORT_THREADS + threadIdx.x;
-        k[r] = idx < n ? kin[idx] : (KeyT)0;
-    }
-#pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r)
-        if (tile_base + r * SORT_THREADS + threadIdx.x < n) atomicAdd(&s_h[digit_of(k[r], shift)], 1u);
-    __syncthreads();
-    ws.tile_counts[(uint64_t)threadIdx.x * nb_max + blockIdx.x] = s_h[threadIdx.x];
-}
-
-// Digit d (one workgroup each): exclusive scan of its per-tile counts, in
-// place, and the size of the digit's bucket.  Each thread scans a contiguous
-// chunk of the row in registers; one block scan joins the chunks.
-constexpr int OFFSETS_CHUNK = 16;
-
-__global__ __launch_bounds__(256) void k_radix_offsets(WsDev ws, uint32_t nb_max, uint32_t tile_size) {
-    __shared__ uint32_t s_wtot[4];
-    const uint32_t d = blockIdx.x;
-    const uint32_t n = entry_count(ws.header);
-    const uint32_t nb = (n + tile_size - 1) / tile_size;
-    uint32_t* row = ws.tile_counts + (uint64_t)d * nb_max;
-    uint32_t carry = 0;
-    for (uint32_t c0 = 0; c0 < nb; c0 += 256 * OFFSETS_CHUNK) {
-        const uint32_t b = c0 + threadIdx.x * OFFSETS_CHUNK;
-        uint32_t v[OFFSETS_CHUNK];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int k = 0; k < OFFSETS_CHUNK; ++k) {
-            v[k] = b + k < nb ? row[b + k] : 0u;
-            sum += v[k];
+        for (int m = 0; m < BATCH; ++m) {
+            const uint32_t rr = r + m * SORT_SPLIT;
+            v[m] = rr < r1 ? ld_state(&tab[(uint64_t)rr * RADIX + d]) : SORT_READY;
         }
-        const uint32_t incl = block256_inclusive_scan(sum, s_wtot);
-        uint32_t run = carry + incl - sum;
 #pragma unroll
-        for (int k = 0; k < OFFSETS_CHUNK; ++k) {
-            if (b + k < nb) row[b + k] = run;
-            run += v[k];
+        for (int m = 0; m < BATCH; ++m) {
+            const uint32_t rr = r + m * SORT_SPLIT;
+            uint32_t spins = 0;
+            while (!(v[m] & SORT_READY)) {
+                if (++spins > SPIN_LIMIT) {
+                    atomicOr(&hdr->error, 8u);
+                    v[m] = SORT_READY;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                v[m] = ld_state(&tab[(uint64_t)rr * RADIX + d]);
+            }
+            sum += v[m] & ~SORT_READY;
         }
-        carry += s_wtot[0] + s_wtot[1] + s_wtot[2] + s_wtot[3];
-        __syncthreads();
     }
-    if (threadIdx.x == 0) ws.hist[d] = carry;
+    return sum;
 }
 
 template <typename KeyT>
-__global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const KeyT* __restrict__ kin,
-                                                                const uint32_t* __restrict__ vin,
-                                                                KeyT* __restrict__ kout,
-                                                                uint32_t* __restrict__ vout, WsDev ws,
-                                                                uint32_t shift, uint32_t nb_max) {
-    constexpr int WAVES = SORT_THREADS / 64;
-    constexpr int SORT_ITEMS = SortTile<KeyT>::ITEMS;
-    constexpr int SORT_TILE = SortTile<KeyT>::SIZE;
-    static_assert(SORT_THREADS == RADIX, "one thread per digit");
-    __shared__ uint32_t s_whist[WAVES * RADIX];
-    __shared__ uint32_t s_bstart[RADIX];
-    __shared__ uint32_t s_gbase[RADIX];
-    __shared__ uint32_t s_wtot[4];
-    __shared__ KeyT s_keys[SORT_TILE];
-    __shared__ uint32_t s_vals[SORT_TILE];
+__global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restrict__ kin,
+                                                             const uint32_t* __restrict__ vin,
+                                                             KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                             WsDev ws, uint32_t pass) {
+    constexpr int ITEMS = SortTile<KeyT>::ITEMS;
+    constexpr int SIZE = SortTile<KeyT>::SIZE;
+    // per-wave digit counts, then each wave's offset inside the tile's digit
+    // run; reused for the look-back's partial sums once the tile is reordered
+    __shared__ uint32_t s_whist[SORT_WAVES * RADIX];
+    __shared__ uint32_t s_bstart[RADIX];   // first LDS position of digit d in the reordered tile
+    __shared__ uint32_t s_gbase[RADIX];    // bucket base of d, then output position minus s_bstart[d]
+    __shared__ uint32_t s_tot[RADIX];      // the tile's count of digit d
+    __shared__ uint32_t s_wtot[RADIX / 64];
+    __shared__ uint32_t s_vb;
+    __shared__ KeyT s_keys[SIZE];
+    __shared__ uint32_t s_vals[SIZE];
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
-    const uint32_t vb = blockIdx.x;
+    // only the first ceil(n / SIZE) blocks take a ticket (tickets on one
+    // address serialise); the others have no tile
     const uint32_t n = entry_count(ws.header);
-    const uint32_t tile_base = vb * SORT_TILE;
-    if (tile_base >= n) return;
-    for (uint32_t i = tid; i < WAVES * RADIX; i += SORT_THREADS) s_whist[i] = 0;
+    if (blockIdx.x * SIZE >= n) return;
+    if (tid == 0) s_vb = atomicAdd(&ws.header->sort_ticket[pass], 1u);
+    for (uint32_t i = tid; i < SORT_WAVES * RADIX; i += SORT_THREADS) s_whist[i] = 0;
     __syncthreads();
-    const uint32_t n_valid = min((uint32_t)SORT_TILE, n - tile_base);
-    // this tile's offset inside digit tid's bucket and the bucket's size do not
-    // depend on the keys: start both loads before the keys'
-    const uint32_t tile_off = ws.tile_counts[(uint64_t)tid * nb_max + vb];
-    const uint32_t bucket = ws.hist[tid];
+    const uint32_t vb = s_vb;
+    const uint32_t tile_base = vb * SIZE;
+    if (tile_base >= n) return;      // cannot happen: tickets stop at the number of blocks that take one
+    const uint32_t shift = 8 * pass;
+    const uint32_t n_valid = min((uint32_t)SIZE, n - tile_base);
+    uint32_t* cur_tiles = sort_state_tiles(ws, pass & 1);
+    uint32_t* cur_groups = sort_state_groups(ws, pass & 1);
+    // the bucket sizes do not depend on this tile: start the loads first
+    uint32_t bucket = 0;
+    if (tid < RADIX) {
+#pragma unroll
+        for (int c = 0; c < HIST_COPIES; ++c) bucket += ws.hist[((uint64_t)c * MAX_PASSES + pass) * RADIX + tid];
+    }
 
     // wave w owns entries [tile_base + w*ITEMS*64, +ITEMS*64); round r, lane l
     // holds entry tile_base + w*ITEMS*64 + r*64 + l
-    const uint32_t wbase = tile_base + wave * (SORT_ITEMS * 64);
-    KeyT k[SORT_ITEMS];
-    uint32_t v[SORT_ITEMS];
-    uint32_t rank[SORT_ITEMS];
+    const uint32_t wbase = tile_base + wave * (ITEMS * 64);
+    KeyT k[ITEMS];
+    uint32_t v[ITEMS];
+    uint32_t rank[ITEMS];
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = wbase + r * 64 + lane;
         const bool valid = idx < n;
         k[r] = valid ? kin[idx] : (KeyT)0;
         v[r] = valid ? vin[idx] : 0u;
     }
+    // the next pass's look-back words of this tile (its set was last read by
+    // the previous pass, which has finished)
+    if (tid < RADIX) {
+        st_state(&sort_state_tiles(ws, (pass + 1) & 1)[(uint64_t)vb * RADIX + tid], 0u);
+        if (vb % SORT_GROUP == 0)
+            st_state(&sort_state_groups(ws, (pass + 1) & 1)[(uint64_t)(vb / SORT_GROUP) * RADIX + tid], 0u);
+    }
     const uint64_t lt = lanemask_lt();
-    // lanes of a wave read counters that other lanes of the same wave wrote in
-    // the previous round (LDS keeps one wave's accesses in order); volatile
-    // keeps the compiler from reusing an earlier read
-    volatile uint32_t* my_hist = s_whist + wave * RADIX;
+    // Lanes of a wave read counters that other lanes of the same wave wrote in
+    // the previous round.  The LDS unit executes one wave's accesses in issue
+    // order; the empty asm with a memory clobber keeps the compiler from
+    // moving or reusing accesses across rounds.  (A volatile pointer would do
+    // the same but loses the LDS address space: every access becomes a flat
+    // access that waits on all outstanding global memory operations.)
+    uint32_t* my_hist = s_whist + wave * RADIX;
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
+        asm volatile("" ::: "memory");
         const uint32_t idx = wbase + r * 64 + lane;
         const bool valid = idx < n;
         const uint32_t d = digit_of(k[r], shift);
-        uint64_t peers = __ballot(valid);
+        // lanes whose digit differs from this lane's: for each bit b the
+        // ballot M_b of lanes holding a 1, XOR-ed with this lane's bit spread
+        // to a whole word (0 or all ones), marks the lanes that disagree on b.
+        // One three-input bit operation per half-mask folds M_b ^ spread into
+        // the running OR (truth table 0xBE: S2 | (S0 ^ S1)).
+        uint32_t diff_lo = 0, diff_hi = 0;
 #pragma unroll
         for (int b = 0; b < RADIX_BITS; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(bit);
-            peers &= bit ? m : ~m;
+            const uint32_t spread = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+            const uint64_t m = __ballot(spread != 0);
+            diff_lo = __builtin_amdgcn_bitop3_b32((uint32_t)m, spread, diff_lo, 0xBE);
+            diff_hi = __builtin_amdgcn_bitop3_b32((uint32_t)(m >> 32), spread, diff_hi, 0xBE);
         }
-        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint64_t vmask = __ballot(valid);
+        const uint32_t peers_lo = ~diff_lo & (uint32_t)vmask, peers_hi = ~diff_hi & (uint32_t)(vmask >> 32);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
         const uint32_t prev = valid ? my_hist[d] : 0u;
         rank[r] = prev + below;
-        if (valid && below == 0) my_hist[d] = prev + (uint32_t)__popcll(peers);
+        if (valid && below == 0) my_hist[d] = prev + (uint32_t)(__popc(peers_lo) + __popc(peers_hi));
     }
     __syncthreads();
 
-    // digit d = tid: wave offsets, tile count, tile-local start, global base
-    {
-        const uint32_t d = tid;
-        uint32_t tot = 0;
+    // digit d = tid: wave offsets and the tile's count, published at once
+    uint32_t tot = 0;
+    if (tid < RADIX) {
 #pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-            const uint32_t c = s_whist[w * RADIX + d];
-            s_whist[w * RADIX + d] = tot;
+        for (int w = 0; w < SORT_WAVES; ++w) {
+            const uint32_t c = s_whist[w * RADIX + tid];
+            s_whist[w * RADIX + tid] = tot;
             tot += c;
         }
-        const uint32_t incl = block256_inclusive_scan(tot, s_wtot);
-        s_bstart[d] = incl - tot;
-        const uint32_t bincl = block256_inclusive_scan(bucket, s_wtot);
-        s_gbase[d] = (bincl - bucket) + tile_off - (incl - tot);
+        st_state(&cur_tiles[(uint64_t)vb * RADIX + tid], SORT_READY | tot);
+        s_tot[tid] = tot;
+    }
+    const uint32_t bstart = digit_exclusive_scan(tot, s_wtot);
+    const uint32_t bbase = digit_exclusive_scan(bucket, s_wtot);
+    if (tid < RADIX) {
+        s_bstart[tid] = bstart;
+        s_gbase[tid] = bbase;
     }
     __syncthreads();
 
+    // reorder the tile by digit in LDS
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
         const uint32_t idx = wbase + r * 64 + lane;
         if (idx < n) {
             const uint32_t d = digit_of(k[r], shift);
@@ -206,6 +226,36 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const KeyT* __re
         }
     }
     __syncthreads();
+
+    // keys of digit d in earlier tiles: SORT_SPLIT threads per digit share the rows
+    const uint32_t d = tid % RADIX, s = tid / RADIX;
+    const uint32_t g = vb / SORT_GROUP, g0 = g * SORT_GROUP;
+    uint32_t* s_part = s_whist;    // [SORT_SPLIT][RADIX]
+    uint32_t part = lookback_sum(cur_tiles, g0, vb, s, d, ws.header);
+    if (vb % SORT_GROUP == SORT_GROUP - 1) {
+        // last tile of its group: publish the group's counts before reading
+        // the earlier groups, so that later groups wait as little as possible
+        s_part[s * RADIX + d] = part;
+        __syncthreads();
+        if (tid < RADIX) {
+            uint32_t gsum = s_tot[tid];
+#pragma unroll
+            for (uint32_t q = 0; q < SORT_SPLIT; ++q) gsum += s_part[q * RADIX + tid];
+            st_state(&cur_groups[(uint64_t)g * RADIX + tid], SORT_READY | gsum);
+        }
+        __syncthreads();
+    }
+    part += lookback_sum(cur_groups, 0, g, s, d, ws.header);
+    s_part[s * RADIX + d] = part;
+    __syncthreads();
+    if (tid < RADIX) {
+        uint32_t before = 0;
+#pragma unroll
+        for (uint32_t q = 0; q < SORT_SPLIT; ++q) before += s_part[q * RADIX + tid];
+        s_gbase[tid] = s_gbase[tid] + before - s_bstart[tid];
+    }
+    __syncthreads();
+
     for (uint32_t p = tid; p < n_valid; p += SORT_THREADS) {
         const KeyT kk = s_keys[p];
         const uint32_t dst = s_gbase[digit_of(kk, shift)] + p;
@@ -217,29 +267,24 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_scatter(const KeyT* __re
 }
 
 template <typename KeyT>
-static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, uint32_t nb_max,
-                       bool* result_in_b) {
+static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, bool* result_in_b) {
     KeyT* ka = reinterpret_cast<KeyT*>(ws.keys_a);
     KeyT* kb = reinterpret_cast<KeyT*>(ws.keys_b);
+    const dim3 grid(ws.sort_rows), block(SORT_THREADS);
     for (uint32_t p = 0; p < passes; ++p) {
         const bool from_a = (p % 2) == 0;
-        const KeyT* kin = from_a ? ka : kb;
-        hipLaunchKernelGGL(k_radix_upsweep<KeyT>, dim3(nb_max), dim3(SORT_THREADS), 0, s, kin, ws, 8 * p,
-                           nb_max);
-        hipLaunchKernelGGL(k_radix_offsets, dim3(RADIX), dim3(256), 0, s, ws, nb_max,
-                           (uint32_t)SortTile<KeyT>::SIZE);
-        hipLaunchKernelGGL(k_radix_scatter<KeyT>, dim3(nb_max), dim3(SORT_THREADS), 0, s, kin,
+        hipLaunchKernelGGL(k_radix_pass<KeyT>, grid, block, 0, s, from_a ? ka : kb,
                            from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
-                           ws, 8 * p, nb_max);
+                           ws, p);
     }
     *result_in_b = (passes % 2) == 1;
 }
 
-void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
-                 uint32_t passes, uint32_t sort_blocks_max, bool* result_in_b) {
+void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes, uint32_t passes,
+                 bool* result_in_b) {
     (void)f;
-    if (key_bytes == 8) sort_typed<uint64_t>(s, ws, passes, sort_blocks_max, result_in_b);
-    else sort_typed<uint32_t>(s, ws, passes, sort_blocks_max, result_in_b);
+    if (key_bytes == 8) sort_typed<uint64_t>(s, ws, passes, result_in_b);
+    else sort_typed<uint32_t>(s, ws, passes, result_in_b);
 }
 
 // ---------------------------------------------------------------------------

@@ -444,7 +444,7 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     L.fe_state = off;
     off = align256(off + (uint64_t)L.fe_blocks * 8);
     L.hist = off;
-    off = align256(off + (uint64_t)MAX_PASSES * RADIX * 4);
+    off = align256(off + (uint64_t)HIST_COPIES * MAX_PASSES * RADIX * 4);
     L.zero_end = off;
     L.params = off;                  // written by the reset kernel, outside the zeroed span
     off = align256(off + sizeof(FrameParams));
@@ -469,8 +469,11 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     off = align256(off + capacity * 4);
     L.vals_b = off;
     off = align256(off + capacity * 4);
-    L.tile_counts = off;
-    off = align256(off + (uint64_t)L.sort_blocks_max * RADIX * 4);
+    L.sort_state = off;
+    {
+        const uint64_t groups = (L.sort_blocks_max + SORT_GROUP - 1) / SORT_GROUP;
+        off = align256(off + 2 * ((uint64_t)L.sort_blocks_max + groups) * RADIX * 4);
+    }
     L.t_final = off;
     off = align256(off + (uint64_t)p.width * p.height * 4);
     L.n_proc = off;
@@ -549,7 +552,9 @@ static WsDev ws_pointers(void* base, const WsLayout& L) {
     w.vals_a = reinterpret_cast<uint32_t*>(b + L.vals_a);
     w.vals_b = reinterpret_cast<uint32_t*>(b + L.vals_b);
     w.hist = reinterpret_cast<uint32_t*>(b + L.hist);
-    w.tile_counts = reinterpret_cast<uint32_t*>(b + L.tile_counts);
+    w.sort_state = reinterpret_cast<uint32_t*>(b + L.sort_state);
+    w.sort_rows = L.sort_blocks_max;
+    w.sort_groups = (L.sort_blocks_max + SORT_GROUP - 1) / SORT_GROUP;
     w.t_final = reinterpret_cast<float*>(b + L.t_final);
     w.n_proc = reinterpret_cast<uint32_t*>(b + L.n_proc);
     w.n_blend = reinterpret_cast<uint32_t*>(b + L.n_blend);
@@ -707,7 +712,7 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
         if (s != RGS_OK) return s;
     }
     bool in_b = false;
-    launch_sort(st, fl.f, w, fl.L.key_bytes, fl.L.passes, fl.L.sort_blocks_max, &in_b);
+    launch_sort(st, fl.f, w, fl.L.key_bytes, fl.L.passes, &in_b);
     mark(3);
     launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
     mark(4);

@@ -29,20 +29,29 @@ constexpr int FE_THREADS = 1024;     // threads per front-end / duplication bloc
 constexpr int FE_ITEMS = 2;          // Gaussians per thread (block-strided)
 constexpr int FE_TILE = FE_THREADS * FE_ITEMS;   // Gaussians per block
 constexpr int LB_PER_LANE = 8;       // look-back states each lane polls per round trip
-constexpr int SORT_THREADS = 256;    // 4 waves
-// Keys per thread of a radix tile: 16 for 32-bit keys (4096-key tiles), 8 for
-// 64-bit keys (2048-key tiles, which keep the scatter's LDS at 24 KB).
+constexpr int SORT_THREADS = 512;    // 8 waves per radix tile
+// Keys per thread of a radix tile: 8, so a tile is 4096 keys.  A 32-bit tile's
+// LDS (keys, values, per-wave digit counts) is 43 KB and a 64-bit tile's 59 KB:
+// three or two tiles share a CU, and a frame's tiles are spread evenly.
 template <typename KeyT>
 struct SortTile {
-    static constexpr int ITEMS = sizeof(KeyT) == 8 ? 8 : 16;
+    static constexpr int ITEMS = 8;
     static constexpr int SIZE = SORT_THREADS * ITEMS;
 };
 inline uint32_t sort_tile_size(uint32_t key_bytes) {
     return key_bytes == 8 ? (uint32_t)SortTile<uint64_t>::SIZE : (uint32_t)SortTile<uint32_t>::SIZE;
 }
+// Radix tiles per look-back group: the last tile of each group publishes the
+// group's digit counts, so a tile reads at most SORT_GROUP - 1 tile states plus
+// one state per earlier group.
+constexpr uint32_t SORT_GROUP = 16;
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
+// Copies of the digit histogram that the histogram kernel's blocks spread
+// their atomics over (block b adds into copy b % HIST_COPIES): device-scope
+// atomics on one address serialise at about 11 ns each.
+constexpr int HIST_COPIES = 16;
 
 // Plain-format planes (float32, one per scalar, each n_pad long).
 // P_LNO holds ln o rounded to float32 (computed in double on the host); only
@@ -116,12 +125,14 @@ struct WsHeader {
     uint32_t n_visible;
     uint32_t overflow;
     uint32_t error;           // bit 0: front-end look-back gave up;
-                              // bit 2: a sorted key named a tile outside the grid
+                              // bit 2: a sorted key named a tile outside the grid;
+                              // bit 3: a sort pass's look-back gave up
     uint32_t capacity;
     uint32_t path;
     uint32_t passes;
     uint32_t fe_ticket;
-    uint32_t pad[55];
+    uint32_t sort_ticket[8];  // radix tiles handed out per sort pass
+    uint32_t pad[47];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte slot");
 
@@ -131,11 +142,11 @@ struct WsLayout {
     uint64_t header, ranges, fe_state, zero_end;
     uint64_t records, counts, rects, depths, offsets;
     uint64_t keys_a, keys_b, vals_a, vals_b;
-    uint64_t hist, tile_counts;
+    uint64_t hist, sort_state;
     uint64_t t_final, n_proc, n_blend;
     uint64_t total;
     uint64_t capacity;
-    uint32_t key_bytes, passes, fe_blocks, sort_blocks_max;
+    uint32_t key_bytes, passes, fe_blocks, sort_blocks_max;   // sort_blocks_max: radix tiles at capacity
 };
 
 // Pointers a kernel needs into the workspace.
@@ -153,8 +164,11 @@ struct WsDev {
     void* keys_b;
     uint32_t* vals_a;
     uint32_t* vals_b;
-    uint32_t* hist;           // [RADIX] digit bucket sizes of the current radix pass
-    uint32_t* tile_counts;    // [RADIX][sort tiles]: per-tile digit counts, then offsets
+    uint32_t* hist;           // [HIST_COPIES][MAX_PASSES][RADIX] digit counts of every radix pass
+    uint32_t* sort_state;     // 2 x [sort_rows + sort_groups][RADIX] look-back words, one set per
+                              // pass parity: ready flag (bit 31) | digit count
+    uint32_t sort_rows;       // radix tiles at capacity
+    uint32_t sort_groups;     // ceil(sort_rows / SORT_GROUP)
     float* t_final;           // [H][W]
     uint32_t* n_proc;         // [H][W] list entries visited per pixel
     uint32_t* n_blend;        // [H][W] pairs blended per pixel (written by counting renders)
@@ -327,6 +341,16 @@ __device__ inline void st_state(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Look-back word sets of the sort: set 0 serves even passes, set 1 odd passes.
+// Each set holds sort_rows tile rows, then sort_groups group rows, of RADIX
+// words.
+__device__ inline uint32_t* sort_state_tiles(const WsDev& ws, uint32_t set) {
+    return ws.sort_state + (uint64_t)set * ((uint64_t)ws.sort_rows + ws.sort_groups) * RADIX;
+}
+__device__ inline uint32_t* sort_state_groups(const WsDev& ws, uint32_t set) {
+    return sort_state_tiles(ws, set) + (uint64_t)ws.sort_rows * RADIX;
+}
+
 // Bounded waits: a look-back that polls this often without progress gives up,
 // flags the header and lets the kernel finish.
 constexpr uint32_t SPIN_LIMIT = 1u << 22;
@@ -380,8 +404,8 @@ void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev&
                           uint32_t fe_blocks, const DebugDev* dbg, uint32_t opts);
 void launch_preprocess_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
                             const DebugDev* dbg, uint32_t opts);
-void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
-                 uint32_t passes, uint32_t sort_blocks_max, bool* result_in_b);
+void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes, uint32_t passes,
+                 bool* result_in_b);
 void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                    bool result_in_b);
 void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
