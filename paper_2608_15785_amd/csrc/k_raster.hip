@@ -271,12 +271,14 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
         __syncthreads();
 
         // ---- blend this wave's list ----
-        const uint32_t n = wave ? n1 : n0;
+        // (the list length is the same for the whole wave: keep it scalar)
+        const uint32_t n = __builtin_amdgcn_readfirstlane(wave ? n1 : n0);
         const float4* __restrict__ la = s_a[wave];
         const float4* __restrict__ lb = s_b[wave];
         const float2* __restrict__ lc = s_c[wave];
         if (__ballot(live0 || live1) != 0) {
-            for (uint32_t k0 = 0; k0 < n; k0 += LIST_UNROLL) {
+            bool wave_done = false;     // every pixel of the wave has stopped
+            for (uint32_t k0 = 0; k0 < n && !wave_done; k0 += LIST_UNROLL) {
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) {
                     const float4 a = la[k0 + u];
@@ -291,10 +293,12 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
                         al0 = pass0 ? fminf(ALPHA_MAX, expf(P0)) : 0.0f;
                         al1 = pass1 ? fminf(ALPHA_MAX, expf(P1)) : 0.0f;
                     } else {
-                        const int I0 = min((int)fmaf(P0, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
-                        const int I1 = min((int)fmaf(P1, FEXP_A, FEXP_B), ALPHA_MAX_BITS);
-                        al0 = pass0 ? __int_as_float(I0) : 0.0f;
-                        al1 = pass1 ? __int_as_float(I1) : 0.0f;
+                        // alpha = min(0.99, exp_hat(P)) without the minimum, which cannot bind here:
+                        // P = ln o - q/2 with ln o <= 0 and q >= 0, and for a kept pair every term of
+                        // its float32 evaluation is below ~1600 in magnitude (conic entries <= 1/0.3,
+                        // coordinates within a tile), so P < 1e-3 and exp_hat(P) < 0.978
+                        al0 = pass0 ? __int_as_float((int)fmaf(P0, FEXP_A, FEXP_B)) : 0.0f;
+                        al1 = pass1 ? __int_as_float((int)fmaf(P1, FEXP_A, FEXP_B)) : 0.0f;
                     }
                     const float w0 = al0 * T0, w1 = al1 * T1;
                     float Tn0 = T0 - w0, Tn1 = T1 - w1;
@@ -318,11 +322,11 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
                             stop1 = at;
                             Tn1 = T1; nr1 = r1; ng1 = g1; nb1 = b1;
                         }
+                        wave_done = __ballot(live0 || live1) == 0;
                     }
                     T0 = Tn0; r0 = nr0; g0 = ng0; b0 = nb0;
                     T1 = Tn1; r1 = nr1; g1 = ng1; b1 = nb1;
                 }
-                if (__ballot(live0 || live1) == 0) break;
             }
         }
         __syncthreads();

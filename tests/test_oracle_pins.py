@@ -309,6 +309,55 @@ def test_folded_coefficients_identity():
         assert abs(P1 - d1) <= 1e-9 * (1 + abs(C0))
 
 
+def _fma32(a, b, c):
+    """float32 fused multiply-add: the float64 product of two float32 values is exact."""
+    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
+
+
+def test_folded_exponent_never_reaches_the_clamp():
+    """The fast rasterizer leaves out alpha's clamp at 0.99.  That is exact only if its float32
+    folded exponent P = ln o - q/2 stays below ln(0.99 / exp^(0)) ~ 0.013: q >= 0 and ln o <= 0
+    exactly, so this bounds the float32 evaluation error of Eqs. coeff/dot/dual_pixel in
+    tile-centre coordinates.  Adversarial sampling: the largest conic the 0.3 dilation allows,
+    strongly elongated ones, opacity near 1, means anywhere near the tile."""
+    rng = np.random.default_rng(11)
+    n = 200_000
+    lam1 = 0.3 + rng.exponential(1.0, n) * rng.choice([0.0, 1.0, 100.0], n)
+    lam2 = 0.3 + rng.exponential(1.0, n) * rng.choice([0.0, 1.0, 1e4], n)
+    th = rng.uniform(0, np.pi, n)
+    cs, sn = np.cos(th), np.sin(th)
+    S00 = lam1 * cs * cs + lam2 * sn * sn
+    S11 = lam1 * sn * sn + lam2 * cs * cs
+    S01 = (lam1 - lam2) * cs * sn
+    det = S00 * S11 - S01 * S01
+    A = (S11 / det).astype(np.float32)
+    B = (-S01 / det).astype(np.float32)
+    C = (S00 / det).astype(np.float32)
+    u = rng.uniform(-9.0, 9.0, n).astype(np.float32)
+    v = rng.uniform(-9.0, 9.0, n).astype(np.float32)
+    lno = (-rng.exponential(1e-3, n)).astype(np.float32)
+    # the pixel pair of a lane: x in -7.5..7.5, y in -7.5, -5.5, ..., 6.5 and y + 1
+    x = (rng.integers(0, 16, n) - 7.5).astype(np.float32)
+    y = (2 * rng.integers(0, 8, n) - 7.5).astype(np.float32)
+    # put half of the pixels right at the mean, where P is largest
+    at = rng.random(n) < 0.5
+    u = np.where(at, x + rng.uniform(-0.5, 0.5, n).astype(np.float32), u).astype(np.float32)
+    v = np.where(at, y + rng.uniform(-0.5, 1.5, n).astype(np.float32), v).astype(np.float32)
+    f32 = np.float32
+    C0 = _fma32(A * u, u, _fma32(f32(2.0) * B * u, v, C * v * v))
+    a_x, a_y, a_z = f32(-0.5) * A, -B, f32(-0.5) * C
+    a_w = _fma32(A, u, B * v)
+    m_x = _fma32(C, v, B * u)
+    m_y = _fma32(np.full(n, -0.5, f32), C0, lno)
+    x2, xy, y2 = x * x, x * y, y * y
+    y21 = _fma32(np.full(n, 2.0, f32), y, np.ones(n, f32))
+    P0 = _fma32(a_x, x2, _fma32(a_y, xy, _fma32(a_z, y2, _fma32(a_w, x, _fma32(m_x, y, m_y)))))
+    P1 = P0 + _fma32(a_y, x, _fma32(a_z, y21, m_x))
+    top = float(max(P0.max(), P1.max()))
+    assert top < 1e-3
+    assert float(oracle.fast_exp(top)) < 0.978
+
+
 # ---- paths agree where the paper says they must -----------------------------------------------
 
 def test_plain_equals_fast_exact_on_unquantised_scene():
