@@ -274,14 +274,15 @@ ABLATIONS = ["fastexp", "dualpixel", "fusion", "extent", "key32", "int8sh", "fp1
 
 def ablation_section(R, ds, cam, steps):
     """The fast path with each of Sec. IV's optimisations removed in turn (and
-    all of them), on the 1M/1080p workload: FPS, stage times, entries, passes."""
+    all of them), and with the exact ellipse-tile test added, on the 1M/1080p
+    workload: FPS, stage times, entries, passes."""
     out = {}
     paths = ["fast"] + ["fast/no-" + a for a in ABLATIONS] + ["fast/" + "/".join("no-" + a for a in ABLATIONS),
-                                                              "plain"]
+                                                              "plain", "fast/exact-tiles"]
     for path in paths:
         r = time_path(R, ds, [cam], path, steps, 10, 20)
         c = frame_counts(R, ds, cam, path)
-        name = "all" if path.count("/") > 1 else path.replace("fast/no-", "no-")
+        name = "all" if path.count("/") > 1 else path.replace("fast/no-", "no-").replace("fast/", "+")
         out[name] = {"fps": round(r["fps"], 1), "ms_per_frame": round(r["ms_per_frame"], 4),
                      "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
                      "n_entries": c["n_entries"], "passes": c["passes"], "pairs_visited": c["pairs_visited"]}

@@ -77,6 +77,15 @@ typedef int32_t rgs_status;
 #define RGS_ABLATE_FP16_GEOM (1 << 14)  /* FP32 rotation, scale and ln o from the plain format     */
 #define RGS_ABLATE_MASK      (0x7f << 8)
 
+/* Extension of the fast path, OR-ed into a `path` argument like the ablation
+ * bits: the exact ellipse-tile test.  Of each rectangle of at most 64 tiles it
+ * keeps only the tiles whose box of pixel centres meets the ellipse where
+ * alpha >= 1/255 (the tile-precise half of the Speedy-Splat culling that
+ * Sec. IV-A adopts; the default fast path keeps the whole alpha-ellipse box).
+ * The image is the same; the entries are fewer.  Not valid with
+ * RGS_ABLATE_EXTENT or RGS_PATH_PLAIN. */
+#define RGS_EXACT_TILES      (1 << 15)
+
 #define RGS_TILE 16
 #define RGS_MAX_DIM 16384     /* largest accepted image width or height                    */
 #define RGS_MAX_ENTRIES ((1ull << 30) - 1) /* largest entry capacity of one frame        */

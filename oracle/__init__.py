@@ -29,7 +29,8 @@ paper is silent or ambiguous are stated where they are used.
 from .plan import TILE, FramePlan, frame_plan, key_bits
 from .quant import FastScene, quantize_scene, dequantize_scene, quantize_sh
 from .project import Projection, project, sh_basis, LN255
-from .tiles import duplicate, sort_entries, tile_ranges, plain_keys, fast_keys
+from .tiles import (duplicate, sort_entries, tile_ranges, plain_keys, fast_keys, ellipse_meets_tile,
+                    exact_tile_filter, EXACT_TILE_MAX_AREA)
 from .fastexp import fast_exp, fast_exp_rel_error, SIGMA
 from .blend import blend_tile, BlendResult
 from .render import OracleFrame, render, prepare_plain, prepare_fast, prepare_fast_ablated

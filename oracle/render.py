@@ -19,7 +19,7 @@ from .blend import blend_tile
 from .plan import TILE, FramePlan, frame_plan
 from .project import Projection, project
 from .quant import FastScene, dequantize_scene
-from .tiles import duplicate, fast_keys, plain_keys, sort_entries, tile_ranges
+from .tiles import duplicate, exact_tile_filter, fast_keys, plain_keys, sort_entries, tile_ranges
 
 
 def prepare_plain(scene) -> dict:
@@ -109,12 +109,14 @@ def _blend_tiles(tiles):
 
 def render(arrays: dict, cam, path: str = "plain", modes=None, tiles=None, margins=None,
            workers: int = 1, blend: bool = True, alpha_extent: bool = True,
-           key64: bool = False) -> OracleFrame:
+           key64: bool = False, exact_tiles: bool = False) -> OracleFrame:
     """Render one frame.  ``tiles`` restricts blending to a subset of tiles.
 
     For the fast path, ``alpha_extent=False`` keeps the 3-sigma tile extent
     and ``key64=True`` sorts on the plain path's (tile, float32 depth) key:
     the ablations of the opacity-culling step and of the 32-bit key.
+    ``exact_tiles=True`` adds the exact ellipse-tile test to the alpha-ellipse
+    extent (see ``tiles.ellipse_meets_tile``).
     """
     if path not in ("plain", "fast"):
         raise ValueError(path)
@@ -124,6 +126,11 @@ def render(arrays: dict, cam, path: str = "plain", modes=None, tiles=None, margi
     plan = frame_plan(cam.width, cam.height)
     proj = project(arrays, cam, plan, fast, alpha_extent)
     eg, et = duplicate(proj.rect, proj.visible, plan)
+    if exact_tiles:
+        if not (fast and alpha_extent):
+            raise ValueError("the exact ellipse-tile test refines the fast path's alpha-ellipse extent")
+        eg, et = exact_tile_filter(eg, et, proj.rect, proj.u, proj.v, proj.cov, proj.det,
+                                   arrays["log_opacity"], plan)
     d = proj.d[eg]
     key32 = fast and not key64
     keys = fast_keys(et, d, cam.z_near, cam.z_far, plan) if key32 else plain_keys(et, d)

@@ -23,6 +23,7 @@ from __future__ import annotations
 import numpy as np
 
 from .plan import FramePlan
+from .project import LN255
 
 
 def duplicate(rect: np.ndarray, visible: np.ndarray, plan: FramePlan):
@@ -37,6 +38,65 @@ def duplicate(rect: np.ndarray, visible: np.ndarray, plan: FramePlan):
     tx = x0[g] + local % w[g]
     ty = y0[g] + local // w[g]
     return idx[g].astype(np.int64), (ty * plan.tiles_x + tx).astype(np.int64)
+
+
+# The exact ellipse-tile test (an extension of the fast path's culling step,
+# Sec. IV-A: the tile-precise half of the Speedy-Splat culling).  A tile is
+# kept iff the box of its pixel centres [16 tx, 16 tx + 15] x [16 ty, 16 ty + 15]
+# holds a point of the ellipse q(p) <= tau, where q(p) = (c11 dx^2 - 2 c01 dx dy
+# + c00 dy^2) / det for p - (u, v) = (dx, dy) and tau = 2 (ln 255 + ln o): the
+# pixels outside that ellipse have alpha < 1/255.  Only rectangles of at most
+# EXACT_TILE_MAX_AREA tiles are filtered; larger ones keep every tile.
+#
+# Reading (the paper names the culling strategy but not its arithmetic): q is
+# convex, so the box meets the ellipse iff it holds the mean or one of its four
+# edges does.  On the line x = X the least q is dx^2 / c00 at dy = c01 dx / c00;
+# if that dy lies off the edge, the least q on the edge is at the nearer
+# corner.  Every comparison is multiplied through by c00, c11 or det (> 0), in
+# float64, evaluated left to right as written (the key-defining arithmetic).
+EXACT_TILE_MAX_AREA = 64
+
+
+def ellipse_meets_tile(u, v, c00, c01, c11, det, tau, tx, ty) -> np.ndarray:
+    """Elementwise: does the alpha >= 1/255 ellipse of a Gaussian meet tile (tx, ty)?"""
+    X0 = 16.0 * np.asarray(tx, np.float64)
+    Y0 = 16.0 * np.asarray(ty, np.float64)
+    X1 = X0 + 15.0
+    Y1 = Y0 + 15.0
+    keep = (u >= X0) & (u <= X1) & (v >= Y0) & (v <= Y1)
+    rhs = tau * det
+    for Xe in (X0, X1):
+        dx = Xe - u
+        t = c01 * dx
+        lo = (Y0 - v) * c00
+        hi = (Y1 - v) * c00
+        inner = (t >= lo) & (t <= hi)
+        dy = np.where(t < lo, Y0 - v, Y1 - v)
+        near = c11 * dx * dx - 2.0 * c01 * dx * dy + c00 * dy * dy <= rhs
+        keep |= np.where(inner, dx * dx <= tau * c00, near)
+    for Ye in (Y0, Y1):
+        dy = Ye - v
+        t = c01 * dy
+        lo = (X0 - u) * c11
+        hi = (X1 - u) * c11
+        inner = (t >= lo) & (t <= hi)
+        dx = np.where(t < lo, X0 - u, X1 - u)
+        near = c11 * dx * dx - 2.0 * c01 * dx * dy + c00 * dy * dy <= rhs
+        keep |= np.where(inner, dy * dy <= tau * c11, near)
+    return keep
+
+
+def exact_tile_filter(entry_gauss, entry_tile, rect, u, v, cov, det, log_opacity, plan: FramePlan):
+    """Entries (in emission order) that the exact ellipse-tile test keeps."""
+    x0, x1, y0, y1 = (rect[entry_gauss, k] for k in range(4))
+    area = (x1 - x0 + 1) * (y1 - y0 + 1)
+    tx = entry_tile % plan.tiles_x
+    ty = entry_tile // plan.tiles_x
+    g = entry_gauss
+    tau = 2.0 * (LN255 + log_opacity[g])
+    meets = ellipse_meets_tile(u[g], v[g], cov[g, 0], cov[g, 1], cov[g, 2], det[g], tau, tx, ty)
+    keep = (area > EXACT_TILE_MAX_AREA) | meets
+    return entry_gauss[keep], entry_tile[keep]
 
 
 def plain_keys(tile: np.ndarray, depth_of_entry: np.ndarray) -> np.ndarray:

@@ -32,18 +32,25 @@ PATH_FAST = 1
 # "fast/no-<name>[/no-<name>...]" removes the named steps.
 ABLATIONS = {"fastexp": 1 << 8, "dualpixel": 1 << 9, "fusion": 1 << 10, "extent": 1 << 11,
              "key32": 1 << 12, "int8sh": 1 << 13, "fp16geom": 1 << 14}
+# Extensions of the fast path (rgs.h): "fast/<name>" adds them.
+EXTENSIONS = {"exact-tiles": 1 << 15}
 
 
 class _Paths(dict):
-    """"plain", "fast", or "fast/no-<ablation>/..." -> the C path argument."""
+    """"plain", "fast", or "fast/no-<ablation>/.../<extension>" -> the C path argument."""
 
     def __missing__(self, key):
         parts = str(key).split("/")
-        if parts[0] != "fast" or len(parts) < 2 or not all(p.startswith("no-") for p in parts[1:]):
+        if parts[0] != "fast" or len(parts) < 2:
             raise KeyError(key)
         code = PATH_FAST
         for p in parts[1:]:
-            code |= ABLATIONS[p[3:]]
+            if p.startswith("no-") and p[3:] in ABLATIONS:
+                code |= ABLATIONS[p[3:]]
+            elif p in EXTENSIONS:
+                code |= EXTENSIONS[p]
+            else:
+                raise KeyError(key)
         return code
 
 

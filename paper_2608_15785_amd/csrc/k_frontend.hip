@@ -282,8 +282,28 @@ __device__ inline uint32_t block_scan_and_chain(const uint32_t (&count)[FE_ITEMS
     return carry;
 }
 
+// Position of the k-th (from 0) set bit of m, which has more than k set bits.
+__device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t k) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (int half = 32; half > 0; half >>= 1) {
+        const uint64_t low = m & ((1ull << half) - 1);
+        const uint32_t c = (uint32_t)__popcll(low);
+        if (k >= c) {
+            k -= c;
+            m >>= half;
+            pos += half;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
 // Entry e of the block belongs to the Gaussian j with s_incl[j-1] <= e < s_incl[j]
-// and is the (e - s_incl[j-1])-th tile of j's rectangle in row-major order.
+// and is the (e - s_incl[j-1])-th tile of j's rectangle in row-major order, or
+// of its kept tiles when s_mask holds them (rectangles of at most
+// EXACT_TILE_MAX_AREA tiles).
 // Each stored key also counts its digits of radix passes p_first..passes-1
 // into the block's LDS histogram s_h[pass][digit] (the passes before p_first
 // read only the depth bits, which all entries of a Gaussian share: those are
@@ -294,7 +314,7 @@ template <typename KeyT, typename KeyFn>
 __device__ inline void emit_entries(uint32_t total, uint64_t base, const uint32_t* s_incl,
                                     const uint64_t* s_rect, uint32_t first_gauss, int tiles_x,
                                     uint32_t capacity, KeyT* keys, uint32_t* vals, KeyFn key_of,
-                                    uint32_t* s_h, uint32_t p_first, uint32_t passes) {
+                                    uint32_t* s_h, uint32_t p_first, uint32_t passes, const uint64_t* s_mask) {
     for (uint32_t e = threadIdx.x; e < total; e += FE_THREADS) {
         int lo = 0, hi = FE_TILE - 1;
         while (lo < hi) {
@@ -307,8 +327,11 @@ __device__ inline void emit_entries(uint32_t total, uint64_t base, const uint32_
         const uint64_t rc = s_rect[j];
         const uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff;
         const uint32_t w = x1 - x0 + 1;
-        const uint32_t ty = y0 + local / w;
-        const uint32_t tx = x0 + local % w;
+        uint32_t b = local;            // row-major index of the tile in the rectangle
+        if (s_mask && w * ((uint32_t)(rc >> 48) - y0 + 1) <= EXACT_TILE_MAX_AREA)
+            b = nth_set_bit(s_mask[j], local);
+        const uint32_t ty = y0 + b / w;
+        const uint32_t tx = x0 + b % w;
         const uint32_t tile = ty * (uint32_t)tiles_x + tx;
         const uint64_t pos = base + e;
         const bool stored = pos < capacity;
@@ -468,6 +491,7 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
     __shared__ uint32_t s_incl[FE_TILE];
     __shared__ uint64_t s_rect[FE_TILE];
     __shared__ uint32_t s_dbits[FE_TILE];
+    __shared__ uint64_t s_mask[FE_TILE];
     __shared__ uint32_t s_wtot[FE_THREADS / 64];
     __shared__ uint32_t s_wvis[FE_THREADS / 64];
     __shared__ uint64_t s_base, s_base_v;
@@ -489,6 +513,7 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
             if (count[k]) {
                 s_rect[j] = ws.rects[i];
                 s_dbits[j] = __float_as_uint(ws.depths[i]);
+                if (ws.masks) s_mask[j] = ws.masks[i];
                 ++n_vis;
             }
         }
@@ -509,7 +534,7 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
     emit_entries<KeyT>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
                        reinterpret_cast<KeyT*>(ws.keys_a), ws.vals_a,
                        [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_dbits[j]; },
-                       s_h, p_depth, (uint32_t)f.passes);
+                       s_h, p_depth, (uint32_t)f.passes, ws.masks ? s_mask : nullptr);
     __syncthreads();
     prepare_sort<KeyT>(ws, s_h, (uint32_t)f.passes, vb, base, total);
     finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
@@ -537,7 +562,7 @@ void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& 
 template <bool DEBUG>
 __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& cam, const FrameDev& f,
                                          WsDev& ws, const DebugDev& dbg, int64_t i, uint64_t& rect,
-                                         uint32_t& klo, uint32_t opts) {
+                                         uint32_t& klo, uint64_t& mask, uint32_t opts) {
     const uint32_t* W = sc.base;
     const uint64_t np = sc.n_pad;
     const float mx = __uint_as_float(W[F_MX * np + i]);
@@ -596,6 +621,18 @@ __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& c
         rect = pack_rect(pr);
         klo = (opts & OPT_KEY32) ? __float_as_uint((float)pr.d) : quantize_depth(pr.d, cam.zn, cam.zf, f.b_d);
         count = rect_count(rect);
+        mask = 0;
+        if ((opts & OPT_EXACT_TILES) && count <= EXACT_TILE_MAX_AREA) {
+            // the exact ellipse-tile test: bit r * w + c for tile (x0 + c, y0 + r)
+            const uint32_t w = (uint32_t)(pr.x1 - pr.x0) + 1, h = (uint32_t)(pr.y1 - pr.y0) + 1;
+            const double tau = 2.0 * (LN255 + (double)lno);
+            for (uint32_t rr = 0; rr < h; ++rr)
+                for (uint32_t cc = 0; cc < w; ++cc)
+                    if (ellipse_meets_tile(pr.u, pr.v, pr.c00, pr.c01, pr.c11, pr.det, tau,
+                                           16.0 * (pr.x0 + (double)cc), 16.0 * (pr.y0 + (double)rr)))
+                        mask |= 1ull << (rr * w + cc);
+            count = (uint32_t)__popcll(mask);
+        }
     }
     if (DEBUG) write_debug(dbg, i, pr, vis, r, g, b);
     return count;
@@ -615,6 +652,7 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
     __shared__ uint32_t s_incl[FE_TILE];
     __shared__ uint64_t s_rect[FE_TILE];
     __shared__ uint32_t s_qd[FE_TILE];
+    __shared__ uint64_t s_mask[FE_TILE];
     __shared__ uint32_t s_wtot[FE_THREADS / 64];
     __shared__ uint32_t s_wvis[FE_THREADS / 64];
     __shared__ uint64_t s_base, s_base_v;
@@ -633,12 +671,13 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
         const int64_t i = (int64_t)vb * FE_TILE + j;
         count[k] = 0;
         if (i < sc.n) {
-            uint64_t rect = 0;
+            uint64_t rect = 0, mask = 0;
             uint32_t klo = 0;
-            count[k] = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, klo, opts);
+            count[k] = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, klo, mask, opts);
             if (count[k]) {
                 s_rect[j] = rect;
                 s_qd[j] = klo;
+                s_mask[j] = mask;
                 ++n_vis;
             }
         }
@@ -651,7 +690,7 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
     emit_entries<KeyT>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
                        reinterpret_cast<KeyT*>(ws.keys_a), ws.vals_a,
                        [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_qd[j]; },
-                       s_h, p_depth, (uint32_t)f.passes);
+                       s_h, p_depth, (uint32_t)f.passes, (opts & OPT_EXACT_TILES) ? s_mask : nullptr);
     __syncthreads();
     prepare_sort<KeyT>(ws, s_h, (uint32_t)f.passes, vb, base, total);
     finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
@@ -687,13 +726,14 @@ __global__ __launch_bounds__(256) void k_preprocess_fast(FastSceneDev sc, FrameD
     const CamDev cam = ws.params->cam;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= sc.n) return;
-    uint64_t rect = 0;
+    uint64_t rect = 0, mask = 0;
     uint32_t klo = 0;
-    const uint32_t count = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, klo, opts);
+    const uint32_t count = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, klo, mask, opts);
     ws.counts[i] = count;
     if (count) {
         ws.rects[i] = rect;
         ws.depths[i] = __uint_as_float(klo);
+        if (ws.masks) ws.masks[i] = mask;
     }
 }
 

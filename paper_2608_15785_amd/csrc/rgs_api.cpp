@@ -425,7 +425,7 @@ static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 // The base path (RGS_PATH_PLAIN / RGS_PATH_FAST) and the ablation bits of a
 // path argument.
 static int32_t path_base(int32_t path) { return path & 0xff; }
-static uint32_t path_opts(int32_t path) { return ((uint32_t)path & RGS_ABLATE_MASK) >> 8; }
+static uint32_t path_opts(int32_t path) { return ((uint32_t)path & (RGS_ABLATE_MASK | RGS_EXACT_TILES)) >> 8; }
 
 static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t capacity, WsLayout& L) {
     const bool plain = path_base(path) == RGS_PATH_PLAIN;
@@ -450,7 +450,11 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     off = align256(off + sizeof(FrameParams));
     L.records = off;
     off = align256(off + (uint64_t)n * sizeof(Record));
-    L.counts = L.rects = L.depths = L.offsets = 0;
+    L.counts = L.rects = L.depths = L.offsets = L.masks = 0;
+    if (!plain && (opts & OPT_FUSION) && (opts & OPT_EXACT_TILES)) {
+        L.masks = off;
+        off = align256(off + (uint64_t)n * 8);
+    }
     if (plain || (opts & OPT_FUSION)) {
         L.counts = off;
         off = align256(off + (uint64_t)n * 4);
@@ -485,10 +489,12 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
 
 static rgs_status check_path(int32_t path) {
     const int32_t base = path_base(path);
-    if ((base != RGS_PATH_PLAIN && base != RGS_PATH_FAST) || (path & ~(0xff | RGS_ABLATE_MASK)))
+    if ((base != RGS_PATH_PLAIN && base != RGS_PATH_FAST) || (path & ~(0xff | RGS_ABLATE_MASK | RGS_EXACT_TILES)))
         return fail(RGS_E_INVALID, "path 0x%x is neither RGS_PATH_PLAIN nor RGS_PATH_FAST with ablation bits", path);
     if (base == RGS_PATH_PLAIN && path_opts(path))
-        return fail(RGS_E_INVALID, "ablation bits apply to the fast path only");
+        return fail(RGS_E_INVALID, "ablation and extension bits apply to the fast path only");
+    if ((path & RGS_EXACT_TILES) && (path & RGS_ABLATE_EXTENT))
+        return fail(RGS_E_INVALID, "RGS_EXACT_TILES refines the alpha-ellipse extent that RGS_ABLATE_EXTENT removes");
     return RGS_OK;
 }
 
@@ -547,6 +553,7 @@ static WsDev ws_pointers(void* base, const WsLayout& L) {
     w.rects = L.rects ? reinterpret_cast<uint64_t*>(b + L.rects) : nullptr;
     w.depths = L.depths ? reinterpret_cast<float*>(b + L.depths) : nullptr;
     w.offsets = L.offsets ? reinterpret_cast<uint32_t*>(b + L.offsets) : nullptr;
+    w.masks = L.masks ? reinterpret_cast<uint64_t*>(b + L.masks) : nullptr;
     w.keys_a = b + L.keys_a;
     w.keys_b = b + L.keys_b;
     w.vals_a = reinterpret_cast<uint32_t*>(b + L.vals_a);

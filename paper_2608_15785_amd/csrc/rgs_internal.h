@@ -61,7 +61,7 @@ enum PlainPlane { P_MX = 0, P_MY, P_MZ, P_SX, P_SY, P_SZ, P_QW, P_QX, P_QY, P_QZ
 
 // Fast-path ablation bits (the path argument's bits 8..14, shifted down).
 constexpr uint32_t OPT_FASTEXP = 1u, OPT_DUALPIXEL = 2u, OPT_FUSION = 4u, OPT_EXTENT = 8u, OPT_KEY32 = 16u,
-                   OPT_INT8_SH = 32u, OPT_FP16_GEOM = 64u;
+                   OPT_INT8_SH = 32u, OPT_FP16_GEOM = 64u, OPT_EXACT_TILES = 128u;
 // Fast-format planes (32-bit words, one per plane, each n_pad long).
 //   F_MX..F_MZ   float32 mean
 //   F_QWX, F_QYZ FP16 pairs (w, x), (y, z) of the quaternion
@@ -140,7 +140,7 @@ static_assert(sizeof(WsHeader) == 256, "header is one 256-byte slot");
 struct WsLayout {
     uint64_t params;
     uint64_t header, ranges, fe_state, zero_end;
-    uint64_t records, counts, rects, depths, offsets;
+    uint64_t records, counts, rects, depths, offsets, masks;
     uint64_t keys_a, keys_b, vals_a, vals_b;
     uint64_t hist, sort_state;
     uint64_t t_final, n_proc, n_blend;
@@ -160,6 +160,8 @@ struct WsDev {
     uint64_t* rects;          // plain: packed x0 | x1 << 16 | y0 << 32 | y1 << 48
     float* depths;            // plain: float32 depth per Gaussian
     uint32_t* offsets;        // plain: position of the Gaussian's first entry in emission order
+    uint64_t* masks;          // fast path, fusion ablated, exact tiles: kept tiles of the rectangle
+                              // (row-major bits)
     void* keys_a;
     void* keys_b;
     uint32_t* vals_a;
@@ -286,6 +288,52 @@ __host__ __device__ inline bool project_gaussian(const CamDev& c, double mx, dou
     o.y0 = fmax(0.0, floor((v - hy) / 16.0));
     o.y1 = fmin(tiles_y - 1.0, floor((v + hy) / 16.0));
     return o.x0 <= o.x1 && o.y0 <= o.y1;
+}
+
+// Exact ellipse-tile test, the tile-precise half of the Speedy-Splat culling
+// that the fast path adopts (Sec. IV-A): does the ellipse q(p) <= tau of a
+// projected Gaussian, q(p) = (c11 dx^2 - 2 c01 dx dy + c00 dy^2) / det with
+// (dx, dy) = p - (u, v) and tau = 2 (ln 255 + ln o), meet the box of a tile's
+// pixel centres [X0, X0 + 15] x [Y0, Y0 + 15]?  q is convex, so the box holds
+// a point of the ellipse iff it holds the mean or the least q on one of its
+// edges is <= tau.  On the line x = X the least q is dx^2 / c00, at
+// dy = c01 dx / c00; when that dy is off the edge, the least q on the edge is
+// at the nearer corner.  Multiplying through by c00, c11 or det (all > 0)
+// leaves no division or square root.  Applied to rectangles of at most
+// EXACT_TILE_MAX_AREA tiles (their kept tiles fit a 64-bit mask); larger
+// rectangles keep every tile.  Evaluation order as written, as everywhere in
+// the key-defining arithmetic.
+constexpr uint32_t EXACT_TILE_MAX_AREA = 64;
+__host__ __device__ inline bool ellipse_meets_tile(double u, double v, double c00, double c01, double c11,
+                                                   double det, double tau, double X0, double Y0) {
+    const double X1 = X0 + 15.0, Y1 = Y0 + 15.0;
+    if (u >= X0 && u <= X1 && v >= Y0 && v <= Y1) return true;
+    const double rhs = tau * det;
+    for (int e = 0; e < 2; ++e) {           // vertical edges x = X0, X1
+        const double dx = (e ? X1 : X0) - u;
+        const double t = c01 * dx;
+        const double lo = (Y0 - v) * c00;
+        const double hi = (Y1 - v) * c00;
+        if (t >= lo && t <= hi) {
+            if (dx * dx <= tau * c00) return true;
+        } else {
+            const double dy = t < lo ? Y0 - v : Y1 - v;
+            if (c11 * dx * dx - 2.0 * c01 * dx * dy + c00 * dy * dy <= rhs) return true;
+        }
+    }
+    for (int e = 0; e < 2; ++e) {           // horizontal edges y = Y0, Y1
+        const double dy = (e ? Y1 : Y0) - v;
+        const double t = c01 * dy;
+        const double lo = (X0 - u) * c11;
+        const double hi = (X1 - u) * c11;
+        if (t >= lo && t <= hi) {
+            if (dy * dy <= tau * c11) return true;
+        } else {
+            const double dx = t < lo ? X0 - u : X1 - u;
+            if (c11 * dx * dx - 2.0 * c01 * dx * dy + c00 * dy * dy <= rhs) return true;
+        }
+    }
+    return false;
 }
 
 // Eq. depth_quant: q = clamp(floor((d - zn) / (zf - zn) * (2^b_d - 1)), 0, 2^b_d - 1).

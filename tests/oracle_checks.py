@@ -315,3 +315,28 @@ def check_brute_force(path="plain", seed=5, n=40, W=45, H=37, key64=False, alpha
         fr = oracle.render(arr, cam, "plain")
     ref = brute_force_image(arr, cam, path, mode, key64, alpha_extent)
     return float(np.max(np.abs(fr.image - ref)))
+
+
+def check_exact_tile_test(n=2000, seed=5):
+    """Share of random (Gaussian, tile) pairs, away from the decision boundary, on which the
+    oracle's exact ellipse-tile test disagrees with the least q over a dense grid of the
+    tile's box (0 when the closed-form edge minimum is right)."""
+    rng = np.random.default_rng(seed)
+    xs = np.linspace(0.0, 15.0, 121)
+    wrong = total = 0
+    for _ in range(n):
+        L = rng.normal(size=(2, 2)) * rng.choice([1.0, 3.0, 10.0])
+        S = L @ L.T + 0.3 * np.eye(2)
+        c00, c01, c11 = S[0, 0], S[0, 1], S[1, 1]
+        det = c00 * c11 - c01 * c01
+        tau = 2.0 * (math.log(255.0) + math.log(rng.uniform(1.0 / 255.0, 1.0)))
+        u, v = rng.uniform(-40.0, 56.0, 2)
+        dx = xs[None, :] - u
+        dy = xs[:, None] - v
+        qmin = float(((c11 * dx * dx - 2.0 * c01 * dx * dy + c00 * dy * dy) / det).min())
+        if abs(qmin - tau) <= 0.02 * tau + 0.05:
+            continue
+        total += 1
+        keep = bool(oracle.ellipse_meets_tile(u, v, c00, c01, c11, det, tau, 0, 0))
+        wrong += keep != (qmin <= tau)
+    return wrong / max(total, 1)

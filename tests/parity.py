@@ -38,15 +38,16 @@ def oracle_frame(scene, cam, path, tiles=None, workers=8):
                          margins=FAST_MARGINS, workers=workers)
 
 
-def oracle_frame_ablated(scene, cam, ablations, tiles=None, workers=8):
+def oracle_frame_ablated(scene, cam, ablations, tiles=None, workers=8, exact_tiles=False):
     """The oracle's fast path with the named steps removed (see the binding's
-    ABLATIONS): storage read in FP32, 3-sigma extent, 64-bit key, exact exp."""
+    ABLATIONS): storage read in FP32, 3-sigma extent, 64-bit key, exact exp;
+    with ``exact_tiles`` it adds the exact ellipse-tile test."""
     ab = set(ablations)
     fs = oracle.quantize_scene(scene)
     arr = oracle.prepare_fast_ablated(scene, fs, int8_sh="int8sh" not in ab, fp16_geometry="fp16geom" not in ab)
     modes = ("fast-exact",) if "fastexp" in ab else ("fast-def", "fast-exact")
     return oracle.render(arr, cam, "fast", modes=modes, tiles=tiles, margins=FAST_MARGINS, workers=workers,
-                         alpha_extent="extent" not in ab, key64="key32" in ab)
+                         alpha_extent="extent" not in ab, key64="key32" in ab, exact_tiles=exact_tiles)
 
 
 def compare_front_end(g, fr):

@@ -110,6 +110,31 @@ def _tile_index_transposed(mp):
     return lambda: oc.check_brute_force("plain")
 
 
+def _exact_tile_off_diagonal_sign(mp):
+    orig = TILES.ellipse_meets_tile
+    mp.setattr(TILES, "ellipse_meets_tile",
+               lambda u, v, c00, c01, c11, det, tau, tx, ty: orig(u, v, c00, -c01, c11, det, tau, tx, ty))
+    mp.setattr(oc.oracle, "ellipse_meets_tile", TILES.ellipse_meets_tile)
+    return oc.check_exact_tile_test
+
+
+def _exact_tile_swapped_axes(mp):
+    orig = TILES.ellipse_meets_tile
+    mp.setattr(TILES, "ellipse_meets_tile",
+               lambda u, v, c00, c01, c11, det, tau, tx, ty: orig(u, v, c11, c01, c00, det, tau, tx, ty))
+    mp.setattr(oc.oracle, "ellipse_meets_tile", TILES.ellipse_meets_tile)
+    return oc.check_exact_tile_test
+
+
+def _exact_tile_box_one_short(mp):
+    orig = TILES.ellipse_meets_tile
+    mp.setattr(TILES, "ellipse_meets_tile",
+               lambda u, v, c00, c01, c11, det, tau, tx, ty: orig(u - 1.0, v - 1.0, c00, c01, c11, det, tau, tx, ty)
+               & orig(u, v, c00, c01, c11, det, tau, tx, ty))
+    mp.setattr(oc.oracle, "ellipse_meets_tile", TILES.ellipse_meets_tile)
+    return oc.check_exact_tile_test
+
+
 MUTATIONS = {
     "transposed rotation": _transposed_rotation,
     "conic off-diagonal sign": _conic_sign,
@@ -123,6 +148,9 @@ MUTATIONS = {
     "sigma sign": _sigma_sign,
     "short tile rectangle": _short_rect,
     "transposed tile index": _tile_index_transposed,
+    "exact tile test: off-diagonal sign": _exact_tile_off_diagonal_sign,
+    "exact tile test: swapped axes": _exact_tile_swapped_axes,
+    "exact tile test: box one pixel short": _exact_tile_box_one_short,
 }
 
 

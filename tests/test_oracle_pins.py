@@ -358,6 +358,87 @@ def test_folded_exponent_never_reaches_the_clamp():
     assert float(oracle.fast_exp(top)) < 0.978
 
 
+# ---- the exact ellipse-tile test (an extension of the Sec. IV-A culling step) -----------------
+
+def _dense_min_q(u, v, c00, c01, c11, det, X0, Y0, n=161):
+    """Least q over an n x n grid of the box [X0, X0+15] x [Y0, Y0+15], corners included."""
+    xs = np.linspace(X0, X0 + 15.0, n)
+    ys = np.linspace(Y0, Y0 + 15.0, n)
+    dx = xs[None, :] - u
+    dy = ys[:, None] - v
+    q = (c11 * dx * dx - 2.0 * c01 * dx * dy + c00 * dy * dy) / det
+    return float(q.min())
+
+
+def test_exact_tile_test_against_dense_sampling():
+    """The closed-form edge minimum against brute force: a kept tile has a sampled point
+    with q within sampling error of tau, a dropped tile has none below tau; pixel centres
+    with alpha >= 1/255 never sit in a dropped tile."""
+    rng = np.random.default_rng(5)
+    checked = dropped = 0
+    for _ in range(3000):
+        L = rng.normal(size=(2, 2)) * rng.choice([1.0, 3.0, 10.0])
+        S = L @ L.T + 0.3 * np.eye(2)
+        c00, c01, c11 = S[0, 0], S[0, 1], S[1, 1]
+        det = c00 * c11 - c01 * c01
+        tau = 2.0 * (math.log(255.0) + math.log(rng.uniform(1.0 / 255.0, 1.0)))
+        u, v = rng.uniform(-40.0, 56.0, 2)
+        tx, ty = 0, 0
+        keep = bool(oracle.ellipse_meets_tile(u, v, c00, c01, c11, det, tau, tx, ty))
+        qmin = _dense_min_q(u, v, c00, c01, c11, det, 0.0, 0.0)
+        # pixel centres of the tile
+        px, py = np.meshgrid(np.arange(16.0), np.arange(16.0))
+        qpix = (c11 * (px - u) ** 2 - 2.0 * c01 * (px - u) * (py - v) + c00 * (py - v) ** 2) / det
+        if not keep:
+            dropped += 1
+            assert qpix.min() > tau
+            assert qmin > tau
+        if abs(qmin - tau) > 0.02 * tau + 0.05:      # away from the boundary the sampling decides
+            checked += 1
+            assert keep == (qmin <= tau), (u, v, S.tolist(), tau, qmin)
+    assert checked > 2000 and dropped > 300
+
+
+def test_exact_tiles_change_entries_not_the_image():
+    """Dropped tiles hold no pixel with alpha >= 1/255: the entries shrink, the image does not change."""
+    sc = wl.config_scene("cfg0", n=3000)
+    cam = wl.config_camera("cfg0")
+    arr = oracle.prepare_fast(oracle.quantize_scene(sc))
+    a = oracle.render(arr, cam, "fast", modes=("fast-def", "fast-exact"))
+    b = oracle.render(arr, cam, "fast", modes=("fast-def", "fast-exact"), exact_tiles=True)
+    assert b.keys.size < 0.95 * a.keys.size
+    for m in ("fast-def", "fast-exact"):
+        assert np.array_equal(a.images[m], b.images[m])
+    # the kept entries are a subset, in the same emission order
+    ka = list(zip(a.entry_gauss.tolist(), a.entry_tile.tolist()))
+    kb = list(zip(b.entry_gauss.tolist(), b.entry_tile.tolist()))
+    it = iter(ka)
+    assert all(e in it for e in kb)
+
+
+def test_exact_tiles_keep_large_rectangles():
+    """Rectangles of more than 64 tiles keep every tile, even those the ellipse misses."""
+    plan = oracle.frame_plan(320, 320)
+    # a thin diagonal ellipse spanning a 9 x 9 tile rectangle
+    c00 = c11 = 2000.0
+    c01 = 1999.0
+    det = c00 * c11 - c01 * c01
+    rect = np.array([[0, 8, 0, 8]])
+    eg, et = oracle.duplicate(rect, np.array([True]), plan)
+    args = (rect, np.array([72.0]), np.array([72.0]), np.array([[c00, c01, c11]]), np.array([det]),
+            np.array([0.0]), plan)
+    g, t = oracle.exact_tile_filter(eg, et, *args)
+    assert g.size == 81
+    meets = oracle.ellipse_meets_tile(72.0, 72.0, c00, c01, c11, det, 2.0 * math.log(255.0),
+                                      et % plan.tiles_x, et // plan.tiles_x)
+    assert 0 < int(meets.sum()) < 81
+    # the same ellipse in a rectangle of 8 x 8 tiles is filtered
+    rect8 = np.array([[0, 7, 0, 7]])
+    eg8, et8 = oracle.duplicate(rect8, np.array([True]), plan)
+    g8, _ = oracle.exact_tile_filter(eg8, et8, rect8, *args[1:])
+    assert 0 < g8.size < 64
+
+
 # ---- paths agree where the paper says they must -----------------------------------------------
 
 def test_plain_equals_fast_exact_on_unquantised_scene():
