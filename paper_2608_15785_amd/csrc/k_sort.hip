@@ -290,31 +290,59 @@ void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key
 // ---------------------------------------------------------------------------
 // Tile ranges: the run of each tile in the sorted keys.  Entry i starts a run
 // when its tile differs from entry i-1's, and ends the previous run there.
+// Each thread takes RANGES_ITEMS consecutive keys with 16-byte loads.
+
+constexpr int RANGES_ITEMS = 8;
+
+template <typename KeyT>
+__device__ inline void load_run(const KeyT* __restrict__ keys, uint64_t i0, uint32_t n, KeyT (&k)[RANGES_ITEMS]) {
+    if (i0 + RANGES_ITEMS <= n) {
+        // i0 is a multiple of RANGES_ITEMS and the buffers are 256-byte aligned
+        const uint4* p = reinterpret_cast<const uint4*>(keys + i0);
+        constexpr int VEC = RANGES_ITEMS * sizeof(KeyT) / 16;
+        uint4 v[VEC];
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) v[q] = p[q];
+        __builtin_memcpy(k, v, sizeof(k));
+    } else {
+#pragma unroll
+        for (int r = 0; r < RANGES_ITEMS; ++r) k[r] = i0 + r < n ? keys[i0 + r] : (KeyT)0;
+    }
+}
 
 template <typename KeyT>
 __global__ __launch_bounds__(256) void k_ranges(const KeyT* __restrict__ keys, WsDev ws,
                                                 uint32_t shift, uint32_t n_tiles) {
     const uint32_t n = entry_count(ws.header);
-    uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    uint32_t t = (uint32_t)(keys[i] >> shift);
-    uint32_t tp = i ? (uint32_t)(keys[i - 1] >> shift) : 0xffffffffu;
-    if (t >= n_tiles || (i && tp >= n_tiles)) {     // only after a failed sort
-        atomicOr(&ws.header->error, 4u);
-        return;
+    const uint64_t i0 = ((uint64_t)blockIdx.x * 256 + threadIdx.x) * RANGES_ITEMS;
+    if (i0 >= n) return;
+    KeyT k[RANGES_ITEMS];
+    load_run(keys, i0, n, k);
+    uint32_t tp = i0 ? (uint32_t)(keys[i0 - 1] >> shift) : 0xffffffffu;
+#pragma unroll
+    for (int r = 0; r < RANGES_ITEMS; ++r) {
+        const uint64_t i = i0 + r;
+        if (i >= n) break;
+        const uint32_t t = (uint32_t)(k[r] >> shift);
+        if (t >= n_tiles || (i && tp >= n_tiles)) {     // only after a failed sort
+            atomicOr(&ws.header->error, 4u);
+            return;
+        }
+        if (i == 0) {
+            ws.ranges[2 * t] = 0;
+        } else if (tp != t) {
+            ws.ranges[2 * tp + 1] = (uint32_t)i;
+            ws.ranges[2 * t] = (uint32_t)i;
+        }
+        if (i == n - 1) ws.ranges[2 * t + 1] = n;
+        tp = t;
     }
-    if (i == 0) {
-        ws.ranges[2 * t] = 0;
-    } else if (tp != t) {
-        ws.ranges[2 * tp + 1] = i;
-        ws.ranges[2 * t] = i;
-    }
-    if (i == n - 1) ws.ranges[2 * t + 1] = n;
 }
 
 void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                    bool result_in_b) {
-    uint32_t blocks = (f.capacity + 255) / 256;
+    const uint64_t per_block = 256ull * RANGES_ITEMS;
+    const uint32_t blocks = (uint32_t)((f.capacity + per_block - 1) / per_block);
     if (key_bytes == 8)
         hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(blocks), dim3(256), 0, s,
                            reinterpret_cast<const uint64_t*>(result_in_b ? ws.keys_b : ws.keys_a), ws, 32u,
