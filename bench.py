@@ -274,11 +274,12 @@ ABLATIONS = ["fastexp", "dualpixel", "fusion", "extent", "key32", "int8sh", "fp1
 
 def ablation_section(R, ds, cam, steps):
     """The fast path with each of Sec. IV's optimisations removed in turn (and
-    all of them), and with the exact ellipse-tile test added, on the 1M/1080p
-    workload: FPS, stage times, entries, passes."""
+    all of them), and with each extension (the exact ellipse-tile test, the
+    hardware exp2) added, on the 1M/1080p workload: FPS, stage times, entries,
+    passes."""
     out = {}
     paths = ["fast"] + ["fast/no-" + a for a in ABLATIONS] + ["fast/" + "/".join("no-" + a for a in ABLATIONS),
-                                                              "plain", "fast/exact-tiles"]
+                                                              "plain", "fast/exact-tiles", "fast/hw-exp2"]
     for path in paths:
         r = time_path(R, ds, [cam], path, steps, 10, 20)
         c = frame_counts(R, ds, cam, path)

@@ -85,6 +85,12 @@ typedef int32_t rgs_status;
  * The image is the same; the entries are fewer.  Not valid with
  * RGS_ABLATE_EXTENT or RGS_PATH_PLAIN. */
 #define RGS_EXACT_TILES      (1 << 15)
+/* Extension of the fast path: alpha = min(0.99, exp2(P log2 e)) by gfx950's
+ * hardware exp2 instruction, with log2 e folded into the coefficients of
+ * Eq. coeff, instead of the bit-level exponential of Eq. fma_exp (Sec. IV-B).
+ * The image is that of the exact exponential to within the instruction's
+ * 1-ulp error.  Not valid with RGS_ABLATE_FASTEXP or RGS_ABLATE_DUALPIXEL. */
+#define RGS_HW_EXP2          (1 << 16)
 
 #define RGS_TILE 16
 #define RGS_MAX_DIM 16384     /* largest accepted image width or height                    */

@@ -33,7 +33,7 @@ PATH_FAST = 1
 ABLATIONS = {"fastexp": 1 << 8, "dualpixel": 1 << 9, "fusion": 1 << 10, "extent": 1 << 11,
              "key32": 1 << 12, "int8sh": 1 << 13, "fp16geom": 1 << 14}
 # Extensions of the fast path (rgs.h): "fast/<name>" adds them.
-EXTENSIONS = {"exact-tiles": 1 << 15}
+EXTENSIONS = {"exact-tiles": 1 << 15, "hw-exp2": 1 << 16}
 
 
 class _Paths(dict):

@@ -705,6 +705,9 @@ static void launch_fe(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, 
 
 void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
                           uint32_t fe_blocks, const DebugDev* dbg, uint32_t opts) {
+    // only these bits change the front end; the others (the exponential, the
+    // pixel layout) leave it to the production instance
+    opts &= OPT_EXTENT | OPT_KEY32 | OPT_INT8_SH | OPT_FP16_GEOM | OPT_EXACT_TILES;
     const bool key64 = (opts & OPT_KEY32) != 0;
     if (opts == 0) {
         if (dbg) launch_fe<true, false, uint32_t>(s, sc, f, ws, fe_blocks, dbg, 0);

@@ -176,9 +176,19 @@ __device__ inline float conic_rect_min(float u, float v, float A, float B, float
     return best;
 }
 
-template <bool COUNT, bool EXACT>
+// How the fast rasterizer takes alpha from the folded exponent P.
+enum ExpMode : int {
+    EXP_BITS = 0,   // Eq. fma_exp: the bit-level exponential (the paper's fast path)
+    EXP_LIBM = 1,   // min(0.99, expf(P)): the exponential's ablation
+    EXP_HW2 = 2,    // min(0.99, v_exp_f32(P log2 e)) with log2 e folded into C1..C6
+};
+constexpr float LOG2E_F = 1.4426950408889634f;
+constexpr float LOG2_255F = 7.994353436858858f;     // ln 255 * log2 e
+
+template <bool COUNT, int EXPM>
 __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev ws,
                                                               const uint32_t* __restrict__ vals) {
+    constexpr bool EXACT = EXPM == EXP_LIBM;
     // per-wave lists of folded Gaussians, in depth order
     __shared__ float4 s_a[2][LIST_CAP];   // C1, C2, C3, C4
     __shared__ float4 s_b[2][LIST_CAP];   // C5, C6, r, g
@@ -222,6 +232,11 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
             ca = make_float4(-0.5f * A, -B, -0.5f * C, fmaf(A, u, B * v));
             cbv = make_float4(fmaf(C, v, B * u), fmaf(-0.5f, C0, rec.opa), rec.r, rec.g);
             cb = rec.b;
+            if (EXPM == EXP_HW2) {       // P log2 e directly: alpha = exp2 of it
+                ca = make_float4(ca.x * LOG2E_F, ca.y * LOG2E_F, ca.z * LOG2E_F, ca.w * LOG2E_F);
+                cbv.x *= LOG2E_F;
+                cbv.y *= LOG2E_F;
+            }
             // the box |x - u| <= hx, |y - v| <= hy holds every pixel with
             // P >= -ln 255 (half-extents from the front end, rounded up, then
             // widened); a half-tile outside it has no pair that passes the skip
@@ -286,12 +301,16 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
                     const float2 c = lc[k0 + u];
                     const float P0 = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(m.x, y, m.y)))));
                     const float P1 = P0 + fmaf(a.y, x, fmaf(a.z, y21, m.x));
-                    const bool pass0 = live0 && P0 >= -LN255F;
-                    const bool pass1 = live1 && P1 >= -LN255F;
+                    constexpr float SKIP = EXPM == EXP_HW2 ? -LOG2_255F : -LN255F;
+                    const bool pass0 = live0 && P0 >= SKIP;
+                    const bool pass1 = live1 && P1 >= SKIP;
                     float al0, al1;
                     if (EXACT) {          // the exponential's ablation: alpha = min(0.99, exp(P))
                         al0 = pass0 ? fminf(ALPHA_MAX, expf(P0)) : 0.0f;
                         al1 = pass1 ? fminf(ALPHA_MAX, expf(P1)) : 0.0f;
+                    } else if (EXPM == EXP_HW2) {
+                        al0 = pass0 ? fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(P0)) : 0.0f;
+                        al1 = pass1 ? fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(P1)) : 0.0f;
                     } else {
                         // alpha = min(0.99, exp_hat(P)) without the minimum, which cannot bind here:
                         // P = ln o - q/2 with ln o <= 0 and q >= 0, and for a kept pair every term of
@@ -557,13 +576,13 @@ __global__ __launch_bounds__(256 / PIX) void k_raster_fast_px(FrameDev f, WsDev 
     }
 }
 
-template <bool EXACT>
+template <int EXPM>
 static void launch_fast_dual(hipStream_t s, const FrameDev& f, const WsDev& ws, const uint32_t* vals, bool count) {
     if (count)
-        hipLaunchKernelGGL((k_raster_fast<true, EXACT>), dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
+        hipLaunchKernelGGL((k_raster_fast<true, EXPM>), dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
                            vals);
     else
-        hipLaunchKernelGGL((k_raster_fast<false, EXACT>), dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
+        hipLaunchKernelGGL((k_raster_fast<false, EXPM>), dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
                            vals);
 }
 
@@ -582,8 +601,9 @@ void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool 
                         uint32_t opts) {
     const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
     const bool exact = (opts & OPT_FASTEXP) != 0, single = (opts & OPT_DUALPIXEL) != 0;
-    if (!exact && !single) launch_fast_dual<false>(s, f, ws, vals, count);
-    else if (exact && !single) launch_fast_dual<true>(s, f, ws, vals, count);
+    if (opts & OPT_HW_EXP2) launch_fast_dual<EXP_HW2>(s, f, ws, vals, count);   // not with the two above
+    else if (!exact && !single) launch_fast_dual<EXP_BITS>(s, f, ws, vals, count);
+    else if (exact && !single) launch_fast_dual<EXP_LIBM>(s, f, ws, vals, count);
     else if (!exact && single) launch_fast_single<false>(s, f, ws, vals, count);
     else launch_fast_single<true>(s, f, ws, vals, count);
 }

@@ -425,7 +425,8 @@ static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 // The base path (RGS_PATH_PLAIN / RGS_PATH_FAST) and the ablation bits of a
 // path argument.
 static int32_t path_base(int32_t path) { return path & 0xff; }
-static uint32_t path_opts(int32_t path) { return ((uint32_t)path & (RGS_ABLATE_MASK | RGS_EXACT_TILES)) >> 8; }
+static constexpr uint32_t PATH_BITS = RGS_ABLATE_MASK | RGS_EXACT_TILES | RGS_HW_EXP2;
+static uint32_t path_opts(int32_t path) { return ((uint32_t)path & PATH_BITS) >> 8; }
 
 static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t capacity, WsLayout& L) {
     const bool plain = path_base(path) == RGS_PATH_PLAIN;
@@ -487,14 +488,17 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     L.total = off;
 }
 
-static rgs_status check_path(int32_t path) {
+rgs_status rgs::check_path(int32_t path) {
     const int32_t base = path_base(path);
-    if ((base != RGS_PATH_PLAIN && base != RGS_PATH_FAST) || (path & ~(0xff | RGS_ABLATE_MASK | RGS_EXACT_TILES)))
+    if ((base != RGS_PATH_PLAIN && base != RGS_PATH_FAST) || ((uint32_t)path & ~(0xffu | PATH_BITS)))
         return fail(RGS_E_INVALID, "path 0x%x is neither RGS_PATH_PLAIN nor RGS_PATH_FAST with ablation bits", path);
     if (base == RGS_PATH_PLAIN && path_opts(path))
         return fail(RGS_E_INVALID, "ablation and extension bits apply to the fast path only");
     if ((path & RGS_EXACT_TILES) && (path & RGS_ABLATE_EXTENT))
         return fail(RGS_E_INVALID, "RGS_EXACT_TILES refines the alpha-ellipse extent that RGS_ABLATE_EXTENT removes");
+    if ((path & RGS_HW_EXP2) && (path & (RGS_ABLATE_FASTEXP | RGS_ABLATE_DUALPIXEL)))
+        return fail(RGS_E_INVALID, "RGS_HW_EXP2 replaces the exponential of the dual-pixel rasterizer; "
+                                   "not with RGS_ABLATE_FASTEXP or RGS_ABLATE_DUALPIXEL");
     return RGS_OK;
 }
 

@@ -42,6 +42,8 @@ struct FrameLaunch {
 rgs_status prepare_frame(const rgs_scene* sc, int32_t width, int32_t height, int32_t path, void* ws,
                          uint64_t ws_bytes, FrameLaunch* fl);
 rgs_status check_camera(const rgs_camera* c);
+// A `path` argument: RGS_PATH_PLAIN, or RGS_PATH_FAST with ablation and extension bits.
+rgs_status check_path(int32_t path);
 FrameParams frame_params(const rgs_camera* c, float* out);
 int scene_device(const rgs_scene* sc);
 

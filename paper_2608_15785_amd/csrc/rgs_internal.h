@@ -61,7 +61,7 @@ enum PlainPlane { P_MX = 0, P_MY, P_MZ, P_SX, P_SY, P_SZ, P_QW, P_QX, P_QY, P_QZ
 
 // Fast-path ablation bits (the path argument's bits 8..14, shifted down).
 constexpr uint32_t OPT_FASTEXP = 1u, OPT_DUALPIXEL = 2u, OPT_FUSION = 4u, OPT_EXTENT = 8u, OPT_KEY32 = 16u,
-                   OPT_INT8_SH = 32u, OPT_FP16_GEOM = 64u, OPT_EXACT_TILES = 128u;
+                   OPT_INT8_SH = 32u, OPT_FP16_GEOM = 64u, OPT_EXACT_TILES = 128u, OPT_HW_EXP2 = 256u;
 // Fast-format planes (32-bit words, one per plane, each n_pad long).
 //   F_MX..F_MZ   float32 mean
 //   F_QWX, F_QYZ FP16 pairs (w, x), (y, z) of the quaternion

@@ -279,9 +279,7 @@ rgs_status check_request(const rgs_server* s, const rgs_request& r, double prev_
     if (!(std::isfinite(r.arrival) && r.arrival >= prev_arrival))
         return fail(RGS_E_INVALID, "arrivals must be finite, >= 0 and non-decreasing");
     const int32_t base = r.path & 0xff;
-    if ((base != RGS_PATH_PLAIN && base != RGS_PATH_FAST) || (r.path & ~(0xff | RGS_ABLATE_MASK)) ||
-        (base == RGS_PATH_PLAIN && (r.path & RGS_ABLATE_MASK)))
-        return fail(RGS_E_INVALID, "bad path 0x%x", r.path);
+    if (check_path(r.path) != RGS_OK) return fail(RGS_E_INVALID, "bad path 0x%x", r.path);
     int64_t n = 0;
     uint32_t formats = 0;
     uint64_t bytes = 0;

@@ -73,13 +73,16 @@ def test_path_words_are_validated():
     """Ablation and extension bits: accepted on the fast path, rejected on the plain path, and the
     exact ellipse-tile test is rejected together with the extent ablation it refines."""
     ok = ["fast/no-fusion", "fast/exact-tiles", "fast/no-fusion/exact-tiles", "fast/no-key32/exact-tiles",
+          "fast/hw-exp2", "fast/hw-exp2/exact-tiles", "fast/no-key32/hw-exp2",
           "fast/" + "/".join("no-" + a for a in B.ABLATIONS)]
     for p in ok:
         assert rgs.workspace_size(1000, 64, 64, p, 4096) > 0
     size = C.c_uint64()
     for word in (B.PATH_FAST | B.ABLATIONS["extent"] | B.EXTENSIONS["exact-tiles"],
                  B.PATH_PLAIN | B.EXTENSIONS["exact-tiles"], B.PATH_PLAIN | B.ABLATIONS["fusion"],
-                 B.PATH_FAST | (1 << 16), 2):
+                 B.PATH_FAST | B.ABLATIONS["fastexp"] | B.EXTENSIONS["hw-exp2"],
+                 B.PATH_FAST | B.ABLATIONS["dualpixel"] | B.EXTENSIONS["hw-exp2"],
+                 B.PATH_PLAIN | B.EXTENSIONS["hw-exp2"], B.PATH_FAST | (1 << 17), 2):
         assert B.lib.rgs_workspace_size(1000, 64, 64, word, 4096, C.byref(size)) == B.RGS_E_INVALID, hex(word)
     for bad in ("fast/no-nothing", "fast/exact", "plain/exact-tiles", "fast/"):
         with pytest.raises(KeyError):

@@ -1,0 +1,71 @@
+"""gfx950 variants of the fast rasterizer, through the C ABI, against the oracle
+(needs an MI355X).  RGS_HW_EXP2 takes alpha = min(0.99, exp2(P log2 e)) from
+the hardware exp2 instruction: its image is the exact-exponential oracle's, to
+the same 2e-3 bar as the exponential's ablation; front end and entries are the
+fast path's, bit-exact."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from parity import compare_entries, compare_front_end, compare_image, oracle_frame_ablated
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2608_15785_amd as rgs
+    return rgs.Renderer(0)
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def run(R, scene, cam, path, exact_tiles=False):
+    _log(f"[variant] {path} n={scene.n} {cam.width}x{cam.height}")
+    ds = R.upload(scene, ("plain", "fast"))
+    g = R.render_debug(ds, cam, path)
+    ds.release()
+    # the oracle with the exact exponential (the hardware exp2 is exact to an ulp)
+    fr = oracle_frame_ablated(scene, cam, ["fastexp"], exact_tiles=exact_tiles)
+    compare_front_end(g, fr)
+    compare_entries(g, fr)
+    rep = compare_image(g["image"], fr, "fast")
+    mask = ~fr.flagged & ~(fr.mode_slack > 0) & ~np.isnan(fr.T_final)
+    assert np.array_equal(g["n_proc"][mask], fr.n_proc[mask].astype(np.uint32)), "pair counts differ"
+    _log(f"[variant] {path}: {rep}")
+    return g
+
+
+def test_hw_exp2_cfg0(R):
+    run(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), "fast/hw-exp2")
+
+
+def test_hw_exp2_ragged(R):
+    run(R, wl.config_scene("cfg0", n=2500), wl.config_camera("cfg0", width=250, height=170), "fast/hw-exp2")
+
+
+def test_hw_exp2_with_exact_tiles(R):
+    run(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), "fast/hw-exp2/exact-tiles", exact_tiles=True)
+
+
+def test_hw_exp2_close_to_exact_exp_ablation(R):
+    """The hardware exp2 and the accurate expf give the same image to float32 rounding."""
+    sc = wl.config_scene("cfg0")
+    cam = wl.config_camera("cfg0")
+    ds = R.upload(sc, ("plain", "fast"))
+    a = R.render_debug(ds, cam, "fast/hw-exp2")
+    b = R.render_debug(ds, cam, "fast/no-fastexp")
+    ds.release()
+    d = np.abs(a["image"] - b["image"])
+    _log(f"[variant] hw-exp2 vs expf: max {float(d.max()):.2e}, share > 1e-5: {float(np.mean(d > 1e-5)):.2e}")
+    assert float(np.mean(d > 1e-3)) < 1e-3
