@@ -38,7 +38,10 @@ Every key-defining quantity (d, u, v, Sigma', the extents) is computed with
 the elementwise float64 operations below, evaluated left to right exactly as
 written, with no fused multiply-add; division and square root are the
 correctly rounded IEEE operations.  The HIP front end evaluates the same
-expressions in the same order, so both sides produce identical bits.
+expressions in the same order, so both sides produce identical bits.  The
+paper fixes no evaluation order; ours divides once for 1/d and once for the
+quaternion's 1/|q| and multiplies them in (mathematically the definitions
+above).
 
 SH colour (Sec. III-A, degree 3): view-dependent RGB from 16 coefficients per
 channel, evaluated along the unit direction from the camera centre to the
@@ -77,11 +80,11 @@ class Projection:
 def quat_to_rotation(q: np.ndarray) -> np.ndarray:
     """Rotation matrices [n,3,3] of quaternions q = (w, x, y, z), normalised first."""
     qw, qx, qy, qz = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
-    nn = np.sqrt(qw * qw + qx * qx + qy * qy + qz * qz)
-    w = qw / nn
-    x = qx / nn
-    y = qy / nn
-    z = qz / nn
+    inn = 1.0 / np.sqrt(qw * qw + qx * qx + qy * qy + qz * qz)
+    w = qw * inn
+    x = qx * inn
+    y = qy * inn
+    z = qz * inn
     R = np.empty((q.shape[0], 3, 3))
     R[:, 0, 0] = 1.0 - 2.0 * (y * y + z * z)
     R[:, 0, 1] = 2.0 * (x * y - w * z)
@@ -122,12 +125,14 @@ def project_ewa(means, quats, scales, cam):
 
     limx = J_CLAMP * cam.tan_half_fovx
     limy = J_CLAMP * cam.tan_half_fovy
-    xc = np.minimum(limx, np.maximum(-limx, tx / d)) * d
-    yc = np.minimum(limy, np.maximum(-limy, ty / d)) * d
-    j00 = cam.fx / d
-    j02 = -(cam.fx * xc) / (d * d)
-    j11 = cam.fy / d
-    j12 = -(cam.fy * yc) / (d * d)
+    rd = 1.0 / d
+    rd2 = rd * rd
+    xc = np.minimum(limx, np.maximum(-limx, tx * rd)) * d
+    yc = np.minimum(limy, np.maximum(-limy, ty * rd)) * d
+    j00 = cam.fx * rd
+    j02 = -(cam.fx * xc) * rd2
+    j11 = cam.fy * rd
+    j12 = -(cam.fy * yc) * rd2
 
     # T = J R_w (2x3); J has zeros at (0,1) and (1,0)
     T = np.empty((means.shape[0], 2, 3))
@@ -143,8 +148,8 @@ def project_ewa(means, quats, scales, cam):
     cov01 = U[:, 0, 0] * T[:, 1, 0] + U[:, 0, 1] * T[:, 1, 1] + U[:, 0, 2] * T[:, 1, 2]
     cov11 = U[:, 1, 0] * T[:, 1, 0] + U[:, 1, 1] * T[:, 1, 1] + U[:, 1, 2] * T[:, 1, 2] + DILATION
 
-    u = cam.fx * tx / d + cam.cx
-    v = cam.fy * ty / d + cam.cy
+    u = cam.fx * tx * rd + cam.cx
+    v = cam.fy * ty * rd + cam.cy
     return tx, ty, d, u, v, cov00, cov01, cov11
 
 

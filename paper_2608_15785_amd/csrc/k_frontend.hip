@@ -59,7 +59,7 @@ __device__ inline ShBasis sh_basis(float x, float y, float z) {
 
 __device__ inline ShBasis view_basis(float mx, float my, float mz, const CamDev& cam) {
     float dx = mx - cam.campos[0], dy = my - cam.campos[1], dz = mz - cam.campos[2];
-    float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);     // v_rsq_f32, 1 ulp
     return sh_basis(dx * inv, dy * inv, dz * inv);
 }
 
@@ -88,7 +88,8 @@ __device__ inline void write_record(Record* rec, const Projected& p, float opa, 
                                     float b, uint32_t extra) {
     float uh = (float)p.u, vh = (float)p.v;
     float4 a = make_float4(uh, (float)(p.u - (double)uh), vh, (float)(p.v - (double)vh));
-    float4 m = make_float4((float)(p.c11 / p.det), (float)(-p.c01 / p.det), (float)(p.c00 / p.det), opa);
+    const double idet = 1.0 / p.det;
+    float4 m = make_float4((float)(p.c11 * idet), (float)(-p.c01 * idet), (float)(p.c00 * idet), opa);
     float4 c = make_float4(r, g, b, __uint_as_float(extra));
     float4* dst = reinterpret_cast<float4*>(rec);
     dst[0] = a;

@@ -212,8 +212,8 @@ __host__ __device__ inline bool project_gaussian(const CamDev& c, double mx, dou
     if (!(d > c.zn && d <= c.zf)) return false;
     if (fast && alpha_extent && !(lno >= -LN255)) return false;
 
-    double nn = sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-    double w = qw / nn, x = qx / nn, y = qy / nn, z = qz / nn;
+    double inn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    double w = qw * inn, x = qx * inn, y = qy * inn, z = qz * inn;
     double R00 = 1.0 - 2.0 * (y * y + z * z);
     double R01 = 2.0 * (x * y - w * z);
     double R02 = 2.0 * (x * z + w * y);
@@ -236,12 +236,14 @@ __host__ __device__ inline bool project_gaussian(const CamDev& c, double mx, dou
 
     double limx = J_CLAMP * c.tanx;
     double limy = J_CLAMP * c.tany;
-    double xc = fmin(limx, fmax(-limx, tx / d)) * d;
-    double yc = fmin(limy, fmax(-limy, ty / d)) * d;
-    double j00 = c.fx / d;
-    double j02 = -(c.fx * xc) / (d * d);
-    double j11 = c.fy / d;
-    double j12 = -(c.fy * yc) / (d * d);
+    double rd = 1.0 / d;
+    double rd2 = rd * rd;
+    double xc = fmin(limx, fmax(-limx, tx * rd)) * d;
+    double yc = fmin(limy, fmax(-limy, ty * rd)) * d;
+    double j00 = c.fx * rd;
+    double j02 = -(c.fx * xc) * rd2;
+    double j11 = c.fy * rd;
+    double j12 = -(c.fy * yc) * rd2;
     // T = J R_w
     double T00 = j00 * r[0] + j02 * r[6];
     double T01 = j00 * r[1] + j02 * r[7];
@@ -264,8 +266,8 @@ __host__ __device__ inline bool project_gaussian(const CamDev& c, double mx, dou
     o.c11 = c11;
     double det = c00 * c11 - c01 * c01;
     o.det = det;
-    double u = c.fx * tx / d + c.cx;
-    double v = c.fy * ty / d + c.cy;
+    double u = c.fx * tx * rd + c.cx;
+    double v = c.fy * ty * rd + c.cy;
     o.u = u;
     o.v = v;
     if (!(det > 0.0)) return false;
