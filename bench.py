@@ -91,11 +91,12 @@ def kernel_sha(name):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload, src):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current source of the kernel; else None."""
+def measured_counters(kernel, workload, src):
+    """The committed rocprofv3 counter record of a kernel (HBM bytes and VALU
+    wave instructions per launch), if it was taken on the current source of
+    the kernel; else {}."""
     if not os.path.exists(TRAFFIC_FILE):
-        return None
+        return {}
     for line in open(TRAFFIC_FILE):
         line = line.strip()
         if not line.startswith("{"):
@@ -103,8 +104,13 @@ def measured_traffic(kernel, workload, src):
         rec = json.loads(line)
         if rec.get("kernel") == kernel and rec.get("workload") == workload and \
                 rec.get("source_sha") == kernel_sha(src):
-            return rec.get("bytes_per_launch")
-    return None
+            return rec
+    return {}
+
+
+def measured_traffic(kernel, workload, src):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    return measured_counters(kernel, workload, src).get("bytes_per_launch")
 
 
 def time_path(R, ds, cams, path, steps, warmup, lat_frames):
@@ -461,9 +467,16 @@ def main():
     src = {"raster": "k_raster.hip", "frontend": "k_frontend.hip", "duplicate": "k_frontend.hip",
            "sort": "k_sort.hip", "ranges": "k_sort.hip"}[dom]
     rl = dict(stages[dom])
+    counters = measured_counters(kernel, "cfg1-" + main_path, src)
     roofline = {"bound": rl["bound"], "achieved": rl["achieved"], "peak": rl["peak"], "unit": rl["unit"],
-                "frac": rl["frac"], "traffic": measured_traffic(kernel, "cfg1-" + main_path, src),
+                "frac": rl["frac"], "traffic": counters.get("bytes_per_launch"),
                 "kernel": kernel, "stage_ms": rl["ms"]}
+    if counters.get("valu_wave_insts"):
+        # VALU wave instructions the kernel issued (SQ_INSTS_VALU, all pairs it evaluated), per SIMD and
+        # cycle of its measured duration: a wave64 instruction every 4 cycles is 0.25
+        roofline["valu_wave_insts"] = counters["valu_wave_insts"]
+        roofline["valu_insts_per_simd_cycle"] = round(
+            counters["valu_wave_insts"] / (rl["ms"] * 1e-3 * 1024 * 2.4e9), 3)
 
     out = {
         "metric": METRIC,
