@@ -61,22 +61,26 @@ void launch_update_plain(hipStream_t s, float* planes, uint64_t n_pad, int64_t n
 }
 
 // ---------------------------------------------------------------------------
-// Sum over the 64 lanes of a wave, valid in lane 63: two quad permutations,
-// two row shifts, then the row broadcasts 15 and 31 (each a DPP-modified add).
+// Row sums of N values at once: after two quad permutations and two row
+// shifts (each a DPP-modified add) lane 16 r + 15 holds the sum over row r of
+// the wave.  The N chains are independent, so the DPP instructions of one
+// value are spaced by those of the others and need no wait states.
 
-template <int CTRL, int ROW_MASK>
+template <int CTRL>
 __device__ inline float dpp_moved(float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
-__device__ inline float wave_sum_last(float v) {
-    v += dpp_moved<0xb1, 0xf>(v);     // quad_perm [1,0,3,2]
-    v += dpp_moved<0x4e, 0xf>(v);     // quad_perm [2,3,0,1]
-    v += dpp_moved<0x114, 0xf>(v);    // row_shr:4
-    v += dpp_moved<0x118, 0xf>(v);    // row_shr:8
-    v += dpp_moved<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
-    v += dpp_moved<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
-    return v;
+template <int N>
+__device__ inline void row_sums(float (&g)[N]) {
+#pragma unroll
+    for (int c = 0; c < N; ++c) g[c] += dpp_moved<0xb1>(g[c]);     // quad_perm [1,0,3,2]
+#pragma unroll
+    for (int c = 0; c < N; ++c) g[c] += dpp_moved<0x4e>(g[c]);     // quad_perm [2,3,0,1]
+#pragma unroll
+    for (int c = 0; c < N; ++c) g[c] += dpp_moved<0x114>(g[c]);    // row_shr:4
+#pragma unroll
+    for (int c = 0; c < N; ++c) g[c] += dpp_moved<0x118>(g[c]);    // row_shr:8
 }
 
 // Position, in emission order, of Gaussian g's entry for tile (tx, ty).
@@ -91,6 +95,7 @@ __device__ inline uint64_t emission_pos(const WsDev& ws, uint32_t g, uint32_t tx
 constexpr int BWD_LANES = 64;
 constexpr int BWD_PIX = 4;
 constexpr int BWD_BATCH = 64;
+constexpr int BWD_ROWS = BWD_LANES / 16;     // DPP rows of the wave
 
 // Row bands k (tile rows 4k .. 4k+3) that can hold a pixel with alpha >= 1/255
 // for a Gaussian at tile-local (u, v) with conic (A, B, C) and opacity o: the
@@ -119,7 +124,8 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
     __shared__ float4 s_b[BWD_BATCH];          // C, o, r, g
     __shared__ float s_c[BWD_BATCH];           // b
     __shared__ uint32_t s_band[BWD_BATCH];     // row bands the entry can reach
-    __shared__ float s_acc[9][BWD_BATCH];      // the entry sums of the batch
+    __shared__ float4 s_acc4[9 * BWD_ROWS * BWD_BATCH / 4];   // per-row entry sums of the batch
+    float* s_acc = reinterpret_cast<float*>(s_acc4);              // [9][BWD_ROWS][BWD_BATCH]
     const uint32_t tile = bwd_xcd_tile(blockIdx.x, (uint32_t)f.n_tiles);
     if (tile >= (uint32_t)f.n_tiles) return;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
@@ -175,8 +181,8 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
             s_band[lane] = band_mask((rec.v_hi - oy) + rec.v_lo, rec.A, rec.B, rec.C, rec.opa);
             my_pos = emission_pos(ws, g, tx, ty);
         }
-#pragma unroll
-        for (int c = 0; c < 9; ++c) s_acc[c][lane] = 0.0f;
+        for (uint32_t q = lane; q < 9 * BWD_ROWS * BWD_BATCH / 4; q += BWD_LANES)
+            s_acc4[q] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         for (int j = (int)cnt - 1; j >= 0; --j) {
             const uint32_t idx = b0 + (uint32_t)j;
@@ -224,19 +230,26 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
                 }
             }
             if (__ballot(any) != 0) {
+                row_sums(g);
+                if ((lane & 15) == 15) {
+                    const uint32_t r = lane >> 4;
 #pragma unroll
-                for (int c = 0; c < 9; ++c) {
-                    const float sum = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_last(g[c])), 63));
-                    if (lane == 0) s_acc[c][j] = sum;
+                    for (int c = 0; c < 9; ++c) s_acc[(c * BWD_ROWS + r) * BWD_BATCH + j] = g[c];
                 }
             }
         }
         __syncthreads();
         if (lane < cnt) {
             float4* dst = partial + 3ull * my_pos;
-            dst[0] = make_float4(s_acc[0][lane], s_acc[1][lane], s_acc[2][lane], s_acc[3][lane]);
-            dst[1] = make_float4(s_acc[4][lane], s_acc[5][lane], s_acc[6][lane], s_acc[7][lane]);
-            dst[2] = make_float4(s_acc[8][lane], 0.0f, 0.0f, 0.0f);
+            float sum[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                const float* row = s_acc + c * BWD_ROWS * BWD_BATCH + lane;
+                sum[c] = (row[0] + row[BWD_BATCH]) + (row[2 * BWD_BATCH] + row[3 * BWD_BATCH]);
+            }
+            dst[0] = make_float4(sum[0], sum[1], sum[2], sum[3]);
+            dst[1] = make_float4(sum[4], sum[5], sum[6], sum[7]);
+            dst[2] = make_float4(sum[8], 0.0f, 0.0f, 0.0f);
         }
         b_end = b0;
     }
