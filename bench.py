@@ -72,18 +72,37 @@ def parse():
 
 
 def stage_bytes(path, n, n_vis, n_dup, n_tiles, passes):
-    """Algorithmic HBM bytes per frame of each memory-bound stage."""
-    if path == "fast":
-        fe = 28 * n + 72 * n_vis + 48 * n_vis + 8 * n_dup
-        dup = 0
-        kb = 4
-    else:
+    """Algorithmic HBM bytes per frame of each memory-bound stage.  `path` is
+    "plain", "fast", or a fast-path variant "fast/no-<step>/.../<extension>"
+    whose removed steps change what is read and written."""
+    parts = path.split("/")
+    if parts[0] == "plain":
         fe = 44 * n + 192 * n_vis + (48 + 8 + 4) * n_vis + 4 * n
         dup = 4 * n + 12 * n_vis + 12 * n_dup
         kb = 8
+    else:
+        off = {p[3:] for p in parts[1:] if p.startswith("no-")}
+        kb = 8 if "key32" in off else 4
+        geom = 12 + (32 if "fp16geom" in off else 16)      # mean + rotation, scale, ln o
+        sh = 192 if "int8sh" in off else 72                 # FP32 SH, or INT8 SH + FP16 scales
+        fe = geom * n + sh * n_vis + 48 * n_vis
+        if "fusion" in off:       # preprocess writes count, rectangle, depth; duplicate reads them
+            fe += 4 * n + 12 * n_vis
+            dup = 4 * n + 12 * n_vis + (kb + 4) * n_dup
+        else:
+            fe += (kb + 4) * n_dup
+            dup = 0
     sort = passes * 2 * (kb + 4) * n_dup          # Eq. sort_memory: read + write per pass
     ranges = kb * n_dup + 8 * n_tiles
     return dict(frontend=fe, duplicate=dup, sort=sort, ranges=ranges)
+
+
+def ops_per_pair(path):
+    """Algorithmic lane-ops per blended pair of a path or fast-path variant (an
+    exponential counts 2, as in Eq. fma_exp or a scale and an exp2)."""
+    if path == "plain":
+        return OPS_PER_PAIR["plain"]
+    return OPS_PER_PAIR["fast"] + (1 if "no-dualpixel" in path.split("/") else 0)
 
 
 def kernel_sha(name):
@@ -174,11 +193,11 @@ def rooflines(path, counts, stage_ms, n, n_tiles):
             out[s] = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=round(gbs / HBM_PEAK_GBS, 4), bytes=int(b), ms=round(ms, 4))
     ms = stage_ms["raster"]
-    tops = counts["pairs"] * OPS_PER_PAIR[path] / (ms * 1e-3) / 1e12
+    ops = ops_per_pair(path)
+    tops = counts["pairs"] * ops / (ms * 1e-3) / 1e12
     out["raster"] = dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 2),
                          unit="Tops/s", frac=round(tops / VALU_PEAK_TOPS, 4), pairs_blended=counts["pairs"],
-                         pairs_visited=counts["pairs_visited"], ops_per_pair=OPS_PER_PAIR[path],
-                         ms=round(ms, 4))
+                         pairs_visited=counts["pairs_visited"], ops_per_pair=ops, ms=round(ms, 4))
     return out
 
 
@@ -278,7 +297,7 @@ def serving_section(rgs, wl, torch, dev_scenes, args):
 ABLATIONS = ["fastexp", "dualpixel", "fusion", "extent", "key32", "int8sh", "fp16geom"]
 
 
-def ablation_section(R, ds, cam, steps):
+def ablation_section(R, ds, cam, steps, n_tiles):
     """The fast path with each of Sec. IV's optimisations removed in turn (and
     all of them), and with each extension (the exact ellipse-tile test, the
     hardware exp2) added, on the 1M/1080p workload: FPS, stage times, entries,
@@ -290,9 +309,11 @@ def ablation_section(R, ds, cam, steps):
         r = time_path(R, ds, [cam], path, steps, 10, 20)
         c = frame_counts(R, ds, cam, path)
         name = "all" if path.count("/") > 1 else path.replace("fast/no-", "no-").replace("fast/", "+")
+        rl = rooflines(path, c, r["stage_ms"], ds.n, n_tiles)
         out[name] = {"fps": round(r["fps"], 1), "ms_per_frame": round(r["ms_per_frame"], 4),
                      "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
-                     "n_entries": c["n_entries"], "passes": c["passes"], "pairs_visited": c["pairs_visited"]}
+                     "n_entries": c["n_entries"], "passes": c["passes"], "pairs_visited": c["pairs_visited"],
+                     "roofline_frac": {k: v["frac"] for k, v in rl.items()}}
         log(f"[bench] ablation {path}: {out[name]['fps']} FPS, stages {out[name]['stage_ms']}")
     base = out["fast"]["fps"]
     for k, v in out.items():
@@ -417,7 +438,7 @@ def main():
     ablation = None
     if not args.no_ablation and "fast" in paths:
         log("[bench] ablation: the fast path without each optimisation, 1M Gaussians at 1080p")
-        ablation = ablation_section(R, ds1, cam1, args.ablation_steps)
+        ablation = ablation_section(R, ds1, cam1, args.ablation_steps, plan1["n_tiles"])
 
     diff = None
     if not args.no_backward:
