@@ -7,28 +7,35 @@
 //
 // The kernel that writes the keys (the front end) also counts every pass's
 // digits into the workspace histogram and clears the first pass's look-back
-// words; each pass is then one kernel over radix tiles of 4096 keys:
-//   * a tile takes its index from a ticket counter, loads its keys, ranks each
-//     key among equal digits of the tile with wave64 ballots (stable: tile
-//     order is input order) and publishes its 256 digit counts;
+// words; each pass is then one kernel over radix tiles of 4096 keys, block b
+// taking keys [4096 b, 4096 (b + 1)):
+//   * the tile loads its keys, ranks each key among equal digits of the tile
+//     with wave64 ballots (stable: tile order is input order) and publishes
+//     its 256 digit counts;
 //   * it then sums the counts of the tiles before it: the earlier tiles of its
 //     group of SORT_GROUP, and one published total per earlier group (the last
-//     tile of a group publishes the group's total).  A frame's tiles are all
-//     resident at once and publish at about the same time; this two-level sum
-//     keeps every tile's wait at two round trips instead of a chain through all
-//     its predecessors;
+//     tile of a group publishes the group's total).  A frame's tiles mostly
+//     run at once and publish at about the same time; this two-level sum keeps
+//     every tile's wait at two round trips instead of a chain through all its
+//     predecessors;
 //   * it reorders the tile in LDS by digit and writes it out, so consecutive
 //     threads store consecutive positions of a digit bucket.
-// A tile only waits on tiles with smaller tickets, which are already running,
-// so the passes cannot deadlock however many tiles are resident.  The two sets
-// of look-back words alternate between passes: a pass clears its tile's words
-// of the set the next pass uses.
+// Nothing guarantees that the workgroups of a grid run at once or in order
+// (another stream's kernels may hold the CUs), so no tile waits without
+// bound: a word still unpublished after LOOKBACK_POLLS polls is replaced by
+// counting that tile's keys directly (a decoupled look-back with fallback).
+// Taking tiles from an atomic ticket instead, which would make waiting safe,
+// costs more than the whole look-back: tickets on one address serialise at
+// about 11 ns each.  The two sets of look-back words alternate between
+// passes: a pass clears its tile's words of the set the next pass uses.
 // Ties keep input order, and the front end emits entries in Gaussian-index
 // order, so equal keys end ordered by Gaussian index.
 //
 // Grids are sized for the workspace capacity; the entry count is read from
 // the workspace header on the device and tiles beyond it return at once, so
 // no host round trip sits between the front end and the sort.
+#include <cstdlib>
+
 #include "rgs_internal.h"
 
 namespace rgs {
@@ -65,12 +72,64 @@ __device__ inline uint32_t digit_exclusive_scan(uint32_t x, uint32_t* s_wtot) {
     return incl - x + before;
 }
 
-// Sum over rows r0 + s, r0 + s + SORT_SPLIT, ... < r1 of column d of a
-// look-back table, waiting for each word's ready flag (bounded: on giving up
-// the header's error bit 3 is set and the word counts as zero).
-__device__ inline uint32_t lookback_sum(const uint32_t* tab, uint32_t r0, uint32_t r1, uint32_t s, uint32_t d,
-                                        WsHeader* hdr) {
+// Polls of a not yet published look-back word (each a sleep and a reload,
+// about a microsecond) before the waiting tile counts the missing row itself.
+constexpr uint32_t LOOKBACK_POLLS = 64;
+
+// Shared memory of the look-back (inside the pass kernel's s_whist once the
+// tile is reordered): per-thread partial sums, a block-wide flag, and two
+// 256-digit count rows for the fallback.
+struct LookbackLds {
+    uint32_t* part;     // [SORT_SPLIT][RADIX]
+    uint32_t* flag;     // one word
+    uint32_t* fb;       // [RADIX] digit counts of one tile
+    uint32_t* acc;      // [RADIX] digit counts of one group
+};
+
+// Block-wide: fb[d] = keys of tile t (of the pass input) whose digit is d.
+template <typename KeyT>
+__device__ inline void count_tile(const KeyT* __restrict__ kin, uint32_t t, uint32_t n, uint32_t shift,
+                                  uint32_t* fb) {
+    constexpr uint32_t SIZE = SortTile<KeyT>::SIZE;
+    for (uint32_t i = threadIdx.x; i < RADIX; i += SORT_THREADS) fb[i] = 0;
+    __syncthreads();
+    const uint32_t base = t * SIZE, cnt = min(SIZE, n - base);
+    for (uint32_t i = threadIdx.x; i < cnt; i += SORT_THREADS) atomicAdd(&fb[digit_of(kin[base + i], shift)], 1u);
+    __syncthreads();
+}
+
+// Block-wide: out[d] = the counts of tile row t, from its published words
+// where all 256 are ready, else counted from the tile's keys.
+template <typename KeyT>
+__device__ inline void tile_row(const uint32_t* tiles, const KeyT* __restrict__ kin, uint32_t t, uint32_t n,
+                                uint32_t shift, const LookbackLds& L, uint32_t* out, bool force) {
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) *L.flag = force ? 1u : 0u;
+    __syncthreads();
+    uint32_t w = SORT_READY;
+    if (tid < RADIX && !force) {
+        w = ld_state(&tiles[(uint64_t)t * RADIX + tid]);
+        if (!(w & SORT_READY)) *L.flag = 1;
+    }
+    __syncthreads();
+    if (*L.flag) {
+        count_tile(kin, t, n, shift, L.fb);
+        if (tid < RADIX) out[tid] = L.fb[tid];
+    } else if (tid < RADIX) {
+        out[tid] = w & ~SORT_READY;
+    }
+    __syncthreads();
+}
+
+// Keys of digit d = tid % RADIX in rows [r0, r1) of a look-back table (tile
+// rows, or group rows of SORT_GROUP tiles), this thread's share: rows
+// r0 + s, r0 + s + SORT_SPLIT, ... with s = tid / RADIX.  Each word is polled
+// at most LOOKBACK_POLLS times; `ok` turns false when one is still unpublished.  No
+// barrier: the block votes on `ok` later and, if any thread missed a word,
+// takes the range again with fallback_range.
+__device__ inline uint32_t poll_range(const uint32_t* tab, uint32_t r0, uint32_t r1, bool& ok) {
     constexpr int BATCH = 16;
+    const uint32_t d = threadIdx.x % RADIX, s = threadIdx.x / RADIX;
     uint32_t sum = 0;
     for (uint32_t r = r0 + s; r < r1; r += BATCH * SORT_SPLIT) {
         uint32_t v[BATCH];
@@ -84,9 +143,8 @@ __device__ inline uint32_t lookback_sum(const uint32_t* tab, uint32_t r0, uint32
             const uint32_t rr = r + m * SORT_SPLIT;
             uint32_t spins = 0;
             while (!(v[m] & SORT_READY)) {
-                if (++spins > SPIN_LIMIT) {
-                    atomicOr(&hdr->error, 8u);
-                    v[m] = SORT_READY;
+                if (++spins > LOOKBACK_POLLS) {
+                    ok = false;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
@@ -98,7 +156,39 @@ __device__ inline uint32_t lookback_sum(const uint32_t* tab, uint32_t r0, uint32
     return sum;
 }
 
+// The same share as poll_range, taken row by row by the whole block (every
+// thread calls it with the same range): each row is read from its published
+// words where all 256 are there, else counted from the keys.  No tile ever
+// waits on another without bound: the workgroups of a grid are not
+// guaranteed to run at once.
 template <typename KeyT>
+__device__ uint32_t fallback_range(const WsDev& ws, uint32_t pass, bool groups, uint32_t r0, uint32_t r1,
+                                   const KeyT* __restrict__ kin, uint32_t n, uint32_t shift, const LookbackLds& L,
+                                   bool force) {
+    const uint32_t tid = threadIdx.x, d = tid % RADIX, s = tid / RADIX;
+    const uint32_t* tiles = sort_state_tiles(ws, pass & 1);
+    uint32_t sum = 0;
+    for (uint32_t r = r0; r < r1; ++r) {
+        const bool mine = (r - r0) % SORT_SPLIT == s;
+        if (!groups) {
+            tile_row(tiles, kin, r, n, shift, L, L.acc, force);
+        } else {
+            for (uint32_t i = tid; i < RADIX; i += SORT_THREADS) L.acc[i] = 0;
+            __syncthreads();
+            for (uint32_t t = r * SORT_GROUP; t < (r + 1) * SORT_GROUP; ++t) {
+                tile_row(tiles, kin, t, n, shift, L, L.fb, force);
+                if (tid < RADIX) L.acc[tid] += L.fb[tid];
+                __syncthreads();
+            }
+        }
+        if (mine) sum += L.acc[d];
+        __syncthreads();
+    }
+    return sum;
+}
+
+// FORCE: take every look-back from the keys (fallback_range), for tests.
+template <typename KeyT, bool FORCE>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
@@ -112,21 +202,18 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
     __shared__ uint32_t s_gbase[RADIX];    // bucket base of d, then output position minus s_bstart[d]
     __shared__ uint32_t s_tot[RADIX];      // the tile's count of digit d
     __shared__ uint32_t s_wtot[RADIX / 64];
-    __shared__ uint32_t s_vb;
+    __shared__ uint32_t s_missed[2];       // look-back votes: some thread found an unpublished word
     __shared__ KeyT s_keys[SIZE];
     __shared__ uint32_t s_vals[SIZE];
 
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
-    // only the first ceil(n / SIZE) blocks take a ticket (tickets on one
-    // address serialise); the others have no tile
     const uint32_t n = entry_count(ws.header);
-    if (blockIdx.x * SIZE >= n) return;
-    if (tid == 0) s_vb = atomicAdd(&ws.header->sort_ticket[pass], 1u);
-    for (uint32_t i = tid; i < SORT_WAVES * RADIX; i += SORT_THREADS) s_whist[i] = 0;
-    __syncthreads();
-    const uint32_t vb = s_vb;
+    const uint32_t vb = blockIdx.x;      // the radix tile: keys [vb * SIZE, (vb + 1) * SIZE)
     const uint32_t tile_base = vb * SIZE;
-    if (tile_base >= n) return;      // cannot happen: tickets stop at the number of blocks that take one
+    if (tile_base >= n) return;
+    for (uint32_t i = tid; i < SORT_WAVES * RADIX; i += SORT_THREADS) s_whist[i] = 0;
+    if (tid < 2) s_missed[tid] = 0;
+    __syncthreads();
     const uint32_t shift = 8 * pass;
     const uint32_t n_valid = min((uint32_t)SIZE, n - tile_base);
     uint32_t* cur_tiles = sort_state_tiles(ws, pass & 1);
@@ -231,12 +318,23 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
     const uint32_t d = tid % RADIX, s = tid / RADIX;
     const uint32_t g = vb / SORT_GROUP, g0 = g * SORT_GROUP;
     uint32_t* s_part = s_whist;    // [SORT_SPLIT][RADIX]
-    uint32_t part = lookback_sum(cur_tiles, g0, vb, s, d, ws.header);
+    const LookbackLds L{s_whist, s_whist + SORT_SPLIT * RADIX, s_whist + (SORT_SPLIT + 1) * RADIX,
+                        s_whist + (SORT_SPLIT + 2) * RADIX};
+    constexpr bool force = FORCE;
+    bool ok = !force;
+    uint32_t part = force ? 0u : poll_range(cur_tiles, g0, vb, ok);
     if (vb % SORT_GROUP == SORT_GROUP - 1) {
         // last tile of its group: publish the group's counts before reading
         // the earlier groups, so that later groups wait as little as possible
         s_part[s * RADIX + d] = part;
+        if (__ballot(!ok) != 0 && lane == 0) s_missed[0] = 1;
         __syncthreads();
+        if (s_missed[0]) {
+            part = fallback_range(ws, pass, false, g0, vb, kin, n, shift, L, force);
+            s_part[s * RADIX + d] = part;
+            __syncthreads();
+            ok = !force;
+        }
         if (tid < RADIX) {
             uint32_t gsum = s_tot[tid];
 #pragma unroll
@@ -245,9 +343,17 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
         }
         __syncthreads();
     }
-    part += lookback_sum(cur_groups, 0, g, s, d, ws.header);
+    if (!force) part += poll_range(cur_groups, 0, g, ok);
     s_part[s * RADIX + d] = part;
+    if (__ballot(!ok) != 0 && lane == 0) s_missed[1] = 1;
     __syncthreads();
+    if (s_missed[1]) {
+        // a predecessor's counts were not published in time: take both ranges again
+        part = fallback_range(ws, pass, false, g0, vb, kin, n, shift, L, force) +
+               fallback_range(ws, pass, true, 0, g, kin, n, shift, L, force);
+        s_part[s * RADIX + d] = part;
+        __syncthreads();
+    }
     if (tid < RADIX) {
         uint32_t before = 0;
 #pragma unroll
@@ -267,15 +373,20 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
 }
 
 template <typename KeyT>
-static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, bool* result_in_b) {
+static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, bool* result_in_b, bool force) {
     KeyT* ka = reinterpret_cast<KeyT*>(ws.keys_a);
     KeyT* kb = reinterpret_cast<KeyT*>(ws.keys_b);
     const dim3 grid(ws.sort_rows), block(SORT_THREADS);
     for (uint32_t p = 0; p < passes; ++p) {
         const bool from_a = (p % 2) == 0;
-        hipLaunchKernelGGL(k_radix_pass<KeyT>, grid, block, 0, s, from_a ? ka : kb,
-                           from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
-                           ws, p);
+        if (force)
+            hipLaunchKernelGGL((k_radix_pass<KeyT, true>), grid, block, 0, s, from_a ? ka : kb,
+                               from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
+                               ws, p);
+        else
+            hipLaunchKernelGGL((k_radix_pass<KeyT, false>), grid, block, 0, s, from_a ? ka : kb,
+                               from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
+                               ws, p);
     }
     *result_in_b = (passes % 2) == 1;
 }
@@ -283,8 +394,12 @@ static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, bool* re
 void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes, uint32_t passes,
                  bool* result_in_b) {
     (void)f;
-    if (key_bytes == 8) sort_typed<uint64_t>(s, ws, passes, result_in_b);
-    else sort_typed<uint32_t>(s, ws, passes, result_in_b);
+    // RGS_SORT_FALLBACK_ONLY=1 (tests): every look-back counts its rows from
+    // the keys instead of reading the published words
+    const char* e = std::getenv("RGS_SORT_FALLBACK_ONLY");
+    const bool force = e && e[0] == '1';
+    if (key_bytes == 8) sort_typed<uint64_t>(s, ws, passes, result_in_b, force);
+    else sort_typed<uint32_t>(s, ws, passes, result_in_b, force);
 }
 
 // ---------------------------------------------------------------------------

@@ -125,14 +125,12 @@ struct WsHeader {
     uint32_t n_visible;
     uint32_t overflow;
     uint32_t error;           // bit 0: front-end look-back gave up;
-                              // bit 2: a sorted key named a tile outside the grid;
-                              // bit 3: a sort pass's look-back gave up
+                              // bit 2: a sorted key named a tile outside the grid
     uint32_t capacity;
     uint32_t path;
     uint32_t passes;
     uint32_t fe_ticket;
-    uint32_t sort_ticket[8];  // radix tiles handed out per sort pass
-    uint32_t pad[47];
+    uint32_t pad[55];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte slot");
 
