@@ -26,7 +26,12 @@ constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float T_MIN = 1e-4f;       // stop blending a pixel below this transmittance
 
 constexpr int FE_THREADS = 1024;     // threads per front-end / duplication block
-constexpr int FE_ITEMS = 2;          // Gaussians per thread (block-strided)
+// Gaussians per thread (block-strided).  Four makes blocks of 4096 Gaussians:
+// a 1M scene is 245 blocks, one per CU and all resident at once, and every
+// block pays one ticket atomic and one look-back hop of the ordered
+// allocation, so fewer, larger blocks are faster (1M at 1080p: 0.059 ms
+// against 0.065 ms with two per thread).
+constexpr int FE_ITEMS = 4;
 constexpr int FE_TILE = FE_THREADS * FE_ITEMS;   // Gaussians per block
 constexpr int LB_PER_LANE = 8;       // look-back states each lane polls per round trip
 constexpr int SORT_THREADS = 512;    // 8 waves per radix tile
