@@ -311,46 +311,63 @@ __device__ inline uint32_t nth_set_bit(uint64_t m, uint32_t k) {
 // counted once per Gaussian by count_depth_digits).  A wave whose stored keys
 // all share a digit adds it once (the high digits of neighbouring entries are
 // often equal, and LDS atomics on one address serialise).
+// Entries are taken EMIT_ILP per thread at a time (e, e + FE_THREADS, ...),
+// whose searches for their Gaussian advance in lockstep: the search is a
+// chain of dependent LDS reads, and the independent chains share its latency.
+constexpr int EMIT_ILP = 4;
+static_assert((FE_TILE & (FE_TILE - 1)) == 0, "the search takes log2(FE_TILE) halving steps");
+
 template <typename KeyT, typename KeyFn>
 __device__ inline void emit_entries(uint32_t total, uint64_t base, const uint32_t* s_incl,
                                     const uint64_t* s_rect, uint32_t first_gauss, int tiles_x,
                                     uint32_t capacity, KeyT* keys, uint32_t* vals, KeyFn key_of,
                                     uint32_t* s_h, uint32_t p_first, uint32_t passes, const uint64_t* s_mask) {
-    for (uint32_t e = threadIdx.x; e < total; e += FE_THREADS) {
-        int lo = 0, hi = FE_TILE - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_incl[mid] > e) hi = mid;
-            else lo = mid + 1;
+    for (uint32_t e0 = threadIdx.x; e0 < total; e0 += EMIT_ILP * FE_THREADS) {
+        // j = #{i : s_incl[i] <= e}, the first Gaussian whose inclusive count
+        // exceeds e, by binary lifting: after the steps of 2^k and above, j
+        // <= FE_TILE - 2^k, so every index read is below FE_TILE (an e at or
+        // past the total ends on some j < FE_TILE and is not emitted)
+        uint32_t j[EMIT_ILP];
+#pragma unroll
+        for (int u = 0; u < EMIT_ILP; ++u) j[u] = 0;
+#pragma unroll
+        for (uint32_t step = FE_TILE / 2; step >= 1; step >>= 1) {
+#pragma unroll
+            for (int u = 0; u < EMIT_ILP; ++u)
+                if (s_incl[j[u] + step - 1] <= e0 + u * FE_THREADS) j[u] += step;
         }
-        const uint32_t j = (uint32_t)lo;
-        const uint32_t local = e - (j ? s_incl[j - 1] : 0u);
-        const uint64_t rc = s_rect[j];
-        const uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff;
-        const uint32_t w = x1 - x0 + 1;
-        uint32_t b = local;            // row-major index of the tile in the rectangle
-        if (s_mask && w * ((uint32_t)(rc >> 48) - y0 + 1) <= EXACT_TILE_MAX_AREA)
-            b = nth_set_bit(s_mask[j], local);
-        const uint32_t ty = y0 + b / w;
-        const uint32_t tx = x0 + b % w;
-        const uint32_t tile = ty * (uint32_t)tiles_x + tx;
-        const uint64_t pos = base + e;
-        const bool stored = pos < capacity;
-        const KeyT key = key_of(tile, j);
-        if (stored) {
-            keys[pos] = key;
-            vals[pos] = first_gauss + j;
-        }
-        const uint64_t active = __ballot(true);
-        const bool all_stored = __ballot(stored) == active;
-        for (uint32_t p = p_first; p < passes; ++p) {
-            const uint32_t dg = (uint32_t)(key >> (RADIX_BITS * p)) & (RADIX - 1);
-            const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
-            if (all_stored && __ballot(dg == d0) == active) {
-                if (lane_id() == (uint32_t)__builtin_ctzll(active))
-                    atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(active));
-            } else if (stored) {
-                atomicAdd(&s_h[p * RADIX + dg], 1u);
+#pragma unroll
+        for (int u = 0; u < EMIT_ILP; ++u) {
+            const uint32_t e = e0 + u * FE_THREADS;
+            if (e >= total) break;
+            const uint32_t local = e - (j[u] ? s_incl[j[u] - 1] : 0u);
+            const uint64_t rc = s_rect[j[u]];
+            const uint32_t x0 = rc & 0xffff, x1 = (rc >> 16) & 0xffff, y0 = (rc >> 32) & 0xffff;
+            const uint32_t w = x1 - x0 + 1;
+            uint32_t b = local;            // row-major index of the tile in the rectangle
+            if (s_mask && w * ((uint32_t)(rc >> 48) - y0 + 1) <= EXACT_TILE_MAX_AREA)
+                b = nth_set_bit(s_mask[j[u]], local);
+            const uint32_t ty = y0 + b / w;
+            const uint32_t tx = x0 + b % w;
+            const uint32_t tile = ty * (uint32_t)tiles_x + tx;
+            const uint64_t pos = base + e;
+            const bool stored = pos < capacity;
+            const KeyT key = key_of(tile, j[u]);
+            if (stored) {
+                keys[pos] = key;
+                vals[pos] = first_gauss + j[u];
+            }
+            const uint64_t active = __ballot(true);
+            const bool all_stored = __ballot(stored) == active;
+            for (uint32_t p = p_first; p < passes; ++p) {
+                const uint32_t dg = (uint32_t)(key >> (RADIX_BITS * p)) & (RADIX - 1);
+                const uint32_t d0 = __builtin_amdgcn_readfirstlane(dg);
+                if (all_stored && __ballot(dg == d0) == active) {
+                    if (lane_id() == (uint32_t)__builtin_ctzll(active))
+                        atomicAdd(&s_h[p * RADIX + d0], (uint32_t)__popcll(active));
+                } else if (stored) {
+                    atomicAdd(&s_h[p * RADIX + dg], 1u);
+                }
             }
         }
     }
