@@ -599,6 +599,18 @@ __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& c
         sx = half_lo(sxy); sy = half_hi(sxy); sz = half_lo(szl);
         lno = half_hi(szl);
     }
+    // the quantised SH words are loaded before the projection, whose FP64
+    // arithmetic then covers their latency (nearly every Gaussian of a scene
+    // in view is visible, so the culled ones' loads cost little)
+    uint32_t qwd[12], sw[6];
+    if (!(opts & OPT_INT8_SH)) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) qwd[k] = W[(F_SHQ0 + k) * np + i];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sw[k] = W[(F_SHS0 + k) * np + i];
+        // keeps the compiler from sinking the loads to their use
+        asm volatile("" ::: "memory");
+    }
     Projected pr;
     const bool vis = project_gaussian(cam, mx, my, mz, qw, qx, qy, qz, sx, sy, sz, true, (double)lno,
                                       (double)f.tiles_x, (double)f.tiles_y, pr, !(opts & OPT_EXTENT));
@@ -614,11 +626,6 @@ __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& c
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) acc[ch] = fmaf(y.y[k], P[(P_SH0 + 3 * k + ch) * np + i], acc[ch]);
         } else {
-            uint32_t qwd[12], sw[6];
-#pragma unroll
-            for (int k = 0; k < 12; ++k) qwd[k] = W[(F_SHQ0 + k) * np + i];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) sw[k] = W[(F_SHS0 + k) * np + i];
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int deg = k == 0 ? 0 : (k < 4 ? 1 : (k < 9 ? 2 : 3));
