@@ -35,12 +35,15 @@ constexpr int FE_ITEMS = 4;
 constexpr int FE_TILE = FE_THREADS * FE_ITEMS;   // Gaussians per block
 constexpr int LB_PER_LANE = 8;       // look-back states each lane polls per round trip
 constexpr int SORT_THREADS = 512;    // 8 waves per radix tile
-// Keys per thread of a radix tile: 8, so a tile is 4096 keys.  A 32-bit tile's
-// LDS (keys, values, per-wave digit counts) is 43 KB and a 64-bit tile's 59 KB:
-// three or two tiles share a CU, and a frame's tiles are spread evenly.
+// Keys per thread of a radix tile: 9 for 32-bit keys (4608-key tiles, 48 KB
+// of LDS: keys, values, per-wave digit counts) and 8 for 64-bit keys (4096,
+// 59 KB), so three or two tiles share a CU.  A pass takes as long as its most
+// loaded CU: the 2.2M entries of a 1M / 1080p frame make 479 tiles of 4608,
+// at most two per CU, where 539 tiles of 4096 left some CUs three (sort 0.075
+// -> 0.072 ms).
 template <typename KeyT>
 struct SortTile {
-    static constexpr int ITEMS = 8;
+    static constexpr int ITEMS = sizeof(KeyT) == 4 ? 9 : 8;
     static constexpr int SIZE = SORT_THREADS * ITEMS;
 };
 inline uint32_t sort_tile_size(uint32_t key_bytes) {
