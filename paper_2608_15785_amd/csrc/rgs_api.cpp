@@ -197,8 +197,14 @@ extern "C" rgs_status rgs_quantize_host(const rgs_scene_desc* desc, rgs_fast_hos
 // ---------------------------------------------------------------------------
 // Context
 
+// Stage boundaries of one timed frame.  A boundary that a path does not have
+// (the fused front end has no separate duplication) is not recorded: the
+// stage before it counts zero, and the next stage starts at the last recorded
+// boundary.  (Two events recorded back to back measure a few microseconds of
+// idle GPU, not work.)
 struct FrameEvents {
     hipEvent_t ev[RGS_N_STAGES + 1];
+    bool skipped[RGS_N_STAGES + 1];
 };
 
 struct rgs_ctx {
@@ -258,10 +264,14 @@ static rgs_status harvest_events(rgs_ctx* ctx) {
     if (ctx->events_used == 0) return RGS_OK;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     for (size_t f = 0; f < ctx->events_used; ++f) {
+        const FrameEvents& fe = ctx->events[f];
+        int last = 0;
         for (int s = 0; s < RGS_N_STAGES; ++s) {
+            if (fe.skipped[s + 1]) continue;
             float ms = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&ms, ctx->events[f].ev[s], ctx->events[f].ev[s + 1]));
+            HIP_TRY(hipEventElapsedTime(&ms, fe.ev[last], fe.ev[s + 1]));
             ctx->stage_ms[s] += ms;
+            last = s + 1;
         }
         ctx->frames += 1;
     }
@@ -294,6 +304,7 @@ static rgs_status next_events(rgs_ctx* ctx, FrameEvents** fe) {
         ctx->events.push_back(f);
     }
     *fe = &ctx->events[ctx->events_used++];
+    std::fill((*fe)->skipped, (*fe)->skipped + RGS_N_STAGES + 1, false);
     return RGS_OK;
 }
 
@@ -716,7 +727,7 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
     } else {
         launch_frontend_fast(st, fl.fast, fl.f, w, fl.L.fe_blocks, dbg, fl.opts);
         mark(1);
-        mark(2);
+        mark(-2);       // no duplication stage
     }
     if (hooks && hooks->after_front) {
         rgs_status s = hooks->after_front(hooks->user);
@@ -751,7 +762,9 @@ struct RenderHooks {
 
 void hook_mark(void* user, int k) {
     RenderHooks* h = static_cast<RenderHooks*>(user);
-    if (h->fe) (void)hipEventRecord(h->fe->ev[k], h->ctx->stream);
+    if (!h->fe) return;
+    if (k < 0) h->fe->skipped[-k] = true;
+    else (void)hipEventRecord(h->fe->ev[k], h->ctx->stream);
 }
 
 rgs_status hook_after_front(void* user) {

@@ -51,6 +51,7 @@ int scene_device(const rgs_scene* sc);
 // launches (k = 0 before the first), after_front(user) between the front end
 // and the sort (it may read the header; a non-OK status stops the frame).
 struct FrameHooks {
+    // stage boundary k reached (0..RGS_N_STAGES); -k: this path has no boundary k
     void (*mark)(void* user, int k);
     rgs_status (*after_front)(void* user);
     void* user;
