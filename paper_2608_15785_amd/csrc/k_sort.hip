@@ -72,9 +72,14 @@ __device__ inline uint32_t digit_exclusive_scan(uint32_t x, uint32_t* s_wtot) {
     return incl - x + before;
 }
 
-// Polls of a not yet published look-back word (each a sleep and a reload,
-// about a microsecond) before the waiting tile counts the missing row itself.
-constexpr uint32_t LOOKBACK_POLLS = 64;
+// Polls of a not yet published look-back word (each a short sleep and a
+// reload, a microsecond or two) before the waiting tile counts the missing row
+// itself: a bound of milliseconds, far above any real wait.  When several
+// streams' frames share the GPU, a running predecessor can be slow for tens of
+// microseconds; 64 polls then sent ~47K rows per pass into the fallback over a
+// 600-request serving burst on four streams (2040 frames/s), 4096 polls none
+// (3270 frames/s).
+constexpr uint32_t LOOKBACK_POLLS = 4096;
 
 // Shared memory of the look-back (inside the pass kernel's s_whist once the
 // tile is reordered): per-thread partial sums, a block-wide flag, and two
