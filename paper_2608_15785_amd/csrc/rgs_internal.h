@@ -51,8 +51,9 @@ inline uint32_t sort_tile_size(uint32_t key_bytes) {
 }
 // Radix tiles per look-back group: the last tile of each group publishes the
 // group's digit counts, so a tile reads at most SORT_GROUP - 1 tile states plus
-// one state per earlier group.
-constexpr uint32_t SORT_GROUP = 16;
+// one state per earlier group.  32 balances the two (1M / 1080p fast sort:
+// 0.0729 ms with 16, 0.0712 with 32, 0.0742 with 64, 0.0757 with 8).
+constexpr uint32_t SORT_GROUP = 32;
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int MAX_PASSES = 8;
