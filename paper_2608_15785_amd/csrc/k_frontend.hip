@@ -241,32 +241,37 @@ __device__ void chained_exclusive(uint64_t* states, uint32_t vb, uint64_t agg_e,
 // Block-wide inclusive scan of FE_ITEMS rows of per-thread counts (Gaussian
 // j = k * FE_THREADS + tid of the block sits in row k), leaving s_incl[j], then
 // the block's global base by chained scan.  Returns the block's entry total;
-// *s_base / *s_base_v receive the exclusive entry and visible counts.
+// *s_base / *s_base_v receive the exclusive entry and visible counts.  Every
+// wave scans its share of all rows at once; the FE_ITEMS x WAVES wave totals
+// (one wave's worth) are then scanned by wave 0 in row-major order, so the
+// block takes two barriers instead of two per row.  s_wtot holds
+// FE_ITEMS * WAVES + 1 words.
 __device__ inline uint32_t block_scan_and_chain(const uint32_t (&count)[FE_ITEMS], uint32_t n_vis,
                                                 uint32_t vb, WsDev& ws, uint32_t* s_incl,
                                                 uint32_t* s_wtot, uint32_t* s_wvis, uint64_t* s_base,
                                                 uint64_t* s_base_v, uint32_t* vis_total) {
     constexpr int WAVES = FE_THREADS / 64;
+    static_assert(FE_ITEMS * WAVES <= 64, "one wave scans the wave totals");
     const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
     const uint32_t wv = wave_sum(n_vis);
     if (lane == 0) s_wvis[wave] = wv;
-    uint32_t carry = 0;
+    uint32_t incl[FE_ITEMS];
 #pragma unroll
     for (int k = 0; k < FE_ITEMS; ++k) {
-        const uint32_t incl = wave_inclusive_scan(count[k]);
-        if (lane == 63) s_wtot[wave] = incl;
-        __syncthreads();
-        uint32_t before = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < WAVES; ++w) {
-            const uint32_t t = s_wtot[w];
-            if ((uint32_t)w < wave) before += t;
-            tot += t;
-        }
-        s_incl[k * FE_THREADS + threadIdx.x] = carry + before + incl;
-        carry += tot;
-        __syncthreads();
+        incl[k] = wave_inclusive_scan(count[k]);
+        if (lane == 63) s_wtot[k * WAVES + wave] = incl[k];
     }
+    __syncthreads();
+    if (wave == 0) {
+        const uint32_t t = lane < (uint32_t)(FE_ITEMS * WAVES) ? s_wtot[lane] : 0u;
+        const uint32_t in = wave_inclusive_scan(t);
+        if (lane < (uint32_t)(FE_ITEMS * WAVES)) s_wtot[lane] = in - t;
+        if (lane == 63) s_wtot[FE_ITEMS * WAVES] = in;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < FE_ITEMS; ++k) s_incl[k * FE_THREADS + threadIdx.x] = s_wtot[k * WAVES + wave] + incl[k];
+    const uint32_t carry = s_wtot[FE_ITEMS * WAVES];
     uint32_t vtot = 0;
 #pragma unroll
     for (int w = 0; w < WAVES; ++w) vtot += s_wvis[w];
@@ -510,7 +515,7 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
     __shared__ uint64_t s_rect[FE_TILE];
     __shared__ uint32_t s_dbits[FE_TILE];
     __shared__ uint64_t s_mask[FE_TILE];
-    __shared__ uint32_t s_wtot[FE_THREADS / 64];
+    __shared__ uint32_t s_wtot[FE_ITEMS * FE_THREADS / 64 + 1];
     __shared__ uint32_t s_wvis[FE_THREADS / 64];
     __shared__ uint64_t s_base, s_base_v;
     __shared__ uint32_t s_h[MAX_PASSES * RADIX];
@@ -678,7 +683,7 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
     __shared__ uint64_t s_rect[FE_TILE];
     __shared__ uint32_t s_qd[FE_TILE];
     __shared__ uint64_t s_mask[FE_TILE];
-    __shared__ uint32_t s_wtot[FE_THREADS / 64];
+    __shared__ uint32_t s_wtot[FE_ITEMS * FE_THREADS / 64 + 1];
     __shared__ uint32_t s_wvis[FE_THREADS / 64];
     __shared__ uint64_t s_base, s_base_v;
     __shared__ uint32_t s_h[MAX_PASSES * RADIX];
