@@ -7,8 +7,9 @@
 // starts after its last blended pair (the forward pass left its final T, the
 // number of pairs it visited and whether it stopped); T before each blended
 // pair is recovered as T_after / (1 - alpha), and the colour accumulated behind
-// the pair, S, is carried along, so that
-//   dC/dc_j = alpha_j T_j,   dC/dalpha_j = c_j T_j - (S_j + T_final bg) / (1 - alpha_j).
+// the pair plus the background's share, S' = S + T_final bg, is carried along
+// (it starts at T_final bg), so that
+//   dC/dc_j = alpha_j T_j,   dC/dalpha_j = c_j T_j - S'_j / (1 - alpha_j).
 // The nine image-space derivatives of a pair (u, v, A, B, C, o, r, g, b) are
 // summed over a lane's four pixels, then over the wave with DPP adds, and each
 // entry receives one 48-byte partial at its position in emission order: no
@@ -94,7 +95,7 @@ __device__ inline uint64_t emission_pos(const WsDev& ws, uint32_t g, uint32_t tx
 // and adds its four pixels' terms before the wave reduction of an entry.
 constexpr int BWD_LANES = 64;
 constexpr int BWD_PIX = 4;
-constexpr int BWD_BATCH = 64;
+constexpr int BWD_BATCH = 32;
 constexpr int BWD_ROWS = BWD_LANES / 16;     // DPP rows of the wave
 
 // Row bands k (tile rows 4k .. 4k+3) that can hold a pixel with alpha >= 1/255
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
     const uint64_t plane = (uint64_t)f.width * f.height;
     const float bg0 = ws.params->cam.bg[0], bg1 = ws.params->cam.bg[1], bg2 = ws.params->cam.bg[2];
 
-    float T[BWD_PIX], fb[BWD_PIX][3], d[BWD_PIX][3], S[BWD_PIX][3];
+    float T[BWD_PIX], d[BWD_PIX][3], S[BWD_PIX][3];   // S: colour behind the pair + T_final bg
     uint32_t last[BWD_PIX];                    // pairs [start, last) may have been blended
     uint32_t lane_last = start;
 #pragma unroll
@@ -147,7 +148,7 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
         T[k] = 1.0f;
         last[k] = start;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) d[k][c] = 0.0f, S[k][c] = 0.0f;
+        for (int c = 0; c < 3; ++c) d[k][c] = 0.0f;
         if (px < (uint32_t)f.width && py < (uint32_t)f.height) {
             const uint64_t o = (uint64_t)py * f.width + px;
             T[k] = ws.t_final[o];
@@ -157,9 +158,9 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
             d[k][1] = dimg[plane + o];
             d[k][2] = dimg[2 * plane + o];
         }
-        fb[k][0] = T[k] * bg0;
-        fb[k][1] = T[k] * bg1;
-        fb[k][2] = T[k] * bg2;
+        S[k][0] = T[k] * bg0;
+        S[k][1] = T[k] * bg1;
+        S[k][2] = T[k] * bg2;
         lane_last = max(lane_last, last[k]);
     }
     uint32_t wave_last = lane_last;
@@ -211,9 +212,9 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
                         g[6] = fmaf(w, d[k][0], g[6]);
                         g[7] = fmaf(w, d[k][1], g[7]);
                         g[8] = fmaf(w, d[k][2], g[8]);
-                        const float dA = d[k][0] * (m.z * Tb - (S[k][0] + fb[k][0]) * inv) +
-                                         d[k][1] * (m.w * Tb - (S[k][1] + fb[k][1]) * inv) +
-                                         d[k][2] * (cb * Tb - (S[k][2] + fb[k][2]) * inv);
+                        const float dA = d[k][0] * (m.z * Tb - S[k][0] * inv) +
+                                         d[k][1] * (m.w * Tb - S[k][1] * inv) +
+                                         d[k][2] * (cb * Tb - S[k][2] * inv);
                         S[k][0] = fmaf(m.z, w, S[k][0]);
                         S[k][1] = fmaf(m.w, w, S[k][1]);
                         S[k][2] = fmaf(cb, w, S[k][2]);
