@@ -249,7 +249,9 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
             // then the ellipse itself: the half-tile must hold a point with
             // q <= tau = 2 (ln 255 + ln o), up to the margin
             const float qlim = fmaf(2.0f * (LN255F + rec.opa), 1.0f + Q_MARGIN_REL, Q_MARGIN_ABS);
-            const float iA = 1.0f / A, iC = 1.0f / C;
+            // the reciprocals only place the nearest point of an edge, where q is
+            // then evaluated exactly; an error of an ulp moves q by ~C (1e-6 px)^2
+            const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
             if (hit0) hit0 = !(conic_rect_min(u, v, A, B, C, iA, iC, -7.5f, -0.5f) > qlim);
             if (hit1) hit1 = !(conic_rect_min(u, v, A, B, C, iA, iC, 0.5f, 7.5f) > qlim);
         }
@@ -439,7 +441,9 @@ __global__ __launch_bounds__(256 / PIX) void k_raster_fast_px(FrameDev f, WsDev 
             const float hy = fmaf(half_hi(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
             const bool x_out = u - hx > 7.5f || u + hx < -7.5f;
             const float qlim = fmaf(2.0f * (LN255F + rec.opa), 1.0f + Q_MARGIN_REL, Q_MARGIN_ABS);
-            const float iA = 1.0f / A, iC = 1.0f / C;
+            // the reciprocals only place the nearest point of an edge, where q is
+            // then evaluated exactly; an error of an ulp moves q by ~C (1e-6 px)^2
+            const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
 #pragma unroll
             for (int w = 0; w < WAVES; ++w) {
                 const float y0 = (float)(w * ROWS) - 7.5f, y1 = (float)(w * ROWS + ROWS - 1) - 7.5f;
