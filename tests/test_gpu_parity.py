@@ -165,6 +165,21 @@ def test_cfg2_keys_and_sampled_tiles(R, path, pose):
     run_parity(R, sc, cam, path, tiles=tiles)
 
 
+@pytest.mark.parametrize("path", ["plain", "fast"])
+def test_largest_frame(R, path):
+    """The largest accepted frame, 16384x16384: 2^20 tiles, so the fast key keeps only
+    12 depth bits and many keys tie.  Every key and range bit-exact; the image on 16
+    random tiles, nine tiles around the centre and the four corners."""
+    cam = wl.config_camera("cfg0", width=16384, height=16384)
+    plan = oracle.frame_plan(cam.width, cam.height)
+    assert plan.b_t == 20 and plan.b_d == 12
+    tx0, ty0 = plan.tiles_x // 2, plan.tiles_y // 2
+    centre = [(ty0 + dy) * plan.tiles_x + tx0 + dx for dy in (-2, 0, 2) for dx in (-2, 0, 2)]
+    corners = [0, plan.tiles_x - 1, plan.n_tiles - plan.tiles_x, plan.n_tiles - 1]
+    tiles = np.concatenate([np.random.default_rng(11).choice(plan.n_tiles, 16, replace=False), centre, corners])
+    run_parity(R, wl.config_scene("cfg0", n=2000), cam, path, tiles=tiles)
+
+
 _CFG2 = {}
 
 
