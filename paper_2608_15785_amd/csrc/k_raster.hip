@@ -360,18 +360,22 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
         out[o] = fmaf(T0, bg0, r0);
         out[plane + o] = fmaf(T0, bg1, g0);
         out[2 * plane + o] = fmaf(T0, bg2, b0);
-        ws.t_final[o] = T0;
-        ws.n_proc[o] = stop0 != 0xffffffffu ? (stop0 - start + 1) | N_PROC_STOPPED : end - start;
-        if (COUNT) ws.n_blend[o] = nbl0;
+        if (COUNT) {                // the debug render's per-pixel outputs
+            ws.t_final[o] = T0;
+            ws.n_proc[o] = stop0 != 0xffffffffu ? (stop0 - start + 1) | N_PROC_STOPPED : end - start;
+            ws.n_blend[o] = nbl0;
+        }
     }
     if (in1) {
         const uint64_t o = (uint64_t)(py + 1) * f.width + px;
         out[o] = fmaf(T1, bg0, r1);
         out[plane + o] = fmaf(T1, bg1, g1);
         out[2 * plane + o] = fmaf(T1, bg2, b1);
-        ws.t_final[o] = T1;
-        ws.n_proc[o] = stop1 != 0xffffffffu ? (stop1 - start + 1) | N_PROC_STOPPED : end - start;
-        if (COUNT) ws.n_blend[o] = nbl1;
+        if (COUNT) {                // the debug render's per-pixel outputs
+            ws.t_final[o] = T1;
+            ws.n_proc[o] = stop1 != 0xffffffffu ? (stop1 - start + 1) | N_PROC_STOPPED : end - start;
+            ws.n_blend[o] = nbl1;
+        }
     }
 }
 
