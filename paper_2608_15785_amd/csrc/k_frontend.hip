@@ -509,6 +509,7 @@ void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const Frame
 
 template <typename KeyT>
 __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f, WsDev ws, uint32_t n_blocks,
+                                                          uint32_t per,
                                                           uint32_t shift) {
     __shared__ uint32_t s_vb;
     __shared__ uint32_t s_incl[FE_TILE];
@@ -529,9 +530,9 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
 #pragma unroll
     for (int k = 0; k < FE_ITEMS; ++k) {
         const uint32_t j = k * FE_THREADS + threadIdx.x;
-        const int64_t i = (int64_t)vb * FE_TILE + j;
+        const int64_t i = (int64_t)vb * per + j;
         count[k] = 0;
-        if (i < n) {
+        if (j < per && i < n) {
             count[k] = ws.counts[i];
             if (count[k]) {
                 s_rect[j] = ws.rects[i];
@@ -550,11 +551,11 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
 #pragma unroll
     for (int k = 0; k < FE_ITEMS; ++k) {
         const uint32_t j = k * FE_THREADS + threadIdx.x;
-        const int64_t i = (int64_t)vb * FE_TILE + j;
-        if (i < n && count[k]) ws.offsets[i] = (uint32_t)(base + (j ? s_incl[j - 1] : 0u));
+        const int64_t i = (int64_t)vb * per + j;
+        if (j < per && i < n && count[k]) ws.offsets[i] = (uint32_t)(base + (j ? s_incl[j - 1] : 0u));
     }
     count_depth_digits(s_h, count, s_dbits, s_incl, base, f.capacity, p_depth);
-    emit_entries<KeyT>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
+    emit_entries<KeyT>(total, base, s_incl, s_rect, vb * per, f.tiles_x, f.capacity,
                        reinterpret_cast<KeyT*>(ws.keys_a), ws.vals_a,
                        [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_dbits[j]; },
                        s_h, p_depth, (uint32_t)f.passes, ws.masks ? s_mask : nullptr);
@@ -563,14 +564,14 @@ __global__ __launch_bounds__(FE_THREADS) void k_duplicate(int64_t n, FrameDev f,
     finish_block(ws, vb, n_blocks, base, s_base_v, total, vis_total, f.capacity);
 }
 
-void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
+void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws, uint32_t fe_blocks, uint32_t fe_per,
                       uint32_t key_bytes) {
     if (key_bytes == 8)
         hipLaunchKernelGGL(k_duplicate<uint64_t>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, n, f, ws, fe_blocks,
-                           32u);
+                           fe_per, 32u);
     else
         hipLaunchKernelGGL(k_duplicate<uint32_t>, dim3(fe_blocks), dim3(FE_THREADS), 0, s, n, f, ws, fe_blocks,
-                           (uint32_t)f.b_d);
+                           fe_per, (uint32_t)f.b_d);
 }
 
 // ---------------------------------------------------------------------------
@@ -674,7 +675,7 @@ __device__ inline uint32_t fast_gaussian(const FastSceneDev& sc, const CamDev& c
 // instances honour the ablation bits in `opts`, the production one ignores it.
 template <bool DEBUG, bool GENERIC, typename KeyT>
 __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, FrameDev f, WsDev ws,
-                                                              uint32_t n_blocks, DebugDev dbg,
+                                                              uint32_t n_blocks, uint32_t per, DebugDev dbg,
                                                               uint32_t opts_arg) {
     const CamDev cam = ws.params->cam;
     const uint32_t opts = GENERIC ? opts_arg : 0u;
@@ -698,9 +699,9 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
 #pragma unroll
     for (int k = 0; k < FE_ITEMS; ++k) {
         const uint32_t j = k * FE_THREADS + threadIdx.x;
-        const int64_t i = (int64_t)vb * FE_TILE + j;
+        const int64_t i = (int64_t)vb * per + j;
         count[k] = 0;
-        if (i < sc.n) {
+        if (j < per && i < sc.n) {
             uint64_t rect = 0, mask = 0;
             uint32_t klo = 0;
             count[k] = fast_gaussian<DEBUG>(sc, cam, f, ws, dbg, i, rect, klo, mask, opts);
@@ -717,7 +718,7 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
                                                 &s_base_v, &vis_total);
     const uint64_t base = s_base;
     count_depth_digits(s_h, count, s_qd, s_incl, base, f.capacity, p_depth);
-    emit_entries<KeyT>(total, base, s_incl, s_rect, vb * FE_TILE, f.tiles_x, f.capacity,
+    emit_entries<KeyT>(total, base, s_incl, s_rect, vb * per, f.tiles_x, f.capacity,
                        reinterpret_cast<KeyT*>(ws.keys_a), ws.vals_a,
                        [&](uint32_t tile, uint32_t j) { return ((KeyT)tile << shift) | (KeyT)s_qd[j]; },
                        s_h, p_depth, (uint32_t)f.passes, (opts & OPT_EXACT_TILES) ? s_mask : nullptr);
@@ -728,26 +729,26 @@ __global__ __launch_bounds__(FE_THREADS) void k_frontend_fast(FastSceneDev sc, F
 
 template <bool DEBUG, bool GENERIC, typename KeyT>
 static void launch_fe(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
-                      uint32_t fe_blocks, const DebugDev* dbg, uint32_t opts) {
+                      uint32_t fe_blocks, uint32_t fe_per, const DebugDev* dbg, uint32_t opts) {
     hipLaunchKernelGGL((k_frontend_fast<DEBUG, GENERIC, KeyT>), dim3(fe_blocks), dim3(FE_THREADS), 0, s, sc, f,
-                       ws, fe_blocks, dbg ? *dbg : DebugDev{}, opts);
+                       ws, fe_blocks, fe_per, dbg ? *dbg : DebugDev{}, opts);
 }
 
 void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
-                          uint32_t fe_blocks, const DebugDev* dbg, uint32_t opts) {
+                          uint32_t fe_blocks, uint32_t fe_per, const DebugDev* dbg, uint32_t opts) {
     // only these bits change the front end; the others (the exponential, the
     // pixel layout) leave it to the production instance
     opts &= OPT_EXTENT | OPT_KEY32 | OPT_INT8_SH | OPT_FP16_GEOM | OPT_EXACT_TILES;
     const bool key64 = (opts & OPT_KEY32) != 0;
     if (opts == 0) {
-        if (dbg) launch_fe<true, false, uint32_t>(s, sc, f, ws, fe_blocks, dbg, 0);
-        else launch_fe<false, false, uint32_t>(s, sc, f, ws, fe_blocks, dbg, 0);
+        if (dbg) launch_fe<true, false, uint32_t>(s, sc, f, ws, fe_blocks, fe_per, dbg, 0);
+        else launch_fe<false, false, uint32_t>(s, sc, f, ws, fe_blocks, fe_per, dbg, 0);
     } else if (key64) {
-        if (dbg) launch_fe<true, true, uint64_t>(s, sc, f, ws, fe_blocks, dbg, opts);
-        else launch_fe<false, true, uint64_t>(s, sc, f, ws, fe_blocks, dbg, opts);
+        if (dbg) launch_fe<true, true, uint64_t>(s, sc, f, ws, fe_blocks, fe_per, dbg, opts);
+        else launch_fe<false, true, uint64_t>(s, sc, f, ws, fe_blocks, fe_per, dbg, opts);
     } else {
-        if (dbg) launch_fe<true, true, uint32_t>(s, sc, f, ws, fe_blocks, dbg, opts);
-        else launch_fe<false, true, uint32_t>(s, sc, f, ws, fe_blocks, dbg, opts);
+        if (dbg) launch_fe<true, true, uint32_t>(s, sc, f, ws, fe_blocks, fe_per, dbg, opts);
+        else launch_fe<false, true, uint32_t>(s, sc, f, ws, fe_blocks, fe_per, dbg, opts);
     }
 }
 

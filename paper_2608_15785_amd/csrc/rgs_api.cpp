@@ -445,7 +445,7 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     L.capacity = capacity;
     L.key_bytes = (plain || (opts & OPT_KEY32)) ? 8 : 4;
     L.passes = L.key_bytes == 8 ? (uint32_t)p.plain_passes : (uint32_t)p.fast_passes;
-    L.fe_blocks = (uint32_t)((n + FE_TILE - 1) / FE_TILE);
+    fe_block_shape(n, L.fe_blocks, L.fe_per);
     const uint64_t st = sort_tile_size(L.key_bytes);
     L.sort_blocks_max = (uint32_t)((capacity + st - 1) / st);
     uint64_t off = 0;
@@ -717,15 +717,15 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
     if (fl.path == RGS_PATH_PLAIN) {
         launch_preprocess_plain(st, fl.plain, fl.f, w, dbg);
         mark(1);
-        launch_duplicate(st, fl.n, fl.f, w, fl.L.fe_blocks, fl.L.key_bytes);
+        launch_duplicate(st, fl.n, fl.f, w, fl.L.fe_blocks, fl.L.fe_per, fl.L.key_bytes);
         mark(2);
     } else if (fl.opts & OPT_FUSION) {
         launch_preprocess_fast(st, fl.fast, fl.f, w, dbg, fl.opts);
         mark(1);
-        launch_duplicate(st, fl.n, fl.f, w, fl.L.fe_blocks, fl.L.key_bytes);
+        launch_duplicate(st, fl.n, fl.f, w, fl.L.fe_blocks, fl.L.fe_per, fl.L.key_bytes);
         mark(2);
     } else {
-        launch_frontend_fast(st, fl.fast, fl.f, w, fl.L.fe_blocks, dbg, fl.opts);
+        launch_frontend_fast(st, fl.fast, fl.f, w, fl.L.fe_blocks, fl.L.fe_per, dbg, fl.opts);
         mark(1);
         mark(-2);       // no duplication stage
     }

@@ -32,7 +32,28 @@ constexpr int FE_THREADS = 1024;     // threads per front-end / duplication bloc
 // allocation, so fewer, larger blocks are faster (1M at 1080p: 0.059 ms
 // against 0.065 ms with two per thread).
 constexpr int FE_ITEMS = 4;
-constexpr int FE_TILE = FE_THREADS * FE_ITEMS;   // Gaussians per block
+constexpr int FE_TILE = FE_THREADS * FE_ITEMS;   // most Gaussians a block takes
+
+// How n Gaussians are split over front-end workgroups.  A scene that fits in
+// one round of FE_CU_QUANTUM workgroups (MI355X has 256 CUs; one workgroup
+// fills a CU) is spread evenly over up to that many, at least FE_MIN_PER_BLOCK
+// Gaussians each: a 1M scene becomes 253 workgroups of 3968 instead of 245 of
+// 4096, which left 11 CUs idle.  Larger scenes take FE_TILE per workgroup.
+constexpr uint32_t FE_CU_QUANTUM = 256;
+constexpr uint32_t FE_MIN_PER_BLOCK = 1024;
+inline void fe_block_shape(int64_t n, uint32_t& blocks, uint32_t& per) {
+    const uint64_t un = n > 0 ? (uint64_t)n : 1u;
+    uint64_t b = (un + FE_TILE - 1) / FE_TILE;
+    if (b <= FE_CU_QUANTUM) {
+        const uint64_t most = (un + FE_MIN_PER_BLOCK - 1) / FE_MIN_PER_BLOCK;
+        b = most < FE_CU_QUANTUM ? most : FE_CU_QUANTUM;
+    }
+    // a multiple of 64, so that every wave's loads of an attribute plane start
+    // on a 256-byte boundary (the planes are padded to 64 Gaussians)
+    const uint64_t p = ((un + b - 1) / b + 63) / 64 * 64;
+    per = (uint32_t)(p < (uint64_t)FE_TILE ? p : (uint64_t)FE_TILE);
+    blocks = (uint32_t)((un + per - 1) / per);
+}
 constexpr int LB_PER_LANE = 8;       // look-back states each lane polls per round trip
 constexpr int SORT_THREADS = 512;    // 8 waves per radix tile
 // Keys per thread of a radix tile: 9 for 32-bit keys (4608-key tiles, 48 KB
@@ -154,6 +175,7 @@ struct WsLayout {
     uint64_t total;
     uint64_t capacity;
     uint32_t key_bytes, passes, fe_blocks, sort_blocks_max;   // sort_blocks_max: radix tiles at capacity
+    uint32_t fe_per;          // Gaussians per front-end / duplication workgroup (<= FE_TILE)
 };
 
 // Pointers a kernel needs into the workspace.
@@ -455,10 +477,10 @@ const void* reset_kernel();          // host handle of the reset kernel (graph n
 void launch_export_status(hipStream_t s, const WsDev& ws, FrameStatus* dst);
 void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const FrameDev& f,
                              const WsDev& ws, const DebugDev* dbg);
-void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws, uint32_t fe_blocks,
+void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws, uint32_t fe_blocks, uint32_t fe_per,
                       uint32_t key_bytes);
 void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
-                          uint32_t fe_blocks, const DebugDev* dbg, uint32_t opts);
+                          uint32_t fe_blocks, uint32_t fe_per, const DebugDev* dbg, uint32_t opts);
 void launch_preprocess_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
                             const DebugDev* dbg, uint32_t opts);
 void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes, uint32_t passes,
