@@ -8,7 +8,7 @@
 // The kernel that writes the keys (the front end) also counts every pass's
 // digits into the workspace histogram and clears the first pass's look-back
 // words; each pass is then one kernel over radix tiles of SIZE keys (4608 for
-// 32-bit keys, 4096 for 64-bit ones), block b taking keys [SIZE b, SIZE (b + 1)):
+// 32-bit keys, 5632 for 64-bit ones), block b taking keys [SIZE b, SIZE (b + 1)):
 //   * the tile loads its keys, ranks each key among equal digits of the tile
 //     with wave64 ballots (stable: tile order is input order) and publishes
 //     its 256 digit counts;

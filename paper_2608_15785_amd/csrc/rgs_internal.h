@@ -57,14 +57,16 @@ inline void fe_block_shape(int64_t n, uint32_t& blocks, uint32_t& per) {
 constexpr int LB_PER_LANE = 8;       // look-back states each lane polls per round trip
 constexpr int SORT_THREADS = 512;    // 8 waves per radix tile
 // Keys per thread of a radix tile: 9 for 32-bit keys (4608-key tiles, 48 KB
-// of LDS: keys, values, per-wave digit counts) and 8 for 64-bit keys (4096,
-// 59 KB), so three or two tiles share a CU.  A pass takes as long as its most
-// loaded CU: the 2.2M entries of a 1M / 1080p frame make 479 tiles of 4608,
-// at most two per CU, where 539 tiles of 4096 left some CUs three (sort 0.075
-// -> 0.072 ms).
+// of LDS: keys, values, per-wave digit counts) and 11 for 64-bit keys (5632,
+// 79 KB), so three or two tiles share a CU.  A pass takes as long as its most
+// loaded CU: the 2.2M fast entries of a 1M / 1080p frame make 479 tiles of
+// 4608, at most two per CU, where 539 tiles of 4096 left some CUs three (sort
+// 0.075 -> 0.072 ms); its 2.87M plain entries make 510 tiles of 5632, one
+// round of two per CU, where 702 tiles of 4096 took two rounds (plain sort
+// 0.169 -> 0.135 ms).
 template <typename KeyT>
 struct SortTile {
-    static constexpr int ITEMS = sizeof(KeyT) == 4 ? 9 : 8;
+    static constexpr int ITEMS = sizeof(KeyT) == 4 ? 9 : 11;
     static constexpr int SIZE = SORT_THREADS * ITEMS;
 };
 inline uint32_t sort_tile_size(uint32_t key_bytes) {
