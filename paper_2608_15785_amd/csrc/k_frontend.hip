@@ -352,8 +352,20 @@ __device__ inline void emit_entries(uint32_t total, uint64_t base, const uint32_
             uint32_t b = local;            // row-major index of the tile in the rectangle
             if (s_mask && w * ((uint32_t)(rc >> 48) - y0 + 1) <= EXACT_TILE_MAX_AREA)
                 b = nth_set_bit(s_mask[j[u]], local);
-            const uint32_t ty = y0 + b / w;
-            const uint32_t tx = x0 + b % w;
+            // b / w and b % w: b < 2^20 (a rectangle holds at most 2^20 tiles)
+            // and w <= 1024, so the float quotient is within 0.25 of b / w and
+            // one correction of its truncation makes it exact
+            uint32_t q = (uint32_t)((float)b * __builtin_amdgcn_rcpf((float)w));
+            int32_t rem = (int32_t)b - (int32_t)(q * w);
+            if (rem < 0) {
+                q -= 1;
+                rem += (int32_t)w;
+            } else if (rem >= (int32_t)w) {
+                q += 1;
+                rem -= (int32_t)w;
+            }
+            const uint32_t ty = y0 + q;
+            const uint32_t tx = x0 + (uint32_t)rem;
             const uint32_t tile = ty * (uint32_t)tiles_x + tx;
             const uint64_t pos = base + e;
             const bool stored = pos < capacity;
