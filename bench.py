@@ -34,8 +34,12 @@ METRIC = "FPS at 1080p/4K (1M/3M Gaussians) fast vs plain path; p50/p99 latency"
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # Algorithmic VALU lane-operations per blended (pixel, Gaussian) pair -- a pair
-# past the skip test that the method must composite; the counts are derived in
-# the design doc from the operations the method defines.
+# past the skip test that the method must composite.  Fast: the folded exponent
+# (5 FMA for the first pixel of a lane, 2 FMA + 1 add for the second: 4 on
+# average), the skip test 1, the bit-level exp 2 (FMA + convert), the select 1,
+# weight 1, transmittance 1, stop test 1, colour 3.  Plain: offsets 2,
+# quadratic 7, exp 2, opacity 1, clamp 1, skip test 1, T (1 - alpha) 2, stop
+# test 1, weight 1, colour 3.
 OPS_PER_PAIR = {"fast": 14, "plain": 21}
 # ... and per blended pair of the backward pass (recomputed alpha, recovered T,
 # the nine derivatives and the running colour behind the pair).
