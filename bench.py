@@ -404,7 +404,7 @@ def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build renders on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the renderer runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

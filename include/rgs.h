@@ -51,7 +51,7 @@ typedef int32_t rgs_status;
 #define RGS_E_HIP        -3   /* a HIP runtime call failed                                 */
 #define RGS_E_CAPACITY   -4   /* more duplicated entries than the workspace holds          */
 #define RGS_E_NODEVICE   -5   /* no usable GPU                                             */
-#define RGS_E_UNSUPPORTED -6  /* entry point or option not available in this build         */
+#define RGS_E_UNSUPPORTED -6  /* entry point or option not available in this library       */
 #define RGS_E_DEVICE     -7   /* a kernel reported an internal failure (bounded wait hit)  */
 
 #define RGS_ABI_VERSION 1
