@@ -180,6 +180,19 @@ def test_largest_frame(R, path):
     run_parity(R, wl.config_scene("cfg0", n=2000), cam, path, tiles=tiles)
 
 
+@pytest.mark.parametrize("path", ["plain", "fast"])
+@pytest.mark.parametrize("n", [1, 65, 1025, 256 * 4096, 256 * 4096 + 1])
+def test_front_end_block_shapes(R, path, n):
+    """Scene sizes at the edges of how the front end splits Gaussians over workgroups:
+    one Gaussian, a count just past a multiple of 64 and past 1024, exactly 256 full
+    workgroups of 4096 (the even split) and one more (4096 per workgroup).  Every key
+    bit-exact; the image on 8 sampled tiles of the small frame."""
+    cam = wl.config_camera("cfg0")
+    plan = oracle.frame_plan(cam.width, cam.height)
+    tiles = None if n < 100_000 else np.random.default_rng(n % 97).choice(plan.n_tiles, 8, replace=False)
+    run_parity(R, wl.config_scene("cfg0", n=n), cam, path, tiles=tiles)
+
+
 _CFG2 = {}
 
 
