@@ -390,7 +390,7 @@ def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup):
     ds.release()
     bwd_s = parts["backward"] * 1e-3
     achieved = pairs * OPS_PER_PAIR_BACKWARD / bwd_s / 1e12
-    return {"workload": "cfg4: 1,000,000 Gaussians, 1920x1080, plain path, L1 loss against a render with "
+    return {"workload": "training: 1,000,000 Gaussians, 1920x1080, plain path, L1 loss against a render with "
                         "means + N(0, 0.01)",
             "steps": steps, "ms_per_step": round((t1 - t0) / steps * 1e3, 4),
             "steps_per_s": round(steps / (t1 - t0), 2), "stage_ms": parts, "l1_loss": loss,
@@ -426,9 +426,9 @@ def main():
     paths = [p for p in args.paths.split(",") if p]
     R = rgs.Renderer(0)
 
-    log("[bench] cfg1: 1,000,000 Gaussians, 1920x1080")
-    sc1 = wl.config_scene("cfg1")
-    cam1 = wl.config_camera("cfg1")
+    log("[bench] 1080p: 1,000,000 Gaussians, 1920x1080")
+    sc1 = wl.config_scene("1080p")
+    cam1 = wl.config_camera("1080p")
     ds1 = R.upload(sc1)
     plan1 = rgs.frame_plan(cam1.width, cam1.height)
     res1 = {}
@@ -437,7 +437,7 @@ def main():
         r.update(frame_counts(R, ds1, cam1, path))
         r["roofline"] = rooflines(path, r, r["stage_ms"], sc1.n, plan1["n_tiles"])
         res1[path] = r
-        log(f"[bench] cfg1 {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
+        log(f"[bench] 1080p {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
 
     ablation = None
     if not args.no_ablation and "fast" in paths:
@@ -452,10 +452,10 @@ def main():
 
     res2 = {}
     if not args.no_4k:
-        log("[bench] cfg2: 3,000,000 Gaussians, 3840x2160, 64-pose orbit")
+        log("[bench] 4k: 3,000,000 Gaussians, 3840x2160, 64-pose orbit")
         ds1.release()
-        sc2 = wl.config_scene("cfg2")
-        cams = [wl.config_camera("cfg2", pose=k) for k in range(64)]
+        sc2 = wl.config_scene("4k")
+        cams = [wl.config_camera("4k", pose=k) for k in range(64)]
         ds2 = R.upload(sc2)
         plan2 = rgs.frame_plan(3840, 2160)
         for path in paths:
@@ -463,7 +463,7 @@ def main():
             r.update(frame_counts(R, ds2, cams[0], path))
             r["roofline_pose0"] = rooflines(path, r, r["stage_ms"], sc2.n, plan2["n_tiles"])
             res2[path] = r
-            log(f"[bench] cfg2 {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
+            log(f"[bench] 4k {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
         if args.no_serving:
             ds2.release()
 
@@ -471,7 +471,7 @@ def main():
     if not args.no_serving:
         log("[bench] serving: 1M and 3M scenes resident, Poisson arrivals")
         if args.no_4k:
-            sc2 = wl.config_scene("cfg2")
+            sc2 = wl.config_scene("4k")
             ds2 = R.upload(sc2, ("fast",))
         ds1b = R.upload(sc1, ("fast",))
         try:
@@ -492,7 +492,7 @@ def main():
     src = {"raster": "k_raster.hip", "frontend": "k_frontend.hip", "duplicate": "k_frontend.hip",
            "sort": "k_sort.hip", "ranges": "k_sort.hip"}[dom]
     rl = dict(stages[dom])
-    counters = measured_counters(kernel, "cfg1-" + main_path, src)
+    counters = measured_counters(kernel, "1080p-" + main_path, src)
     roofline = {"bound": rl["bound"], "achieved": rl["achieved"], "peak": rl["peak"], "unit": rl["unit"],
                 "frac": rl["frac"], "traffic": counters.get("bytes_per_launch"),
                 "kernel": kernel, "stage_ms": rl["ms"]}
@@ -516,10 +516,10 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": f"cfg1: 1,000,000 seeded Gaussians, 1920x1080, {main_path} path "
+        "config": {"workload": f"1080p: 1,000,000 seeded Gaussians, 1920x1080, {main_path} path "
                                "(INT8 SH + FP16 geometry, 32-bit key, fused front end, dual-pixel, "
                                "bit-level exp)" if main_path == "fast" else
-                               "cfg1: 1,000,000 seeded Gaussians, 1920x1080, plain path",
+                               "1080p: 1,000,000 seeded Gaussians, 1920x1080, plain path",
                    "n_gaussians": sc1.n, "width": 1920, "height": 1080, "path": main_path},
         "roofline": roofline,
     }

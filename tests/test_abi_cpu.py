@@ -93,7 +93,7 @@ def test_path_words_are_validated():
 
 
 def _edge_scene():
-    sc = wl.config_scene("cfg0", n=3000)
+    sc = wl.config_scene("small", n=3000)
     sh = sc.sh.copy()
     sh[0] = 0.0                                     # all-zero SH
     sh[1, 1:4, :] = 0.0                             # zero degree-1 blocks
@@ -129,7 +129,7 @@ def test_quantize_host_bit_exact_vs_oracle():
     ("scales", (5, 1), 1e6),
 ])
 def test_quantize_host_rejects(field, index, value):
-    sc = wl.config_scene("cfg0", n=50)
+    sc = wl.config_scene("small", n=50)
     arr = getattr(sc, field).copy()
     arr[index] = value
     setattr(sc, field, arr)

@@ -51,22 +51,22 @@ def run(R, scene, cam, ablations):
 
 @pytest.mark.parametrize("ablation", ABLATIONS)
 def test_each_ablation_matches_its_oracle(R, ablation):
-    run(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), [ablation])
+    run(R, wl.config_scene("small"), wl.config_camera("small"), [ablation])
 
 
 def test_all_ablations_together(R):
-    run(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), ABLATIONS)
+    run(R, wl.config_scene("small"), wl.config_camera("small"), ABLATIONS)
 
 
 @pytest.mark.parametrize("ablation", ["dualpixel", "fusion", "key32"])
 def test_ragged_frame(R, ablation):
-    run(R, wl.config_scene("cfg0", n=2500), wl.config_camera("cfg0", width=250, height=170), [ablation])
+    run(R, wl.config_scene("small", n=2500), wl.config_camera("small", width=250, height=170), [ablation])
 
 
 def test_unfused_front_end_is_the_fused_one(R):
     """Fusion changes where the front end's work happens, not its results."""
-    sc = wl.config_scene("cfg0")
-    cam = wl.config_camera("cfg0")
+    sc = wl.config_scene("small")
+    cam = wl.config_camera("small")
     ds = R.upload(sc, ("plain", "fast"))
     a = R.render_debug(ds, cam, "fast")
     b = R.render_debug(ds, cam, "fast/no-fusion")

@@ -96,7 +96,7 @@ def compare(g, adj, n_expect_min=1):
 @pytest.mark.parametrize("W,H", [(128, 96), (120, 88)])
 def test_small_scene_all_tiles(R, W, H):
     sc = wl.make_scene(3000, 1.0, -3.0, 0.5, 31)
-    cam = wl.config_camera("cfg0", width=W, height=H)
+    cam = wl.config_camera("small", width=W, height=H)
     cam.bg = np.array([0.1, 0.2, 0.3], np.float32)
     rng = np.random.Generator(np.random.PCG64(41))
     dimg = rng.normal(0.0, 1.0, (3, H, W)).astype(np.float32)
@@ -108,7 +108,7 @@ def test_small_scene_all_tiles(R, W, H):
 
 def test_deterministic(R):
     sc = wl.make_scene(2000, 1.0, -3.0, 0.5, 32)
-    cam = wl.config_camera("cfg0", width=96, height=80)
+    cam = wl.config_camera("small", width=96, height=80)
     dimg = np.random.Generator(np.random.PCG64(3)).normal(0, 1, (3, 80, 96)).astype(np.float32)
     a = gpu_backward(R, sc, cam, dimg)
     b = gpu_backward(R, sc, cam, dimg)
@@ -117,13 +117,13 @@ def test_deterministic(R):
     assert np.abs(a["screen"]).sum() > 0
 
 
-def test_cfg4_l1_loss_sampled_tiles(R):
+def test_training_l1_loss_sampled_tiles(R):
     """1M Gaussians at 1080p; L1 loss against a render of the same scene with
     means perturbed by N(0, 0.01); dL/d(image) kept on 40 sampled tiles so that
     the oracle differentiates exactly the same loss."""
     import torch
-    sc = wl.config_scene("cfg1")
-    cam = wl.config_camera("cfg1")
+    sc = wl.config_scene("1080p")
+    cam = wl.config_camera("1080p")
     H, W = cam.height, cam.width
     target_scene = wl.Scene(means=wl.perturbed_means(sc), scales=sc.scales, quats=sc.quats,
                             opacity=sc.opacity, sh=sc.sh)
@@ -145,7 +145,7 @@ def test_cfg4_l1_loss_sampled_tiles(R):
         tx, ty = t % plan.tiles_x, t // plan.tiles_x
         mask[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
     dimg = (np.sign(img - target) / img.size * mask[None]).astype(np.float32)
-    _log(f"[bwd] cfg4: L1 loss {np.abs(img - target).mean():.6g}, {len(tiles)} tiles")
+    _log(f"[bwd] training: L1 loss {np.abs(img - target).mean():.6g}, {len(tiles)} tiles")
     g = gpu_backward(R, sc, cam, dimg)
     assert np.array_equal(g["image"], img)
     adj = OB.render_adjoint(oracle.prepare_plain(sc), cam, dimg.astype(np.float64), tiles=tiles,
@@ -158,7 +158,7 @@ def test_autograd_function_chains_activations(R):
     from paper_2608_15785_amd.autograd import GaussianRasterizer
     import paper_2608_15785_amd as rgs
     sc = wl.make_scene(1500, 1.0, -3.0, 0.5, 33)
-    cam = wl.config_camera("cfg0", width=64, height=64)
+    cam = wl.config_camera("small", width=64, height=64)
     dev = "cuda:0"
     means = torch.tensor(sc.means, device=dev, requires_grad=True)
     log_scales = torch.tensor(np.log(sc.scales.astype(np.float64)).astype(np.float32), device=dev,
@@ -196,7 +196,7 @@ def test_backward_refuses_a_fast_frame_and_small_scratch(R):
     import paper_2608_15785_amd as rgs
     from paper_2608_15785_amd import _binding as B
     sc = wl.make_scene(500, 1.0, -3.0, 0.5, 34)
-    cam = wl.config_camera("cfg0", width=48, height=32)
+    cam = wl.config_camera("small", width=48, height=32)
     ds = R.upload(sc)
     dimg = torch.zeros((3, 32, 48), device="cuda:0")
     R.render(ds, cam, "fast")

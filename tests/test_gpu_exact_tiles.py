@@ -46,25 +46,25 @@ def run(R, scene, cam, ablations=(), tiles=None):
     return g, fr
 
 
-def test_cfg0(R):
-    run(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"))
+def test_small(R):
+    run(R, wl.config_scene("small"), wl.config_camera("small"))
 
 
 @pytest.mark.parametrize("ablations", [("fusion",), ("key32",), ("fastexp", "dualpixel")])
 def test_with_ablations(R, ablations):
-    run(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), ablations)
+    run(R, wl.config_scene("small"), wl.config_camera("small"), ablations)
 
 
 def test_ragged_frame(R):
-    run(R, wl.config_scene("cfg0", n=2500), wl.config_camera("cfg0", width=250, height=170))
+    run(R, wl.config_scene("small", n=2500), wl.config_camera("small", width=250, height=170))
 
 
 def test_fewer_entries_same_image(R):
     """Against the default fast path on the GPU: fewer entries, and the image within the
     bit-level exponential's tolerance (pixels at alpha = 1/255 may be decided differently
     by the float32 skip test and the float64 tile test)."""
-    sc = wl.config_scene("cfg0")
-    cam = wl.config_camera("cfg0")
+    sc = wl.config_scene("small")
+    cam = wl.config_camera("small")
     ds = R.upload(sc, ("fast",))
     a = R.render_debug(ds, cam, "fast")
     b = R.render_debug(ds, cam, "fast/exact-tiles")
@@ -76,10 +76,10 @@ def test_fewer_entries_same_image(R):
     assert float(np.mean(np.abs(a["image"] - b["image"]) > 1e-6)) < 1e-3
 
 
-def test_cfg1_keys_and_sampled_tiles(R):
+def test_1080p_keys_and_sampled_tiles(R):
     """1M Gaussians at 1920x1080: every key bit-exact, image on 32 sampled tiles."""
-    sc = wl.config_scene("cfg1")
-    cam = wl.config_camera("cfg1")
+    sc = wl.config_scene("1080p")
+    cam = wl.config_camera("1080p")
     plan = oracle.frame_plan(cam.width, cam.height)
     tiles = np.random.default_rng(9).choice(plan.n_tiles, 32, replace=False)
     run(R, sc, cam, tiles=tiles)

@@ -47,20 +47,20 @@ def run_parity(R, scene, cam, path, tiles=None, entries=True):
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
-def test_cfg0_full(R, path):
-    run_parity(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), path)
+def test_small_full(R, path):
+    run_parity(R, wl.config_scene("small"), wl.config_camera("small"), path)
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
 @pytest.mark.parametrize("W,H", [(250, 170), (17, 33), (1, 1), (64, 16)])
 def test_ragged_sizes(R, path, W, H):
-    run_parity(R, wl.config_scene("cfg0", n=2500), wl.config_camera("cfg0", width=W, height=H), path)
+    run_parity(R, wl.config_scene("small", n=2500), wl.config_camera("small", width=W, height=H), path)
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
 def test_background_and_termination(R, path):
     sc = wl.make_scene(4000, 1.0, -2.8, 0.4, 21)        # larger Gaussians: many pixels stop early
-    cam = wl.config_camera("cfg0", width=160, height=120)
+    cam = wl.config_camera("small", width=160, height=120)
     cam.bg = np.array([0.2, 0.5, 0.7], np.float32)
     rep = run_parity(R, sc, cam, path)
     assert rep["n_entries"] > 0
@@ -69,7 +69,7 @@ def test_background_and_termination(R, path):
 @pytest.mark.parametrize("path", ["plain", "fast"])
 def test_empty_frame(R, path):
     import torch
-    sc = wl.config_scene("cfg0", n=500)
+    sc = wl.config_scene("small", n=500)
     cam = wl.look_at_camera((0, 0, 30.0), (0, 0, 40.0), (0, 1, 0), 60.0, 48, 40, 1.0, 2.0,
                             bg=(0.1, 0.2, 0.3))
     ds = R.upload(sc, (path,))
@@ -83,17 +83,17 @@ def test_empty_frame(R, path):
 @pytest.mark.parametrize("path", ["plain", "fast"])
 def test_equal_keys_keep_index_order(R, path):
     """Many copies of a few Gaussians: long runs of equal keys must end up in index order."""
-    base = wl.config_scene("cfg0", n=40)
+    base = wl.config_scene("small", n=40)
     idx = np.tile(np.arange(40), 150)
     sc = base.subset(idx)
-    run_parity(R, sc, wl.config_camera("cfg0", width=128, height=96), path)
+    run_parity(R, sc, wl.config_camera("small", width=128, height=96), path)
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
 def test_deterministic(R, path):
     import torch
-    sc = wl.config_scene("cfg0")
-    cam = wl.config_camera("cfg0")
+    sc = wl.config_scene("small")
+    cam = wl.config_camera("small")
     ds = R.upload(sc, (path,))
     a = R.render_debug(ds, cam, path)
     b = R.render_debug(ds, cam, path)
@@ -105,8 +105,8 @@ def test_deterministic(R, path):
 def test_capacity_overflow_is_reported(R, path):
     import paper_2608_15785_amd as rgs
     import torch
-    sc = wl.config_scene("cfg0")
-    cam = wl.config_camera("cfg0")
+    sc = wl.config_scene("small")
+    cam = wl.config_camera("small")
     ds = R.upload(sc, (path,))
     ws = rgs.new_workspace(sc.n, cam.width, cam.height, path, 1000)
     with pytest.raises(rgs.RGSError) as e:
@@ -122,32 +122,32 @@ def test_capacity_overflow_is_reported(R, path):
 
 def test_invalid_arguments(R):
     import paper_2608_15785_amd as rgs
-    sc = wl.config_scene("cfg0", n=100)
+    sc = wl.config_scene("small", n=100)
     ds = R.upload(sc, ("fast",))
-    cam = wl.config_camera("cfg0")
+    cam = wl.config_camera("small")
     ws = rgs.new_workspace(sc.n, 256, 256, "plain", 10000)
     with pytest.raises(rgs.RGSError) as e:          # plain path on a fast-only scene
         rgs.render(R.ctx, ds, cam, "plain", ws)
     assert e.value.status == -1
-    bad = wl.config_camera("cfg0")
+    bad = wl.config_camera("small")
     bad.z_near, bad.z_far = 3.0, 2.0
     with pytest.raises(rgs.RGSError):
         rgs.render(R.ctx, ds, bad, "fast", ws)
-    bad = wl.config_camera("cfg0")
+    bad = wl.config_camera("small")
     bad.width = 0
     with pytest.raises(rgs.RGSError):
         rgs.render(R.ctx, ds, bad, "fast", ws)
-    bad = wl.config_camera("cfg0")
+    bad = wl.config_camera("small")
     bad.height = 20000
     with pytest.raises(rgs.RGSError):
         rgs.render(R.ctx, ds, bad, "fast", ws)
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
-def test_cfg1_keys_and_sampled_tiles(R, path):
+def test_1080p_keys_and_sampled_tiles(R, path):
     """1M Gaussians at 1920x1080: every key bit-exact, image on 64 sampled tiles."""
-    sc = wl.config_scene("cfg1")
-    cam = wl.config_camera("cfg1")
+    sc = wl.config_scene("1080p")
+    cam = wl.config_camera("1080p")
     plan = oracle.frame_plan(cam.width, cam.height)
     tiles = np.random.default_rng(7).choice(plan.n_tiles, 64, replace=False)
     tiles = np.concatenate([tiles, [plan.n_tiles - 1]])          # the ragged corner tile
@@ -156,10 +156,10 @@ def test_cfg1_keys_and_sampled_tiles(R, path):
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
 @pytest.mark.parametrize("pose", [0, 21])
-def test_cfg2_keys_and_sampled_tiles(R, path, pose):
+def test_4k_keys_and_sampled_tiles(R, path, pose):
     """3M Gaussians at 3840x2160 on orbit poses: every key bit-exact, 48 sampled tiles."""
-    sc = _cfg2_scene()
-    cam = wl.config_camera("cfg2", pose=pose)
+    sc = _4k_scene()
+    cam = wl.config_camera("4k", pose=pose)
     plan = oracle.frame_plan(cam.width, cam.height)
     tiles = np.random.default_rng(pose).choice(plan.n_tiles, 48, replace=False)
     run_parity(R, sc, cam, path, tiles=tiles)
@@ -170,14 +170,14 @@ def test_largest_frame(R, path):
     """The largest accepted frame, 16384x16384: 2^20 tiles, so the fast key keeps only
     12 depth bits and many keys tie.  Every key and range bit-exact; the image on 16
     random tiles, nine tiles around the centre and the four corners."""
-    cam = wl.config_camera("cfg0", width=16384, height=16384)
+    cam = wl.config_camera("small", width=16384, height=16384)
     plan = oracle.frame_plan(cam.width, cam.height)
     assert plan.b_t == 20 and plan.b_d == 12
     tx0, ty0 = plan.tiles_x // 2, plan.tiles_y // 2
     centre = [(ty0 + dy) * plan.tiles_x + tx0 + dx for dy in (-2, 0, 2) for dx in (-2, 0, 2)]
     corners = [0, plan.tiles_x - 1, plan.n_tiles - plan.tiles_x, plan.n_tiles - 1]
     tiles = np.concatenate([np.random.default_rng(11).choice(plan.n_tiles, 16, replace=False), centre, corners])
-    run_parity(R, wl.config_scene("cfg0", n=2000), cam, path, tiles=tiles)
+    run_parity(R, wl.config_scene("small", n=2000), cam, path, tiles=tiles)
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
@@ -187,18 +187,18 @@ def test_front_end_block_shapes(R, path, n):
     one Gaussian, a count just past a multiple of 64 and past 1024, exactly 256 full
     workgroups of 4096 (the even split) and one more (4096 per workgroup).  Every key
     bit-exact; the image on 8 sampled tiles of the small frame."""
-    cam = wl.config_camera("cfg0")
+    cam = wl.config_camera("small")
     plan = oracle.frame_plan(cam.width, cam.height)
     tiles = None if n < 100_000 else np.random.default_rng(n % 97).choice(plan.n_tiles, 8, replace=False)
-    run_parity(R, wl.config_scene("cfg0", n=n), cam, path, tiles=tiles)
+    run_parity(R, wl.config_scene("small", n=n), cam, path, tiles=tiles)
 
 
 _CFG2 = {}
 
 
-def _cfg2_scene():
+def _4k_scene():
     if "s" not in _CFG2:
-        _CFG2["s"] = wl.config_scene("cfg2")
+        _CFG2["s"] = wl.config_scene("4k")
     return _CFG2["s"]
 
 
@@ -207,9 +207,9 @@ def test_sort_fallback_counts_match(R, path, monkeypatch):
     """Every radix tile counting its predecessors from their keys (the look-back's fallback,
     forced) gives the same bit-exact entries, at 1M / 1080p and on the small frame."""
     monkeypatch.setenv("RGS_SORT_FALLBACK_ONLY", "1")
-    run_parity(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), path)
-    sc = wl.config_scene("cfg1")
-    cam = wl.config_camera("cfg1")
+    run_parity(R, wl.config_scene("small"), wl.config_camera("small"), path)
+    sc = wl.config_scene("1080p")
+    cam = wl.config_camera("1080p")
     plan = oracle.frame_plan(cam.width, cam.height)
     tiles = np.random.default_rng(3).choice(plan.n_tiles, 16, replace=False)
     run_parity(R, sc, cam, path, tiles=tiles)

@@ -31,8 +31,8 @@ def env():
         pytest.skip("no GPU")
     import paper_2608_15785_amd as rgs
     R = rgs.Renderer(0)
-    scenes = [wl.config_scene("cfg1", n=200_000), wl.config_scene("cfg2", n=300_000)]
-    small = wl.config_scene("cfg0")
+    scenes = [wl.config_scene("1080p", n=200_000), wl.config_scene("4k", n=300_000)]
+    small = wl.config_scene("small")
     dev = [R.upload(s) for s in scenes]
     dsmall = R.upload(small)
     return dict(rgs=rgs, R=R, scenes=scenes, dev=dev, small=small, dsmall=dsmall, torch=torch)
@@ -170,7 +170,7 @@ def test_budget_admits_one_workspace_at_a_time(env):
 def test_small_request_in_the_mix_matches_the_oracle(env):
     rgs, torch = env["rgs"], env["torch"]
     reqs = schedule(env, 8, rate=3000.0, burst=8, seed=9)
-    cam = wl.config_camera("cfg0")
+    cam = wl.config_camera("small")
     out = torch.full((3, cam.height, cam.width), float("nan"), dtype=torch.float32, device="cuda:0")
     reqs.insert(3, (env["dsmall"], cam, "fast", 0.0, out))
     _log("[serve] 9 requests, one of them the 10k-Gaussian 256x256 frame")

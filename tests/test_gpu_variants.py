@@ -46,22 +46,22 @@ def run(R, scene, cam, path, exact_tiles=False):
     return g
 
 
-def test_hw_exp2_cfg0(R):
-    run(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), "fast/hw-exp2")
+def test_hw_exp2_small(R):
+    run(R, wl.config_scene("small"), wl.config_camera("small"), "fast/hw-exp2")
 
 
 def test_hw_exp2_ragged(R):
-    run(R, wl.config_scene("cfg0", n=2500), wl.config_camera("cfg0", width=250, height=170), "fast/hw-exp2")
+    run(R, wl.config_scene("small", n=2500), wl.config_camera("small", width=250, height=170), "fast/hw-exp2")
 
 
 def test_hw_exp2_with_exact_tiles(R):
-    run(R, wl.config_scene("cfg0"), wl.config_camera("cfg0"), "fast/hw-exp2/exact-tiles", exact_tiles=True)
+    run(R, wl.config_scene("small"), wl.config_camera("small"), "fast/hw-exp2/exact-tiles", exact_tiles=True)
 
 
 def test_hw_exp2_close_to_exact_exp_ablation(R):
     """The hardware exp2 and the accurate expf give the same image to float32 rounding."""
-    sc = wl.config_scene("cfg0")
-    cam = wl.config_camera("cfg0")
+    sc = wl.config_scene("small")
+    cam = wl.config_camera("small")
     ds = R.upload(sc, ("plain", "fast"))
     a = R.render_debug(ds, cam, "fast/hw-exp2")
     b = R.render_debug(ds, cam, "fast/no-fastexp")

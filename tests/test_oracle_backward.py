@@ -41,7 +41,7 @@ def activate(raw):
 
 
 def camera(bg=(0.1, 0.3, 0.2)):
-    cam = wl.config_camera("cfg0", width=W, height=H)
+    cam = wl.config_camera("small", width=W, height=H)
     cam.bg = np.asarray(bg, np.float32)
     return cam
 

@@ -120,7 +120,7 @@ def test_alpha_extent_changes_entries_not_the_image():
     P is below -ln 255, which the skip test rejects: the image is the same bit
     for bit, with fewer entries."""
     sc = wl.make_scene(3000, 1.0, -3.0, 0.5, 17)
-    cam = wl.config_camera("cfg0", width=96, height=80)
+    cam = wl.config_camera("small", width=96, height=80)
     arr = oracle.prepare_fast(oracle.quantize_scene(sc))
     a = oracle.render(arr, cam, "fast")
     b = oracle.render(arr, cam, "fast", alpha_extent=False)
@@ -166,8 +166,8 @@ def test_one_pixel_image():
 
 
 def test_sorted_entries_grouped_and_stable():
-    sc = wl.config_scene("cfg0", n=3000)
-    cam = wl.config_camera("cfg0")
+    sc = wl.config_scene("small", n=3000)
+    cam = wl.config_camera("small")
     for path, arr in (("plain", oracle.prepare_plain(sc)),
                       ("fast", oracle.prepare_fast(oracle.quantize_scene(sc)))):
         fr = oracle.render(arr, cam, path, blend=False)
@@ -401,8 +401,8 @@ def test_exact_tile_test_against_dense_sampling():
 
 def test_exact_tiles_change_entries_not_the_image():
     """Dropped tiles hold no pixel with alpha >= 1/255: the entries shrink, the image does not change."""
-    sc = wl.config_scene("cfg0", n=3000)
-    cam = wl.config_camera("cfg0")
+    sc = wl.config_scene("small", n=3000)
+    cam = wl.config_camera("small")
     arr = oracle.prepare_fast(oracle.quantize_scene(sc))
     a = oracle.render(arr, cam, "fast", modes=("fast-def", "fast-exact"))
     b = oracle.render(arr, cam, "fast", modes=("fast-def", "fast-exact"), exact_tiles=True)
@@ -444,8 +444,8 @@ def test_exact_tiles_keep_large_rectangles():
 def test_plain_equals_fast_exact_on_unquantised_scene():
     """Without quantisation and without depth-bin ties, the fast path's culling and
     32-bit key change nothing: the images agree (Sec. IV-A, Eq. depth_quant)."""
-    sc = wl.config_scene("cfg0", n=1500)
-    cam = wl.config_camera("cfg0")
+    sc = wl.config_scene("small", n=1500)
+    cam = wl.config_camera("small")
     arr = oracle.prepare_plain(sc)
     fr_p = oracle.render(arr, cam, "plain")
     arr_f = dict(arr)
@@ -458,9 +458,9 @@ def test_plain_equals_fast_exact_on_unquantised_scene():
     assert np.max(np.abs(fr_f.image - fr_p.image)) < 1e-12
 
 
-def test_oracle_invariants_cfg0_subset():
-    sc = wl.config_scene("cfg0", n=2000)
-    cam = wl.config_camera("cfg0")
+def test_oracle_invariants_small_subset():
+    sc = wl.config_scene("small", n=2000)
+    cam = wl.config_camera("small")
     fr = oracle.render(oracle.prepare_plain(sc), cam, "plain")
     assert np.all((fr.T_final >= 0) & (fr.T_final <= 1))
     assert np.all(fr.image >= 0)

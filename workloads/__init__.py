@@ -11,15 +11,15 @@ The paper measures on trained scenes (Mip-NeRF 360, Tanks & Temples, Deep
 Blending) that are not available here; these seeded scenes stand in for them
 with the sizes and distributions of the five named workloads:
 
-* ``cfg0`` 10,000 Gaussians in [-1,1]^3, log-scale N(-3.5, 0.5), 256x256, camera
+* ``small`` 10,000 Gaussians in [-1,1]^3, log-scale N(-3.5, 0.5), 256x256, camera
   at distance 3, fovx 60 deg (the small parity case);
-* ``cfg1`` 1,000,000 Gaussians in [-10,10]^3, log-scale N(-4, 0.6), 1920x1080,
+* ``1080p`` 1,000,000 Gaussians in [-10,10]^3, log-scale N(-4, 0.6), 1920x1080,
   camera at distance 25, fovx 60 deg;
-* ``cfg2`` 3,000,000 Gaussians in [-20,20]^3, log-scale N(-4, 0.6), 3840x2160,
+* ``4k`` 3,000,000 Gaussians in [-20,20]^3, log-scale N(-4, 0.6), 3840x2160,
   64-pose orbit of radius 40 at 20 deg elevation, fovx 50 deg;
-* ``cfg3`` serving: the cfg1 and cfg2 scenes, Poisson arrivals, mixed 720p /
+* ``serving``: the 1080p and 4k scenes, Poisson arrivals, mixed 720p /
   1080p / 4K orbit poses;
-* ``cfg4`` differentiation: the cfg1 scene and camera, target rendered from means
+* ``training`` (differentiation): the 1080p scene and camera, target rendered from means
   perturbed by N(0, 0.01).
 
 Draw order for a scene (one ``numpy.random.Generator(PCG64(seed))``):
@@ -149,16 +149,16 @@ def orbit_camera(k: int, n_poses: int, radius: float, elevation_deg: float,
 
 # name -> (n, half_extent, log-scale mean, log-scale std, seed)
 SCENE_CONFIGS = {
-    "cfg0": (10_000, 1.0, -3.5, 0.5, 0),
-    "cfg1": (1_000_000, 10.0, -4.0, 0.6, 1),
-    "cfg2": (3_000_000, 20.0, -4.0, 0.6, 2),
+    "small": (10_000, 1.0, -3.5, 0.5, 0),
+    "1080p": (1_000_000, 10.0, -4.0, 0.6, 1),
+    "4k": (3_000_000, 20.0, -4.0, 0.6, 2),
 }
 
 # name -> camera recipe
 CAMERA_CONFIGS = {
-    "cfg0": dict(distance=3.0, fovx=60.0, width=256, height=256, half_extent=1.0),
-    "cfg1": dict(distance=25.0, fovx=60.0, width=1920, height=1080, half_extent=10.0),
-    "cfg2": dict(orbit_radius=40.0, elevation=20.0, n_poses=64, fovx=50.0,
+    "small": dict(distance=3.0, fovx=60.0, width=256, height=256, half_extent=1.0),
+    "1080p": dict(distance=25.0, fovx=60.0, width=1920, height=1080, half_extent=10.0),
+    "4k": dict(orbit_radius=40.0, elevation=20.0, n_poses=64, fovx=50.0,
                  width=3840, height=2160, half_extent=20.0),
 }
 
@@ -171,7 +171,7 @@ def config_scene(name: str, n: int | None = None) -> Scene:
 
 def config_camera(name: str, pose: int = 0, width: int | None = None,
                   height: int | None = None) -> Camera:
-    """The camera of a named workload; cfg2 takes an orbit pose index.
+    """The camera of a named workload; 4k takes an orbit pose index.
 
     ``width``/``height`` override the resolution (the serving mix renders the
     same poses at 720p, 1080p and 4K).
@@ -207,8 +207,8 @@ def poisson_requests(rate_hz: float, n_requests: int, seed: int = 3):
 # Orbits of the two resident scenes of the serving workload: the 1M scene is
 # viewed from its single-frame distance, the 3M scene from its 64-pose orbit.
 SERVING_ORBITS = (
-    dict(scene="cfg1", orbit_radius=25.0, elevation=20.0, n_poses=64, fovx=60.0, half_extent=10.0),
-    dict(scene="cfg2", orbit_radius=40.0, elevation=20.0, n_poses=64, fovx=50.0, half_extent=20.0),
+    dict(scene="1080p", orbit_radius=25.0, elevation=20.0, n_poses=64, fovx=60.0, half_extent=10.0),
+    dict(scene="4k", orbit_radius=40.0, elevation=20.0, n_poses=64, fovx=50.0, half_extent=20.0),
 )
 
 
