@@ -91,6 +91,13 @@ typedef int32_t rgs_status;
  * The image is that of the exact exponential to within the instruction's
  * 1-ulp error.  Not valid with RGS_ABLATE_FASTEXP or RGS_ABLATE_DUALPIXEL. */
 #define RGS_HW_EXP2          (1 << 16)
+/* Extension of the fast path: four pixels per lane instead of two.  Eq.
+ * dual_pixel is applied along the column three times, P(x, y + 1) =
+ * P(x, y) + C2 x + C3 (2y + 1) + C5, so a wave of 64 lanes covers a whole
+ * 16x16 tile and culls the tile's list against the tile instead of against
+ * half-tiles (Sec. IV-B).  Same image definition as RGS_PATH_FAST.  Not valid
+ * with RGS_ABLATE_FASTEXP, RGS_ABLATE_DUALPIXEL or RGS_HW_EXP2. */
+#define RGS_QUAD_PIXEL       (1 << 17)
 
 #define RGS_TILE 16
 #define RGS_MAX_DIM 16384     /* largest accepted image width or height                    */
@@ -153,6 +160,17 @@ rgs_status rgs_ctx_set_timing(rgs_ctx* ctx, int32_t enable);
  * renders recorded since timing was switched on (stage_ms[RGS_N_STAGES], ms)
  * and the number of renders.  Clears the accumulators. */
 rgs_status rgs_ctx_collect_timing(rgs_ctx* ctx, double* stage_ms, int64_t* n_frames);
+
+/* Roofline calibration probe (Sec. III measures each stage against the
+ * chip's peaks).  Enqueues one kernel of `blocks` workgroups of 256 threads;
+ * every wave issues exactly 8 * iters float32 FMA instructions in its main
+ * loop (plus at most a few dozen other VALU instructions) with eight
+ * independent chains per lane, and each thread writes one float to out.
+ * Profiled together with its duration, its VALU-instruction and busy-cycle
+ * counters calibrate those of the rasterizers.  out: device, blocks * 256
+ * floats, caller-owned.  Asynchronous.  Errors: INVALID (NULL, blocks outside
+ * [1, 2^20], iters < 0), HIP. */
+rgs_status rgs_probe_valu(rgs_ctx* ctx, int32_t blocks, int32_t iters, float* out);
 
 /* ---------------------------------------------------------------------------
  * Scene upload (once per scene, not per frame).
@@ -330,8 +348,12 @@ rgs_status rgs_render_debug(rgs_ctx* ctx, const rgs_scene* scene, const rgs_came
  * the workspace's capacity; a request replays it after its camera and output
  * pointer are written into the argument block of the graph's reset kernel.
  * With use_graphs = 0 the kernels are launched per request.  A frame whose
- * entries exceed its workspace is rendered again, uncaptured, in a workspace
- * sized for it, and later workspaces of its class are allocated larger.
+ * entries exceed its workspace grows its class to the frame's entry count
+ * plus a quarter, and the request returns to the head of the queue: it is
+ * admitted again like any other request, in a workspace of the grown class
+ * obtained within mem_budget, while frames in other slots keep running (its
+ * response then has retried = 1; a second overflow fails it with
+ * RGS_E_CAPACITY).
  *
  * Requests' device pointers (scenes, outputs) must stay valid, and outputs
  * untouched by other work, until rgs_serve returns.  rgs_serve synchronises:
@@ -365,8 +387,8 @@ typedef struct {
                                      workspace alone exceeds the budget)                      */
     int32_t slot;                 /* frame slot that ran it (-1 if none)                      */
     int32_t graph;                /* 1 if the frame was a graph replay                        */
-    int32_t retried;              /* 1 if it was rendered again after running out of entries */
-    double t_admit;               /* host clock, s after start, when its work was enqueued     */
+    int32_t retried;              /* 1 if it was admitted again after running out of entries   */
+    double t_admit;               /* host clock, s after start, when its (last) frame was enqueued */
     double t_done;                /* device clock, s after start, when its image was complete  */
     double latency;               /* t_done - arrival                                          */
     int64_t n_entries;            /* duplicated (key, index) entries of the frame              */

@@ -33,7 +33,7 @@ PATH_FAST = 1
 ABLATIONS = {"fastexp": 1 << 8, "dualpixel": 1 << 9, "fusion": 1 << 10, "extent": 1 << 11,
              "key32": 1 << 12, "int8sh": 1 << 13, "fp16geom": 1 << 14}
 # Extensions of the fast path (rgs.h): "fast/<name>" adds them.
-EXTENSIONS = {"exact-tiles": 1 << 15, "hw-exp2": 1 << 16}
+EXTENSIONS = {"exact-tiles": 1 << 15, "hw-exp2": 1 << 16, "quad-pixel": 1 << 17}
 
 
 class _Paths(dict):
@@ -169,6 +169,7 @@ SIGNATURES = [
     ("rgs_render_debug", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(CameraC), C.c_int32, C.c_int32,
                                      C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(DebugOut),
                                      C.POINTER(FrameStats)]),
+    ("rgs_probe_valu", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     ("rgs_server_create", C.c_int32, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
     ("rgs_server_destroy", None, [C.c_void_p]),
     ("rgs_serve", C.c_int32, [C.c_void_p, C.POINTER(Request), C.c_int64, C.POINTER(Response),
@@ -284,6 +285,15 @@ def camera_struct(cam) -> CameraC:
 def _torch():
     import torch
     return torch
+
+
+def probe_valu(ctx: "Context", blocks: int, iters: int, out) -> None:
+    """Enqueues the VALU calibration probe (rgs_probe_valu): blocks x 256
+    threads, 8 * iters FMA instructions per wave; out is a float32 device
+    tensor of at least blocks * 256 elements."""
+    if out.numel() < blocks * 256 or out.dtype != _torch().float32 or not out.is_cuda:
+        raise ValueError("out must be a float32 device tensor of blocks * 256 elements")
+    _check(lib.rgs_probe_valu(ctx.handle, int(blocks), int(iters), _ptr(out)), "rgs_probe_valu")
 
 
 class Context:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -291,6 +292,16 @@ extern "C" rgs_status rgs_ctx_collect_timing(rgs_ctx* ctx, double* stage_ms, int
     return ok();
 }
 
+extern "C" rgs_status rgs_probe_valu(rgs_ctx* ctx, int32_t blocks, int32_t iters, float* out) {
+    if (!ctx || !out) return fail(RGS_E_INVALID, "rgs_probe_valu: NULL argument");
+    if (blocks < 1 || blocks > (1 << 20) || iters < 0)
+        return fail(RGS_E_INVALID, "rgs_probe_valu: blocks %d outside [1, 2^20] or iters %d < 0", blocks, iters);
+    HIP_TRY(hipSetDevice(ctx->device));
+    launch_probe_valu(ctx->stream, out, (uint32_t)blocks, (uint32_t)iters);
+    HIP_TRY(hipGetLastError());
+    return ok();
+}
+
 // Events of the next timed frame (the pool grows on demand; full pools are
 // harvested, which synchronises the stream only every 1024 frames).
 static rgs_status next_events(rgs_ctx* ctx, FrameEvents** fe) {
@@ -313,6 +324,7 @@ static rgs_status next_events(rgs_ctx* ctx, FrameEvents** fe) {
 
 struct rgs_scene {
     int device;
+    uint64_t tag;        // new at upload and at every rgs_scene_update_plain
     int64_t n;
     uint64_t n_pad;
     uint32_t formats;
@@ -320,6 +332,11 @@ struct rgs_scene {
     uint32_t* fast;      // F_COUNT planes of n_pad words
     uint64_t bytes;
 };
+
+// Scene tags: a process-wide counter, so that no two states of any scenes
+// share a tag.
+static std::atomic<uint64_t> g_scene_tags{1};
+static uint64_t next_scene_tag() { return g_scene_tags.fetch_add(1, std::memory_order_relaxed); }
 
 extern "C" rgs_status rgs_scene_upload(rgs_ctx* ctx, const rgs_scene_desc* d, uint32_t formats,
                                        rgs_scene** out) {
@@ -334,6 +351,7 @@ extern "C" rgs_status rgs_scene_upload(rgs_ctx* ctx, const rgs_scene_desc* d, ui
     const uint64_t np = ((uint64_t)n + 63) & ~63ull;
     rgs_scene* sc = new rgs_scene();
     sc->device = ctx->device;
+    sc->tag = next_scene_tag();
     sc->n = n;
     sc->n_pad = np;
     sc->formats = formats;
@@ -436,7 +454,7 @@ static uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
 // The base path (RGS_PATH_PLAIN / RGS_PATH_FAST) and the ablation bits of a
 // path argument.
 static int32_t path_base(int32_t path) { return path & 0xff; }
-static constexpr uint32_t PATH_BITS = RGS_ABLATE_MASK | RGS_EXACT_TILES | RGS_HW_EXP2;
+static constexpr uint32_t PATH_BITS = RGS_ABLATE_MASK | RGS_EXACT_TILES | RGS_HW_EXP2 | RGS_QUAD_PIXEL;
 static uint32_t path_opts(int32_t path) { return ((uint32_t)path & PATH_BITS) >> 8; }
 
 static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t capacity, WsLayout& L) {
@@ -510,6 +528,9 @@ rgs_status rgs::check_path(int32_t path) {
     if ((path & RGS_HW_EXP2) && (path & (RGS_ABLATE_FASTEXP | RGS_ABLATE_DUALPIXEL)))
         return fail(RGS_E_INVALID, "RGS_HW_EXP2 replaces the exponential of the dual-pixel rasterizer; "
                                    "not with RGS_ABLATE_FASTEXP or RGS_ABLATE_DUALPIXEL");
+    if ((path & RGS_QUAD_PIXEL) && (path & (RGS_ABLATE_FASTEXP | RGS_ABLATE_DUALPIXEL | RGS_HW_EXP2)))
+        return fail(RGS_E_INVALID, "RGS_QUAD_PIXEL extends the dual-pixel rasterizer with the bit-level "
+                                   "exponential; not with RGS_ABLATE_FASTEXP, RGS_ABLATE_DUALPIXEL or RGS_HW_EXP2");
     return RGS_OK;
 }
 
@@ -652,10 +673,26 @@ static rgs_status header_status(const WsHeader& h, rgs_frame_stats* st, int64_t 
     return RGS_OK;
 }
 
-FrameParams rgs::frame_params(const rgs_camera* c, float* out) {
+// FNV-1a over the camera's bytes and the image size.
+static uint64_t camera_hash(const rgs_camera* c, int32_t width, int32_t height) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    };
+    mix(c, sizeof(rgs_camera));
+    mix(&width, sizeof(width));
+    mix(&height, sizeof(height));
+    return h;
+}
+
+FrameParams rgs::frame_params(const rgs_camera* c, float* out, const rgs_scene* sc, int32_t width,
+                              int32_t height) {
     FrameParams p;
     p.cam = cam_dev(c);
     p.out = out;
+    p.scene_tag = sc ? sc->tag : 0;
+    p.cam_hash = camera_hash(c, width, height);
     return p;
 }
 
@@ -825,7 +862,7 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
     }
     FrameHooks hooks{hook_mark, hook_after_front, &rh};
     bool in_b = false;
-    s = enqueue_frame(st, fl, frame_params(cam, out), dbg ? &dd : nullptr, dbg != nullptr, nullptr,
+    s = enqueue_frame(st, fl, frame_params(cam, out, sc, W, H), dbg ? &dd : nullptr, dbg != nullptr, nullptr,
                       (rh.fe || dbg) ? &hooks : nullptr, &in_b);
     if (s != RGS_OK) return s;
 
@@ -899,6 +936,7 @@ extern "C" rgs_status rgs_scene_update_plain(rgs_ctx* ctx, rgs_scene* sc, const 
     launch_update_plain(ctx->stream, sc->plain, sc->n_pad, sc->n, p->means, p->scales, p->quats, p->opacity,
                         p->sh);
     HIP_TRY(hipGetLastError());
+    sc->tag = next_scene_tag();
     return ok();
 }
 
@@ -940,6 +978,15 @@ extern "C" rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, 
     if (s != RGS_OK) return s;
     if (h.path != (uint32_t)RGS_PATH_PLAIN || h.capacity != fl.f.capacity || h.passes != fl.L.passes)
         return fail(RGS_E_INVALID, "the workspace does not hold a plain render of this size");
+    FrameParams prm;
+    HIP_TRY(hipMemcpyAsync(&prm, static_cast<const char*>(workspace) + fl.L.params, sizeof(prm),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    if (prm.scene_tag != scene->tag)
+        return fail(RGS_E_INVALID, "the workspace's last frame is not a render of this scene in its current state "
+                                   "(another scene, or its parameters were updated since)");
+    if (prm.cam_hash != camera_hash(cam, width, height))
+        return fail(RGS_E_INVALID, "the workspace's last frame was rendered with another camera or size");
     s = header_status(h, nullptr, scene->n);
     if (s != RGS_OK) return s;
     const bool in_b = (fl.L.passes % 2) == 1;

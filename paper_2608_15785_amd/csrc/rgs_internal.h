@@ -93,7 +93,8 @@ enum PlainPlane { P_MX = 0, P_MY, P_MZ, P_SX, P_SY, P_SZ, P_QW, P_QX, P_QY, P_QZ
 
 // Fast-path ablation bits (the path argument's bits 8..14, shifted down).
 constexpr uint32_t OPT_FASTEXP = 1u, OPT_DUALPIXEL = 2u, OPT_FUSION = 4u, OPT_EXTENT = 8u, OPT_KEY32 = 16u,
-                   OPT_INT8_SH = 32u, OPT_FP16_GEOM = 64u, OPT_EXACT_TILES = 128u, OPT_HW_EXP2 = 256u;
+                   OPT_INT8_SH = 32u, OPT_FP16_GEOM = 64u, OPT_EXACT_TILES = 128u, OPT_HW_EXP2 = 256u,
+                   OPT_QUAD = 512u;
 // Fast-format planes (32-bit words, one per plane, each n_pad long).
 //   F_MX..F_MZ   float32 mean
 //   F_QWX, F_QYZ FP16 pairs (w, x), (y, z) of the quaternion
@@ -121,6 +122,12 @@ struct CamDev {
 struct FrameParams {
     CamDev cam;
     float* out;          // [3][H][W]
+    // What the frame was rendered from, for the backward pass's check that the
+    // workspace still holds the frame it is asked to differentiate: the
+    // scene's tag (new at every upload and every parameter update) and a hash
+    // of the camera and the image size.
+    uint64_t scene_tag;
+    uint64_t cam_hash;
 };
 static_assert(sizeof(FrameParams) <= 256, "frame parameters fit one 256-byte slot");
 
@@ -494,6 +501,7 @@ void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool
 void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count,
                         uint32_t opts);
 void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n);
+void launch_probe_valu(hipStream_t s, float* out, uint32_t blocks, uint32_t iters);
 
 // The n_proc word of a pixel: pairs visited, with this bit set when blending
 // stopped at the last of them (that pair was not blended).

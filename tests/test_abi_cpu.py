@@ -73,7 +73,8 @@ def test_path_words_are_validated():
     """Ablation and extension bits: accepted on the fast path, rejected on the plain path, and the
     exact ellipse-tile test is rejected together with the extent ablation it refines."""
     ok = ["fast/no-fusion", "fast/exact-tiles", "fast/no-fusion/exact-tiles", "fast/no-key32/exact-tiles",
-          "fast/hw-exp2", "fast/hw-exp2/exact-tiles", "fast/no-key32/hw-exp2",
+          "fast/hw-exp2", "fast/hw-exp2/exact-tiles", "fast/no-key32/hw-exp2", "fast/quad-pixel",
+          "fast/quad-pixel/exact-tiles", "fast/no-int8sh/quad-pixel",
           "fast/" + "/".join("no-" + a for a in B.ABLATIONS)]
     for p in ok:
         assert rgs.workspace_size(1000, 64, 64, p, 4096) > 0
@@ -82,7 +83,11 @@ def test_path_words_are_validated():
                  B.PATH_PLAIN | B.EXTENSIONS["exact-tiles"], B.PATH_PLAIN | B.ABLATIONS["fusion"],
                  B.PATH_FAST | B.ABLATIONS["fastexp"] | B.EXTENSIONS["hw-exp2"],
                  B.PATH_FAST | B.ABLATIONS["dualpixel"] | B.EXTENSIONS["hw-exp2"],
-                 B.PATH_PLAIN | B.EXTENSIONS["hw-exp2"], B.PATH_FAST | (1 << 17), 2):
+                 B.PATH_PLAIN | B.EXTENSIONS["hw-exp2"], B.PATH_FAST | (1 << 18), 2,
+                 B.PATH_FAST | B.EXTENSIONS["quad-pixel"] | B.EXTENSIONS["hw-exp2"],
+                 B.PATH_FAST | B.EXTENSIONS["quad-pixel"] | B.ABLATIONS["fastexp"],
+                 B.PATH_FAST | B.EXTENSIONS["quad-pixel"] | B.ABLATIONS["dualpixel"],
+                 B.PATH_PLAIN | B.EXTENSIONS["quad-pixel"]):
         assert B.lib.rgs_workspace_size(1000, 64, 64, word, 4096, C.byref(size)) == B.RGS_E_INVALID, hex(word)
     for bad in ("fast/no-nothing", "fast/exact", "plain/exact-tiles", "fast/"):
         with pytest.raises(KeyError):
