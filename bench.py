@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device copies of MIB MiB (scale reference for HBM counters)")
+    ap.add_argument("--calibrate-valu", action="store_true",
+                    help="only run the VALU probe at 1, 2, 4 and 8 waves per SIMD (issue-rate and clock "
+                         "reference for the VALU counters)")
     return ap.parse_args()
 
 
@@ -203,6 +206,37 @@ def rooflines(path, counts, stage_ms, n, n_tiles):
                          unit="Tops/s", frac=round(tops / VALU_PEAK_TOPS, 4), pairs_blended=counts["pairs"],
                          pairs_visited=counts["pairs_visited"], ops_per_pair=ops, ms=round(ms, 4))
     return out
+
+
+PROBE_ITERS = 20000
+
+
+def calibrate_valu(rgs, torch):
+    """The VALU probe (8 * PROBE_ITERS FMA instructions per wave) at 1, 2, 4
+    and 8 waves per SIMD, each dispatch timed with events on its stream; a
+    profiler run of this mode reads the same dispatches' VALU and cycle
+    counters."""
+    from paper_2608_15785_amd import _binding as B
+    R = rgs.Renderer(0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = []
+    for waves_per_simd in (1, 2, 4, 8):
+        blocks = cus * waves_per_simd          # 256-thread workgroups: 4 waves, one per SIMD
+        buf = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+        for rep in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            B.probe_valu(R.ctx, blocks, PROBE_ITERS, buf)
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b)
+        waves = blocks * 4
+        insts = waves * 8 * PROBE_ITERS
+        out.append({"waves_per_simd": waves_per_simd, "blocks": blocks, "ms": round(ms, 4),
+                    "fma_wave_insts": insts,
+                    "insts_per_simd_cycle_at_2.4GHz": round(insts / (ms * 1e-3 * cus * 4 * 2.4e9), 4)})
+        del buf
+    return {"calibrate_valu": out, "iters": PROBE_ITERS, "cus": cus}
 
 
 def cpu_baseline(scene, cam, n_tiles_sample):
@@ -422,6 +456,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": n * 4, "copies": 5}))
+        return
+    if args.calibrate_valu:
+        print(json.dumps(calibrate_valu(rgs, torch)), flush=True)
         return
     paths = [p for p in args.paths.split(",") if p]
     R = rgs.Renderer(0)

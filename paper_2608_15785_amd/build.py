@@ -23,7 +23,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librgs.so")
 ARCH = "gfx950"
 
-SOURCES = ["rgs_api.cpp", "rgs_serve.cpp", "k_frontend.hip", "k_sort.hip", "k_raster.hip", "k_backward.hip"]
+SOURCES = ["rgs_api.cpp", "rgs_serve.cpp", "k_frontend.hip", "k_sort.hip", "k_raster.hip", "k_backward.hip",
+           "k_probe.hip"]
 
 COMMON = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
