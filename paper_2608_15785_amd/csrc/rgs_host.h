@@ -44,7 +44,8 @@ rgs_status prepare_frame(const rgs_scene* sc, int32_t width, int32_t height, int
 rgs_status check_camera(const rgs_camera* c);
 // A `path` argument: RGS_PATH_PLAIN, or RGS_PATH_FAST with ablation and extension bits.
 rgs_status check_path(int32_t path);
-FrameParams frame_params(const rgs_camera* c, float* out);
+// The frame parameters of a render of scene sc with camera c at W x H into out.
+FrameParams frame_params(const rgs_camera* c, float* out, const rgs_scene* sc, int32_t width, int32_t height);
 int scene_device(const rgs_scene* sc);
 
 // Optional instrumentation of enqueue_frame: mark(user, k) after stage k's

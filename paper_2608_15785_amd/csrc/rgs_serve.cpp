@@ -216,7 +216,7 @@ rgs_status acquire(rgs_server* s, const ClassKey& k, const FrameParams& first, h
 
 rgs_status launch(rgs_server* s, Slot& slot, Workspace* w, const rgs_request& r) {
     w->status->done = 0;
-    const FrameParams prm = frame_params(&r.camera, r.out_chw);
+    const FrameParams prm = frame_params(&r.camera, r.out_chw, r.scene, r.width, r.height);
     if (w->exec) {
         ResetArgs ra = reset_args(w->fl.w, w->fl.L.zero_end, w->fl.f, w->fl.path_word, prm);
         void* args[] = {&ra};
@@ -233,36 +233,6 @@ rgs_status launch(rgs_server* s, Slot& slot, Workspace* w, const rgs_request& r)
     w->busy = true;
     w->last_used = ++s->tick;
     slot.ws = w;
-    return RGS_OK;
-}
-
-// Renders request r again, uncaptured, in a workspace sized for `entries`.
-rgs_status rerender(rgs_server* s, Slot& slot, const rgs_request& r, uint64_t entries, FrameStatus* st_host,
-                    int64_t* n_entries) {
-    uint64_t bytes = 0;
-    rgs_status e = rgs_workspace_size(scene_size(r.scene), r.width, r.height, r.path, (int64_t)entries, &bytes);
-    if (e != RGS_OK) return e;
-    void* mem = nullptr;
-    HIP_TRY(hipMalloc(&mem, bytes));
-    FrameLaunch fl;
-    e = prepare_frame(r.scene, r.width, r.height, r.path, mem, bytes, &fl);
-    if (e == RGS_OK) {
-        st_host->done = 0;
-        e = enqueue_frame(slot.stream, fl, frame_params(&r.camera, r.out_chw), nullptr, false, st_host,
-                          nullptr, nullptr);
-    }
-    hipError_t he = hipSuccess;
-    if (e == RGS_OK) {
-        he = hipEventRecord(slot.done, slot.stream);
-        if (he == hipSuccess) he = hipEventSynchronize(slot.done);
-    }
-    (void)hipStreamSynchronize(slot.stream);
-    (void)hipFree(mem);
-    if (e != RGS_OK) return e;
-    if (he != hipSuccess) return fail(RGS_E_HIP, "re-render: %s", hipGetErrorString(he));
-    *n_entries = (int64_t)st_host->n_entries;
-    if (st_host->error) return fail(RGS_E_DEVICE, "a kernel's bounded wait gave up (flags 0x%x)", st_host->error);
-    if (st_host->overflow) return fail(RGS_E_CAPACITY, "re-render overflowed");
     return RGS_OK;
 }
 
@@ -383,12 +353,32 @@ extern "C" rgs_status rgs_serve(rgs_server* s, const rgs_request* reqs, int64_t 
                 rp.status = fail(RGS_E_HIP, "frame ran with another request's parameters");
             else if (w->status->error) rp.status = fail(RGS_E_DEVICE, "bounded wait gave up (0x%x)", w->status->error);
             else if (w->status->overflow) {
-                uint64_t& need = need_of(s, w->key);
-                const uint64_t want = std::min<uint64_t>(
-                    RGS_MAX_ENTRIES, (uint64_t)std::ceil(GROWTH * (double)w->status->n_entries));
-                need = std::max(need, want);
-                rp.retried = 1;
-                rp.status = rerender(s, sl, r, want, w->status, &rp.n_entries);
+                // The frame needed more entries than its workspace holds.  Its
+                // class grows to the frame's count plus headroom, and the
+                // request goes back to the head of the queue: it is admitted
+                // again like any other, in a workspace of the grown class that
+                // acquire() obtains within the budget, while the other slots'
+                // frames keep running.  The count is exact even on overflow, so
+                // the second render fits unless the class is at the largest
+                // capacity already.
+                if (rp.retried || w->entries >= RGS_MAX_ENTRIES) {
+                    rp.status = fail(RGS_E_CAPACITY, "the frame needs %llu entries, more than its workspace of "
+                                     "%llu", (unsigned long long)w->status->n_entries,
+                                     (unsigned long long)w->entries);
+                } else {
+                    uint64_t& need = need_of(s, w->key);
+                    const uint64_t want = std::min<uint64_t>(
+                        RGS_MAX_ENTRIES, (uint64_t)std::ceil(GROWTH * (double)w->status->n_entries));
+                    need = std::max(need, want);
+                    rp.retried = 1;
+                    queue.push_front(sl.req);
+                    w->busy = false;
+                    sl.req = -1;
+                    sl.ws = nullptr;
+                    --in_flight;
+                    progress = true;
+                    continue;
+                }
             }
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, s->ev0, sl.done) == hipSuccess) rp.t_done = ms * 1e-3;
@@ -418,7 +408,8 @@ extern "C" rgs_status rgs_serve(rgs_server* s, const rgs_request* reqs, int64_t 
             const rgs_request& r = reqs[i];
             const ClassKey k{r.scene, r.width, r.height, r.path};
             Workspace* w = nullptr;
-            rgs_status e = acquire(s, k, frame_params(&r.camera, r.out_chw), free_slot->stream, &w);
+            rgs_status e = acquire(s, k, frame_params(&r.camera, r.out_chw, r.scene, r.width, r.height),
+                                   free_slot->stream, &w);
             if (e != RGS_OK) {             // this request cannot run at all
                 resp[i].status = e;
                 resp[i].t_done = resp[i].t_admit = seconds_since(t0);

@@ -136,6 +136,24 @@ def test_overflow_is_rendered_again_and_the_class_grows(env):
     srv.close()
 
 
+def test_overflow_while_others_run_stays_within_budget(env):
+    """Every class starts with a 65536-entry workspace and overflows on its first
+    frame while other frames of the burst are in flight; each overflowed request
+    is admitted again through the budget, so the peak never exceeds it."""
+    rgs = env["rgs"]
+    reqs = schedule(env, 12, rate=1000.0, burst=12, seed=11)
+    budget = 1 << 30
+    _log(f"[serve] overflow under load: 12 requests at once, budget {budget} bytes")
+    srv = rgs.Server(0, n_streams=4, mem_budget=budget, use_graphs=True, entries_per_gaussian=0.01)
+    resp, st = srv.serve(reqs)
+    _log(f"[serve] {st}; retried {[r['retried'] for r in resp]}")
+    assert sum(r["retried"] for r in resp) >= 2
+    assert st["max_in_flight"] >= 2
+    assert st["ws_bytes_peak"] <= budget
+    assert_same_as_alone(env, reqs, resp)
+    srv.close()
+
+
 def test_budget_admits_one_workspace_at_a_time(env):
     rgs, torch = env["rgs"], env["torch"]
     from paper_2608_15785_amd import _binding as B
