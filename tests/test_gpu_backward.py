@@ -221,3 +221,85 @@ def test_backward_refuses_a_fast_frame_and_small_scratch(R):
     assert e.value.status == B.RGS_E_INVALID
     torch.cuda.synchronize()
     ds.release()
+
+
+def test_backward_refuses_a_stale_workspace(R):
+    """The workspace records which scene state, camera and size its last frame
+    came from; the backward call refuses any other frame."""
+    import torch
+    import paper_2608_15785_amd as rgs
+    from paper_2608_15785_amd import _binding as B
+    sc = wl.make_scene(500, 1.0, -3.0, 0.5, 35)
+    other = wl.make_scene(500, 1.0, -3.0, 0.5, 36)
+    cam = wl.config_camera("small", width=48, height=32)
+    cam2 = wl.look_at_camera((0.3, 0.1, -3.0), (0, 0, 0), (0, 1, 0), 60.0, 48, 32, cam.z_near, cam.z_far)
+    ds, ds2 = R.upload(sc, ("plain",)), R.upload(other, ("plain",))
+    dimg = torch.ones((3, 32, 48), device="cuda:0")
+    ws = R.workspace(sc.n, 48, 32, "plain")
+    R.render(ds, cam, "plain")
+    rgs.render_backward(R.ctx, ds, cam, ws, dimg)              # the frame it holds: accepted
+    R.render(ds2, cam, "plain")                                # another scene into the same workspace
+    assert R.workspace(sc.n, 48, 32, "plain").data_ptr() == ws.data_ptr()
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.render_backward(R.ctx, ds, cam, ws, dimg)
+    assert e.value.status == B.RGS_E_INVALID and "scene" in str(e.value)
+    R.render(ds, cam, "plain")
+    with pytest.raises(rgs.RGSError) as e:                     # another camera of the same size
+        rgs.render_backward(R.ctx, ds, cam2, ws, dimg)
+    assert e.value.status == B.RGS_E_INVALID and "camera" in str(e.value)
+    params = [torch.tensor(np.ascontiguousarray(a, np.float32), device="cuda:0")
+              for a in (sc.means, sc.scales, sc.quats, sc.opacity, sc.sh)]
+    rgs.scene_update_plain(R.ctx, ds, *params)                 # same values, but a new scene state
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.render_backward(R.ctx, ds, cam, ws, dimg)
+    assert e.value.status == B.RGS_E_INVALID
+    R.render(ds, cam, "plain")
+    rgs.render_backward(R.ctx, ds, cam, ws, dimg)
+    torch.cuda.synchronize()
+    ds.release()
+    ds2.release()
+
+
+def test_autograd_gradients_survive_interleaved_renders(R):
+    """Between a forward call and its backward: a render of another scene of the
+    same size through the shared renderer, or a forward at another image size
+    with other parameters, leave the gradients bit for bit as they are without
+    them."""
+    import torch
+    from paper_2608_15785_amd.autograd import GaussianRasterizer
+    sc = wl.make_scene(1200, 1.0, -3.0, 0.5, 37)
+    other = wl.make_scene(1200, 1.0, -3.0, 0.5, 38)
+    cam = wl.config_camera("small", width=64, height=64)
+    cam_b = wl.config_camera("small", width=80, height=48)
+    dev = "cuda:0"
+    leaves = [torch.tensor(np.ascontiguousarray(a, np.float32), device=dev, requires_grad=True)
+              for a in (sc.means, sc.scales, sc.quats, sc.opacity, sc.sh)]
+    rast = GaussianRasterizer(R)
+
+    def loss_of(img):
+        return (img - 0.25).abs().mean()
+
+    def grads():
+        g = [p.grad.detach().clone() for p in leaves]
+        for p in leaves:
+            p.grad = None
+        return g
+
+    loss_of(rast(*leaves, cam)).backward()
+    ref = grads()
+    # another scene of the same size rendered through the renderer in between
+    ds_other = R.upload(other, ("plain",))
+    img = rast(*leaves, cam)
+    R.render(ds_other, cam, "plain")
+    loss_of(img).backward()
+    for a, b in zip(grads(), ref):
+        assert torch.equal(a, b)
+    # a forward at another size with other parameters in between
+    img = rast(*leaves, cam)
+    with torch.no_grad():
+        moved = [p.detach() + 0.01 if k == 0 else p.detach() for k, p in enumerate(leaves)]
+    rast(*moved, cam_b)
+    loss_of(img).backward()
+    for a, b in zip(grads(), ref):
+        assert torch.equal(a, b)
+    ds_other.release()
