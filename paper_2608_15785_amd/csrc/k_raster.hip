@@ -55,7 +55,10 @@ constexpr float FEXP_B = 1064970048.0f;
 
 // ---------------------------------------------------------------------------
 
-template <bool COUNT>
+// HW2: alpha = min(0.99, o exp2(p log2 e)) by the hardware exp2 instruction
+// instead of expf (the training variant; its backward pass takes the same
+// bits, see k_backward.hip).
+template <bool COUNT, bool HW2>
 __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
                                                       const uint32_t* __restrict__ vals) {
     __shared__ float4 s_a[256];   // u, v (tile-local), A, B
@@ -94,7 +97,8 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
                 const float4 m = s_b[j];
                 const float dx = x - a.x, dy = y - a.y;
                 const float p = fmaf(-0.5f, fmaf(a.z * dx, dx, m.x * dy * dy), -a.w * dx * dy);
-                const float alpha = fminf(ALPHA_MAX, m.y * expf(p));
+                const float e = HW2 ? __builtin_amdgcn_exp2f(p * LOG2E_PLAIN) : expf(p);
+                const float alpha = fminf(ALPHA_MAX, m.y * e);
                 if (alpha < ALPHA_MIN) continue;
                 const float Tn = T * (1.0f - alpha);
                 if (Tn < T_MIN) {
@@ -127,44 +131,22 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
 }
 
 void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                         bool count) {
+                         bool count, bool hw_exp2) {
     const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
-    if (count)
-        hipLaunchKernelGGL(k_raster_plain<true>, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, ws, vals);
-    else
-        hipLaunchKernelGGL(k_raster_plain<false>, dim3(xcd_grid(f.n_tiles)), dim3(256), 0, s, f, ws, vals);
+    const dim3 grid(xcd_grid(f.n_tiles)), block(256);
+    if (hw_exp2) {
+        if (count) hipLaunchKernelGGL((k_raster_plain<true, true>), grid, block, 0, s, f, ws, vals);
+        else hipLaunchKernelGGL((k_raster_plain<false, true>), grid, block, 0, s, f, ws, vals);
+    } else {
+        if (count) hipLaunchKernelGGL((k_raster_plain<true, false>), grid, block, 0, s, f, ws, vals);
+        else hipLaunchKernelGGL((k_raster_plain<false, false>), grid, block, 0, s, f, ws, vals);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Fast rasterizer.
-//
-// Every wave of a tile's workgroup owns a band of rows and works through the
-// tile's list on its own (no workgroup barrier): it stages 64 entries at a
-// time (one per lane), folds each (Eqs. expand, c0, coeff), culls it against
-// its band, and compacts the survivors in depth order into its own LDS list.
-// The 64 lanes of a wave form four row groups of 16 columns; group j owns PIX
-// consecutive rows starting at y_j and each lane PIX pixels of one column
-// (PIX = 2 is Eq. dual_pixel; 1 is its ablation, 4 extends it along the
-// column).  At staging the folded exponent is reduced further to each row
-// group: with E_j = C2 y_j + C4 and F_j = (C3 y_j + C5) y_j + C6,
-//     P(x, y_j) = C1 x^2 + E_j x + F_j                       (Eq. dot)
-//     P(x, y + 1) = P(x, y) + C2 x + G(y),  G(y) = C3 (2y + 1) + C5
-//                                                            (Eq. dual_pixel)
-// so a lane's first pixel costs two FMAs and each further pixel an FMA and an
-// add; every lane reads its group's (E, F, G) and the shared (C1, C2, colour)
-// with two LDS broadcasts.
-//
-// The blend of a batch runs without the per-pair stop test: a pixel passing
-// the skip test takes alpha, its weight alpha T, the new T and the colour in
-// place, only in the lanes that pass (exec-masked).  Transmittance never
-// grows, so a pixel whose T is still >= 1e-4 at the end of the batch never met
-// the stop condition inside it.  If any pixel of the wave ends the batch below
-// 1e-4, the wave restores the state it saved at the start of the batch and
-// blends the batch again with the stop test at every pair (careful mode): the
-// same operations in the same order, so both modes give the same bits.
-// Counting (debug) renders always take careful mode.
 
-constexpr int FAST_BATCH = 64;               // entries a wave stages at once, one per lane
+constexpr int FAST_THREADS = 128;    // 2 waves: wave w owns tile rows 8w .. 8w+7
+constexpr int FAST_BATCH = FAST_THREADS;
 constexpr int LIST_UNROLL = 4;
 constexpr int LIST_CAP = FAST_BATCH + LIST_UNROLL;
 // Margin added to the alpha-ellipse half-extents before culling a Gaussian for
@@ -176,16 +158,6 @@ constexpr float BOX_MARGIN_ABS = 0.05f;
 // (P = ln o - q / 2): a band is kept when min q <= tau (1 + 1e-3) + 0.02.
 constexpr float Q_MARGIN_REL = 1.0e-3f;
 constexpr float Q_MARGIN_ABS = 0.02f;
-
-template <int PIX>
-struct FastShape {
-    static constexpr int ROWS = 4 * PIX;            // rows of a wave's band
-    static constexpr int WAVES = TILE / ROWS;       // waves per tile
-    static constexpr int THREADS = 64 * WAVES;
-    static constexpr int NG = PIX > 1 ? PIX - 1 : 1;   // row increments G per row group
-    // LDS per list entry: shared float4, per-group float4 (E, F, G_0, b), per-group extra G's
-    static constexpr int EXTRA = PIX > 2 ? 1 : 0;
-};
 
 // Smallest q over the rectangle [-7.5, 7.5] x [y0, y1] (tile-centre
 // coordinates) for a Gaussian at (u, v) with a positive-definite conic: 0 when
@@ -216,6 +188,220 @@ enum ExpMode : int {
 constexpr float LOG2E_F = 1.4426950408889634f;
 constexpr float LOG2_255F = 7.994353436858858f;     // ln 255 * log2 e
 
+template <bool COUNT, int EXPM>
+__global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev ws,
+                                                              const uint32_t* __restrict__ vals) {
+    constexpr bool EXACT = EXPM == EXP_LIBM;
+    // per-wave lists of folded Gaussians, in depth order
+    __shared__ float4 s_a[2][LIST_CAP];   // C1, C2, C3, C4
+    __shared__ float4 s_b[2][LIST_CAP];   // C5, C6, r, g
+    __shared__ float2 s_c[2][LIST_CAP];   // b, list position (as float bits)
+    __shared__ uint32_t s_cnt[2][2];      // [wave of the staging thread][list]
+    const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)f.n_tiles);
+    if (tile >= (uint32_t)f.n_tiles) return;
+    const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / 64, lane = tid % 64;
+    const uint32_t lx = tid % TILE, ly = 2 * (tid / TILE);
+    const uint32_t px = tx * TILE + lx, py = ty * TILE + ly;
+    const bool in0 = px < (uint32_t)f.width && py < (uint32_t)f.height;
+    const bool in1 = px < (uint32_t)f.width && py + 1 < (uint32_t)f.height;
+    const uint32_t start = ws.ranges[2 * tile], end = ws.ranges[2 * tile + 1];
+    // tile-centre coordinates
+    const float ox = (float)(tx * TILE) + 7.5f, oy = (float)(ty * TILE) + 7.5f;
+    const float x = (float)lx - 7.5f, y = (float)ly - 7.5f;
+    const float x2 = x * x, xy = x * y, y2 = y * y, y21 = fmaf(2.0f, y, 1.0f);
+
+    float T0 = 1.0f, r0 = 0.0f, g0 = 0.0f, b0 = 0.0f;
+    float T1 = 1.0f, r1 = 0.0f, g1 = 0.0f, b1 = 0.0f;
+    bool live0 = in0, live1 = in1;
+    uint32_t stop0 = 0xffffffffu, stop1 = 0xffffffffu;
+    uint32_t nbl0 = 0, nbl1 = 0;
+    uint32_t steps = 0;         // counting renders: list entries this wave evaluated
+
+    for (uint32_t base = start; base < end; base += FAST_BATCH) {
+        if (__syncthreads_count(live0 || live1) == 0) break;
+        // ---- stage: fold, cull against both half-tiles, compact per wave ----
+        const uint32_t idx = base + tid;
+        bool hit0 = false, hit1 = false;
+        float4 ca = make_float4(0.f, 0.f, 0.f, 0.f), cbv = make_float4(0.f, 0.f, 0.f, 0.f);
+        float cb = 0.f;
+        if (idx < end) {
+            const uint32_t g = vals[idx];
+            const Record rec = ws.records[g < f.n_gaussians ? g : 0u];
+            const float u = (rec.u_hi - ox) + rec.u_lo;
+            const float v = (rec.v_hi - oy) + rec.v_lo;
+            const float A = rec.A, B = rec.B, C = rec.C;
+            const float C0 = fmaf(A * u, u, fmaf(2.0f * B * u, v, C * v * v));
+            ca = make_float4(-0.5f * A, -B, -0.5f * C, fmaf(A, u, B * v));
+            cbv = make_float4(fmaf(C, v, B * u), fmaf(-0.5f, C0, rec.opa), rec.r, rec.g);
+            cb = rec.b;
+            if (EXPM == EXP_HW2) {       // P log2 e directly: alpha = exp2 of it
+                ca = make_float4(ca.x * LOG2E_F, ca.y * LOG2E_F, ca.z * LOG2E_F, ca.w * LOG2E_F);
+                cbv.x *= LOG2E_F;
+                cbv.y *= LOG2E_F;
+            }
+            // the box |x - u| <= hx, |y - v| <= hy holds every pixel with
+            // P >= -ln 255 (half-extents from the front end, rounded up, then
+            // widened); a half-tile outside it has no pair that passes the skip
+            // test.  Comparisons are phrased so that a NaN keeps the Gaussian.
+            const float hx = fmaf(half_lo(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
+            const float hy = fmaf(half_hi(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
+            const bool x_out = u - hx > 7.5f || u + hx < -7.5f;
+            hit0 = !(x_out || v - hy > -0.5f || v + hy < -7.5f);
+            hit1 = !(x_out || v - hy > 7.5f || v + hy < 0.5f);
+            // then the ellipse itself: the half-tile must hold a point with
+            // q <= tau = 2 (ln 255 + ln o), up to the margin
+            const float qlim = fmaf(2.0f * (LN255F + rec.opa), 1.0f + Q_MARGIN_REL, Q_MARGIN_ABS);
+            // the reciprocals only place the nearest point of an edge, where q is
+            // then evaluated exactly; an error of an ulp moves q by ~C (1e-6 px)^2
+            const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
+            if (hit0) hit0 = !(conic_rect_min(u, v, A, B, C, iA, iC, -7.5f, -0.5f) > qlim);
+            if (hit1) hit1 = !(conic_rect_min(u, v, A, B, C, iA, iC, 0.5f, 7.5f) > qlim);
+        }
+        const uint64_t m0 = __ballot(hit0), m1 = __ballot(hit1);
+        const uint64_t lt = lanemask_lt();
+        if (lane == 0) {
+            s_cnt[wave][0] = (uint32_t)__popcll(m0);
+            s_cnt[wave][1] = (uint32_t)__popcll(m1);
+        }
+        __syncthreads();
+        const uint32_t off0 = wave ? s_cnt[0][0] : 0u, off1 = wave ? s_cnt[0][1] : 0u;
+        const float posf = __uint_as_float(idx);
+        if (hit0) {
+            const uint32_t p = off0 + (uint32_t)__popcll(m0 & lt);
+            s_a[0][p] = ca;
+            s_b[0][p] = cbv;
+            s_c[0][p] = make_float2(cb, posf);
+        }
+        if (hit1) {
+            const uint32_t p = off1 + (uint32_t)__popcll(m1 & lt);
+            s_a[1][p] = ca;
+            s_b[1][p] = cbv;
+            s_c[1][p] = make_float2(cb, posf);
+        }
+        const uint32_t n0 = s_cnt[0][0] + s_cnt[1][0], n1 = s_cnt[0][1] + s_cnt[1][1];
+        // inert padding up to a multiple of the unroll: P = -1e30 is always skipped
+        if (tid < 2 * LIST_UNROLL) {
+            const uint32_t w = tid / LIST_UNROLL, k = tid % LIST_UNROLL;
+            const uint32_t p = (w ? n1 : n0) + k;
+            s_a[w][p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_b[w][p] = make_float4(0.f, -1.0e30f, 0.f, 0.f);
+            s_c[w][p] = make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+
+        // ---- blend this wave's list ----
+        // (the list length is the same for the whole wave: keep it scalar)
+        const uint32_t n = __builtin_amdgcn_readfirstlane(wave ? n1 : n0);
+        const float4* __restrict__ la = s_a[wave];
+        const float4* __restrict__ lb = s_b[wave];
+        const float2* __restrict__ lc = s_c[wave];
+        if (__ballot(live0 || live1) != 0) {
+            bool wave_done = false;     // every pixel of the wave has stopped
+            for (uint32_t k0 = 0; k0 < n && !wave_done; k0 += LIST_UNROLL) {
+                if (COUNT) steps += LIST_UNROLL;
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) {
+                    const float4 a = la[k0 + u];
+                    const float4 m = lb[k0 + u];
+                    const float2 c = lc[k0 + u];
+                    const float P0 = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(m.x, y, m.y)))));
+                    const float P1 = P0 + fmaf(a.y, x, fmaf(a.z, y21, m.x));
+                    constexpr float SKIP = EXPM == EXP_HW2 ? -LOG2_255F : -LN255F;
+                    const bool pass0 = live0 && P0 >= SKIP;
+                    const bool pass1 = live1 && P1 >= SKIP;
+                    float al0, al1;
+                    if (EXACT) {          // the exponential's ablation: alpha = min(0.99, exp(P))
+                        al0 = pass0 ? fminf(ALPHA_MAX, expf(P0)) : 0.0f;
+                        al1 = pass1 ? fminf(ALPHA_MAX, expf(P1)) : 0.0f;
+                    } else if (EXPM == EXP_HW2) {
+                        al0 = pass0 ? fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(P0)) : 0.0f;
+                        al1 = pass1 ? fminf(ALPHA_MAX, __builtin_amdgcn_exp2f(P1)) : 0.0f;
+                    } else {
+                        // alpha = min(0.99, exp_hat(P)) without the minimum, which cannot bind here:
+                        // P = ln o - q/2 with ln o <= 0 and q >= 0, and for a kept pair every term of
+                        // its float32 evaluation is below ~1600 in magnitude (conic entries <= 1/0.3,
+                        // coordinates within a tile), so P < 1e-3 and exp_hat(P) < 0.978
+                        al0 = pass0 ? __int_as_float((int)fmaf(P0, FEXP_A, FEXP_B)) : 0.0f;
+                        al1 = pass1 ? __int_as_float((int)fmaf(P1, FEXP_A, FEXP_B)) : 0.0f;
+                    }
+                    const float w0 = al0 * T0, w1 = al1 * T1;
+                    float Tn0 = T0 - w0, Tn1 = T1 - w1;
+                    float nr0 = fmaf(w0, m.z, r0), ng0 = fmaf(w0, m.w, g0), nb0 = fmaf(w0, c.x, b0);
+                    float nr1 = fmaf(w1, m.z, r1), ng1 = fmaf(w1, m.w, g1), nb1 = fmaf(w1, c.x, b1);
+                    const bool s0 = Tn0 < T_MIN, s1 = Tn1 < T_MIN;
+                    if (COUNT) {
+                        nbl0 += (al0 > 0.0f && !s0) ? 1u : 0u;
+                        nbl1 += (al1 > 0.0f && !s1) ? 1u : 0u;
+                    }
+                    if (__ballot(s0 || s1) != 0) {
+                        // a pixel reached the stop: that pair is not blended
+                        const uint32_t at = __float_as_uint(c.y);
+                        if (s0) {
+                            live0 = false;
+                            stop0 = at;
+                            Tn0 = T0; nr0 = r0; ng0 = g0; nb0 = b0;
+                        }
+                        if (s1) {
+                            live1 = false;
+                            stop1 = at;
+                            Tn1 = T1; nr1 = r1; ng1 = g1; nb1 = b1;
+                        }
+                        wave_done = __ballot(live0 || live1) == 0;
+                    }
+                    T0 = Tn0; r0 = nr0; g0 = ng0; b0 = nb0;
+                    T1 = Tn1; r1 = nr1; g1 = ng1; b1 = nb1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (COUNT && lane == 0 && steps) atomicAdd(reinterpret_cast<unsigned long long*>(&ws.header->list_steps),
+                                               (unsigned long long)steps);
+    const uint64_t plane = (uint64_t)f.width * f.height;
+    float* __restrict__ out = ws.params->out;
+    const float bg0 = ws.params->cam.bg[0], bg1 = ws.params->cam.bg[1], bg2 = ws.params->cam.bg[2];
+    if (in0) {
+        const uint64_t o = (uint64_t)py * f.width + px;
+        out[o] = fmaf(T0, bg0, r0);
+        out[plane + o] = fmaf(T0, bg1, g0);
+        out[2 * plane + o] = fmaf(T0, bg2, b0);
+        if (COUNT) {                // the debug render's per-pixel outputs
+            ws.t_final[o] = T0;
+            ws.n_proc[o] = stop0 != 0xffffffffu ? (stop0 - start + 1) | N_PROC_STOPPED : end - start;
+            ws.n_blend[o] = nbl0;
+        }
+    }
+    if (in1) {
+        const uint64_t o = (uint64_t)(py + 1) * f.width + px;
+        out[o] = fmaf(T1, bg0, r1);
+        out[plane + o] = fmaf(T1, bg1, g1);
+        out[2 * plane + o] = fmaf(T1, bg2, b1);
+        if (COUNT) {                // the debug render's per-pixel outputs
+            ws.t_final[o] = T1;
+            ws.n_proc[o] = stop1 != 0xffffffffu ? (stop1 - start + 1) | N_PROC_STOPPED : end - start;
+            ws.n_blend[o] = nbl1;
+        }
+    }
+}
+
+// One, or four, pixels per lane: the dual-pixel ablation (one pixel per
+// thread, four waves of 16x4 rows) and its extension along the column (four
+// pixels per lane, Eq. dual_pixel applied three times, one wave per tile).  A
+// tile's workgroup has one wave per band of 4 PIX rows: the 64 lanes of a wave
+// form four row groups of 16 columns, group j owning PIX consecutive rows and
+// each lane PIX pixels of one column.  Staging, culling and the per-pair
+// decisions are those of the dual-pixel kernel above, written for any PIX.
+template <int PIX>
+struct FastShape {
+    static constexpr int ROWS = 4 * PIX;            // rows of a wave's band
+    static constexpr int WAVES = TILE / ROWS;       // waves per tile
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int BATCH = THREADS;           // entries staged at once, one per thread
+    static constexpr int CAP = BATCH + LIST_UNROLL;
+};
+
 template <int EXPM>
 __device__ inline float fast_alpha(float P) {
     if (EXPM == EXP_LIBM) return fminf(ALPHA_MAX, expf(P));
@@ -228,57 +414,64 @@ __device__ inline float fast_alpha(float P) {
 }
 
 template <bool COUNT, int EXPM, int PIX>
-__global__ __launch_bounds__(FastShape<PIX>::THREADS) void k_raster_fast(FrameDev f, WsDev ws,
+__global__ __launch_bounds__(FastShape<PIX>::THREADS) void k_raster_fast_px(FrameDev f, WsDev ws,
                                                                          const uint32_t* __restrict__ vals) {
     using S = FastShape<PIX>;
+    constexpr int WAVES = S::WAVES;
+    constexpr int CAP = S::CAP;
     constexpr float SKIP = EXPM == EXP_HW2 ? -LOG2_255F : -LN255F;
     // per-wave lists of folded Gaussians, in depth order
-    __shared__ float4 s_sh[S::WAVES][LIST_CAP];            // C1, C2, r, g
-    __shared__ float4 s_rg[S::WAVES][LIST_CAP][4];         // E_j, F_j, G_j0, b   (row group j)
-    __shared__ float4 s_rx[S::WAVES][S::EXTRA ? LIST_CAP : 1][4];   // G_j1, G_j2 (PIX = 4)
-    __shared__ uint32_t s_pos[S::WAVES][LIST_CAP];         // list position of the entry
+    __shared__ float4 s_a[WAVES][CAP];               // C1, C2, C3, C4
+    __shared__ float4 s_b[WAVES][CAP];               // C5, C6, r, g
+    __shared__ float2 s_c[WAVES][CAP];               // b, list position (as float bits)
+    __shared__ uint32_t s_cnt[WAVES][WAVES];         // [wave of the staging thread][list]
     const uint32_t tile = xcd_tile(blockIdx.x, (uint32_t)f.n_tiles);
     if (tile >= (uint32_t)f.n_tiles) return;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
     const uint32_t tid = threadIdx.x;
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
-    const uint32_t grp = lane / 16;
-    const uint32_t lx = lane % 16, ly = wave * S::ROWS + grp * PIX;
+    const uint32_t wave = tid / 64, lane = tid % 64;
+    const uint32_t lx = tid % TILE, ly = PIX * (tid / TILE);
     const uint32_t px = tx * TILE + lx, py = ty * TILE + ly;
     const uint32_t start = ws.ranges[2 * tile], end = ws.ranges[2 * tile + 1];
     // tile-centre coordinates
     const float ox = (float)(tx * TILE) + 7.5f, oy = (float)(ty * TILE) + 7.5f;
-    const float x = (float)lx - 7.5f, x2 = x * x;
-    const float band_lo = (float)(wave * S::ROWS) - 7.5f, band_hi = band_lo + (float)(S::ROWS - 1);
+    const float x = (float)lx - 7.5f, y = (float)ly - 7.5f;
+    const float x2 = x * x, xy = x * y, y2 = y * y;
+    // the row factor 2 (y + k) + 1 of Eq. dual_pixel's step from row y + k to y + k + 1
+    float yk[PIX > 1 ? PIX - 1 : 1];
+#pragma unroll
+    for (int k = 0; k + 1 < PIX; ++k) yk[k] = fmaf(2.0f, y + (float)k, 1.0f);
 
     float T[PIX], cr[PIX], cg[PIX], cb[PIX];
-    bool live[PIX];
     uint32_t stop[PIX], nbl[PIX];
+    // Whether pixel i is still blending.  Held in four scalars rather than an
+    // array, so that each stays a lane mask in scalar registers (an array of
+    // bools is kept as bytes in vector registers, two more VALU per pixel).
+    bool live0 = px < (uint32_t)f.width && py < (uint32_t)f.height;
+    bool live1 = PIX > 1 && px < (uint32_t)f.width && py + 1 < (uint32_t)f.height;
+    bool live2 = PIX > 2 && px < (uint32_t)f.width && py + 2 < (uint32_t)f.height;
+    bool live3 = PIX > 3 && px < (uint32_t)f.width && py + 3 < (uint32_t)f.height;
+    auto live = [&](int i) -> bool& { return i == 0 ? live0 : i == 1 ? live1 : i == 2 ? live2 : live3; };
 #pragma unroll
     for (int i = 0; i < PIX; ++i) {
         T[i] = 1.0f;
         cr[i] = cg[i] = cb[i] = 0.0f;
-        live[i] = px < (uint32_t)f.width && py + i < (uint32_t)f.height;
         stop[i] = 0xffffffffu;
         nbl[i] = 0;
     }
+    uint32_t steps = 0;         // counting renders: list entries this wave evaluated
     const uint64_t lt = lanemask_lt();
-    // LDS addresses through the per-lane wave index: the list reads of the
-    // blend then take their address from a VGPR that advances once per
-    // unrolled step, not from a scalar copied into a VGPR at every read
-    const uint32_t wave_v = tid / 64;
-    float4* lsh = s_sh[wave_v];
-    uint32_t* lpos = s_pos[wave_v];
 
-    for (uint32_t base = start; base < end; base += FAST_BATCH) {
-        bool any = false;
+    for (uint32_t base = start; base < end; base += S::BATCH) {
+        const bool any = live0 || live1 || live2 || live3;
+        if (__syncthreads_count(any) == 0) break;
+        // ---- stage: fold, cull against every wave's band, compact per wave ----
+        const uint32_t idx = base + tid;
+        bool hit[WAVES];
 #pragma unroll
-        for (int i = 0; i < PIX; ++i) any |= live[i];
-        if (__ballot(any) == 0) break;
-        // ---- stage: fold, cull against this wave's band, compact ----
-        const uint32_t idx = base + lane;
-        bool hit = false;
-        float C1 = 0.f, C2 = 0.f, C3 = 0.f, C4 = 0.f, C5 = 0.f, C6 = 0.f, rr = 0.f, rg = 0.f, rb = 0.f;
+        for (int w = 0; w < WAVES; ++w) hit[w] = false;
+        float4 ca = make_float4(0.f, 0.f, 0.f, 0.f), cbv = make_float4(0.f, 0.f, 0.f, 0.f);
+        float cbb = 0.f;
         if (idx < end) {
             const uint32_t g = vals[idx];
             const Record rec = ws.records[g < f.n_gaussians ? g : 0u];
@@ -286,23 +479,14 @@ __global__ __launch_bounds__(FastShape<PIX>::THREADS) void k_raster_fast(FrameDe
             const float v = (rec.v_hi - oy) + rec.v_lo;
             const float A = rec.A, B = rec.B, C = rec.C;
             const float C0 = fmaf(A * u, u, fmaf(2.0f * B * u, v, C * v * v));
-            C1 = -0.5f * A;
-            C2 = -B;
-            C3 = -0.5f * C;
-            C4 = fmaf(A, u, B * v);
-            C5 = fmaf(C, v, B * u);
-            C6 = fmaf(-0.5f, C0, rec.opa);
+            ca = make_float4(-0.5f * A, -B, -0.5f * C, fmaf(A, u, B * v));
+            cbv = make_float4(fmaf(C, v, B * u), fmaf(-0.5f, C0, rec.opa), rec.r, rec.g);
+            cbb = rec.b;
             if (EXPM == EXP_HW2) {       // P log2 e directly: alpha = exp2 of it
-                C1 *= LOG2E_F;
-                C2 *= LOG2E_F;
-                C3 *= LOG2E_F;
-                C4 *= LOG2E_F;
-                C5 *= LOG2E_F;
-                C6 *= LOG2E_F;
+                ca = make_float4(ca.x * LOG2E_F, ca.y * LOG2E_F, ca.z * LOG2E_F, ca.w * LOG2E_F);
+                cbv.x *= LOG2E_F;
+                cbv.y *= LOG2E_F;
             }
-            rr = rec.r;
-            rg = rec.g;
-            rb = rec.b;
             // the box |x - u| <= hx, |y - v| <= hy holds every pixel with
             // P >= -ln 255 (half-extents from the front end, rounded up, then
             // widened); a band outside it has no pair that passes the skip
@@ -311,144 +495,119 @@ __global__ __launch_bounds__(FastShape<PIX>::THREADS) void k_raster_fast(FrameDe
             // phrased so that a NaN keeps the Gaussian.
             const float hx = fmaf(half_lo(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
             const float hy = fmaf(half_hi(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
-            hit = !(u - hx > 7.5f || u + hx < -7.5f || v - hy > band_hi || v + hy < band_lo);
-            if (hit) {
-                const float qlim = fmaf(2.0f * (LN255F + rec.opa), 1.0f + Q_MARGIN_REL, Q_MARGIN_ABS);
-                // the reciprocals only place the nearest point of an edge, where q is
-                // then evaluated exactly; an error of an ulp moves q by ~C (1e-6 px)^2
-                const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
-                hit = !(conic_rect_min(u, v, A, B, C, iA, iC, band_lo, band_hi) > qlim);
+            const bool x_out = u - hx > 7.5f || u + hx < -7.5f;
+            const float qlim = fmaf(2.0f * (LN255F + rec.opa), 1.0f + Q_MARGIN_REL, Q_MARGIN_ABS);
+            // the reciprocals only place the nearest point of an edge, where q is
+            // then evaluated exactly; an error of an ulp moves q by ~C (1e-6 px)^2
+            const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) {
+                const float y0 = (float)(w * S::ROWS) - 7.5f, y1 = y0 + (float)(S::ROWS - 1);
+                hit[w] = !(x_out || v - hy > y1 || v + hy < y0);
+                if (hit[w]) hit[w] = !(conic_rect_min(u, v, A, B, C, iA, iC, y0, y1) > qlim);
             }
         }
-        const uint64_t m = __ballot(hit);
-        const uint32_t n = (uint32_t)__popcll(m);
-        if (hit) {
-            const uint32_t p = (uint32_t)__popcll(m & lt);
-            lsh[p] = make_float4(C1, C2, rr, rg);
+        uint64_t mk[WAVES];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const float y = band_lo + (float)(j * PIX);
-                const float E = fmaf(C2, y, C4);
-                const float F = fmaf(fmaf(C3, y, C5), y, C6);
-                const float G0 = fmaf(C3, fmaf(2.0f, y, 1.0f), C5);
-                s_rg[wave_v][p][j] = make_float4(E, F, G0, rb);
-                if (S::EXTRA) {
-                    const float G1 = fmaf(C3, fmaf(2.0f, y + 1.0f, 1.0f), C5);
-                    const float G2 = fmaf(C3, fmaf(2.0f, y + 2.0f, 1.0f), C5);
-                    s_rx[wave_v][S::EXTRA ? p : 0][j] = make_float4(G1, G2, 0.f, 0.f);
-                }
+        for (int w = 0; w < WAVES; ++w) mk[w] = __ballot(hit[w]);
+        if (lane == 0) {
+#pragma unroll
+            for (int w = 0; w < WAVES; ++w) s_cnt[wave][w] = (uint32_t)__popcll(mk[w]);
+        }
+        __syncthreads();
+        const float posf = __uint_as_float(idx);
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            if (hit[w]) {
+                uint32_t p = (uint32_t)__popcll(mk[w] & lt);
+                for (uint32_t sw = 0; sw < wave; ++sw) p += s_cnt[sw][w];
+                s_a[w][p] = ca;
+                s_b[w][p] = cbv;
+                s_c[w][p] = make_float2(cbb, posf);
             }
-            lpos[p] = idx;
+        }
+        uint32_t nl[WAVES];
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) {
+            nl[w] = 0;
+#pragma unroll
+            for (int sw = 0; sw < WAVES; ++sw) nl[w] += s_cnt[sw][w];
         }
         // inert padding up to a multiple of the unroll: P = -1e30 is always skipped
-        if (lane < LIST_UNROLL) {
-            const uint32_t p = n + lane;
-            lsh[p] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                s_rg[wave_v][p][j] = make_float4(0.f, -1.0e30f, 0.f, 0.f);
-                if (S::EXTRA) s_rx[wave_v][S::EXTRA ? p : 0][j] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-            lpos[p] = 0;
+        if (tid < WAVES * LIST_UNROLL) {
+            const uint32_t w = tid / LIST_UNROLL, k = tid % LIST_UNROLL;
+            const uint32_t p = nl[w] + k;
+            s_a[w][p] = make_float4(0.f, 0.f, 0.f, 0.f);
+            s_b[w][p] = make_float4(0.f, -1.0e30f, 0.f, 0.f);
+            s_c[w][p] = make_float2(0.f, 0.f);
         }
-        // the list is read by other lanes of this wave: the wave's LDS
-        // accesses complete in program order, so a compiler barrier suffices
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        __syncthreads();
 
-        const float4* lrg = &s_rg[wave_v][0][grp];
-        const float4* lrx = &s_rx[wave_v][0][grp];
-        // the exponents of this lane's pixels for list entry k
-        auto exponents = [&](uint32_t k, float (&P)[PIX], float4& sh, float4& q) {
-            sh = lsh[k];
-            q = lrg[4 * k];
-            P[0] = fmaf(sh.x, x2, fmaf(q.x, x, q.y));
-            if (PIX > 1) P[1] = P[0] + fmaf(sh.y, x, q.z);
-            if (PIX > 2) {
-                const float4 q2 = lrx[S::EXTRA ? 4 * k : 0];
-                P[2] = P[1] + fmaf(sh.y, x, q2.x);
-                P[3] = P[2] + fmaf(sh.y, x, q2.y);
-            }
-        };
-        bool careful = COUNT;
-        float Ts[PIX], rs[PIX], gs[PIX], bs[PIX];
-        if (!COUNT) {
-#pragma unroll
-            for (int i = 0; i < PIX; ++i) {
-                Ts[i] = T[i];
-                rs[i] = cr[i];
-                gs[i] = cg[i];
-                bs[i] = cb[i];
-            }
-            for (uint32_t k0 = 0; k0 < n; k0 += LIST_UNROLL) {
+        // ---- blend this wave's list ----
+        // (the list length is the same for the whole wave: keep it scalar)
+        const uint32_t n = __builtin_amdgcn_readfirstlane(nl[wave]);
+        const float4* la = s_a[wave];
+        const float4* lb = s_b[wave];
+        const float2* lc = s_c[wave];
+        if (__ballot(any) != 0) {
+            bool wave_done = false;     // every pixel of the wave has stopped
+            for (uint32_t k0 = 0; k0 < n && !wave_done; k0 += LIST_UNROLL) {
+                if (COUNT) steps += LIST_UNROLL;
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) {
+                    const float4 a = la[k0 + u];
+                    const float4 m = lb[k0 + u];
+                    const float2 c = lc[k0 + u];
                     float P[PIX];
-                    float4 sh, q;
-                    exponents(k0 + u, P, sh, q);
+                    P[0] = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(m.x, y, m.y)))));
+#pragma unroll
+                    for (int i = 1; i < PIX; ++i) P[i] = P[i - 1] + fmaf(a.y, x, fmaf(a.z, yk[i - 1], m.x));
+                    float Tn[PIX], nr[PIX], ng[PIX], nb[PIX];
+                    bool st[PIX];
+                    bool any_stop = false;
 #pragma unroll
                     for (int i = 0; i < PIX; ++i) {
-                        if (live[i] && P[i] >= SKIP) {
-                            const float w = fast_alpha<EXPM>(P[i]) * T[i];
-                            T[i] = T[i] - w;
-                            cr[i] = fmaf(w, sh.z, cr[i]);
-                            cg[i] = fmaf(w, sh.w, cg[i]);
-                            cb[i] = fmaf(w, q.w, cb[i]);
-                        }
+                        // a skipped or finished pixel takes alpha = 0
+                        const float al = (live(i) && P[i] >= SKIP) ? fast_alpha<EXPM>(P[i]) : 0.0f;
+                        const float w = al * T[i];
+                        Tn[i] = T[i] - w;
+                        nr[i] = fmaf(w, m.z, cr[i]);
+                        ng[i] = fmaf(w, m.w, cg[i]);
+                        nb[i] = fmaf(w, c.x, cb[i]);
+                        st[i] = Tn[i] < T_MIN;
+                        any_stop |= st[i];
+                        if (COUNT) nbl[i] += (al > 0.0f && !st[i]) ? 1u : 0u;
                     }
-                }
-            }
-            bool below = false;
+                    if (__ballot(any_stop) != 0) {
+                        // a pixel reached the stop: that pair is not blended
+                        const uint32_t at = __float_as_uint(c.y);
 #pragma unroll
-            for (int i = 0; i < PIX; ++i) below |= T[i] < T_MIN;
-            careful = __ballot(below) != 0;
-            if (careful) {
-                // a pixel met the stop condition in this batch: start it again
-#pragma unroll
-                for (int i = 0; i < PIX; ++i) {
-                    T[i] = Ts[i];
-                    cr[i] = rs[i];
-                    cg[i] = gs[i];
-                    cb[i] = bs[i];
-                }
-            }
-        }
-        if (careful) {
-            for (uint32_t k0 = 0; k0 < n; k0 += LIST_UNROLL) {
-#pragma unroll
-                for (int u = 0; u < LIST_UNROLL; ++u) {
-                    float P[PIX];
-                    float4 sh, q;
-                    exponents(k0 + u, P, sh, q);
-#pragma unroll
-                    for (int i = 0; i < PIX; ++i) {
-                        if (live[i] && P[i] >= SKIP) {
-                            const float w = fast_alpha<EXPM>(P[i]) * T[i];
-                            const float Tn = T[i] - w;
-                            if (Tn < T_MIN) {
-                                // the pixel stops here: this pair is not blended
-                                live[i] = false;
-                                stop[i] = lpos[k0 + u];
-                            } else {
-                                T[i] = Tn;
-                                cr[i] = fmaf(w, sh.z, cr[i]);
-                                cg[i] = fmaf(w, sh.w, cg[i]);
-                                cb[i] = fmaf(w, q.w, cb[i]);
-                                if (COUNT) ++nbl[i];
+                        for (int i = 0; i < PIX; ++i) {
+                            if (st[i]) {
+                                live(i) = false;
+                                stop[i] = at;
+                                Tn[i] = T[i];
+                                nr[i] = cr[i];
+                                ng[i] = cg[i];
+                                nb[i] = cb[i];
                             }
                         }
+                        wave_done = __ballot(live0 || live1 || live2 || live3) == 0;
+                    }
+#pragma unroll
+                    for (int i = 0; i < PIX; ++i) {
+                        T[i] = Tn[i];
+                        cr[i] = nr[i];
+                        cg[i] = ng[i];
+                        cb[i] = nb[i];
                     }
                 }
-                bool any2 = false;
-#pragma unroll
-                for (int i = 0; i < PIX; ++i) any2 |= live[i];
-                if (__ballot(any2) == 0) break;
             }
         }
-        // the next batch overwrites the list: this wave's reads come first
-        __builtin_amdgcn_wave_barrier();
+        __syncthreads();
     }
+    if (COUNT && lane == 0 && steps) atomicAdd(reinterpret_cast<unsigned long long*>(&ws.header->list_steps),
+                                               (unsigned long long)steps);
     const uint64_t plane = (uint64_t)f.width * f.height;
     float* __restrict__ out = ws.params->out;
     const float bg0 = ws.params->cam.bg[0], bg1 = ws.params->cam.bg[1], bg2 = ws.params->cam.bg[2];
@@ -468,32 +627,35 @@ __global__ __launch_bounds__(FastShape<PIX>::THREADS) void k_raster_fast(FrameDe
     }
 }
 
+template <int EXPM>
+static void launch_fast_dual(hipStream_t s, const FrameDev& f, const WsDev& ws, const uint32_t* vals, bool count) {
+    if (count)
+        hipLaunchKernelGGL((k_raster_fast<true, EXPM>), dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
+                           vals);
+    else
+        hipLaunchKernelGGL((k_raster_fast<false, EXPM>), dim3(xcd_grid(f.n_tiles)), dim3(FAST_THREADS), 0, s, f, ws,
+                           vals);
+}
+
 template <int EXPM, int PIX>
-static void launch_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, const uint32_t* vals, bool count) {
+static void launch_fast_px(hipStream_t s, const FrameDev& f, const WsDev& ws, const uint32_t* vals, bool count) {
     const dim3 grid(xcd_grid(f.n_tiles)), block(FastShape<PIX>::THREADS);
     if (count)
-        hipLaunchKernelGGL((k_raster_fast<true, EXPM, PIX>), grid, block, 0, s, f, ws, vals);
+        hipLaunchKernelGGL((k_raster_fast_px<true, EXPM, PIX>), grid, block, 0, s, f, ws, vals);
     else
-        hipLaunchKernelGGL((k_raster_fast<false, EXPM, PIX>), grid, block, 0, s, f, ws, vals);
+        hipLaunchKernelGGL((k_raster_fast_px<false, EXPM, PIX>), grid, block, 0, s, f, ws, vals);
 }
 
 void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count,
                         uint32_t opts) {
     const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
     const bool exact = (opts & OPT_FASTEXP) != 0, single = (opts & OPT_DUALPIXEL) != 0;
-    if (opts & OPT_QUAD) {                       // not with the two above or the hardware exp2
-        launch_fast<EXP_BITS, 4>(s, f, ws, vals, count);
-    } else if (opts & OPT_HW_EXP2) {             // not with the two above
-        launch_fast<EXP_HW2, 2>(s, f, ws, vals, count);
-    } else if (!exact && !single) {
-        launch_fast<EXP_BITS, 2>(s, f, ws, vals, count);
-    } else if (exact && !single) {
-        launch_fast<EXP_LIBM, 2>(s, f, ws, vals, count);
-    } else if (!exact && single) {
-        launch_fast<EXP_BITS, 1>(s, f, ws, vals, count);
-    } else {
-        launch_fast<EXP_LIBM, 1>(s, f, ws, vals, count);
-    }
+    if (opts & OPT_QUAD) launch_fast_px<EXP_BITS, 4>(s, f, ws, vals, count);        // not with the two below
+    else if (opts & OPT_HW_EXP2) launch_fast_dual<EXP_HW2>(s, f, ws, vals, count);  // not with the two below
+    else if (!exact && !single) launch_fast_dual<EXP_BITS>(s, f, ws, vals, count);
+    else if (exact && !single) launch_fast_dual<EXP_LIBM>(s, f, ws, vals, count);
+    else if (!exact && single) launch_fast_px<EXP_BITS, 1>(s, f, ws, vals, count);
+    else launch_fast_px<EXP_LIBM, 1>(s, f, ws, vals, count);
 }
 
 }  // namespace rgs

@@ -1,13 +1,11 @@
-"""The fast rasterizer's two blend modes and its pixels-per-lane variants,
-through the C ABI (needs an MI355X).
+"""The fast rasterizer's production and counting renders, and its
+pixels-per-lane variants, through the C ABI (needs an MI355X).
 
-A production render blends each batch without the per-pair stop test and
-redoes a batch with it only when some pixel ended the batch below the stop
-threshold; a counting (debug) render always tests every pair.  Both take the
-same operations in the same order, so their images must agree bit for bit,
-in scenes where no pixel stops and in scenes where many do.  The four-pixel
-variant (Eq. dual_pixel applied along the column) is checked against the
-oracle like the fast path."""
+A production render and a counting (debug) render take the same operations in
+the same order (the counting render only adds per-pixel counters), so their
+images must agree bit for bit, in scenes where no pixel stops and in scenes
+where many do.  The four-pixel variant (Eq. dual_pixel applied along the
+column, one wave per tile) is checked against the oracle like the fast path."""
 from __future__ import annotations
 
 import sys
