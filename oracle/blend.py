@@ -30,6 +30,19 @@ bookkeeping run beside it, and neither changes the primary result:
   tracking of that pixel ends);
 * when the definitions stop a pixel at different pairs, the larger T at the
   first difference times c_max is recorded as ``mode_slack``.
+
+The margins may also scale with each pair.  A float32 evaluation of the
+exponent rounds every term it adds, so its error is bounded by a multiple of
+the sum of the terms' magnitudes, not of the result.  With ``margins`` =
+(delta_alpha_rel, delta_P_abs, kappa, t_round), each pair's margins on P and on
+the relative alpha grow by kappa M, where M bounds the magnitudes of the terms
+of its exponent in the frame the fast rasterizer folds them in (coordinates
+relative to the centre of the pixel's 16x16 tile, Sec. IV-B):
+    M = 1/2 (|A| (|x| + |u|)^2 + 2 |B| (|x| + |u|) (|y| + |v|) + |C| (|y| + |v|)^2) + |ln o|
+(for the plain mode, with the pixel-to-mean offsets of Eq. power:
+M = 1/2 (|A| dx^2 + 2 |B| |dx dy| + |C| dy^2)), and every blended pair widens
+the transmittance interval by the relative rounding t_round of one float32
+update.
 c_max is the largest colour component of any pair at the pixel that passes,
 or may pass, the skip test.
 """
@@ -81,7 +94,8 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
     """Blend the sorted Gaussians ``gauss_ids`` at pixel positions X, Y (float arrays).
 
     ``opa`` holds opacity o for the plain mode and ln o for the fast modes.
-    ``margins`` = (delta_alpha_rel, delta_P_abs) turns on decision tracking.
+    ``margins`` = (delta_alpha_rel, delta_P_abs[, kappa, t_round]) turns on
+    decision tracking.
     """
     X = np.asarray(X, np.float64)
     Y = np.asarray(Y, np.float64)
@@ -100,7 +114,13 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
     T_hi = np.ones(n)
     mode_slack_T = np.zeros(n)
     modes_agree = np.ones(n, bool)
-    d_alpha, d_P = margins if margins is not None else (0.0, 0.0)
+    mg = tuple(margins) if margins is not None else (0.0, 0.0)
+    d_alpha0, d_P0 = mg[0], mg[1]
+    kappa = mg[2] if len(mg) > 2 else 0.0
+    t_round = mg[3] if len(mg) > 3 else 0.0
+    # pixel coordinates relative to the centre of their 16x16 tile
+    tcx = np.floor(X / 16.0) * 16.0 + 7.5
+    tcy = np.floor(Y / 16.0) * 16.0 + 7.5
 
     for g in gauss_ids:
         if all(dm.all() for dm in done):
@@ -109,6 +129,17 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
         dy = Y - v[g]
         A, B, Cc = conic[g]
         p = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+        if kappa > 0.0:
+            if modes[0] == "plain":
+                M = 0.5 * (abs(A) * dx * dx + 2.0 * abs(B) * np.abs(dx * dy) + abs(Cc) * dy * dy)
+            else:
+                ax = np.abs(X - tcx) + np.abs(u[g] - tcx)
+                ay = np.abs(Y - tcy) + np.abs(v[g] - tcy)
+                M = 0.5 * (abs(A) * ax * ax + 2.0 * abs(B) * ax * ay + abs(Cc) * ay * ay) + abs(opa[g])
+            d_alpha = d_alpha0 + kappa * M
+            d_P = d_P0 + kappa * M
+        else:
+            d_alpha, d_P = d_alpha0, d_P0
         col = color[g]
         T_before = [t.copy() for t in T]
         any_active = ~np.logical_and.reduce(done)
@@ -140,8 +171,8 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
                     amb = live & amb_skip
                     slack_units += np.where(amb, a_hi * T_hi, 0.0)
                     flagged |= amb
-                    new_lo = np.where(passes | amb, T_lo * (1.0 - a_hi), T_lo)
-                    new_hi = np.where(passes, T_hi * (1.0 - a_lo), T_hi)
+                    new_lo = np.where(passes | amb, T_lo * (1.0 - a_hi) * (1.0 - t_round), T_lo)
+                    new_hi = np.where(passes, T_hi * (1.0 - a_lo) * (1.0 + t_round), T_hi)
                     amb_stop = (passes | amb) & (new_lo < T_MIN) & (new_hi >= T_MIN)
                     slack_units += np.where(amb_stop, T_hi, 0.0)
                     flagged |= amb_stop

@@ -6,11 +6,24 @@ Bars (see the oracle's blend module for the decision bookkeeping):
 * duplicated entries in emission order, sorted keys and indices, tile ranges:
   bit-exact;
 * plain image: |gpu - oracle| <= 2e-3 + slack at every pixel;
-* fast image: |gpu - oracle(bit-level exp)| <= 2e-3 + slack, and
-  |gpu - oracle(exact exp)| <= eps/(1-eps) c_max (1 - T_final) + 1e-3 + slack
-  (the per-pixel bound of the bit-level exponential, Sec. IV-B), where slack is
-  the colour at stake in skip/stop decisions that lie within the float32
-  margin of their thresholds, or that the two exponentials decide differently.
+* fast image: |gpu - oracle(bit-level exp)| <= 1e-4 at every pixel whose
+  decisions all lie outside the float32 margins, <= 2e-3 + slack at the
+  flagged ones, and |gpu - oracle(exact exp)| <= eps/(1-eps) c_max
+  (1 - T_final) + 1e-3 + slack (the per-pixel bound of the bit-level
+  exponential, Sec. IV-B), where slack is the colour at stake in skip/stop
+  decisions that lie within the float32 margin of their thresholds, or that
+  the two exponentials decide differently.  The flagged share of the pixels is
+  capped.
+
+Fast-path margins.  A float32 evaluation of the folded exponent (Eqs. expand,
+coeff, dot, dual_pixel in tile-centre coordinates) rounds each term it adds,
+so its error is bounded by a multiple of M, the sum of the terms' magnitudes
+(see the oracle's blend module).  A float32 replica of that arithmetic over 2M
+random conics, means and pixels stays within 3.5e-7 M; the margin on P and on
+the relative alpha is 4e-6 M per pair (about 12 times that), plus 1e-5 on
+alpha for the bit-level exponential's float32 rounding (its integer is a
+multiple of 64 at these magnitudes, 5.3e-6 relative), and every blended pair
+widens the transmittance interval by one float32 rounding.
 """
 from __future__ import annotations
 
@@ -25,16 +38,34 @@ FASTEXP = importlib.import_module("oracle.fastexp")
 
 PLAIN_TOL = 2e-3
 FAST_TOL = 1e-3
+FAST_UNFLAGGED_TOL = 1e-4        # fast image vs the bit-level-exp oracle where no decision is flagged
+# most pixels whose fast-path decisions may be flagged: 1.5 % of a comparison of
+# at least 4096 pixels (measured 0.2 - 1.1 % on every such case), 5 % below that
+FAST_FLAG_CAP = (0.015, 0.05)
 PLAIN_MARGINS = (1e-4, 0.0)      # relative alpha uncertainty of float32 + expf
-FAST_MARGINS = (2e-3, 2e-3)      # relative alpha, absolute P uncertainty of float32 folding
+# relative alpha, absolute P, per-pair scale of the terms' magnitudes, float32 rounding of T
+FAST_MARGINS = (1e-5, 1e-6, 4e-6, 2.0 ** -22)
+
+_PREPARED = {}
+
+
+def _prepared(scene, kind):
+    """Oracle arrays of a scene ("plain" or "fast"), kept for the scene object."""
+    key = (id(scene), kind)
+    hit = _PREPARED.get(key)
+    if hit is None or hit[0] is not scene:
+        arr = oracle.prepare_plain(scene) if kind == "plain" else oracle.prepare_fast(oracle.quantize_scene(scene))
+        if len(_PREPARED) > 8:
+            _PREPARED.clear()
+        _PREPARED[key] = hit = (scene, arr)
+    return hit[1]
 
 
 def oracle_frame(scene, cam, path, tiles=None, workers=8):
     if path == "plain":
-        arr = oracle.prepare_plain(scene)
-        return oracle.render(arr, cam, "plain", tiles=tiles, margins=PLAIN_MARGINS, workers=workers)
-    arr = oracle.prepare_fast(oracle.quantize_scene(scene))
-    return oracle.render(arr, cam, "fast", modes=("fast-def", "fast-exact"), tiles=tiles,
+        return oracle.render(_prepared(scene, "plain"), cam, "plain", tiles=tiles, margins=PLAIN_MARGINS,
+                             workers=workers)
+    return oracle.render(_prepared(scene, "fast"), cam, "fast", modes=("fast-def", "fast-exact"), tiles=tiles,
                          margins=FAST_MARGINS, workers=workers)
 
 
@@ -107,20 +138,30 @@ def compare_image(img, fr, path):
         err = np.abs(gpu - ref)
         bad = err > PLAIN_TOL + slack
         assert not bad.any(), f"fast, exact exp: {int(bad.sum())} over, worst {float((err - PLAIN_TOL - slack).max())}"
-        rep.update(max_err=float(err.max()), psnr=psnr(gpu, ref))
+        unflagged = ~fr.flagged[mask]
+        err_unflagged = float(err[:, unflagged].max()) if unflagged.any() else 0.0
+        assert err_unflagged <= FAST_UNFLAGGED_TOL, f"fast, exact exp, at unflagged pixels: {err_unflagged}"
+        rep.update(max_err=float(err.max()), max_err_unflagged=err_unflagged, psnr=psnr(gpu, ref))
         return rep
     ref_def = fr.images["fast-def"][:, mask]
     ref_exact = fr.images["fast-exact"][:, mask]
     err_def = np.abs(gpu - ref_def)
     bad = err_def > PLAIN_TOL + slack
     assert not bad.any(), f"fast vs bit-level-exp oracle: {int(bad.sum())} over, worst {float((err_def - PLAIN_TOL - slack).max())}"
+    unflagged = ~fr.flagged[mask]
+    share = 1.0 - float(unflagged.mean()) if unflagged.size else 0.0
+    err_unflagged = float(err_def[:, unflagged].max()) if unflagged.any() else 0.0
+    assert err_unflagged <= FAST_UNFLAGGED_TOL, f"fast vs bit-level-exp oracle at unflagged pixels: {err_unflagged}"
+    cap = FAST_FLAG_CAP[0] if unflagged.size >= 4096 else FAST_FLAG_CAP[1]
+    assert share <= cap, f"{share:.2%} of the pixels flagged"
     eps = FASTEXP.eps_star()
     bound = eps / (1 - eps) * fr.c_max[mask] * (1 - fr.T_final[mask])
     allowed = bound[None] + FAST_TOL + slack + fr.mode_slack[mask][None]
     err_ex = np.abs(gpu - ref_exact)
     bad = err_ex > allowed
     assert not bad.any(), f"fast vs exact oracle: {int(bad.sum())} over the bound, worst {float((err_ex - allowed).max())}"
-    rep.update(max_err_vs_def=float(err_def.max()), max_err_vs_exact=float(err_ex.max()),
+    rep.update(max_err_vs_def=float(err_def.max()), max_err_vs_def_unflagged=err_unflagged,
+               flagged_share=round(share, 5), max_err_vs_exact=float(err_ex.max()),
                psnr_vs_def=psnr(gpu, ref_def), psnr_vs_exact=psnr(gpu, ref_exact),
                max_bound=float(bound.max()), mode_flagged=int((fr.mode_slack[mask] > 0).sum()))
     return rep

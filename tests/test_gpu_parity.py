@@ -155,13 +155,26 @@ def test_1080p_keys_and_sampled_tiles(R, path):
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
-@pytest.mark.parametrize("pose", [0, 21])
+@pytest.mark.parametrize("pose", [0, 8, 16, 21, 32, 40, 48, 56])
 def test_4k_keys_and_sampled_tiles(R, path, pose):
-    """3M Gaussians at 3840x2160 on orbit poses: every key bit-exact, 48 sampled tiles."""
+    """3M Gaussians at 3840x2160 on eight orbit poses: every key bit-exact, 24 sampled tiles each."""
     sc = _4k_scene()
     cam = wl.config_camera("4k", pose=pose)
     plan = oracle.frame_plan(cam.width, cam.height)
-    tiles = np.random.default_rng(pose).choice(plan.n_tiles, 48, replace=False)
+    tiles = np.random.default_rng(pose).choice(plan.n_tiles, 24, replace=False)
+    run_parity(R, sc, cam, path, tiles=tiles)
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
+@pytest.mark.parametrize("pose", [0, 37])
+def test_720p_keys_and_sampled_tiles(R, path, pose):
+    """The serving mix's 1280x720 class (half of its requests): the 1M scene on its serving
+    orbit, every key bit-exact, 48 sampled tiles and the ragged last tile."""
+    sc = wl.config_scene("1080p")
+    cam = wl.serving_camera(0, pose, 1280, 720)
+    plan = oracle.frame_plan(cam.width, cam.height)
+    tiles = np.concatenate([np.random.default_rng(72 + pose).choice(plan.n_tiles, 48, replace=False),
+                            [plan.n_tiles - 1]])
     run_parity(R, sc, cam, path, tiles=tiles)
 
 

@@ -85,3 +85,49 @@ def test_fast_skip_margin_on_P():
     u, v, c, o, col = seq(np.exp(P), [0.3, 2.0], lno=True)
     r = oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, modes=("fast-def",), margins=(2e-3, 2e-3))
     assert r.flagged[0] and r.slack[0] > 0
+
+
+def test_per_pair_margin_scales_with_the_terms():
+    """With (d_alpha, d_P, kappa, t_round), a pair's margin on P is d_P + kappa M, M the
+    magnitude sum of its exponent's terms in tile-centre coordinates.  The pixel at (0, 0)
+    sits at (-7.5, -7.5) from its tile's centre; a Gaussian on it with conic I has
+    M = (15^2 + 15^2) / 2 + |ln o| = 225 + |ln o|."""
+    kappa = 4e-6
+    for off, flagged in ((5e-4, True), (2e-3, False), (-5e-4, True), (-2e-3, False)):
+        P = [math.log(0.6), -math.log(255.0) + off]
+        u, v, c, o, col = seq(np.exp(P), [0.3, 2.0], lno=True)
+        M = 225.0 + abs(P[1])
+        assert kappa * M > 5e-4 and kappa * M < 2e-3
+        r = oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, modes=("fast-def",),
+                              margins=(1e-5, 0.0, kappa, 0.0))
+        assert bool(r.flagged[0]) == flagged, (off, r.flagged[0])
+        # with kappa = 0 only the absolute margin counts: nothing is within 1e-6
+        r = oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, modes=("fast-def",),
+                              margins=(1e-5, 1e-6, 0.0, 0.0))
+        assert not r.flagged[0]
+
+
+def test_per_pair_margin_grows_with_distance_from_the_tile_centre():
+    """The same pair evaluated at a pixel next to its tile's centre has smaller terms, so a
+    P that is flagged at the tile corner is not flagged there."""
+    P = [math.log(0.6), -math.log(255.0) + 5e-4]
+    u, v, c, o, col = seq(np.exp(P), [0.3, 2.0], lno=True)
+    Xc, Yc = np.full(1, 8.0), np.full(1, 8.0)         # 0.5 px from the centre (7.5, 7.5)
+    uc, vc = u + 8.0, v + 8.0                          # the Gaussians on that pixel
+    r = oracle.blend_tile(np.arange(2), Xc, Yc, uc, vc, c, o, col, modes=("fast-def",),
+                          margins=(1e-5, 0.0, 4e-6, 0.0))
+    # M = (1^2 + 1^2) / 2 + 5.54: kappa M = 2.6e-5 < 5e-4
+    assert not r.flagged[0]
+
+
+def test_transmittance_rounding_widens_the_stop_interval():
+    """A pixel whose T ends a hair above the stop threshold is flagged once each blended pair
+    may round T by one float32 unit, and not without that term."""
+    alphas = [0.9] * 3 + [0.5]
+    T = 0.1 ** 3 * 0.5                                  # 5e-4 after four pairs
+    a5 = 1.0 - 1e-4 * (1.0 + 5e-7) / T                  # takes T to 1e-4 (1 + 5e-7)
+    u, v, c, o, col = seq(alphas + [a5, 0.2], [0.5] * 6)
+    r = oracle.blend_tile(np.arange(6), X, Y, u, v, c, o, col, margins=(0.0, 0.0, 0.0, 0.0))
+    assert not r.flagged[0]
+    r = oracle.blend_tile(np.arange(6), X, Y, u, v, c, o, col, margins=(0.0, 0.0, 0.0, 2.0 ** -22))
+    assert r.flagged[0] and r.slack[0] > 0
