@@ -54,7 +54,7 @@ typedef int32_t rgs_status;
 #define RGS_E_UNSUPPORTED -6  /* entry point or option not available in this library       */
 #define RGS_E_DEVICE     -7   /* a kernel reported an internal failure (bounded wait hit)  */
 
-#define RGS_ABI_VERSION 1
+#define RGS_ABI_VERSION 2
 
 #define RGS_FMT_PLAIN 1u      /* FP32 structure-of-arrays, 240 bytes per Gaussian (the
                                  plain path reads 236 of them; ln o is kept for ablations)   */
@@ -89,7 +89,12 @@ typedef int32_t rgs_status;
  * hardware exp2 instruction, with log2 e folded into the coefficients of
  * Eq. coeff, instead of the bit-level exponential of Eq. fma_exp (Sec. IV-B).
  * The image is that of the exact exponential to within the instruction's
- * 1-ulp error.  Not valid with RGS_ABLATE_FASTEXP or RGS_ABLATE_DUALPIXEL. */
+ * 1-ulp error.  Not valid with RGS_ABLATE_FASTEXP or RGS_ABLATE_DUALPIXEL.
+ * With RGS_PATH_PLAIN (and no other bit) it selects the plain path's training
+ * variant: Eq. alpha_computation's exp(p) taken as exp2(p log2 e) by the same
+ * instruction in the forward rasterizer and in rgs_render_backward, which
+ * therefore recomputes the forward pass's alpha bit for bit; the image
+ * definition stays the plain one (exact exponential). */
 #define RGS_HW_EXP2          (1 << 16)
 /* Extension of the fast path: four pixels per lane instead of two.  Eq.
  * dual_pixel is applied along the column three times, P(x, y + 1) =
@@ -249,6 +254,9 @@ typedef struct {
     int32_t passes;           /* radix passes run                                         */
     int32_t overflow;         /* n_entries > capacity                                     */
     int32_t device_error;     /* a bounded wait in a kernel gave up                        */
+    int64_t list_steps;       /* fast path, counting renders (rgs_render_debug) only: list
+                                 entries the rasterizer's waves evaluated, each for all of
+                                 the wave's pixels (64 lanes x pixels per lane); else 0      */
 } rgs_frame_stats;
 
 /* ---------------------------------------------------------------------------
@@ -479,10 +487,13 @@ rgs_status rgs_backward_scratch_size(int64_t n, int32_t width, int32_t height, u
  * Gaussian then gathers its entries (one per covered tile) and applies the
  * chain rule through projection and SH in double precision.  Enqueued on the
  * context's stream after one synchronous read of the workspace header.
+ * The frame may be a render of RGS_PATH_PLAIN or of its training variant
+ * RGS_PATH_PLAIN | RGS_HW_EXP2; the backward pass takes the exponential the
+ * frame took.
  * Errors: INVALID (NULL, bad size, a workspace whose last frame was not a
- * plain render of this scene, scratch too small); CAPACITY (that frame
- * overflowed its workspace); DEVICE (that frame reported an internal
- * failure). */
+ * plain render of this scene in its current state, with this camera and
+ * size, scratch too small); CAPACITY (that frame overflowed its workspace);
+ * DEVICE (that frame reported an internal failure). */
 rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
                                int32_t width, int32_t height, const float* dL_dimg,
                                void* workspace, uint64_t ws_bytes, rgs_grads* grads);

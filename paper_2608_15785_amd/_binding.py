@@ -37,10 +37,14 @@ EXTENSIONS = {"exact-tiles": 1 << 15, "hw-exp2": 1 << 16, "quad-pixel": 1 << 17}
 
 
 class _Paths(dict):
-    """"plain", "fast", or "fast/no-<ablation>/.../<extension>" -> the C path argument."""
+    """"plain", "fast", "fast/no-<ablation>/.../<extension>", or "plain/hw-exp2" (the
+    plain path's training variant: forward and backward take exp through the hardware
+    exp2) -> the C path argument."""
 
     def __missing__(self, key):
         parts = str(key).split("/")
+        if parts == ["plain", "hw-exp2"]:
+            return PATH_PLAIN | EXTENSIONS["hw-exp2"]
         if parts[0] != "fast" or len(parts) < 2:
             raise KeyError(key)
         code = PATH_FAST
@@ -94,7 +98,7 @@ class CameraC(C.Structure):
 class FrameStats(C.Structure):
     _fields_ = [("n_gaussians", C.c_int64), ("n_visible", C.c_int64), ("n_entries", C.c_int64),
                 ("capacity", C.c_int64), ("path", C.c_int32), ("passes", C.c_int32),
-                ("overflow", C.c_int32), ("device_error", C.c_int32)]
+                ("overflow", C.c_int32), ("device_error", C.c_int32), ("list_steps", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

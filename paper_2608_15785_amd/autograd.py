@@ -29,8 +29,12 @@ _frames = itertools.count(1)
 
 
 class GaussianRasterizer:
-    def __init__(self, renderer: Renderer | None = None, device: int = 0):
+    """hw_exp2=True renders and differentiates with the plain path's training
+    variant (exp through the hardware exp2 in both passes; "plain/hw-exp2")."""
+
+    def __init__(self, renderer: Renderer | None = None, device: int = 0, hw_exp2: bool = False):
         self.R = renderer if renderer is not None else Renderer(device)
+        self.path = "plain/hw-exp2" if hw_exp2 else "plain"
         self.scene = None
         self.n = 0
         self._gen = 0            # parameter writes into the device scene so far
@@ -70,7 +74,7 @@ class GaussianRasterizer:
         ws = self.workspace(cam)
         for _ in range(4):
             try:
-                img, _ = B.render(self.R.ctx, scene, cam, "plain", ws, stats=True)
+                img, _ = B.render(self.R.ctx, scene, cam, self.path, ws, stats=True)
                 break
             except B.RGSError as e:
                 if e.status != B.RGS_E_CAPACITY:

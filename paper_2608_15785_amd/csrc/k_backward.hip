@@ -117,6 +117,10 @@ __device__ inline uint32_t band_mask(float v, float A, float B, float C, float o
     return m;
 }
 
+// HW2: the frame was rendered with the hardware exp2 (the training variant of
+// the plain path); exp(p) is recomputed as exp2(p * LOG2E_PLAIN), the forward
+// pass's very bits.
+template <bool HW2>
 __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev ws,
                                                                const uint32_t* __restrict__ vals,
                                                                const float* __restrict__ dimg,
@@ -201,7 +205,7 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
                 if (((band >> k) & 1u) && idx < last[k]) {
                     const float dx = x - a.x, dy = (float)(ly0 + 4 * k) - a.y;
                     const float p = fmaf(-0.5f, fmaf(a.z * dx, dx, m.x * dy * dy), -a.w * dx * dy);
-                    const float e = expf(p);
+                    const float e = HW2 ? __builtin_amdgcn_exp2f(p * LOG2E_PLAIN) : expf(p);
                     const float raw = m.y * e;
                     const float alpha = fminf(ALPHA_MAX, raw);
                     if (alpha >= ALPHA_MIN) {
@@ -265,9 +269,11 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
 }
 
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                            const float* dimg, float4* partial) {
-    hipLaunchKernelGGL(k_raster_backward, dim3(bwd_xcd_grid(f.n_tiles)), dim3(BWD_LANES), 0, s, f, ws,
-                       result_in_b ? ws.vals_b : ws.vals_a, dimg, partial);
+                            const float* dimg, float4* partial, bool hw_exp2) {
+    const dim3 grid(bwd_xcd_grid(f.n_tiles)), block(BWD_LANES);
+    const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
+    if (hw_exp2) hipLaunchKernelGGL(k_raster_backward<true>, grid, block, 0, s, f, ws, vals, dimg, partial);
+    else hipLaunchKernelGGL(k_raster_backward<false>, grid, block, 0, s, f, ws, vals, dimg, partial);
 }
 
 // ---------------------------------------------------------------------------

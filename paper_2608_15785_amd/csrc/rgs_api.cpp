@@ -521,8 +521,8 @@ rgs_status rgs::check_path(int32_t path) {
     const int32_t base = path_base(path);
     if ((base != RGS_PATH_PLAIN && base != RGS_PATH_FAST) || ((uint32_t)path & ~(0xffu | PATH_BITS)))
         return fail(RGS_E_INVALID, "path 0x%x is neither RGS_PATH_PLAIN nor RGS_PATH_FAST with ablation bits", path);
-    if (base == RGS_PATH_PLAIN && path_opts(path))
-        return fail(RGS_E_INVALID, "ablation and extension bits apply to the fast path only");
+    if (base == RGS_PATH_PLAIN && (path_opts(path) & ~OPT_HW_EXP2))
+        return fail(RGS_E_INVALID, "ablation and extension bits other than RGS_HW_EXP2 apply to the fast path only");
     if ((path & RGS_EXACT_TILES) && (path & RGS_ABLATE_EXTENT))
         return fail(RGS_E_INVALID, "RGS_EXACT_TILES refines the alpha-ellipse extent that RGS_ABLATE_EXTENT removes");
     if ((path & RGS_HW_EXP2) && (path & (RGS_ABLATE_FASTEXP | RGS_ABLATE_DUALPIXEL)))
@@ -664,6 +664,7 @@ static rgs_status header_status(const WsHeader& h, rgs_frame_stats* st, int64_t 
         st->passes = (int32_t)h.passes;
         st->overflow = (int32_t)h.overflow;
         st->device_error = (int32_t)h.error;
+        st->list_steps = (int64_t)h.list_steps;
     }
     if (h.error)
         return fail(RGS_E_DEVICE, "a kernel's bounded wait gave up (flags 0x%x)", h.error);
@@ -775,7 +776,7 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
     mark(3);
     launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
     mark(4);
-    if (fl.path == RGS_PATH_PLAIN) launch_raster_plain(st, fl.f, w, in_b, count);
+    if (fl.path == RGS_PATH_PLAIN) launch_raster_plain(st, fl.f, w, in_b, count, (fl.opts & OPT_HW_EXP2) != 0);
     else launch_raster_fast(st, fl.f, w, in_b, count, fl.opts);
     mark(5);
     if (status) launch_export_status(st, w, status);
@@ -976,7 +977,8 @@ extern "C" rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, 
     WsHeader h;
     s = read_header(ctx, workspace, &h);
     if (s != RGS_OK) return s;
-    if (h.path != (uint32_t)RGS_PATH_PLAIN || h.capacity != fl.f.capacity || h.passes != fl.L.passes)
+    if ((h.path != (uint32_t)RGS_PATH_PLAIN && h.path != (uint32_t)(RGS_PATH_PLAIN | RGS_HW_EXP2)) ||
+        h.capacity != fl.f.capacity || h.passes != fl.L.passes)
         return fail(RGS_E_INVALID, "the workspace does not hold a plain render of this size");
     FrameParams prm;
     HIP_TRY(hipMemcpyAsync(&prm, static_cast<const char*>(workspace) + fl.L.params, sizeof(prm),
@@ -991,7 +993,7 @@ extern "C" rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, 
     if (s != RGS_OK) return s;
     const bool in_b = (fl.L.passes % 2) == 1;
     float4* partial = static_cast<float4*>(grads->scratch);
-    launch_raster_backward(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial);
+    launch_raster_backward(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial, (h.path & RGS_HW_EXP2) != 0);
     GradOut go{grads->d_means, grads->d_scales, grads->d_quats, grads->d_opacity, grads->d_sh, grads->d_screen};
     launch_grad_gaussian(ctx->stream, fl.plain, cam_dev(cam), fl.w, partial, go);
     HIP_TRY(hipGetLastError());

@@ -24,6 +24,9 @@ constexpr double J_CLAMP = 1.3;      // Jacobian clamp factor on t_x/t_z, t_y/t_
 constexpr float ALPHA_MAX = 0.99f;   // Eq. opacity_clamped
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float T_MIN = 1e-4f;       // stop blending a pixel below this transmittance
+// log2(e) rounded to float32: the plain path's hardware-exp2 variant takes
+// exp(p) as exp2(p * LOG2E_PLAIN) in its forward and backward rasterizers alike.
+constexpr float LOG2E_PLAIN = 1.4426950408889634f;
 
 constexpr int FE_THREADS = 1024;     // threads per front-end / duplication block
 // Gaussians per thread (block-strided).  Four makes blocks of 4096 Gaussians:
@@ -169,7 +172,8 @@ struct WsHeader {
     uint32_t path;
     uint32_t passes;
     uint32_t fe_ticket;
-    uint32_t pad[55];
+    uint64_t list_steps;      // counting renders of the fast path: list entries the waves evaluated
+    uint32_t pad[52];
 };
 static_assert(sizeof(WsHeader) == 256, "header is one 256-byte slot");
 
@@ -497,7 +501,7 @@ void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key
 void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                    bool result_in_b);
 void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                         bool count);
+                         bool count, bool hw_exp2);
 void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count,
                         uint32_t opts);
 void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n);
@@ -520,7 +524,7 @@ struct GradOut {
 void launch_update_plain(hipStream_t s, float* planes, uint64_t n_pad, int64_t n, const float* means,
                          const float* scales, const float* quats, const float* opacity, const float* sh);
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                            const float* dimg, float4* partial);
+                            const float* dimg, float4* partial, bool hw_exp2);
 void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
                           const float4* partial, const GradOut& go);
 

@@ -32,7 +32,7 @@ def test_every_declared_symbol_is_exported():
     for n in names:
         assert hasattr(lib, n), n
     assert {n for n, _, _ in B.SIGNATURES} == set(names)
-    assert B.lib.rgs_abi_version() == 1
+    assert B.lib.rgs_abi_version() == 2
 
 
 @pytest.mark.parametrize("W,H", [(1, 1), (16, 16), (17, 1), (256, 256), (1280, 720), (1920, 1080),
@@ -74,7 +74,7 @@ def test_path_words_are_validated():
     exact ellipse-tile test is rejected together with the extent ablation it refines."""
     ok = ["fast/no-fusion", "fast/exact-tiles", "fast/no-fusion/exact-tiles", "fast/no-key32/exact-tiles",
           "fast/hw-exp2", "fast/hw-exp2/exact-tiles", "fast/no-key32/hw-exp2", "fast/quad-pixel",
-          "fast/quad-pixel/exact-tiles", "fast/no-int8sh/quad-pixel",
+          "fast/quad-pixel/exact-tiles", "fast/no-int8sh/quad-pixel", "plain/hw-exp2",
           "fast/" + "/".join("no-" + a for a in B.ABLATIONS)]
     for p in ok:
         assert rgs.workspace_size(1000, 64, 64, p, 4096) > 0
@@ -83,7 +83,8 @@ def test_path_words_are_validated():
                  B.PATH_PLAIN | B.EXTENSIONS["exact-tiles"], B.PATH_PLAIN | B.ABLATIONS["fusion"],
                  B.PATH_FAST | B.ABLATIONS["fastexp"] | B.EXTENSIONS["hw-exp2"],
                  B.PATH_FAST | B.ABLATIONS["dualpixel"] | B.EXTENSIONS["hw-exp2"],
-                 B.PATH_PLAIN | B.EXTENSIONS["hw-exp2"], B.PATH_FAST | (1 << 18), 2,
+                 B.PATH_PLAIN | B.EXTENSIONS["hw-exp2"] | B.ABLATIONS["fusion"],
+                 B.PATH_PLAIN | B.EXTENSIONS["hw-exp2"] | B.EXTENSIONS["exact-tiles"], B.PATH_FAST | (1 << 18), 2,
                  B.PATH_FAST | B.EXTENSIONS["quad-pixel"] | B.EXTENSIONS["hw-exp2"],
                  B.PATH_FAST | B.EXTENSIONS["quad-pixel"] | B.ABLATIONS["fastexp"],
                  B.PATH_FAST | B.EXTENSIONS["quad-pixel"] | B.ABLATIONS["dualpixel"],

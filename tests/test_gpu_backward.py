@@ -44,12 +44,15 @@ def R():
     return rgs.Renderer(0)
 
 
-def gpu_backward(R, scene, cam, dimg):
+PATHS = ["plain", "plain/hw-exp2"]      # the plain path and its training variant (hardware exp2)
+
+
+def gpu_backward(R, scene, cam, dimg, path="plain"):
     import torch
     import paper_2608_15785_amd as rgs
     ds = R.upload(scene, ("plain",))
-    dbg = R.render_debug(ds, cam, "plain")        # the frame, with its per-pixel decisions
-    ws = R.workspace(scene.n, cam.width, cam.height, "plain")
+    dbg = R.render_debug(ds, cam, path)           # the frame, with its per-pixel decisions
+    ws = R.workspace(scene.n, cam.width, cam.height, path)
     g = rgs.render_backward(R.ctx, ds, cam, ws, torch.from_numpy(dimg).cuda(), screen=True)
     torch.cuda.synchronize()
     chk = rgs.workspace_check(R.ctx, ws, scene.n)
@@ -93,15 +96,16 @@ def compare(g, adj, n_expect_min=1):
         assert rel < 1e-3, (k, rel)
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("W,H", [(128, 96), (120, 88)])
-def test_small_scene_all_tiles(R, W, H):
+def test_small_scene_all_tiles(R, W, H, path):
     sc = wl.make_scene(3000, 1.0, -3.0, 0.5, 31)
     cam = wl.config_camera("small", width=W, height=H)
     cam.bg = np.array([0.1, 0.2, 0.3], np.float32)
     rng = np.random.Generator(np.random.PCG64(41))
     dimg = rng.normal(0.0, 1.0, (3, H, W)).astype(np.float32)
-    _log(f"[bwd] small scene n={sc.n} {W}x{H}")
-    g = gpu_backward(R, sc, cam, dimg)
+    _log(f"[bwd] small scene n={sc.n} {W}x{H} {path}")
+    g = gpu_backward(R, sc, cam, dimg, path)
     adj = OB.render_adjoint(oracle.prepare_plain(sc), cam, dimg.astype(np.float64), decisions=g["decisions"])
     compare(g, adj, n_expect_min=1000)
 
@@ -117,7 +121,8 @@ def test_deterministic(R):
     assert np.abs(a["screen"]).sum() > 0
 
 
-def test_training_l1_loss_sampled_tiles(R):
+@pytest.mark.parametrize("path", PATHS)
+def test_training_l1_loss_sampled_tiles(R, path):
     """1M Gaussians at 1080p; L1 loss against a render of the same scene with
     means perturbed by N(0, 0.01); dL/d(image) kept on 40 sampled tiles so that
     the oracle differentiates exactly the same loss."""
@@ -133,7 +138,7 @@ def test_training_l1_loss_sampled_tiles(R):
     target = target.cpu().numpy()
     dt.release()
     ds = R.upload(sc, ("plain",))
-    img, _ = R.render(ds, cam, "plain")
+    img, _ = R.render(ds, cam, path)
     torch.cuda.synchronize()
     img = img.cpu().numpy()
     ds.release()
@@ -145,8 +150,8 @@ def test_training_l1_loss_sampled_tiles(R):
         tx, ty = t % plan.tiles_x, t // plan.tiles_x
         mask[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
     dimg = (np.sign(img - target) / img.size * mask[None]).astype(np.float32)
-    _log(f"[bwd] training: L1 loss {np.abs(img - target).mean():.6g}, {len(tiles)} tiles")
-    g = gpu_backward(R, sc, cam, dimg)
+    _log(f"[bwd] training ({path}): L1 loss {np.abs(img - target).mean():.6g}, {len(tiles)} tiles")
+    g = gpu_backward(R, sc, cam, dimg, path)
     assert np.array_equal(g["image"], img)
     adj = OB.render_adjoint(oracle.prepare_plain(sc), cam, dimg.astype(np.float64), tiles=tiles,
                             decisions=g["decisions"])
