@@ -29,9 +29,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FPS at 1080p/4K (1M/3M Gaussians) fast vs plain path; p50/p99 latency"
 
-# MI355X peaks: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz issue 39.3e12 VALU
-# lane-operations per second (non-packed); HBM3E 8 TB/s.
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# MI355X peaks.  VALU: 256 CUs x 4 SIMDs, each issuing up to two wave64
+# instructions (from two waves) per four cycles onto its 16 lanes, at 2.4 GHz:
+# 256 x 4 x 2 x 16 x 2.4e9 = 78.6e12 lane-operations per second, non-packed
+# (the published 157.3 TFLOP/s float32 counts an FMA as two).  The dual issue
+# is measured, not assumed: the calibration probe (rgs_probe_valu, eight
+# independent FMA chains per lane) reaches 0.40 wave instructions per SIMD and
+# cycle at eight waves per SIMD, with SQ_ACTIVE_INST_VALU2 counting paired
+# issue for 90 % of them (profiles/valu_calibration.txt).  HBM3E 8 TB/s.
+VALU_PEAK_TOPS = 256 * 4 * 2 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 # Algorithmic VALU lane-operations per blended (pixel, Gaussian) pair -- a pair
 # past the skip test that the method must composite.  Fast: the folded exponent
@@ -61,7 +67,11 @@ def parse():
     ap.add_argument("--orbit-rounds", type=int, default=2)
     ap.add_argument("--no-4k", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-tiles", type=int, default=2048, help="tiles the oracle blends")
+    ap.add_argument("--cpu-tiles", type=int, default=512, help="tiles the oracle blends (1080p, fast path)")
+    ap.add_argument("--cpu-plain-tiles", type=int, default=128, help="of those, tiles the plain oracle blends")
+    ap.add_argument("--cpu-4k-poses", default="0,16,32,48")
+    ap.add_argument("--cpu-4k-tiles", type=int, default=64, help="tiles the oracle blends per 4K pose")
+    ap.add_argument("--cold-frames", type=int, default=50, help="frames of the cold-cache run (0: none)")
     ap.add_argument("--paths", default="fast,plain")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-backward", action="store_true")
@@ -182,12 +192,26 @@ def time_path(R, ds, cams, path, steps, warmup, lat_frames):
                                 mean=float(lat.mean())))
 
 
+def pixels_per_lane(path):
+    parts = path.split("/")
+    if parts[0] == "plain":
+        return 1
+    return 4 if "quad-pixel" in parts else (1 if "no-dualpixel" in parts else 2)
+
+
 def frame_counts(R, ds, cam, path):
+    """Entry and pair counts of one frame from a counting render: pairs visited up to each
+    pixel's stop, pairs blended, and (fast path) pairs evaluated by the rasterizer's waves:
+    every list entry a wave evaluates is evaluated at all of its 64 x pixels-per-lane pixels."""
     g = R.render_debug(ds, cam, path)
     st = g["stats"]
-    return dict(n_visible=int(st["n_visible"]), n_entries=int(st["n_entries"]),
-                pairs_visited=int(g["n_proc"].astype(np.int64).sum()),
-                pairs=int(g["n_blend"].astype(np.int64).sum()), passes=int(st["passes"]))
+    c = dict(n_visible=int(st["n_visible"]), n_entries=int(st["n_entries"]),
+             pairs_visited=int(g["n_proc"].astype(np.int64).sum()),
+             pairs=int(g["n_blend"].astype(np.int64).sum()), passes=int(st["passes"]))
+    if path != "plain":
+        c["list_steps"] = int(st["list_steps"])
+        c["pairs_evaluated"] = int(st["list_steps"]) * 64 * pixels_per_lane(path)
+    return c
 
 
 def rooflines(path, counts, stage_ms, n, n_tiles):
@@ -205,6 +229,9 @@ def rooflines(path, counts, stage_ms, n, n_tiles):
     out["raster"] = dict(bound="alu", achieved=round(tops, 3), peak=round(VALU_PEAK_TOPS, 2),
                          unit="Tops/s", frac=round(tops / VALU_PEAK_TOPS, 4), pairs_blended=counts["pairs"],
                          pairs_visited=counts["pairs_visited"], ops_per_pair=ops, ms=round(ms, 4))
+    if counts.get("pairs_evaluated"):
+        out["raster"]["pairs_evaluated"] = counts["pairs_evaluated"]
+        out["raster"]["evaluated_per_blended"] = round(counts["pairs_evaluated"] / max(counts["pairs"], 1), 3)
     return out
 
 
@@ -239,28 +266,101 @@ def calibrate_valu(rgs, torch):
     return {"calibrate_valu": out, "iters": PROBE_ITERS, "cus": cus}
 
 
-def cpu_baseline(scene, cam, n_tiles_sample):
-    """The FP64 oracle's fast path on the host cores: full front end and sort,
-    blending of a seeded sample of tiles, scaled to one frame."""
-    import oracle
-    cores = min(16, os.cpu_count() or 1)
-    arr = oracle.prepare_fast(oracle.quantize_scene(scene))
+def _oracle_frame_rate(oracle, arr, cam, path, n_tiles_sample, seed, cores):
+    """One frame of the FP64 oracle on the host: front end, keys and sort of all Gaussians
+    (one core), then blending of a seeded sample of tiles on `cores` processes.  Returns the
+    time scaled to the full frame and the sampled frame (its images cover the sample)."""
+    modes = ("fast-def", "fast-exact") if path == "fast" else ("plain",)
     t = time.perf_counter()
-    fr = oracle.render(arr, cam, "fast", modes=("fast-def",), blend=False)
+    fr = oracle.render(arr, cam, path, modes=modes, blend=False)
     t_front = time.perf_counter() - t
     n_t = fr.plan.n_tiles
     k = min(n_tiles_sample, n_t)
-    tiles = np.random.default_rng(0).choice(n_t, k, replace=False)
+    tiles = np.random.default_rng(seed).choice(n_t, k, replace=False)
     t = time.perf_counter()
-    oracle.render(arr, cam, "fast", modes=("fast-def",), tiles=tiles, workers=cores)
-    t_all = time.perf_counter() - t
-    t_blend = max(t_all - t_front, 0.0)
+    fr = oracle.render(arr, cam, path, modes=modes, tiles=tiles, workers=cores)
+    t_blend = max(time.perf_counter() - t - t_front, 0.0)
+    return t_front, t_blend, k, n_t, fr
+
+
+def _tile_mask(fr):
+    m = np.zeros((fr.plan.height, fr.plan.width), bool)
+    for t in fr.tiles:
+        tx, ty = int(t) % fr.plan.tiles_x, int(t) // fr.plan.tiles_x
+        m[ty * 16:(ty + 1) * 16, tx * 16:(tx + 1) * 16] = True
+    return m
+
+
+def _psnr(a, b, mask):
+    d = (a - b)[:, mask]
+    mse = float(np.mean(d * d))
+    return None if mse == 0 else round(10 * math.log10(1.0 / mse), 3)
+
+
+def cpu_baseline(R, ds, scene, cam, n_tiles_sample, plain_tiles):
+    """The FP64 oracle on the host cores (the CPU baseline), and the accuracy of the GPU
+    images measured against the oracle frames it renders: PSNR (peak 1, unclipped values)
+    over the oracle's sampled tiles of the fast GPU image against the bit-level-exp and
+    exact-exp oracles, of the plain GPU image against the plain oracle, and the
+    quantisation loss: the fast GPU image against the plain oracle on the FP32 scene."""
+    import torch
+    import oracle
+    cores = min(16, os.cpu_count() or 1)
+    fast_arr = oracle.prepare_fast(oracle.quantize_scene(scene))
+    t_front, t_blend, k, n_t, fr = _oracle_frame_rate(oracle, fast_arr, cam, "fast", n_tiles_sample, 0, cores)
     frame_s = t_front + t_blend * n_t / k
-    return dict(value=round(1.0 / frame_s, 5), unit="FPS", cores=cores, kind="oracle",
-                sample=f"FP64 oracle, fast path: front end, keys and sort of all {scene.n} Gaussians "
-                       f"({t_front:.1f} s, one core) plus blending of {k} of {n_t} seeded tiles on "
-                       f"{cores} processes ({t_blend:.1f} s), scaled to the full frame "
+    base = dict(value=round(1.0 / frame_s, 5), unit="FPS", cores=cores, kind="oracle",
+                sample=f"FP64 oracle, fast path, {scene.n} Gaussians at {cam.width}x{cam.height}: front end, "
+                       f"keys and sort of all Gaussians ({t_front:.1f} s, one core) plus blending of {k} of "
+                       f"{n_t} seeded tiles on {cores} processes ({t_blend:.1f} s), scaled to the full frame "
                        f"({frame_s:.1f} s per frame)")
+    img_fast = R.render(ds, cam, "fast")[0].cpu().numpy().astype(np.float64)
+    img_plain = R.render(ds, cam, "plain")[0].cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    m = _tile_mask(fr)
+    plain_arr = oracle.prepare_plain(scene)
+    plain_sample = fr.tiles[:plain_tiles]
+    frp = oracle.render(plain_arr, cam, "plain", tiles=plain_sample, workers=cores)
+    mp = _tile_mask(frp)
+    acc = {"tiles_fast": int(k), "tiles_plain": int(len(plain_sample)),
+           "fast_vs_oracle_bitexp": _psnr(img_fast, fr.images["fast-def"], m),
+           "fast_vs_oracle_exactexp": _psnr(img_fast, fr.images["fast-exact"], m),
+           "plain_vs_oracle": _psnr(img_plain, frp.images["plain"], mp),
+           "quantisation_loss_fast_vs_plain_oracle": _psnr(img_fast, frp.images["plain"], mp),
+           "oracle_fast_vs_oracle_plain": _psnr(fr.images["fast-def"], frp.images["plain"], mp),
+           "note": "None = identical; peak 1.0"}
+    return base, acc
+
+
+def cpu_baseline_4k(R, ds, scene, poses, n_tiles_sample):
+    """The FP64 oracle's fast path at 3840x2160 on orbit poses (front end of all 3M
+    Gaussians on one core, blending of a tile sample on the host's processes, scaled to
+    the frame), and the fast GPU image's PSNR against it on those tiles."""
+    import torch
+    import oracle
+    import workloads as wl
+    cores = min(16, os.cpu_count() or 1)
+    arr = oracle.prepare_fast(oracle.quantize_scene(scene))
+    per_pose = {}
+    for pose in poses:
+        cam = wl.config_camera("4k", pose=pose)
+        t_front, t_blend, k, n_t, fr = _oracle_frame_rate(oracle, arr, cam, "fast", n_tiles_sample, 100 + pose,
+                                                          cores)
+        frame_s = t_front + t_blend * n_t / k
+        img = R.render(ds, cam, "fast")[0].cpu().numpy().astype(np.float64)
+        torch.cuda.synchronize()
+        m = _tile_mask(fr)
+        per_pose[str(pose)] = {"s_per_frame": round(frame_s, 2), "front_s": round(t_front, 2),
+                               "blend_s_sample": round(t_blend, 2), "tiles": int(k),
+                               "psnr_fast_vs_oracle_bitexp": _psnr(img, fr.images["fast-def"], m),
+                               "psnr_fast_vs_oracle_exactexp": _psnr(img, fr.images["fast-exact"], m)}
+        log(f"[bench] cpu baseline 4k pose {pose}: {per_pose[str(pose)]}")
+    mean_s = float(np.mean([v["s_per_frame"] for v in per_pose.values()]))
+    return {"value": round(1.0 / mean_s, 5), "unit": "FPS", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 oracle, fast path, 3,000,000 Gaussians at 3840x2160, orbit poses {list(poses)}: "
+                      f"front end, keys and sort of all Gaussians on one core plus blending of {n_tiles_sample} "
+                      f"seeded tiles per pose on {cores} processes, scaled to the frame",
+            "poses": per_pose}
 
 
 def serving_section(rgs, wl, torch, dev_scenes, args):
@@ -332,6 +432,29 @@ def serving_section(rgs, wl, torch, dev_scenes, args):
     return out
 
 
+def cold_cache_section(torch, R, ds, cam, path, frames, n, n_tiles):
+    """Frames of `path` each preceded by a 1 GiB device write, which evicts the scene and
+    the frame's transients from the 256 MB Infinity Cache: per-stage times from the
+    library's stage events (the writes lie outside them) and the stages' roofline
+    fractions against the same algorithmic bytes as the warm frames."""
+    flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    R.render(ds, cam, path)
+    R.ctx.set_timing(True)
+    for k in range(frames):
+        flush.fill_(float(k))
+        R.render(ds, cam, path, check=False)
+    stage_ms, nf = R.ctx.collect_timing()
+    R.ctx.set_timing(False)
+    torch.cuda.synchronize()
+    del flush
+    stage_ms = {k: v / max(nf, 1) for k, v in stage_ms.items()}
+    c = frame_counts(R, ds, cam, path)
+    rl = rooflines(path, c, stage_ms, n, n_tiles)
+    return {"frames": nf, "flush_bytes": 1 << 30, "ms_per_frame": round(sum(stage_ms.values()), 4),
+            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+            "roofline_frac": {k: v["frac"] for k, v in rl.items()}}
+
+
 ABLATIONS = ["fastexp", "dualpixel", "fusion", "extent", "key32", "int8sh", "fp16geom"]
 
 
@@ -342,7 +465,8 @@ def ablation_section(R, ds, cam, steps, n_tiles):
     passes."""
     out = {}
     paths = ["fast"] + ["fast/no-" + a for a in ABLATIONS] + ["fast/" + "/".join("no-" + a for a in ABLATIONS),
-                                                              "plain", "fast/exact-tiles", "fast/hw-exp2"]
+                                                              "plain", "fast/exact-tiles", "fast/hw-exp2",
+                                                              "fast/quad-pixel"]
     for path in paths:
         r = time_path(R, ds, [cam], path, steps, 10, 20)
         c = frame_counts(R, ds, cam, path)
@@ -351,6 +475,7 @@ def ablation_section(R, ds, cam, steps, n_tiles):
         out[name] = {"fps": round(r["fps"], 1), "ms_per_frame": round(r["ms_per_frame"], 4),
                      "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
                      "n_entries": c["n_entries"], "passes": c["passes"], "pairs_visited": c["pairs_visited"],
+                     "pairs_evaluated": c.get("pairs_evaluated"),
                      "roofline_frac": {k: v["frac"] for k, v in rl.items()}}
         log(f"[bench] ablation {path}: {out[name]['fps']} FPS, stages {out[name]['stage_ms']}")
     base = out["fast"]["fps"]
@@ -359,10 +484,12 @@ def ablation_section(R, ds, cam, steps, n_tiles):
     return out
 
 
-def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup):
+def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup, path="plain"):
     """One training step at 1M Gaussians, 1920x1080: write the parameters into the
-    device scene, render the plain path, L1 loss gradient against a render of the
-    scene with means perturbed by N(0, 0.01), backward to the activated parameters."""
+    device scene, render the plain path (or its training variant "plain/hw-exp2",
+    whose forward and backward take exp through the hardware exp2), L1 loss
+    gradient against a render of the scene with means perturbed by N(0, 0.01),
+    backward to the activated parameters."""
     from paper_2608_15785_amd import _binding as B
     W, H = cam.width, cam.height
     dev = "cuda"
@@ -375,8 +502,8 @@ def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup):
     ds = R.upload(sc, ("plain",))
     params = [torch.tensor(np.ascontiguousarray(a, np.float32), device=dev)
               for a in (sc.means, sc.scales, sc.quats, sc.opacity, sc.sh)]
-    _, st = R.render(ds, cam, "plain")
-    ws = R.workspace(sc.n, W, H, "plain", int(st["n_entries"] * 1.05) + 4096)
+    _, st = R.render(ds, cam, path)
+    ws = R.workspace(sc.n, W, H, path, int(st["n_entries"] * 1.05) + 4096)
     out = torch.empty((3, H, W), dtype=torch.float32, device=dev)
     scratch = torch.empty(rgs.backward_scratch_size(sc.n, W, H, ws.numel()), dtype=torch.uint8, device=dev)
     inv_n = 1.0 / out.numel()
@@ -388,7 +515,7 @@ def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup):
         rgs.scene_update_plain(R.ctx, ds, *params)
         if timed:
             ev["b"].record()
-        B.render(R.ctx, ds, cam, "plain", ws, out)
+        B.render(R.ctx, ds, cam, path, ws, out)
         if timed:
             ev["c"].record()
         dimg = torch.sign(out - target) * inv_n
@@ -418,13 +545,13 @@ def differentiation_section(rgs, wl, torch, R, sc, cam, steps, warmup):
         parts["loss_grad"] += ev["c"].elapsed_time(ev["d"])
         parts["backward"] += ev["d"].elapsed_time(ev["e"])
     parts = {k: round(v / steps, 4) for k, v in parts.items()}
-    dbg = R.render_debug(ds, cam, "plain")
+    dbg = R.render_debug(ds, cam, path)
     pairs = int(dbg["n_blend"].astype(np.int64).sum())
     loss = float((out - target).abs().mean())
     ds.release()
     bwd_s = parts["backward"] * 1e-3
     achieved = pairs * OPS_PER_PAIR_BACKWARD / bwd_s / 1e12
-    return {"workload": "training: 1,000,000 Gaussians, 1920x1080, plain path, L1 loss against a render with "
+    return {"workload": f"training: 1,000,000 Gaussians, 1920x1080, {path} path, L1 loss against a render with "
                         "means + N(0, 0.01)",
             "steps": steps, "ms_per_step": round((t1 - t0) / steps * 1e3, 4),
             "steps_per_s": round(steps / (t1 - t0), 2), "stage_ms": parts, "l1_loss": loss,
@@ -476,6 +603,18 @@ def main():
         res1[path] = r
         log(f"[bench] 1080p {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
 
+    cold = {}
+    if args.cold_frames > 0:
+        for path in paths:
+            cold[path] = cold_cache_section(torch, R, ds1, cam1, path, args.cold_frames, sc1.n, plan1["n_tiles"])
+            log(f"[bench] 1080p {path} cold cache: {cold[path]}")
+
+    cpu, accuracy = None, None
+    if not args.no_cpu_baseline and "fast" in paths and "plain" in paths:
+        log("[bench] cpu baseline (oracle) and accuracy against it")
+        cpu, accuracy = cpu_baseline(R, ds1, sc1, cam1, args.cpu_tiles, args.cpu_plain_tiles)
+        log(f"[bench] accuracy: {accuracy}")
+
     ablation = None
     if not args.no_ablation and "fast" in paths:
         log("[bench] ablation: the fast path without each optimisation, 1M Gaussians at 1080p")
@@ -486,8 +625,13 @@ def main():
         log("[bench] differentiation: forward + backward, 1M Gaussians at 1080p")
         diff = differentiation_section(rgs, wl, torch, R, sc1, cam1, args.backward_steps, 5)
         log(f"[bench] differentiation: {diff['ms_per_step']} ms/step, stages {diff['stage_ms']}")
+        diff["hw_exp2_variant"] = differentiation_section(rgs, wl, torch, R, sc1, cam1, args.backward_steps, 5,
+                                                          path="plain/hw-exp2")
+        log(f"[bench] differentiation (plain/hw-exp2): {diff['hw_exp2_variant']['ms_per_step']} ms/step, "
+            f"stages {diff['hw_exp2_variant']['stage_ms']}")
 
     res2 = {}
+    cpu4k = None
     if not args.no_4k:
         log("[bench] 4k: 3,000,000 Gaussians, 3840x2160, 64-pose orbit")
         ds1.release()
@@ -501,6 +645,9 @@ def main():
             r["roofline_pose0"] = rooflines(path, r, r["stage_ms"], sc2.n, plan2["n_tiles"])
             res2[path] = r
             log(f"[bench] 4k {path}: {r['fps']:.1f} FPS, stages {r['stage_ms']}")
+        if not args.no_cpu_baseline and "fast" in paths:
+            poses = [int(p) for p in args.cpu_4k_poses.split(",") if p]
+            cpu4k = cpu_baseline_4k(R, ds2, sc2, poses, args.cpu_4k_tiles)
         if args.no_serving:
             ds2.release()
 
@@ -533,12 +680,21 @@ def main():
     roofline = {"bound": rl["bound"], "achieved": rl["achieved"], "peak": rl["peak"], "unit": rl["unit"],
                 "frac": rl["frac"], "traffic": counters.get("bytes_per_launch"),
                 "kernel": kernel, "stage_ms": rl["ms"]}
+    for k in ("pairs_blended", "pairs_evaluated", "evaluated_per_blended", "ops_per_pair"):
+        if k in rl:
+            roofline[k] = rl[k]
     if counters.get("valu_wave_insts"):
-        # VALU wave instructions the kernel issued (SQ_INSTS_VALU, all pairs it evaluated), per SIMD and
-        # cycle of its measured duration: a wave64 instruction every 4 cycles is 0.25
-        roofline["valu_wave_insts"] = counters["valu_wave_insts"]
-        roofline["valu_insts_per_simd_cycle"] = round(
-            counters["valu_wave_insts"] / (rl["ms"] * 1e-3 * 1024 * 2.4e9), 3)
+        # from the profiling run that counted them (profiles/traffic_counters.txt): VALU wave
+        # instructions per launch (SQ_INSTS_VALU), the launch's duration and the clock
+        # (GRBM_GUI_ACTIVE over the duration, per XCD) in that same run, and the issue rate they
+        # give per SIMD and cycle (the dual-issue ceiling is 0.5)
+        for k in ("valu_wave_insts", "valu_run_duration_us", "valu_run_clock_ghz", "valu_insts_per_simd_cycle",
+                  "valu_dual_issue_share", "lds_insts"):
+            if k in counters:
+                roofline[k] = counters[k]
+        if rl.get("pairs_evaluated"):
+            roofline["valu_lane_ops_per_evaluated_pair"] = round(
+                counters["valu_wave_insts"] * 64 / rl["pairs_evaluated"], 2)
 
     out = {
         "metric": METRIC,
@@ -560,19 +716,31 @@ def main():
                    "n_gaussians": sc1.n, "width": 1920, "height": 1080, "path": main_path},
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(sc1, cam1, args.cpu_tiles)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if cpu4k is not None:
+        out["cpu_baseline_4k"] = cpu4k
+    if accuracy is not None:
+        out["psnr"] = {"1080p": accuracy}
+        if cpu4k is not None:
+            out["psnr"]["4k"] = {p: {k: v for k, v in r.items() if k.startswith("psnr")}
+                                 for p, r in cpu4k["poses"].items()}
     out["latency_ms"] = m["latency_ms"]
-    out["paths_1080p"] = {p: {k: r[k] for k in ("fps", "ms_per_frame", "latency_ms", "stage_ms", "n_visible",
-                                                  "n_entries", "pairs", "pairs_visited", "passes", "roofline")}
+    out["paths_1080p"] = {p: {k: r.get(k) for k in ("fps", "ms_per_frame", "latency_ms", "stage_ms", "n_visible",
+                                                      "n_entries", "pairs", "pairs_visited", "pairs_evaluated",
+                                                      "list_steps", "passes", "roofline")}
                           for p, r in res1.items()}
+    if cold:
+        out["cold_cache_1080p"] = cold
     if "fast" in res1 and "plain" in res1:
         out["speedup_fast_over_plain_1080p"] = round(res1["fast"]["fps"] / res1["plain"]["fps"], 3)
+    if ablation is not None and "all" in ablation:
+        out["speedup_fast_over_all_seven_removed_1080p"] = round(ablation["fast"]["fps"] / ablation["all"]["fps"],
+                                                                 3)
     if res2:
-        out["paths_4k_orbit"] = {p: {k: r[k] for k in ("fps", "ms_per_frame", "latency_ms", "stage_ms",
-                                                         "n_visible", "n_entries", "pairs", "pairs_visited",
-                                                         "passes", "roofline_pose0")}
+        out["paths_4k_orbit"] = {p: {k: r.get(k) for k in ("fps", "ms_per_frame", "latency_ms", "stage_ms",
+                                                             "n_visible", "n_entries", "pairs", "pairs_visited",
+                                                             "pairs_evaluated", "passes", "roofline_pose0")}
                                  for p, r in res2.items()}
         if "fast" in res2 and "plain" in res2:
             out["speedup_fast_over_plain_4k"] = round(res2["fast"]["fps"] / res2["plain"]["fps"], 3)
