@@ -292,6 +292,26 @@ rgs_status rgs_render(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* ca
                       void* workspace, uint64_t ws_bytes, float* out_chw,
                       rgs_frame_stats* stats);
 
+/* Allocation-free render, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  As rgs_render, but the frame's workspace is the library's own
+ * static device array of RGS_STATIC_WORKSPACE_BYTES, one per device, held
+ * from the first rgs_ctx_create on that device until the process ends; the
+ * call allocates nothing (no hipMalloc, no events even when the context times
+ * stages).  The caller still passes the scene and the output image.  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (another thread, context or stream) race and must be serialised by
+ * the caller; each frame clears what it needs at its start.  The entry
+ * capacity is what fits in the array (about 2.4M entries at 1M Gaussians and
+ * 1920x1080 on the fast path).
+ * Errors: as rgs_render; RGS_E_INVALID also when the frame's fixed part
+ * (records, tile ranges, per-pixel buffers) does not fit the array, and
+ * RGS_E_CAPACITY (with stats) when its entries do not. */
+#define RGS_STATIC_WORKSPACE_BYTES (128ull << 20)
+rgs_status rgs_render_static(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
+                             int32_t width, int32_t height, int32_t path, float* out_chw,
+                             rgs_frame_stats* stats);
+
 /* Synchronises the stream and reports the last frame rendered into the
  * workspace (its header sits at offset 0): RGS_E_CAPACITY on overflow,
  * RGS_E_DEVICE on a kernel failure.  stats may be NULL; n_gaussians only fills

@@ -174,6 +174,8 @@ SIGNATURES = [
                                      C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(DebugOut),
                                      C.POINTER(FrameStats)]),
     ("rgs_probe_valu", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    ("rgs_render_static", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(CameraC), C.c_int32, C.c_int32,
+                                      C.c_int32, C.c_void_p, C.POINTER(FrameStats)]),
     ("rgs_server_create", C.c_int32, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
     ("rgs_server_destroy", None, [C.c_void_p]),
     ("rgs_serve", C.c_int32, [C.c_void_p, C.POINTER(Request), C.c_int64, C.POINTER(Response),
@@ -368,6 +370,23 @@ def new_workspace(n: int, width: int, height: int, path: str, max_entries: int, 
     torch = _torch()
     nbytes = workspace_size(n, width, height, path, max_entries)
     return torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{device}")
+
+
+STATIC_WORKSPACE_BYTES = 128 << 20
+
+
+def render_static(ctx: Context, scene: DeviceScene, cam, path: str, out=None, stats: bool = False):
+    """rgs_render_static: one render into the library's static workspace (nothing is
+    allocated by the call; ``out``, if given, is the caller's image)."""
+    torch = _torch()
+    W, H = int(cam.width), int(cam.height)
+    if out is None:
+        out = torch.empty((3, H, W), dtype=torch.float32, device=f"cuda:{ctx.device}")
+    cc = camera_struct(cam)
+    st = FrameStats() if stats else None
+    _check(lib.rgs_render_static(ctx.handle, scene.handle, C.byref(cc), W, H, PATHS[path], out.data_ptr(),
+                                 C.byref(st) if st is not None else None), "rgs_render_static")
+    return out, (st.as_dict() if st is not None else None)
 
 
 def render(ctx: Context, scene: DeviceScene, cam, path: str, workspace, out=None, stats: bool = False):

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -218,6 +219,34 @@ struct rgs_ctx {
     int64_t frames;
 };
 
+// ---------------------------------------------------------------------------
+// The allocation-free render's workspace: a file-scope device array, one copy
+// per device, that the library holds from the first context on a device until
+// the process ends.  Host code never uses the array's name as an address (on
+// the host it is only a stand-in): each device's address is looked up once,
+// with that device current, when the first context on it is created.
+
+constexpr uint64_t STATIC_WS_BYTES = 128ull << 20;      // RGS_STATIC_WORKSPACE_BYTES
+static_assert(STATIC_WS_BYTES == RGS_STATIC_WORKSPACE_BYTES, "static workspace size");
+static __device__ __align__(256) unsigned char scratch[STATIC_WS_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[MAX_DEVICES];
+
+// With `device` current: finds that device's copy of `scratch` (once).
+static rgs_status scratch_setup(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return fail(RGS_E_INVALID, "device %d beyond %d", device, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return RGS_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(RGS_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", device, hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+    return RGS_OK;
+}
+
 extern "C" rgs_status rgs_ctx_create(int32_t device, void* hip_stream, rgs_ctx** out) {
     if (!out) return fail(RGS_E_INVALID, "rgs_ctx_create: out is NULL");
     *out = nullptr;
@@ -227,6 +256,8 @@ extern "C" rgs_status rgs_ctx_create(int32_t device, void* hip_stream, rgs_ctx**
     if (device < 0 || device >= count)
         return fail(RGS_E_INVALID, "device %d outside [0, %d)", device, count);
     HIP_TRY(hipSetDevice(device));
+    rgs_status ss = scratch_setup(device);
+    if (ss != RGS_OK) return ss;
     rgs_ctx* c = new rgs_ctx();
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -835,7 +866,7 @@ rgs_status hook_after_front(void* user) {
 
 static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camera* cam, int32_t W,
                               int32_t H, int32_t path, void* ws, uint64_t ws_bytes, float* out,
-                              rgs_debug_out* dbg, rgs_frame_stats* stats) {
+                              rgs_debug_out* dbg, rgs_frame_stats* stats, bool may_time = true) {
     if (!ctx || !sc) return fail(RGS_E_INVALID, "ctx or scene is NULL");
     FrameLaunch fl;
     rgs_status s = prepare_frame(sc, W, H, path, ws, ws_bytes, &fl);
@@ -857,7 +888,7 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
     }
     hipStream_t st = ctx->stream;
     RenderHooks rh{ctx, nullptr, dbg, &fl, ws, 0};
-    if (ctx->timing) {
+    if (ctx->timing && may_time) {
         s = next_events(ctx, &rh.fe);
         if (s != RGS_OK) return s;
     }
@@ -905,6 +936,22 @@ extern "C" rgs_status rgs_render(rgs_ctx* ctx, const rgs_scene* scene, const rgs
                                  int32_t width, int32_t height, int32_t path, void* workspace,
                                  uint64_t ws_bytes, float* out_chw, rgs_frame_stats* stats) {
     return render_impl(ctx, scene, cam, width, height, path, workspace, ws_bytes, out_chw, nullptr, stats);
+}
+
+extern "C" rgs_status rgs_render_static(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
+                                        int32_t width, int32_t height, int32_t path, float* out_chw,
+                                        rgs_frame_stats* stats) {
+    if (!ctx || !scene) return fail(RGS_E_INVALID, "ctx or scene is NULL");
+    void* ws = (ctx->device >= 0 && ctx->device < MAX_DEVICES) ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!ws) return fail(RGS_E_INVALID, "no static workspace on device %d", ctx->device);
+    int64_t cap = 0;
+    const rgs_status s = rgs_workspace_capacity(scene->n, width, height, path, STATIC_WS_BYTES, &cap);
+    if (s != RGS_OK) return s;
+    if (cap < 1)
+        return fail(RGS_E_INVALID, "a %dx%d frame of %lld Gaussians needs more than the %llu-byte static workspace",
+                    width, height, (long long)scene->n, (unsigned long long)STATIC_WS_BYTES);
+    // no stage events: creating them could allocate
+    return render_impl(ctx, scene, cam, width, height, path, ws, STATIC_WS_BYTES, out_chw, nullptr, stats, false);
 }
 
 extern "C" rgs_status rgs_render_debug(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,
