@@ -301,13 +301,23 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
             bool wave_done = false;     // every pixel of the wave has stopped
             for (uint32_t k0 = 0; k0 < n && !wave_done; k0 += LIST_UNROLL) {
                 if (COUNT) steps += LIST_UNROLL;
+                float P0s[LIST_UNROLL], P1s[LIST_UNROLL];
+                float4 ms[LIST_UNROLL];
+                float2 cs[LIST_UNROLL];
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) {
                     const float4 a = la[k0 + u];
-                    const float4 m = lb[k0 + u];
-                    const float2 c = lc[k0 + u];
-                    const float P0 = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(m.x, y, m.y)))));
-                    const float P1 = P0 + fmaf(a.y, x, fmaf(a.z, y21, m.x));
+                    ms[u] = lb[k0 + u];
+                    cs[u] = lc[k0 + u];
+                    P0s[u] = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(ms[u].x, y, ms[u].y)))));
+                    P1s[u] = P0s[u] + fmaf(a.y, x, fmaf(a.z, y21, ms[u].x));
+                }
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) {
+                    const float4 m = ms[u];
+                    const float2 c = cs[u];
+                    const float P0 = P0s[u];
+                    const float P1 = P1s[u];
                     constexpr float SKIP = EXPM == EXP_HW2 ? -LOG2_255F : -LN255F;
                     const bool pass0 = live0 && P0 >= SKIP;
                     const bool pass1 = live1 && P1 >= SKIP;
