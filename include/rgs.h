@@ -158,6 +158,13 @@ rgs_status rgs_ctx_create(int32_t device, void* hip_stream, rgs_ctx** out);
 void rgs_ctx_destroy(rgs_ctx* ctx);
 /* Re-targets later work to another stream of the same device. */
 rgs_status rgs_ctx_set_stream(rgs_ctx* ctx, void* hip_stream);
+/* Debug flags of a context's renders (0: none).  RGS_DEBUG_SORT_FALLBACK: every
+ * radix tile of the sort takes the digit counts of its predecessors from their
+ * keys, the path a tile takes when a predecessor's counts are not published in
+ * time, so that tests can check it gives the same order.  Errors: INVALID
+ * (NULL, unknown flag). */
+#define RGS_DEBUG_SORT_FALLBACK 1u
+rgs_status rgs_ctx_set_debug(rgs_ctx* ctx, uint32_t flags);
 /* enable != 0: record HIP events around each stage of every render on the
  * context's stream.  Switching it on clears the accumulated times. */
 rgs_status rgs_ctx_set_timing(rgs_ctx* ctx, int32_t enable);

@@ -59,6 +59,7 @@ class _Paths(dict):
 
 
 PATHS = _Paths({"plain": PATH_PLAIN, "fast": PATH_FAST})
+DEBUG_SORT_FALLBACK = 1
 N_STAGES = 5
 STAGE_NAMES = ("frontend", "duplicate", "sort", "ranges", "raster")
 MAX_ENTRIES = (1 << 30) - 1
@@ -174,6 +175,7 @@ SIGNATURES = [
                                      C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(DebugOut),
                                      C.POINTER(FrameStats)]),
     ("rgs_probe_valu", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    ("rgs_ctx_set_debug", C.c_int32, [C.c_void_p, C.c_uint32]),
     ("rgs_render_static", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(CameraC), C.c_int32, C.c_int32,
                                       C.c_int32, C.c_void_p, C.POINTER(FrameStats)]),
     ("rgs_server_create", C.c_int32, [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]),
@@ -315,6 +317,10 @@ class Context:
 
     def set_stream(self, stream: int):
         _check(lib.rgs_ctx_set_stream(self.handle, stream), "rgs_ctx_set_stream")
+
+    def set_debug(self, flags: int):
+        """RGS_DEBUG_* flags for this context's renders (DEBUG_SORT_FALLBACK)."""
+        _check(lib.rgs_ctx_set_debug(self.handle, int(flags)), "rgs_ctx_set_debug")
 
     def set_timing(self, on: bool):
         _check(lib.rgs_ctx_set_timing(self.handle, 1 if on else 0), "rgs_ctx_set_timing")

@@ -34,8 +34,6 @@
 // Grids are sized for the workspace capacity; the entry count is read from
 // the workspace header on the device and tiles beyond it return at once, so
 // no host round trip sits between the front end and the sort.
-#include <cstdlib>
-
 #include "rgs_internal.h"
 
 namespace rgs {
@@ -397,12 +395,10 @@ static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, bool* re
 }
 
 void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes, uint32_t passes,
-                 bool* result_in_b) {
+                 bool force, bool* result_in_b) {
     (void)f;
-    // RGS_SORT_FALLBACK_ONLY=1 (tests): every look-back counts its rows from
-    // the keys instead of reading the published words
-    const char* e = std::getenv("RGS_SORT_FALLBACK_ONLY");
-    const bool force = e && e[0] == '1';
+    // force (a context's RGS_DEBUG_SORT_FALLBACK, for tests): every look-back
+    // counts its rows from the keys instead of reading the published words
     if (key_bytes == 8) sort_typed<uint64_t>(s, ws, passes, result_in_b, force);
     else sort_typed<uint32_t>(s, ws, passes, result_in_b, force);
 }

@@ -213,6 +213,7 @@ struct rgs_ctx {
     int device;
     hipStream_t stream;
     bool timing;
+    uint32_t debug;      // RGS_DEBUG_* flags
     std::vector<FrameEvents> events;
     size_t events_used;
     double stage_ms[RGS_N_STAGES];
@@ -262,6 +263,7 @@ extern "C" rgs_status rgs_ctx_create(int32_t device, void* hip_stream, rgs_ctx**
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->timing = false;
+    c->debug = 0;
     c->events_used = 0;
     std::fill(c->stage_ms, c->stage_ms + RGS_N_STAGES, 0.0);
     c->frames = 0;
@@ -280,6 +282,13 @@ extern "C" void rgs_ctx_destroy(rgs_ctx* ctx) {
 extern "C" rgs_status rgs_ctx_set_stream(rgs_ctx* ctx, void* hip_stream) {
     if (!ctx) return fail(RGS_E_INVALID, "ctx is NULL");
     ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return ok();
+}
+
+extern "C" rgs_status rgs_ctx_set_debug(rgs_ctx* ctx, uint32_t flags) {
+    if (!ctx) return fail(RGS_E_INVALID, "ctx is NULL");
+    if (flags & ~RGS_DEBUG_SORT_FALLBACK) return fail(RGS_E_INVALID, "unknown debug flags 0x%x", flags);
+    ctx->debug = flags;
     return ok();
 }
 
@@ -803,7 +812,7 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
         if (s != RGS_OK) return s;
     }
     bool in_b = false;
-    launch_sort(st, fl.f, w, fl.L.key_bytes, fl.L.passes, &in_b);
+    launch_sort(st, fl.f, w, fl.L.key_bytes, fl.L.passes, fl.sort_fallback, &in_b);
     mark(3);
     launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
     mark(4);
@@ -874,6 +883,7 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
     s = check_camera(cam);
     if (s != RGS_OK) return s;
     if (!out) return fail(RGS_E_INVALID, "output is NULL");
+    fl.sort_fallback = (ctx->debug & RGS_DEBUG_SORT_FALLBACK) != 0;
     HIP_TRY(hipSetDevice(ctx->device));
 
     DebugDev dd{};

@@ -36,6 +36,7 @@ struct FrameLaunch {
     FrameDev f;
     PlainSceneDev plain;
     FastSceneDev fast;
+    bool sort_fallback = false;   // RGS_DEBUG_SORT_FALLBACK of the rendering context
 };
 
 // Checks the scene, resolution, path and workspace and fills fl (no GPU work).

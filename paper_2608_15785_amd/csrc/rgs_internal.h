@@ -497,7 +497,7 @@ void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev&
 void launch_preprocess_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
                             const DebugDev* dbg, uint32_t opts);
 void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes, uint32_t passes,
-                 bool* result_in_b);
+                 bool force_fallback, bool* result_in_b);
 void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                    bool result_in_b);
 void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,

@@ -216,13 +216,18 @@ def _4k_scene():
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
-def test_sort_fallback_counts_match(R, path, monkeypatch):
+def test_sort_fallback_counts_match(R, path):
     """Every radix tile counting its predecessors from their keys (the look-back's fallback,
-    forced) gives the same bit-exact entries, at 1M / 1080p and on the small frame."""
-    monkeypatch.setenv("RGS_SORT_FALLBACK_ONLY", "1")
-    run_parity(R, wl.config_scene("small"), wl.config_camera("small"), path)
-    sc = wl.config_scene("1080p")
-    cam = wl.config_camera("1080p")
-    plan = oracle.frame_plan(cam.width, cam.height)
-    tiles = np.random.default_rng(3).choice(plan.n_tiles, 16, replace=False)
-    run_parity(R, sc, cam, path, tiles=tiles)
+    forced with the context's RGS_DEBUG_SORT_FALLBACK) gives the same bit-exact entries, at
+    1M / 1080p and on the small frame."""
+    from paper_2608_15785_amd import _binding as B
+    R.ctx.set_debug(B.DEBUG_SORT_FALLBACK)
+    try:
+        run_parity(R, wl.config_scene("small"), wl.config_camera("small"), path)
+        sc = wl.config_scene("1080p")
+        cam = wl.config_camera("1080p")
+        plan = oracle.frame_plan(cam.width, cam.height)
+        tiles = np.random.default_rng(3).choice(plan.n_tiles, 16, replace=False)
+        run_parity(R, sc, cam, path, tiles=tiles)
+    finally:
+        R.ctx.set_debug(0)
