@@ -24,12 +24,6 @@
 
 namespace rgs {
 
-__device__ inline uint32_t bwd_xcd_tile(uint32_t block, uint32_t n_tiles) {
-    const uint32_t per = (n_tiles + 7u) / 8u;
-    return (block % 8u) * per + block / 8u;
-}
-
-static uint32_t bwd_xcd_grid(uint32_t n_tiles) { return 8u * ((n_tiles + 7u) / 8u); }
 
 // ---------------------------------------------------------------------------
 // Plain attributes from [n][...] rows.
@@ -131,7 +125,7 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
     __shared__ uint32_t s_band[BWD_BATCH];     // row bands the entry can reach
     __shared__ float4 s_acc4[9 * BWD_ROWS * BWD_BATCH / 4];   // per-row entry sums of the batch
     float* s_acc = reinterpret_cast<float*>(s_acc4);              // [9][BWD_ROWS][BWD_BATCH]
-    const uint32_t tile = bwd_xcd_tile(blockIdx.x, (uint32_t)f.n_tiles);
+    const uint32_t tile = blockIdx.x;      // row-major, as the rasterizers
     if (tile >= (uint32_t)f.n_tiles) return;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
     const uint32_t lane = threadIdx.x;
@@ -270,7 +264,7 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
 
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
                             const float* dimg, float4* partial, bool hw_exp2) {
-    const dim3 grid(bwd_xcd_grid(f.n_tiles)), block(BWD_LANES);
+    const dim3 grid((uint32_t)f.n_tiles), block(BWD_LANES);
     const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
     if (hw_exp2) hipLaunchKernelGGL(k_raster_backward<true>, grid, block, 0, s, f, ws, vals, dimg, partial);
     else hipLaunchKernelGGL(k_raster_backward<false>, grid, block, 0, s, f, ws, vals, dimg, partial);
