@@ -91,10 +91,14 @@ typedef int32_t rgs_status;
  * The image is that of the exact exponential to within the instruction's
  * 1-ulp error.  Not valid with RGS_ABLATE_FASTEXP or RGS_ABLATE_DUALPIXEL.
  * With RGS_PATH_PLAIN (and no other bit) it selects the plain path's training
- * variant: Eq. alpha_computation's exp(p) taken as exp2(p log2 e) by the same
- * instruction in the forward rasterizer and in rgs_render_backward, which
- * therefore recomputes the forward pass's alpha bit for bit; the image
- * definition stays the plain one (exact exponential). */
+ * variant: the plain front end, keys and sort (entries identical to the plain
+ * path's), then the fast path's dual-pixel rasterizer with per-wave culled
+ * lists over the plain path's float32 records: the exponent folded per
+ * Eqs. expand, c0, coeff, dot, dual_pixel in tile-centre coordinates, and
+ * alpha = min(0.99, exp2(P log2 e)) by the hardware exp2.  rgs_render_backward
+ * replays the same lists with the same folding, so it recomputes the forward
+ * pass's alpha bit for bit.  The image definition stays the plain one (exact
+ * exponential, no quantisation); only float32 rounding differs. */
 #define RGS_HW_EXP2          (1 << 16)
 /* Extension of the fast path: four pixels per lane instead of two.  Eq.
  * dual_pixel is applied along the column three times, P(x, y + 1) =
@@ -515,8 +519,9 @@ rgs_status rgs_backward_scratch_size(int64_t n, int32_t width, int32_t height, u
  * chain rule through projection and SH in double precision.  Enqueued on the
  * context's stream after one synchronous read of the workspace header.
  * The frame may be a render of RGS_PATH_PLAIN or of its training variant
- * RGS_PATH_PLAIN | RGS_HW_EXP2; the backward pass takes the exponential the
- * frame took.
+ * RGS_PATH_PLAIN | RGS_HW_EXP2; the backward pass evaluates each pair as the
+ * frame did (for the variant: two waves per tile over the forward's culled
+ * lists, one dual pixel per lane).
  * Errors: INVALID (NULL, bad size, a workspace whose last frame was not a
  * plain render of this scene in its current state, with this camera and
  * size, scratch too small); CAPACITY (that frame overflowed its workspace);

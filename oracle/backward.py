@@ -77,8 +77,14 @@ def blend_tile_adjoint(gauss_ids, X, Y, u, v, conic, opa, color, bg, dC, margins
     relative ``margins`` of its threshold, or when ``force`` [npix] says so.
     ``flip`` = (entry, kind) takes that entry's "skip", "stop" or "clamp"
     decision the other way at every pixel (used one pixel at a time).
+    ``margins`` may carry a fourth value kappa: the skip and clamp margins of
+    each pair then grow by kappa M, M the magnitude sum of the terms of its
+    exponent in coordinates relative to the centre of the pixel's 16x16 tile
+    (the folded form of Sec. IV-B, whose float32 evaluation errs by a multiple
+    of M; the same M as the forward bookkeeping's tile-centre frame).
     """
-    m_skip, m_stop, m_clamp = margins
+    m_skip, m_stop, m_clamp = margins[:3]
+    kappa = margins[3] if len(margins) > 3 else 0.0
     near_list = []
     X = np.asarray(X, np.float64)
     Y = np.asarray(Y, np.float64)
@@ -96,11 +102,20 @@ def blend_tile_adjoint(gauss_ids, X, Y, u, v, conic, opa, color, bg, dC, margins
     flagged = np.zeros(n, bool)
     T = np.ones(n)
     done = np.zeros(n, bool)
+    tcx = np.floor(X / 16.0) * 16.0 + 7.5
+    tcy = np.floor(Y / 16.0) * 16.0 + 7.5
     for j, g in enumerate(ids):
         dx = X - u[g]
         dy = Y - v[g]
         A, B, Cc = conic[g]
         p = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
+        ms, mc = m_skip, m_clamp
+        if kappa > 0.0:
+            ax = np.abs(X - tcx) + np.abs(u[g] - tcx)
+            ay = np.abs(Y - tcy) + np.abs(v[g] - tcy)
+            lno = np.log(opa[g]) if opa[g] > 0.0 else 0.0
+            M = 0.5 * (abs(A) * ax * ax + 2.0 * abs(B) * ax * ay + abs(Cc) * ay * ay) + abs(lno)
+            ms, mc = m_skip + kappa * M, m_clamp + kappa * M
         e = np.exp(p)
         raw = opa[g] * e
         a = np.minimum(ALPHA_MAX, raw)
@@ -119,9 +134,9 @@ def blend_tile_adjoint(gauss_ids, X, Y, u, v, conic, opa, color, bg, dC, margins
             stop_test = ~stop_test
         stop = passes & stop_test
         blend = passes & ~stop
-        n_skip = active & (np.abs(raw - ALPHA_MIN) <= m_skip * ALPHA_MIN)
+        n_skip = active & (np.abs(raw - ALPHA_MIN) <= ms * ALPHA_MIN)
         n_stop = passes & (np.abs(Tn - T_MIN) <= m_stop * T_MIN)
-        n_clamp = passes & (np.abs(raw - ALPHA_MAX) <= m_clamp * ALPHA_MAX)
+        n_clamp = passes & (np.abs(raw - ALPHA_MAX) <= mc * ALPHA_MAX)
         for kind, mask in (("skip", n_skip), ("stop", n_stop), ("clamp", n_clamp)):
             for px in np.nonzero(mask)[0]:
                 near_list.append((int(px), j, kind))

@@ -90,12 +90,16 @@ def _alpha(mode: str, p: np.ndarray, opa: float):
 
 
 def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0.0, 0.0, 0.0),
-               margins=None) -> BlendResult:
+               margins=None, margin_frame=None) -> BlendResult:
     """Blend the sorted Gaussians ``gauss_ids`` at pixel positions X, Y (float arrays).
 
     ``opa`` holds opacity o for the plain mode and ln o for the fast modes.
     ``margins`` = (delta_alpha_rel, delta_P_abs[, kappa, t_round]) turns on
-    decision tracking.
+    decision tracking.  ``margin_frame`` names the coordinates the per-pair
+    magnitude M is taken in: "pixel" (offsets from the pixel, Eq. power as
+    written) or "tile-centre" (the folded form); by default the plain mode's
+    is "pixel" and the fast modes' "tile-centre".  It changes no result, only
+    which decisions are flagged.
     """
     X = np.asarray(X, np.float64)
     Y = np.asarray(Y, np.float64)
@@ -118,6 +122,9 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
     d_alpha0, d_P0 = mg[0], mg[1]
     kappa = mg[2] if len(mg) > 2 else 0.0
     t_round = mg[3] if len(mg) > 3 else 0.0
+    frame = margin_frame or ("pixel" if modes[0] == "plain" else "tile-centre")
+    if frame not in ("pixel", "tile-centre"):
+        raise ValueError(margin_frame)
     # pixel coordinates relative to the centre of their 16x16 tile
     tcx = np.floor(X / 16.0) * 16.0 + 7.5
     tcy = np.floor(Y / 16.0) * 16.0 + 7.5
@@ -130,12 +137,13 @@ def blend_tile(gauss_ids, X, Y, u, v, conic, opa, color, modes=("plain",), bg=(0
         A, B, Cc = conic[g]
         p = -0.5 * (A * dx * dx + Cc * dy * dy) - B * dx * dy
         if kappa > 0.0:
-            if modes[0] == "plain":
+            if frame == "pixel":
                 M = 0.5 * (abs(A) * dx * dx + 2.0 * abs(B) * np.abs(dx * dy) + abs(Cc) * dy * dy)
             else:
                 ax = np.abs(X - tcx) + np.abs(u[g] - tcx)
                 ay = np.abs(Y - tcy) + np.abs(v[g] - tcy)
-                M = 0.5 * (abs(A) * ax * ax + 2.0 * abs(B) * ax * ay + abs(Cc) * ay * ay) + abs(opa[g])
+                lno = opa[g] if modes[0] != "plain" else (np.log(opa[g]) if opa[g] > 0.0 else 0.0)
+                M = 0.5 * (abs(A) * ax * ax + 2.0 * abs(B) * ax * ay + abs(Cc) * ay * ay) + abs(lno)
             d_alpha = d_alpha0 + kappa * M
             d_P = d_P0 + kappa * M
         else:

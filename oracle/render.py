@@ -102,21 +102,22 @@ def _blend_tiles(tiles):
         X, Y = _tile_pixels(int(t), s["plan"])
         r = blend_tile(s["sorted_gauss"][a:b], X.astype(np.float64), Y.astype(np.float64),
                        s["u"], s["v"], s["conic"], s["opa"], s["color"], modes=s["modes"],
-                       bg=s["bg"], margins=s["margins"])
+                       bg=s["bg"], margins=s["margins"], margin_frame=s["margin_frame"])
         out.append((int(t), X, Y, r))
     return out
 
 
 def render(arrays: dict, cam, path: str = "plain", modes=None, tiles=None, margins=None,
            workers: int = 1, blend: bool = True, alpha_extent: bool = True,
-           key64: bool = False, exact_tiles: bool = False) -> OracleFrame:
+           key64: bool = False, exact_tiles: bool = False, margin_frame=None) -> OracleFrame:
     """Render one frame.  ``tiles`` restricts blending to a subset of tiles.
 
     For the fast path, ``alpha_extent=False`` keeps the 3-sigma tile extent
     and ``key64=True`` sorts on the plain path's (tile, float32 depth) key:
     the ablations of the opacity-culling step and of the 32-bit key.
     ``exact_tiles=True`` adds the exact ellipse-tile test to the alpha-ellipse
-    extent (see ``tiles.ellipse_meets_tile``).
+    extent (see ``tiles.ellipse_meets_tile``).  ``margin_frame`` is passed to
+    ``blend.blend_tile``: decision bookkeeping only.
     """
     if path not in ("plain", "fast"):
         raise ValueError(path)
@@ -160,7 +161,8 @@ def render(arrays: dict, cam, path: str = "plain", modes=None, tiles=None, margi
     _SHARED.clear()
     _SHARED.update(plan=plan, ranges=ranges, sorted_gauss=sg, u=proj.u, v=proj.v, conic=proj.conic,
                    opa=arrays["log_opacity"] if fast else arrays["opacity"], color=proj.color,
-                   modes=tuple(modes), bg=np.asarray(cam.bg, np.float64), margins=margins)
+                   modes=tuple(modes), bg=np.asarray(cam.bg, np.float64), margins=margins,
+                   margin_frame=margin_frame)
     if workers > 1 and tiles.size > workers:
         chunks = np.array_split(tiles, workers * 4)
         with mp.get_context("fork").Pool(workers) as pool:

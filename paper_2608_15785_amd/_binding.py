@@ -38,8 +38,9 @@ EXTENSIONS = {"exact-tiles": 1 << 15, "hw-exp2": 1 << 16, "quad-pixel": 1 << 17}
 
 class _Paths(dict):
     """"plain", "fast", "fast/no-<ablation>/.../<extension>", or "plain/hw-exp2" (the
-    plain path's training variant: forward and backward take exp through the hardware
-    exp2) -> the C path argument."""
+    plain path's training variant: the dual-pixel rasterizer with folded coefficients,
+    culled lists and the hardware exp2 over the plain records, in both passes) -> the C
+    path argument."""
 
     def __missing__(self, key):
         parts = str(key).split("/")

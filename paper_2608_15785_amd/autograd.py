@@ -30,7 +30,8 @@ _frames = itertools.count(1)
 
 class GaussianRasterizer:
     """hw_exp2=True renders and differentiates with the plain path's training
-    variant (exp through the hardware exp2 in both passes; "plain/hw-exp2")."""
+    variant ("plain/hw-exp2": the dual-pixel rasterizer with folded coefficients,
+    culled lists and the hardware exp2, in both passes)."""
 
     def __init__(self, renderer: Renderer | None = None, device: int = 0, hw_exp2: bool = False):
         self.R = renderer if renderer is not None else Renderer(device)

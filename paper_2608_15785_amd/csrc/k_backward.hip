@@ -20,7 +20,7 @@
 // grad_gaussian: one thread per Gaussian sums its contiguous partials and
 // applies the chain rule through the EWA projection and the SH colour in
 // double precision; the SH gradients leave through LDS in coalesced rows.
-#include "rgs_internal.h"
+#include "rgs_fold.h"
 
 namespace rgs {
 
@@ -111,10 +111,6 @@ __device__ inline uint32_t band_mask(float v, float A, float B, float C, float o
     return m;
 }
 
-// HW2: the frame was rendered with the hardware exp2 (the training variant of
-// the plain path); exp(p) is recomputed as exp2(p * LOG2E_PLAIN), the forward
-// pass's very bits.
-template <bool HW2>
 __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev ws,
                                                                const uint32_t* __restrict__ vals,
                                                                const float* __restrict__ dimg,
@@ -199,7 +195,7 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
                 if (((band >> k) & 1u) && idx < last[k]) {
                     const float dx = x - a.x, dy = (float)(ly0 + 4 * k) - a.y;
                     const float p = fmaf(-0.5f, fmaf(a.z * dx, dx, m.x * dy * dy), -a.w * dx * dy);
-                    const float e = HW2 ? __builtin_amdgcn_exp2f(p * LOG2E_PLAIN) : expf(p);
+                    const float e = expf(p);
                     const float raw = m.y * e;
                     const float alpha = fminf(ALPHA_MAX, raw);
                     if (alpha >= ALPHA_MIN) {
@@ -263,11 +259,226 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
 }
 
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                            const float* dimg, float4* partial, bool hw_exp2) {
-    const dim3 grid((uint32_t)f.n_tiles), block(BWD_LANES);
+                            const float* dimg, float4* partial) {
     const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
-    if (hw_exp2) hipLaunchKernelGGL(k_raster_backward<true>, grid, block, 0, s, f, ws, vals, dimg, partial);
-    else hipLaunchKernelGGL(k_raster_backward<false>, grid, block, 0, s, f, ws, vals, dimg, partial);
+    hipLaunchKernelGGL(k_raster_backward, dim3((uint32_t)f.n_tiles), dim3(BWD_LANES), 0, s, f, ws, vals, dimg,
+                       partial);
+}
+
+// ---------------------------------------------------------------------------
+// The training variant's backward pass.  Its forward pass is the dual-pixel
+// rasterizer with culled lists over the plain records (k_raster_fast with
+// EXP_HW2 and TRAIN).  Here the tile's list is replayed back to front in the
+// forward's layout: two waves, wave w owning rows 8w .. 8w+7, each lane the
+// dual pixel (x, y), (x, y+1).  Each batch is staged, folded and culled per
+// wave by the forward's own functions (rgs_fold.h), so every exponent, alpha
+// and skip decision is the forward's, bit for bit, and T before a pair is
+// recovered from the forward's final T as in the plain backward.  A pair's
+// exponent P = ln o + p in natural units gives dalpha/dP = alpha, and
+// dP/d(ln o) = 1: the opacity slot of the partials carries dL/d(ln o), which
+// the per-Gaussian pass divides by o.  The nine sums of an entry are reduced
+// over the wave with DPP row operations and kept per wave in LDS; the batch's
+// entries then write their two waves' totals to their emission positions.
+
+constexpr int TB_THREADS = 128;
+constexpr int TB_BATCH = 64;
+
+// Sum over the 64 lanes of the wave of N values, left in lane 63: row sums by
+// row_sums, then row 0's total is added into row 1 and row 2's into row 3 by
+// row_bcast:15, and row 1's (now rows 0 + 1) into row 3 by row_bcast:31.
+template <int N>
+__device__ inline void wave_sums(float (&g)[N]) {
+    row_sums(g);
+#pragma unroll
+    for (int c = 0; c < N; ++c) g[c] += dpp_moved<0x142>(g[c]);    // row_bcast:15
+#pragma unroll
+    for (int c = 0; c < N; ++c) g[c] += dpp_moved<0x143>(g[c]);    // row_bcast:31
+}
+
+// Adds one blended pair's terms at one pixel (tile-centre coordinates px, py
+// for the mean offsets) to g[9] and steps the pixel's state back over the pair.
+__device__ inline void pair_adjoint(float P, float px, float py, const float4& mg, const float4& abc,
+                                    const float (&d)[3], float& T, float (&S)[3], float (&g)[9]) {
+    const float raw = __builtin_amdgcn_exp2f(P);
+    const float alpha = fminf(ALPHA_MAX, raw);
+    const float inv = __builtin_amdgcn_rcpf(1.0f - alpha);
+    const float Tb = T * inv;
+    const float w = alpha * Tb;
+    g[6] = fmaf(w, d[0], g[6]);
+    g[7] = fmaf(w, d[1], g[7]);
+    g[8] = fmaf(w, d[2], g[8]);
+    const float dA = d[0] * (mg.x * Tb - S[0] * inv) + d[1] * (mg.y * Tb - S[1] * inv) +
+                     d[2] * (mg.z * Tb - S[2] * inv);
+    S[0] = fmaf(mg.x, w, S[0]);
+    S[1] = fmaf(mg.y, w, S[1]);
+    S[2] = fmaf(mg.z, w, S[2]);
+    T = Tb;
+    const float dP = raw <= ALPHA_MAX ? dA * raw : 0.0f;     // a clamped alpha is constant
+    g[5] += dP;                                               // dL/d(ln o)
+    const float dx = px - abc.w, dy = py - mg.w;
+    g[0] = fmaf(dP, fmaf(abc.x, dx, abc.y * dy), g[0]);       // dp/du = A dx + B dy
+    g[1] = fmaf(dP, fmaf(abc.z, dy, abc.y * dx), g[1]);       // dp/dv = C dy + B dx
+    g[2] = fmaf(-0.5f * dP, dx * dx, g[2]);
+    g[3] = fmaf(-dP, dx * dy, g[3]);
+    g[4] = fmaf(-0.5f * dP, dy * dy, g[4]);
+}
+
+__global__ __launch_bounds__(TB_THREADS) void k_raster_backward_train(FrameDev f, WsDev ws,
+                                                                      const uint32_t* __restrict__ vals,
+                                                                      const float* __restrict__ dimg,
+                                                                      float4* __restrict__ partial) {
+    // per-wave lists of the batch's folded entries, in depth order
+    __shared__ float4 s_a[2][TB_BATCH];      // C1, C2, C3, C4 (log2 units)
+    __shared__ float4 s_b[2][TB_BATCH];      // C5, C6, entry index, slot in the batch (bits)
+    __shared__ float4 s_m[2][TB_BATCH];      // r, g, b, v (tile-centre)
+    __shared__ float4 s_q[2][TB_BATCH];      // A, B, C, u (tile-centre)
+    __shared__ uint32_t s_cnt[2];
+    __shared__ uint32_t s_wlast[2];
+    __shared__ float s_acc[2][9][TB_BATCH];  // [wave][term][slot]: the wave's sums of an entry
+    const uint32_t tile = blockIdx.x;        // row-major, as the rasterizers
+    if (tile >= (uint32_t)f.n_tiles) return;
+    const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid / 64, lane = tid % 64;
+    const uint32_t lx = tid % TILE, ly = 2 * (tid / TILE);
+    const uint32_t px = tx * TILE + lx, py = ty * TILE + ly;
+    const uint32_t start = ws.ranges[2 * tile], end = ws.ranges[2 * tile + 1];
+    // tile-centre coordinates, as the forward pass
+    const float ox = (float)(tx * TILE) + 7.5f, oy = (float)(ty * TILE) + 7.5f;
+    const float x = (float)lx - 7.5f, y = (float)ly - 7.5f;
+    const float x2 = x * x, xy = x * y, y2 = y * y, y21 = fmaf(2.0f, y, 1.0f);
+    const float y1 = y + 1.0f;
+    const uint64_t plane = (uint64_t)f.width * f.height;
+    const float bg0 = ws.params->cam.bg[0], bg1 = ws.params->cam.bg[1], bg2 = ws.params->cam.bg[2];
+
+    // per pixel: T after the pairs behind, dL/dC, S = colour behind + T_final bg,
+    // and the end of the pairs [start, last) that may have been blended
+    float T[2], d[2][3], S[2][3];
+    uint32_t last[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        T[k] = 1.0f;
+        last[k] = start;
+        d[k][0] = d[k][1] = d[k][2] = 0.0f;
+        if (px < (uint32_t)f.width && py + k < (uint32_t)f.height) {
+            const uint64_t o = (uint64_t)(py + k) * f.width + px;
+            T[k] = ws.t_final[o];
+            const uint32_t word = ws.n_proc[o];
+            last[k] = start + (word & ~N_PROC_STOPPED) - ((word & N_PROC_STOPPED) ? 1u : 0u);
+            d[k][0] = dimg[o];
+            d[k][1] = dimg[plane + o];
+            d[k][2] = dimg[2 * plane + o];
+        }
+        S[k][0] = T[k] * bg0;
+        S[k][1] = T[k] * bg1;
+        S[k][2] = T[k] * bg2;
+    }
+    uint32_t wlast = max(last[0], last[1]);
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) wlast = max(wlast, (uint32_t)__shfl_xor((int)wlast, off));
+    if (lane == 0) s_wlast[wave] = wlast;
+    __syncthreads();
+    const uint32_t tile_last = max(s_wlast[0], s_wlast[1]);
+
+    for (uint32_t b_end = tile_last; b_end > start;) {
+        const uint32_t b0 = b_end - start > (uint32_t)TB_BATCH ? b_end - TB_BATCH : start;
+        const uint32_t cnt = b_end - b0;
+        __syncthreads();                         // the previous batch is fully read
+        for (uint32_t q = tid; q < 2 * 9 * TB_BATCH; q += TB_THREADS) (&s_acc[0][0][0])[q] = 0.0f;
+        // ---- stage (wave 0, one entry per lane): fold, cull, compact per wave ----
+        uint64_t my_pos = 0;
+        if (wave == 0) {
+            bool hit0 = false, hit1 = false;
+            float4 ca = make_float4(0.f, 0.f, 0.f, 0.f), cbv = ca, q4 = ca;
+            float u = 0.0f, v = 0.0f, cb = 0.0f;
+            const uint32_t idx = b0 + lane;
+            if (lane < cnt) {
+                const uint32_t g0 = vals[idx];
+                const uint32_t g = g0 < f.n_gaussians ? g0 : 0u;
+                const Record rec = ws.records[g];
+                fold_record<true>(rec, ox, oy, u, v, ca, cbv);
+                cb = rec.b;
+                q4 = make_float4(rec.A, rec.B, rec.C, u);
+                cull_half_tiles(rec, u, v, hit0, hit1);
+                my_pos = emission_pos(ws, g, tx, ty);
+            }
+            const uint64_t m0 = __ballot(hit0), m1 = __ballot(hit1);
+            const uint64_t lt = lanemask_lt();
+            const float4 b4 = make_float4(cbv.x, cbv.y, __uint_as_float(idx), __uint_as_float(lane));
+            const float4 m4 = make_float4(cbv.z, cbv.w, cb, v);
+            if (hit0) {
+                const uint32_t p = (uint32_t)__popcll(m0 & lt);
+                s_a[0][p] = ca;
+                s_b[0][p] = b4;
+                s_m[0][p] = m4;
+                s_q[0][p] = q4;
+            }
+            if (hit1) {
+                const uint32_t p = (uint32_t)__popcll(m1 & lt);
+                s_a[1][p] = ca;
+                s_b[1][p] = b4;
+                s_m[1][p] = m4;
+                s_q[1][p] = q4;
+            }
+            if (lane == 0) {
+                s_cnt[0] = (uint32_t)__popcll(m0);
+                s_cnt[1] = (uint32_t)__popcll(m1);
+            }
+        }
+        __syncthreads();
+        // ---- this wave's list, back to front ----
+        const uint32_t n = __builtin_amdgcn_readfirstlane(s_cnt[wave]);
+        for (int k = (int)n - 1; k >= 0; --k) {
+            const float4 b4 = s_b[wave][k];
+            const uint32_t idx = __float_as_uint(b4.z);
+            if (idx >= wlast) continue;          // no pixel of the wave got this far
+            const float4 a = s_a[wave][k];
+            float P0, P1;
+            folded_exponents(a, b4.x, b4.y, x, y, x2, xy, y2, y21, P0, P1);
+            const bool pass0 = idx < last[0] && P0 >= -LOG2_255F;
+            const bool pass1 = idx < last[1] && P1 >= -LOG2_255F;
+            if (__ballot(pass0 || pass1) == 0) continue;
+            const float4 mg = s_m[wave][k];
+            const float4 abc = s_q[wave][k];
+            float g[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) g[c] = 0.0f;
+            if (pass0) pair_adjoint(P0, x, y, mg, abc, d[0], T[0], S[0], g);
+            if (pass1) pair_adjoint(P1, x, y1, mg, abc, d[1], T[1], S[1], g);
+            wave_sums(g);
+            if (lane == 63) {
+                const uint32_t slot = __float_as_uint(b4.w);
+#pragma unroll
+                for (int c = 0; c < 9; ++c) s_acc[wave][c][slot] = g[c];
+            }
+        }
+        __syncthreads();
+        if (tid < cnt) {
+            float4* dst = partial + 3ull * my_pos;
+            float sum[9];
+#pragma unroll
+            for (int c = 0; c < 9; ++c) sum[c] = s_acc[0][c][tid] + s_acc[1][c][tid];
+            dst[0] = make_float4(sum[0], sum[1], sum[2], sum[3]);
+            dst[1] = make_float4(sum[4], sum[5], sum[6], sum[7]);
+            dst[2] = make_float4(sum[8], 0.0f, 0.0f, 0.0f);
+        }
+        b_end = b0;
+    }
+    // entries no pixel of the tile reached
+    for (uint32_t idx = tile_last + tid; idx < end; idx += TB_THREADS) {
+        const uint32_t g = vals[idx];
+        float4* dst = partial + 3ull * emission_pos(ws, g < f.n_gaussians ? g : 0u, tx, ty);
+        dst[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        dst[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        dst[2] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+void launch_raster_backward_train(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
+                                  const float* dimg, float4* partial) {
+    const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
+    hipLaunchKernelGGL(k_raster_backward_train, dim3((uint32_t)f.n_tiles), dim3(TB_THREADS), 0, s, f, ws, vals,
+                       dimg, partial);
 }
 
 // ---------------------------------------------------------------------------
@@ -329,7 +540,7 @@ constexpr int GRAD_THREADS = 128;
 // gradients go to dsh (48 floats, LDS), the rest straight to global memory.
 __device__ inline void grad_one(const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
                                 const float4* __restrict__ partial, const GradOut& go, int64_t i,
-                                float* dsh) {
+                                float* dsh, bool lno_opacity) {
     const uint32_t count = ws.counts[i];
     double gs[9];
 #pragma unroll
@@ -347,6 +558,10 @@ __device__ inline void grad_one(const PlainSceneDev& sc, const CamDev& cam, cons
         }
 #pragma unroll
         for (int c = 0; c < 9; ++c) gs[c] = acc[c];
+        if (lno_opacity) {      // dL/do = dL/d(ln o) / o
+            const double o = sc.base[P_OPA * sc.n_pad + i];
+            gs[5] = o > 0.0 ? gs[5] / o : 0.0;
+        }
     }
     if (go.screen) {
 #pragma unroll
@@ -498,13 +713,14 @@ __device__ inline void grad_one(const PlainSceneDev& sc, const CamDev& cam, cons
     for (int k = 0; k < 3; ++k) dm[k] = (float)gmu[k];
 }
 
+template <bool LNO>
 __global__ __launch_bounds__(GRAD_THREADS) void k_grad_gaussian(PlainSceneDev sc, CamDev cam, WsDev ws,
                                                                 const float4* __restrict__ partial,
                                                                 GradOut go) {
     __shared__ float s_sh[GRAD_THREADS * 48];
     const int64_t first = (int64_t)blockIdx.x * GRAD_THREADS;
     const int64_t i = first + threadIdx.x;
-    if (i < sc.n) grad_one(sc, cam, ws, partial, go, i, s_sh + 48 * threadIdx.x);
+    if (i < sc.n) grad_one(sc, cam, ws, partial, go, i, s_sh + 48 * threadIdx.x, LNO);
     __syncthreads();
     const int64_t rows = sc.n - first < GRAD_THREADS ? sc.n - first : GRAD_THREADS;
     float* dst = go.sh + 48 * first;
@@ -512,10 +728,11 @@ __global__ __launch_bounds__(GRAD_THREADS) void k_grad_gaussian(PlainSceneDev sc
 }
 
 void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
-                          const float4* partial, const GradOut& go) {
+                          const float4* partial, const GradOut& go, bool lno_opacity) {
     if (sc.n <= 0) return;
-    hipLaunchKernelGGL(k_grad_gaussian, dim3((uint32_t)((sc.n + GRAD_THREADS - 1) / GRAD_THREADS)),
-                       dim3(GRAD_THREADS), 0, s, sc, cam, ws, partial, go);
+    const dim3 grid((uint32_t)((sc.n + GRAD_THREADS - 1) / GRAD_THREADS)), block(GRAD_THREADS);
+    if (lno_opacity) hipLaunchKernelGGL(k_grad_gaussian<true>, grid, block, 0, s, sc, cam, ws, partial, go);
+    else hipLaunchKernelGGL(k_grad_gaussian<false>, grid, block, 0, s, sc, cam, ws, partial, go);
 }
 
 }  // namespace rgs

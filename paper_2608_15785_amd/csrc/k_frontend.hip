@@ -463,7 +463,11 @@ __device__ inline void finish_block(WsDev& ws, uint32_t vb, uint32_t n_blocks, u
 // ---------------------------------------------------------------------------
 // Plain preprocess: one thread per Gaussian over the FP32 planes.
 
-template <bool DEBUG>
+// TRAIN (the plain path's training variant): the same projection, colour and
+// 3-sigma tile rectangle, but the record holds ln o and the FP16 box of the
+// alpha >= 1/255 ellipse, as the fast path's records do, for the dual-pixel
+// rasterizer with culled lists.  Entries and keys are the plain path's.
+template <bool DEBUG, bool TRAIN>
 __global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, FrameDev f, WsDev ws,
                                                           DebugDev dbg) {
     const CamDev cam = ws.params->cam;
@@ -475,10 +479,11 @@ __global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, Fram
         const uint64_t np = sc.n_pad;
         float mx = P[P_MX * np + i], my = P[P_MY * np + i], mz = P[P_MZ * np + i];
         Projected pr;
+        const double lno = TRAIN ? (double)P[P_LNO * np + i] : 0.0;
         vis = project_gaussian(cam, mx, my, mz, P[P_QW * np + i], P[P_QX * np + i],
                                P[P_QY * np + i], P[P_QZ * np + i], P[P_SX * np + i],
-                               P[P_SY * np + i], P[P_SZ * np + i], false, 0.0,
-                               (double)f.tiles_x, (double)f.tiles_y, pr);
+                               P[P_SY * np + i], P[P_SZ * np + i], TRAIN, lno,
+                               (double)f.tiles_x, (double)f.tiles_y, pr, false);
         float r = 0.f, g = 0.f, b = 0.f;
         if (vis) {
             ShBasis y = view_basis(mx, my, mz, cam);
@@ -491,7 +496,13 @@ __global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, Fram
             r = fmaxf(acc[0], 0.f);
             g = fmaxf(acc[1], 0.f);
             b = fmaxf(acc[2], 0.f);
-            write_record(&ws.records[i], pr, P[P_OPA * np + i], r, g, b, __float_as_uint((float)pr.d));
+            if (TRAIN) {
+                // no pixel reaches alpha >= 1/255 when ln o < -ln 255: an empty box
+                const uint32_t box = LN255 + lno > 0.0 ? half_bits_up(pr.ax) | (half_bits_up(pr.ay) << 16) : 0u;
+                write_record(&ws.records[i], pr, (float)lno, r, g, b, box);
+            } else {
+                write_record(&ws.records[i], pr, P[P_OPA * np + i], r, g, b, __float_as_uint((float)pr.d));
+            }
             uint64_t rc = pack_rect(pr);
             ws.rects[i] = rc;
             ws.depths[i] = (float)pr.d;
@@ -504,13 +515,13 @@ __global__ __launch_bounds__(256) void k_preprocess_plain(PlainSceneDev sc, Fram
 }
 
 void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const FrameDev& f,
-                             const WsDev& ws, const DebugDev* dbg) {
-    uint32_t blocks = (uint32_t)((sc.n + 255) / 256);
-    if (dbg)
-        hipLaunchKernelGGL(k_preprocess_plain<true>, dim3(blocks), dim3(256), 0, s, sc, f, ws, *dbg);
-    else
-        hipLaunchKernelGGL(k_preprocess_plain<false>, dim3(blocks), dim3(256), 0, s, sc, f, ws,
-                           DebugDev{});
+                             const WsDev& ws, const DebugDev* dbg, bool train) {
+    const uint32_t blocks = (uint32_t)((sc.n + 255) / 256);
+    const DebugDev d = dbg ? *dbg : DebugDev{};
+    if (dbg && train) hipLaunchKernelGGL((k_preprocess_plain<true, true>), dim3(blocks), dim3(256), 0, s, sc, f, ws, d);
+    else if (dbg) hipLaunchKernelGGL((k_preprocess_plain<true, false>), dim3(blocks), dim3(256), 0, s, sc, f, ws, d);
+    else if (train) hipLaunchKernelGGL((k_preprocess_plain<false, true>), dim3(blocks), dim3(256), 0, s, sc, f, ws, d);
+    else hipLaunchKernelGGL((k_preprocess_plain<false, false>), dim3(blocks), dim3(256), 0, s, sc, f, ws, d);
 }
 
 // ---------------------------------------------------------------------------

@@ -34,6 +34,13 @@
 //     float32 error of P; each wave blends only its survivors, in depth order.
 //     A culled pair would have failed the skip test, so no result changes.
 //
+// `raster_train` is the training variant of the plain path: the dual-pixel
+// rasterizer with the culled lists over the plain path's float32 records
+// (which then carry ln o and the box), with log2 e folded into C1..C6 and
+// alpha = min(0.99, exp2(P)) from the hardware exp2.  It also leaves each
+// pixel's final T and visited-pair count; the backward pass replays the same
+// lists with the same folding, so it recomputes every alpha bit for bit.
+//
 // Workgroup b renders tile b, in row-major order.  Workgroups are dispatched
 // to the 8 XCDs round-robin, so neighbouring tiles run on different XCDs at
 // about the same time: the tiles' uneven work spreads evenly over the XCDs,
@@ -41,7 +48,7 @@
 // Infinity Cache while they are still there.  Giving each XCD one contiguous
 // band of tile rows (for its L2) was 4 % slower at 1M / 1080p, and bands of two
 // rows dealt out round-robin 8 % slower.
-#include "rgs_internal.h"
+#include "rgs_fold.h"
 
 namespace rgs {
 
@@ -52,10 +59,7 @@ constexpr float FEXP_B = 1064970048.0f;
 
 // ---------------------------------------------------------------------------
 
-// HW2: alpha = min(0.99, o exp2(p log2 e)) by the hardware exp2 instruction
-// instead of expf (the training variant; its backward pass takes the same
-// bits, see k_backward.hip).
-template <bool COUNT, bool HW2>
+template <bool COUNT>
 __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
                                                       const uint32_t* __restrict__ vals) {
     __shared__ float4 s_a[256];   // u, v (tile-local), A, B
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
                 const float4 m = s_b[j];
                 const float dx = x - a.x, dy = y - a.y;
                 const float p = fmaf(-0.5f, fmaf(a.z * dx, dx, m.x * dy * dy), -a.w * dx * dy);
-                const float e = HW2 ? __builtin_amdgcn_exp2f(p * LOG2E_PLAIN) : expf(p);
+                const float e = expf(p);
                 const float alpha = fminf(ALPHA_MAX, m.y * e);
                 if (alpha < ALPHA_MIN) continue;
                 const float Tn = T * (1.0f - alpha);
@@ -127,17 +131,11 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
     }
 }
 
-void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                         bool count, bool hw_exp2) {
+void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count) {
     const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
     const dim3 grid((uint32_t)f.n_tiles), block(256);
-    if (hw_exp2) {
-        if (count) hipLaunchKernelGGL((k_raster_plain<true, true>), grid, block, 0, s, f, ws, vals);
-        else hipLaunchKernelGGL((k_raster_plain<false, true>), grid, block, 0, s, f, ws, vals);
-    } else {
-        if (count) hipLaunchKernelGGL((k_raster_plain<true, false>), grid, block, 0, s, f, ws, vals);
-        else hipLaunchKernelGGL((k_raster_plain<false, false>), grid, block, 0, s, f, ws, vals);
-    }
+    if (count) hipLaunchKernelGGL(k_raster_plain<true>, grid, block, 0, s, f, ws, vals);
+    else hipLaunchKernelGGL(k_raster_plain<false>, grid, block, 0, s, f, ws, vals);
 }
 
 // ---------------------------------------------------------------------------
@@ -146,46 +144,18 @@ constexpr int FAST_THREADS = 128;    // 2 waves: wave w owns tile rows 8w .. 8w+
 constexpr int FAST_BATCH = FAST_THREADS;
 constexpr int LIST_UNROLL = 4;
 constexpr int LIST_CAP = FAST_BATCH + LIST_UNROLL;
-// Margin added to the alpha-ellipse half-extents before culling a Gaussian for
-// a wave: float32 rounding of the folded exponent near the 1/255 threshold
-// must never hide a pair that the exact test would keep.
-constexpr float BOX_MARGIN_REL = 1.0e-3f;
-constexpr float BOX_MARGIN_ABS = 0.05f;
-// The same safety margin on the quadratic form q = A dx^2 + 2 B dx dy + C dy^2
-// (P = ln o - q / 2): a band is kept when min q <= tau (1 + 1e-3) + 0.02.
-constexpr float Q_MARGIN_REL = 1.0e-3f;
-constexpr float Q_MARGIN_ABS = 0.02f;
-
-// Smallest q over the rectangle [-7.5, 7.5] x [y0, y1] (tile-centre
-// coordinates) for a Gaussian at (u, v) with a positive-definite conic: 0 when
-// the mean is inside, else the least of the four edge minima (on an edge q is
-// a parabola in the free coordinate, minimised at a clamped closed form).
-__device__ inline float conic_rect_min(float u, float v, float A, float B, float C, float iA, float iC,
-                                       float y0, float y1) {
-    if (u >= -7.5f && u <= 7.5f && v >= y0 && v <= y1) return 0.0f;
-    float best = 3.0e38f;
-#pragma unroll
-    for (int e = 0; e < 2; ++e) {
-        const float dx = (e ? 7.5f : -7.5f) - u;                 // vertical edge x = -7.5 or 7.5
-        const float dy = fminf(y1, fmaxf(y0, fmaf(-B * dx, iC, v))) - v;
-        best = fminf(best, fmaf(A * dx, dx, fmaf(2.0f * B * dx, dy, C * dy * dy)));
-        const float ey = (e ? y1 : y0) - v;                       // horizontal edge y = y0 or y1
-        const float ex = fminf(7.5f, fmaxf(-7.5f, fmaf(-B * ey, iA, u))) - u;
-        best = fminf(best, fmaf(A * ex, ex, fmaf(2.0f * B * ex, ey, C * ey * ey)));
-    }
-    return best;
-}
-
 // How the fast rasterizer takes alpha from the folded exponent P.
 enum ExpMode : int {
     EXP_BITS = 0,   // Eq. fma_exp: the bit-level exponential (the paper's fast path)
     EXP_LIBM = 1,   // min(0.99, expf(P)): the exponential's ablation
     EXP_HW2 = 2,    // min(0.99, v_exp_f32(P log2 e)) with log2 e folded into C1..C6
 };
-constexpr float LOG2E_F = 1.4426950408889634f;
-constexpr float LOG2_255F = 7.994353436858858f;     // ln 255 * log2 e
 
-template <bool COUNT, int EXPM>
+// TRAIN: the training variant of the plain path (EXP_HW2 over the plain
+// path's records, which then hold ln o and the alpha-ellipse box): every
+// render also leaves each pixel's final T and visited-pair count for the
+// backward pass.
+template <bool COUNT, int EXPM, bool TRAIN = false>
 __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev ws,
                                                               const uint32_t* __restrict__ vals) {
     constexpr bool EXACT = EXPM == EXP_LIBM;
@@ -226,35 +196,10 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
         if (idx < end) {
             const uint32_t g = vals[idx];
             const Record rec = ws.records[g < f.n_gaussians ? g : 0u];
-            const float u = (rec.u_hi - ox) + rec.u_lo;
-            const float v = (rec.v_hi - oy) + rec.v_lo;
-            const float A = rec.A, B = rec.B, C = rec.C;
-            const float C0 = fmaf(A * u, u, fmaf(2.0f * B * u, v, C * v * v));
-            ca = make_float4(-0.5f * A, -B, -0.5f * C, fmaf(A, u, B * v));
-            cbv = make_float4(fmaf(C, v, B * u), fmaf(-0.5f, C0, rec.opa), rec.r, rec.g);
+            float u, v;
+            fold_record<EXPM == EXP_HW2>(rec, ox, oy, u, v, ca, cbv);
             cb = rec.b;
-            if (EXPM == EXP_HW2) {       // P log2 e directly: alpha = exp2 of it
-                ca = make_float4(ca.x * LOG2E_F, ca.y * LOG2E_F, ca.z * LOG2E_F, ca.w * LOG2E_F);
-                cbv.x *= LOG2E_F;
-                cbv.y *= LOG2E_F;
-            }
-            // the box |x - u| <= hx, |y - v| <= hy holds every pixel with
-            // P >= -ln 255 (half-extents from the front end, rounded up, then
-            // widened); a half-tile outside it has no pair that passes the skip
-            // test.  Comparisons are phrased so that a NaN keeps the Gaussian.
-            const float hx = fmaf(half_lo(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
-            const float hy = fmaf(half_hi(rec.extra), 1.0f + BOX_MARGIN_REL, BOX_MARGIN_ABS);
-            const bool x_out = u - hx > 7.5f || u + hx < -7.5f;
-            hit0 = !(x_out || v - hy > -0.5f || v + hy < -7.5f);
-            hit1 = !(x_out || v - hy > 7.5f || v + hy < 0.5f);
-            // then the ellipse itself: the half-tile must hold a point with
-            // q <= tau = 2 (ln 255 + ln o), up to the margin
-            const float qlim = fmaf(2.0f * (LN255F + rec.opa), 1.0f + Q_MARGIN_REL, Q_MARGIN_ABS);
-            // the reciprocals only place the nearest point of an edge, where q is
-            // then evaluated exactly; an error of an ulp moves q by ~C (1e-6 px)^2
-            const float iA = __builtin_amdgcn_rcpf(A), iC = __builtin_amdgcn_rcpf(C);
-            if (hit0) hit0 = !(conic_rect_min(u, v, A, B, C, iA, iC, -7.5f, -0.5f) > qlim);
-            if (hit1) hit1 = !(conic_rect_min(u, v, A, B, C, iA, iC, 0.5f, 7.5f) > qlim);
+            cull_half_tiles(rec, u, v, hit0, hit1);
         }
         const uint64_t m0 = __ballot(hit0), m1 = __ballot(hit1);
         const uint64_t lt = lanemask_lt();
@@ -306,8 +251,7 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
                     const float4 a = la[k0 + u];
                     ms[u] = lb[k0 + u];
                     cs[u] = lc[k0 + u];
-                    P0s[u] = fmaf(a.x, x2, fmaf(a.y, xy, fmaf(a.z, y2, fmaf(a.w, x, fmaf(ms[u].x, y, ms[u].y)))));
-                    P1s[u] = P0s[u] + fmaf(a.y, x, fmaf(a.z, y21, ms[u].x));
+                    folded_exponents(a, ms[u].x, ms[u].y, x, y, x2, xy, y2, y21, P0s[u], P1s[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) {
@@ -374,22 +318,22 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
         out[o] = fmaf(T0, bg0, r0);
         out[plane + o] = fmaf(T0, bg1, g0);
         out[2 * plane + o] = fmaf(T0, bg2, b0);
-        if (COUNT) {                // the debug render's per-pixel outputs
+        if (COUNT || TRAIN) {       // the debug render's and the training variant's per-pixel outputs
             ws.t_final[o] = T0;
             ws.n_proc[o] = stop0 != 0xffffffffu ? (stop0 - start + 1) | N_PROC_STOPPED : end - start;
-            ws.n_blend[o] = nbl0;
         }
+        if (COUNT) ws.n_blend[o] = nbl0;
     }
     if (in1) {
         const uint64_t o = (uint64_t)(py + 1) * f.width + px;
         out[o] = fmaf(T1, bg0, r1);
         out[plane + o] = fmaf(T1, bg1, g1);
         out[2 * plane + o] = fmaf(T1, bg2, b1);
-        if (COUNT) {                // the debug render's per-pixel outputs
+        if (COUNT || TRAIN) {       // the debug render's and the training variant's per-pixel outputs
             ws.t_final[o] = T1;
             ws.n_proc[o] = stop1 != 0xffffffffu ? (stop1 - start + 1) | N_PROC_STOPPED : end - start;
-            ws.n_blend[o] = nbl1;
         }
+        if (COUNT) ws.n_blend[o] = nbl1;
     }
 }
 
@@ -634,14 +578,14 @@ __global__ __launch_bounds__(FastShape<PIX>::THREADS) void k_raster_fast_px(Fram
     }
 }
 
-template <int EXPM>
+template <int EXPM, bool TRAIN = false>
 static void launch_fast_dual(hipStream_t s, const FrameDev& f, const WsDev& ws, const uint32_t* vals, bool count) {
     if (count)
-        hipLaunchKernelGGL((k_raster_fast<true, EXPM>), dim3((uint32_t)f.n_tiles), dim3(FAST_THREADS), 0, s, f, ws,
-                           vals);
+        hipLaunchKernelGGL((k_raster_fast<true, EXPM, TRAIN>), dim3((uint32_t)f.n_tiles), dim3(FAST_THREADS), 0, s,
+                           f, ws, vals);
     else
-        hipLaunchKernelGGL((k_raster_fast<false, EXPM>), dim3((uint32_t)f.n_tiles), dim3(FAST_THREADS), 0, s, f, ws,
-                           vals);
+        hipLaunchKernelGGL((k_raster_fast<false, EXPM, TRAIN>), dim3((uint32_t)f.n_tiles), dim3(FAST_THREADS), 0, s,
+                           f, ws, vals);
 }
 
 template <int EXPM, int PIX>
@@ -663,6 +607,10 @@ void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool 
     else if (exact && !single) launch_fast_dual<EXP_LIBM>(s, f, ws, vals, count);
     else if (!exact && single) launch_fast_px<EXP_BITS, 1>(s, f, ws, vals, count);
     else launch_fast_px<EXP_LIBM, 1>(s, f, ws, vals, count);
+}
+
+void launch_raster_train(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count) {
+    launch_fast_dual<EXP_HW2, true>(s, f, ws, result_in_b ? ws.vals_b : ws.vals_a, count);
 }
 
 }  // namespace rgs

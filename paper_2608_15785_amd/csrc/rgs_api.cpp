@@ -793,7 +793,7 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
     mark(0);
     launch_reset(st, reset_args(w, fl.L.zero_end, fl.f, fl.path_word, prm));
     if (fl.path == RGS_PATH_PLAIN) {
-        launch_preprocess_plain(st, fl.plain, fl.f, w, dbg);
+        launch_preprocess_plain(st, fl.plain, fl.f, w, dbg, (fl.opts & OPT_HW_EXP2) != 0);
         mark(1);
         launch_duplicate(st, fl.n, fl.f, w, fl.L.fe_blocks, fl.L.fe_per, fl.L.key_bytes);
         mark(2);
@@ -816,7 +816,8 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
     mark(3);
     launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
     mark(4);
-    if (fl.path == RGS_PATH_PLAIN) launch_raster_plain(st, fl.f, w, in_b, count, (fl.opts & OPT_HW_EXP2) != 0);
+    if (fl.path == RGS_PATH_PLAIN && (fl.opts & OPT_HW_EXP2)) launch_raster_train(st, fl.f, w, in_b, count);
+    else if (fl.path == RGS_PATH_PLAIN) launch_raster_plain(st, fl.f, w, in_b, count);
     else launch_raster_fast(st, fl.f, w, in_b, count, fl.opts);
     mark(5);
     if (status) launch_export_status(st, w, status);
@@ -1050,9 +1051,11 @@ extern "C" rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, 
     if (s != RGS_OK) return s;
     const bool in_b = (fl.L.passes % 2) == 1;
     float4* partial = static_cast<float4*>(grads->scratch);
-    launch_raster_backward(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial, (h.path & RGS_HW_EXP2) != 0);
+    const bool train = (h.path & RGS_HW_EXP2) != 0;
+    if (train) launch_raster_backward_train(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial);
+    else launch_raster_backward(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial);
     GradOut go{grads->d_means, grads->d_scales, grads->d_quats, grads->d_opacity, grads->d_sh, grads->d_screen};
-    launch_grad_gaussian(ctx->stream, fl.plain, cam_dev(cam), fl.w, partial, go);
+    launch_grad_gaussian(ctx->stream, fl.plain, cam_dev(cam), fl.w, partial, go, train);
     HIP_TRY(hipGetLastError());
     return ok();
 }

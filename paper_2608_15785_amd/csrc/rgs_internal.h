@@ -24,9 +24,6 @@ constexpr double J_CLAMP = 1.3;      // Jacobian clamp factor on t_x/t_z, t_y/t_
 constexpr float ALPHA_MAX = 0.99f;   // Eq. opacity_clamped
 constexpr float ALPHA_MIN = 1.0f / 255.0f;
 constexpr float T_MIN = 1e-4f;       // stop blending a pixel below this transmittance
-// log2(e) rounded to float32: the plain path's hardware-exp2 variant takes
-// exp(p) as exp2(p * LOG2E_PLAIN) in its forward and backward rasterizers alike.
-constexpr float LOG2E_PLAIN = 1.4426950408889634f;
 
 constexpr int FE_THREADS = 1024;     // threads per front-end / duplication block
 // Gaussians per thread (block-strided).  Four makes blocks of 4096 Gaussians:
@@ -148,10 +145,11 @@ struct FrameDev {
 // coordinates keep float64 accuracy at 4K.
 struct __align__(16) Record {
     float u_hi, u_lo, v_hi, v_lo;
-    float A, B, C, opa;       // conic; opacity (plain) or ln o (fast)
+    float A, B, C, opa;       // conic; opacity (plain) or ln o (fast, and the plain
+                              // path's training variant)
     float r, g, b;            // colour
-    uint32_t extra;           // plain: float32 depth bits; fast: FP16 pair (hx, hy) of the
-                              // alpha-ellipse box half-extents, rounded up
+    uint32_t extra;           // plain: float32 depth bits; fast and training variant: FP16
+                              // pair (hx, hy) of the alpha-ellipse box half-extents, rounded up
 };
 
 __host__ __device__ inline float half_lo(uint32_t w) {
@@ -489,7 +487,7 @@ void launch_reset(hipStream_t s, const ResetArgs& a);
 const void* reset_kernel();          // host handle of the reset kernel (graph node lookup)
 void launch_export_status(hipStream_t s, const WsDev& ws, FrameStatus* dst);
 void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const FrameDev& f,
-                             const WsDev& ws, const DebugDev* dbg);
+                             const WsDev& ws, const DebugDev* dbg, bool train);
 void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws, uint32_t fe_blocks, uint32_t fe_per,
                       uint32_t key_bytes);
 void launch_frontend_fast(hipStream_t s, const FastSceneDev& sc, const FrameDev& f, const WsDev& ws,
@@ -500,8 +498,8 @@ void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key
                  bool force_fallback, bool* result_in_b);
 void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key_bytes,
                    bool result_in_b);
-void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                         bool count, bool hw_exp2);
+void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count);
+void launch_raster_train(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count);
 void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count,
                         uint32_t opts);
 void launch_widen_keys(hipStream_t s, const uint32_t* in, uint64_t* out, uint64_t n);
@@ -524,8 +522,12 @@ struct GradOut {
 void launch_update_plain(hipStream_t s, float* planes, uint64_t n_pad, int64_t n, const float* means,
                          const float* scales, const float* quats, const float* opacity, const float* sh);
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                            const float* dimg, float4* partial, bool hw_exp2);
+                            const float* dimg, float4* partial);
+void launch_raster_backward_train(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
+                                  const float* dimg, float4* partial);
+// lno_opacity: the partials' opacity slot holds dL/d(ln o) (the training
+// variant's), converted to dL/do here.
 void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
-                          const float4* partial, const GradOut& go);
+                          const float4* partial, const GradOut& go, bool lno_opacity);
 
 }  // namespace rgs

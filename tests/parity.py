@@ -45,6 +45,10 @@ FAST_FLAG_CAP = (0.015, 0.05)
 PLAIN_MARGINS = (1e-4, 0.0)      # relative alpha uncertainty of float32 + expf
 # relative alpha, absolute P, per-pair scale of the terms' magnitudes, float32 rounding of T
 FAST_MARGINS = (1e-5, 1e-6, 4e-6, 2.0 ** -22)
+# the plain path's training variant: the plain definition (exact exponential,
+# alpha = min(0.99, o e^p)) evaluated in the folded form, so the fast path's
+# per-pair margins, with M taken in tile-centre coordinates
+TRAIN_MARGINS = (1e-5, 0.0, 4e-6, 2.0 ** -22)
 
 _PREPARED = {}
 
@@ -65,6 +69,9 @@ def oracle_frame(scene, cam, path, tiles=None, workers=8):
     if path == "plain":
         return oracle.render(_prepared(scene, "plain"), cam, "plain", tiles=tiles, margins=PLAIN_MARGINS,
                              workers=workers)
+    if path == "plain/hw-exp2":
+        return oracle.render(_prepared(scene, "plain"), cam, "plain", tiles=tiles, margins=TRAIN_MARGINS,
+                             margin_frame="tile-centre", workers=workers)
     return oracle.render(_prepared(scene, "fast"), cam, "fast", modes=("fast-def", "fast-exact"), tiles=tiles,
                          margins=FAST_MARGINS, workers=workers)
 

@@ -44,7 +44,12 @@ def R():
     return rgs.Renderer(0)
 
 
-PATHS = ["plain", "plain/hw-exp2"]      # the plain path and its training variant (hardware exp2)
+PATHS = ["plain", "plain/hw-exp2"]      # the plain path and its training variant
+# The training variant evaluates each exponent in the folded form of Sec. IV-B
+# (tile-centre coordinates, float32), whose error scales with the magnitude sum
+# M of its terms: its skip and clamp margins grow by 4e-6 M per pair, as the
+# fast path's forward bookkeeping does.
+MARGINS = {"plain": OB.DECISION_MARGINS, "plain/hw-exp2": OB.DECISION_MARGINS + (4e-6,)}
 
 
 def gpu_backward(R, scene, cam, dimg, path="plain"):
@@ -106,7 +111,8 @@ def test_small_scene_all_tiles(R, W, H, path):
     dimg = rng.normal(0.0, 1.0, (3, H, W)).astype(np.float32)
     _log(f"[bwd] small scene n={sc.n} {W}x{H} {path}")
     g = gpu_backward(R, sc, cam, dimg, path)
-    adj = OB.render_adjoint(oracle.prepare_plain(sc), cam, dimg.astype(np.float64), decisions=g["decisions"])
+    adj = OB.render_adjoint(oracle.prepare_plain(sc), cam, dimg.astype(np.float64), margins=MARGINS[path],
+                            decisions=g["decisions"])
     compare(g, adj, n_expect_min=1000)
 
 
@@ -154,7 +160,7 @@ def test_training_l1_loss_sampled_tiles(R, path):
     g = gpu_backward(R, sc, cam, dimg, path)
     assert np.array_equal(g["image"], img)
     adj = OB.render_adjoint(oracle.prepare_plain(sc), cam, dimg.astype(np.float64), tiles=tiles,
-                            decisions=g["decisions"])
+                            margins=MARGINS[path], decisions=g["decisions"])
     compare(g, adj, n_expect_min=2000)
 
 

@@ -2,8 +2,10 @@
 (needs an MI355X).  RGS_HW_EXP2 takes alpha = min(0.99, exp2(P log2 e)) from
 the hardware exp2 instruction: its image is the exact-exponential oracle's, to
 the same 2e-3 bar as the exponential's ablation; front end and entries are the
-fast path's, bit-exact.  With the plain path (its training variant) the image
-is the plain oracle's, to the plain path's bar, and every key bit-exact."""
+fast path's, bit-exact.  With the plain path (its training variant: the
+dual-pixel rasterizer with folded coefficients and culled lists over the plain
+path's records) the image is the plain oracle's, to the plain path's bar, with
+decision margins for the folded float32 arithmetic, and every key bit-exact."""
 from __future__ import annotations
 
 import sys
@@ -88,7 +90,7 @@ def test_plain_hw_exp2_against_the_plain_oracle(R, case):
     ds = R.upload(sc, ("plain",))
     g = R.render_debug(ds, cam, "plain/hw-exp2")
     ds.release()
-    fr = oracle_frame(sc, cam, "plain", tiles=tiles)
+    fr = oracle_frame(sc, cam, "plain/hw-exp2", tiles=tiles)
     compare_front_end(g, fr)
     compare_entries(g, fr)
     rep = compare_image(g["image"], fr, "plain")

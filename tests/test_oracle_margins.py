@@ -9,6 +9,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 
@@ -138,13 +139,16 @@ def _fma32(a, b, c):
     return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
 
 
-def test_float32_folded_exponent_stays_within_the_per_pair_margin():
+@pytest.mark.parametrize("log2", [False, True])
+def test_float32_folded_exponent_stays_within_the_per_pair_margin(log2):
     """The per-pair margin kappa M on P must cover a float32 evaluation of the folded
     exponent.  This is a float32 replica of that evaluation, in the order the fast
     rasterizer takes it (Eqs. expand, c0, coeff, dot in tile-centre coordinates, then
     Eq. dual_pixel's step to the next row), over random conics (A, C up to 1/0.3, the
     dilated minimum), ln o down to -ln 255, means up to 60 px from the tile centre and
-    every pixel offset of a tile.  Its error against float64 stays below kappa M / 8."""
+    every pixel offset of a tile.  Its error against float64 stays below kappa M / 8.
+    With ``log2`` the coefficients are scaled by log2 e after folding (the hardware-exp2
+    variants, the plain path's training variant among them), and P log2 e is compared."""
     rng = np.random.default_rng(7)
     f = np.float32
     n = 400_000
@@ -169,6 +173,11 @@ def test_float32_folded_exponent_stays_within_the_per_pair_margin():
     C4 = _fma32(A32, u32, B32 * v32)
     C5 = _fma32(C32, v32, B32 * u32)
     C6 = _fma32(np.full(n, -0.5, f), C0, L32)
+    if log2:
+        l2e = f(1.4426950408889634)
+        C1, C2, C3, C4, C5, C6 = (c * l2e for c in (C1, C2, C3, C4, C5, C6))
+        P64 = P64 * (1.0 / math.log(2.0))
+        M = M * (1.0 / math.log(2.0))
     x32, y32 = x.astype(f), y0.astype(f)
     x2, xy, y2 = x32 * x32, x32 * y32, y32 * y32
     y21 = _fma32(np.full(n, 2, f), y32, np.ones(n, f))
@@ -177,6 +186,39 @@ def test_float32_folded_exponent_stays_within_the_per_pair_margin():
     P32 = np.where(second, P1, P0).astype(np.float64)
     ratio = np.abs(P32 - P64) / M
     kappa = 4e-6                                     # the fast path's per-pair margin scale
-    assert ratio.max() < kappa / 8, ratio.max()          # measured 3.6e-7
+    assert ratio.max() < kappa / 8, ratio.max()          # measured 3.6e-7, 4.0e-7 with log2
     # and the margin is not vacuous: the error is a sizeable multiple of one rounding of M
     assert ratio.max() > 2.0 ** -24
+
+
+def test_plain_definition_with_tile_centre_margins():
+    """The plain path's training variant evaluates the plain definition in the folded
+    form: margin_frame="tile-centre" takes M in tile-centre coordinates for the plain
+    mode too (with |ln o| for its opacity term).  A pair just above 1/255 at the tile
+    corner (M = 225 + |ln o|) is flagged that way and not with the pixel frame (M = 0 for
+    a Gaussian on the pixel)."""
+    a = (1.0 / 255.0) * (1.0 + 5e-4)
+    u, v, c, o, col = seq([0.5, a], [0.3, 2.0])
+    mg = (1e-5, 0.0, 4e-6, 0.0)
+    r = oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, margins=mg, margin_frame="tile-centre")
+    assert r.flagged[0] and r.slack[0] > 0
+    r = oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, margins=mg)
+    assert not r.flagged[0]
+    with pytest.raises(ValueError):
+        oracle.blend_tile(np.arange(2), X, Y, u, v, c, o, col, margins=mg, margin_frame="pixels")
+
+
+def test_adjoint_per_pair_margin():
+    """The adjoint's skip margin grows by kappa M per pair (tile-centre frame) when its
+    margins carry a fourth value; the image-space sums are unchanged."""
+    from oracle import backward as OB
+    a = (1.0 / 255.0) * (1.0 + 5e-4)
+    u, v, c, o, col = seq([0.5, a], [0.3, 2.0])
+    dC = np.ones((3, 1))
+    bg = (0.1, 0.2, 0.3)
+    plain = OB.blend_tile_adjoint(np.arange(2), X, Y, u, v, c, o, col, bg, dC)
+    folded = OB.blend_tile_adjoint(np.arange(2), X, Y, u, v, c, o, col, bg, dC,
+                                   margins=OB.DECISION_MARGINS + (4e-6,))
+    assert not plain.flagged[0]
+    assert folded.flagged[0] and (0, 1, "skip") in folded.near
+    assert np.array_equal(plain.grad, folded.grad)
