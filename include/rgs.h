@@ -264,7 +264,9 @@ typedef struct {
     int32_t path;
     int32_t passes;           /* radix passes run                                         */
     int32_t overflow;         /* n_entries > capacity                                     */
-    int32_t device_error;     /* a bounded wait in a kernel gave up                        */
+    int32_t device_error;     /* bits 0, 2: a bounded wait in a kernel gave up, or a sorted
+                                 key named no tile; bit 3: a backward pass found another
+                                 frame in the workspace than its caller's                  */
     int64_t list_steps;       /* fast path, counting renders (rgs_render_debug) only: list
                                  entries the rasterizer's waves evaluated, each for all of
                                  the wave's pixels (64 lanes x pixels per lane); else 0      */
@@ -517,7 +519,15 @@ rgs_status rgs_backward_scratch_size(int64_t n, int32_t width, int32_t height, u
  * tile writes one partial per sorted entry (no atomics); one thread per
  * Gaussian then gathers its entries (one per covered tile) and applies the
  * chain rule through projection and SH in double precision.  Enqueued on the
- * context's stream after one synchronous read of the workspace header.
+ * context's stream.  The checks below need the frame's outcome: when the
+ * workspace's last frame is the one this context rendered last into it (the
+ * usual training loop), the outcome comes from a stamp the frame's last kernel
+ * wrote to host-visible memory, and the call only waits for that frame to
+ * finish (not for later work on the stream); otherwise it reads the workspace
+ * header and frame parameters synchronously.  In the first case the kernels
+ * still compare the workspace's frame with the caller's: if another context
+ * has rendered into the workspace since, they write zero gradients and set bit
+ * 3 of the workspace's device_error, which rgs_workspace_check reports.
  * The frame may be a render of RGS_PATH_PLAIN or of its training variant
  * RGS_PATH_PLAIN | RGS_HW_EXP2; the backward pass evaluates each pair as the
  * frame did (for the variant: two waves per tile over the forward's culled

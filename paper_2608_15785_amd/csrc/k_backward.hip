@@ -111,10 +111,20 @@ __device__ inline uint32_t band_mask(float v, float A, float B, float C, float o
     return m;
 }
 
+// Whether the workspace still holds the frame the caller asked for; if not,
+// the first workgroup flags it in the header and every workgroup leaves.
+__device__ inline bool frame_matches(const WsDev& ws, FrameKey key) {
+    const FrameParams* prm = ws.params;
+    if (prm->scene_tag == key.scene_tag && prm->cam_hash == key.cam_hash) return true;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ws.header->error, 8u);
+    return false;
+}
+
 __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev ws,
                                                                const uint32_t* __restrict__ vals,
                                                                const float* __restrict__ dimg,
-                                                               float4* __restrict__ partial) {
+                                                               float4* __restrict__ partial, FrameKey key) {
+    if (!frame_matches(ws, key)) return;
     __shared__ float4 s_a[BWD_BATCH];          // u, v (tile-local), A, B
     __shared__ float4 s_b[BWD_BATCH];          // C, o, r, g
     __shared__ float s_c[BWD_BATCH];           // b
@@ -259,10 +269,10 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
 }
 
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                            const float* dimg, float4* partial) {
+                            const float* dimg, float4* partial, FrameKey key) {
     const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
     hipLaunchKernelGGL(k_raster_backward, dim3((uint32_t)f.n_tiles), dim3(BWD_LANES), 0, s, f, ws, vals, dimg,
-                       partial);
+                       partial, key);
 }
 
 // ---------------------------------------------------------------------------
@@ -280,9 +290,9 @@ void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, b
 // two pixels added) are summed over each half-wave with DPP row operations and
 // the two half-wave sums kept in LDS; at the end of a batch each entry adds its
 // four half-wave sums and writes them to its emission position.  Measured at
-// 1M / 1080p (training step's backward call): a full-wave DPP reduction per
-// entry, 0.88 -> 1.02 ms with the per-channel colour sums as well; four row
-// sums kept instead of two, or batches of 32, no different.
+// 1M / 1080p (the training step's backward call): 1.02 ms with a full-wave DPP
+// reduction per entry and per-channel colour sums, 0.88 ms as written; four
+// row sums kept instead of two, or batches of 32, made no difference.
 
 constexpr int TB_THREADS = 128;
 constexpr int TB_BATCH = 64;
@@ -322,7 +332,7 @@ __device__ inline void pair_adjoint(float P, float dx, float dy, const float4& c
 __global__ __launch_bounds__(TB_THREADS) void k_raster_backward_train(FrameDev f, WsDev ws,
                                                                       const uint32_t* __restrict__ vals,
                                                                       const float* __restrict__ dimg,
-                                                                      float4* __restrict__ partial) {
+                                                                      float4* __restrict__ partial, FrameKey key) {
     // per-wave lists of the batch's folded entries, in depth order
     __shared__ float4 s_a[2][TB_BATCH];      // C1, C2, C3, C4 (log2 units)
     __shared__ float4 s_b[2][TB_BATCH];      // C5, C6, entry index, slot in the batch (bits)
@@ -333,6 +343,7 @@ __global__ __launch_bounds__(TB_THREADS) void k_raster_backward_train(FrameDev f
     // [wave][term][half][slot]: an entry's sums over each 32-lane half of a wave
     __shared__ float4 s_acc4[2 * 9 * 2 * TB_BATCH / 4];
     float (*s_acc)[9][2][TB_BATCH] = reinterpret_cast<float (*)[9][2][TB_BATCH]>(s_acc4);
+    if (!frame_matches(ws, key)) return;
     const uint32_t tile = blockIdx.x;        // row-major, as the rasterizers
     if (tile >= (uint32_t)f.n_tiles) return;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
@@ -486,10 +497,10 @@ __global__ __launch_bounds__(TB_THREADS) void k_raster_backward_train(FrameDev f
 }
 
 void launch_raster_backward_train(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                                  const float* dimg, float4* partial) {
+                                  const float* dimg, float4* partial, FrameKey key) {
     const uint32_t* vals = result_in_b ? ws.vals_b : ws.vals_a;
     hipLaunchKernelGGL(k_raster_backward_train, dim3((uint32_t)f.n_tiles), dim3(TB_THREADS), 0, s, f, ws, vals,
-                       dimg, partial);
+                       dimg, partial, key);
 }
 
 // ---------------------------------------------------------------------------
@@ -549,10 +560,11 @@ constexpr int GRAD_THREADS = 128;
 
 // Gradients of Gaussian i: sum of its partials, then the chain rule.  The SH
 // gradients go to dsh (48 floats, LDS), the rest straight to global memory.
+// refused: the workspace holds another frame than the caller's; all gradients are zero.
 __device__ inline void grad_one(const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
                                 const float4* __restrict__ partial, const GradOut& go, int64_t i,
-                                float* dsh, bool lno_opacity) {
-    const uint32_t count = ws.counts[i];
+                                float* dsh, bool lno_opacity, bool refused) {
+    const uint32_t count = refused ? 0u : ws.counts[i];
     double gs[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) gs[c] = 0.0;
@@ -727,11 +739,12 @@ __device__ inline void grad_one(const PlainSceneDev& sc, const CamDev& cam, cons
 template <bool LNO>
 __global__ __launch_bounds__(GRAD_THREADS) void k_grad_gaussian(PlainSceneDev sc, CamDev cam, WsDev ws,
                                                                 const float4* __restrict__ partial,
-                                                                GradOut go) {
+                                                                GradOut go, FrameKey key) {
     __shared__ float s_sh[GRAD_THREADS * 48];
     const int64_t first = (int64_t)blockIdx.x * GRAD_THREADS;
     const int64_t i = first + threadIdx.x;
-    if (i < sc.n) grad_one(sc, cam, ws, partial, go, i, s_sh + 48 * threadIdx.x, LNO);
+    const bool refused = ws.params->scene_tag != key.scene_tag || ws.params->cam_hash != key.cam_hash;
+    if (i < sc.n) grad_one(sc, cam, ws, partial, go, i, s_sh + 48 * threadIdx.x, LNO, refused);
     __syncthreads();
     const int64_t rows = sc.n - first < GRAD_THREADS ? sc.n - first : GRAD_THREADS;
     float* dst = go.sh + 48 * first;
@@ -739,11 +752,11 @@ __global__ __launch_bounds__(GRAD_THREADS) void k_grad_gaussian(PlainSceneDev sc
 }
 
 void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
-                          const float4* partial, const GradOut& go, bool lno_opacity) {
+                          const float4* partial, const GradOut& go, bool lno_opacity, FrameKey key) {
     if (sc.n <= 0) return;
     const dim3 grid((uint32_t)((sc.n + GRAD_THREADS - 1) / GRAD_THREADS)), block(GRAD_THREADS);
-    if (lno_opacity) hipLaunchKernelGGL(k_grad_gaussian<true>, grid, block, 0, s, sc, cam, ws, partial, go);
-    else hipLaunchKernelGGL(k_grad_gaussian<false>, grid, block, 0, s, sc, cam, ws, partial, go);
+    if (lno_opacity) hipLaunchKernelGGL(k_grad_gaussian<true>, grid, block, 0, s, sc, cam, ws, partial, go, key);
+    else hipLaunchKernelGGL(k_grad_gaussian<false>, grid, block, 0, s, sc, cam, ws, partial, go, key);
 }
 
 }  // namespace rgs

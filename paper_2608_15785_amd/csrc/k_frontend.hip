@@ -177,6 +177,22 @@ void launch_export_status(hipStream_t s, const WsDev& ws, FrameStatus* dst) {
     hipLaunchKernelGGL(k_export_status, dim3(1), dim3(64), 0, s, ws.header, ws.params, dst);
 }
 
+__global__ void k_export_stamp(const WsHeader* h, const FrameParams* prm, FrameStamp* dst, uint64_t seq) {
+    if (threadIdx.x == 0) {
+        dst->n_entries = h->n_entries;
+        dst->overflow = h->overflow;
+        dst->error = h->error;
+        dst->scene_tag = prm->scene_tag;
+        dst->cam_hash = prm->cam_hash;
+        __threadfence_system();
+        __hip_atomic_store(&dst->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
+void launch_export_stamp(hipStream_t s, const WsDev& ws, FrameStamp* dst, uint64_t seq) {
+    hipLaunchKernelGGL(k_export_stamp, dim3(1), dim3(64), 0, s, ws.header, ws.params, dst, seq);
+}
+
 // ---------------------------------------------------------------------------
 // Chained scan across blocks (decoupled look-back).  Block vb publishes its
 // aggregate (entries, visible Gaussians), then sums predecessors' aggregates

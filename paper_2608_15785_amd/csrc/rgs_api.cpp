@@ -209,6 +209,22 @@ struct FrameEvents {
     bool skipped[RGS_N_STAGES + 1];
 };
 
+// The last plain frame a context rendered into a workspace.  Its outcome and
+// stamp arrive in stamps[slot] (host-visible memory written by the frame's
+// last kernel), so that the backward pass needs no device read when it
+// differentiates a frame its own context rendered.
+struct FrameRecord {
+    const void* ws = nullptr;     // nullptr: slot unused
+    uint64_t ws_bytes = 0;
+    const rgs_scene* scene = nullptr;
+    uint64_t scene_tag = 0, cam_hash = 0;
+    int32_t width = 0, height = 0, path = 0;
+    hipStream_t stream = nullptr;
+    uint64_t seq = 0;             // the stamp's sequence number once written
+    uint64_t last_use = 0;
+};
+constexpr int N_FRAME_RECORDS = 8;
+
 struct rgs_ctx {
     int device;
     hipStream_t stream;
@@ -218,6 +234,9 @@ struct rgs_ctx {
     size_t events_used;
     double stage_ms[RGS_N_STAGES];
     int64_t frames;
+    FrameRecord records[N_FRAME_RECORDS];
+    FrameStamp* stamps = nullptr;     // [N_FRAME_RECORDS], host-visible
+    uint64_t seq = 0, uses = 0;
 };
 
 // ---------------------------------------------------------------------------
@@ -259,7 +278,11 @@ extern "C" rgs_status rgs_ctx_create(int32_t device, void* hip_stream, rgs_ctx**
     HIP_TRY(hipSetDevice(device));
     rgs_status ss = scratch_setup(device);
     if (ss != RGS_OK) return ss;
+    void* stamps = nullptr;
+    HIP_TRY(hipHostMalloc(&stamps, N_FRAME_RECORDS * sizeof(FrameStamp), hipHostMallocCoherent));
+    std::memset(stamps, 0, N_FRAME_RECORDS * sizeof(FrameStamp));
     rgs_ctx* c = new rgs_ctx();
+    c->stamps = static_cast<FrameStamp*>(stamps);
     c->device = device;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->timing = false;
@@ -276,6 +299,9 @@ extern "C" void rgs_ctx_destroy(rgs_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     for (auto& fe : ctx->events)
         for (auto& e : fe.ev) (void)hipEventDestroy(e);
+    // frames still queued on any stream may write their stamps
+    (void)hipDeviceSynchronize();
+    (void)hipHostFree(ctx->stamps);
     delete ctx;
 }
 
@@ -707,7 +733,8 @@ static rgs_status header_status(const WsHeader& h, rgs_frame_stats* st, int64_t 
         st->list_steps = (int64_t)h.list_steps;
     }
     if (h.error)
-        return fail(RGS_E_DEVICE, "a kernel's bounded wait gave up (flags 0x%x)", h.error);
+        return fail(RGS_E_DEVICE, "the frame reported device errors 0x%x (1, 4: a bounded wait gave up or a "
+                    "failed sort; 8: a backward pass found another frame than its caller's)", h.error);
     if (h.overflow)
         return fail(RGS_E_CAPACITY, "frame needs %llu entries, workspace holds %u",
                     (unsigned long long)h.n_entries, h.capacity);
@@ -725,6 +752,76 @@ static uint64_t camera_hash(const rgs_camera* c, int32_t width, int32_t height) 
     mix(&width, sizeof(width));
     mix(&height, sizeof(height));
     return h;
+}
+
+// Notes the frame just enqueued on ctx's stream into ws.  A plain frame gets
+// a record and a stamp export after its last kernel; any other frame only
+// retires the workspace's record.
+static rgs_status note_frame(rgs_ctx* ctx, const FrameLaunch& fl, const void* ws, uint64_t ws_bytes,
+                             const rgs_scene* sc, const FrameParams& prm, int32_t width, int32_t height,
+                             int32_t path) {
+    int slot = -1;
+    for (int i = 0; i < N_FRAME_RECORDS; ++i)
+        if (ctx->records[i].ws == ws) slot = i;
+    if (fl.path != RGS_PATH_PLAIN) {
+        if (slot >= 0) ctx->records[slot] = FrameRecord{};
+        return RGS_OK;
+    }
+    if (slot < 0) {                 // an unused slot, else the least recently used
+        slot = 0;
+        for (int i = 0; i < N_FRAME_RECORDS; ++i) {
+            if (!ctx->records[i].ws) {
+                slot = i;
+                break;
+            }
+            if (ctx->records[i].last_use < ctx->records[slot].last_use) slot = i;
+        }
+    }
+    FrameRecord& r = ctx->records[slot];
+    // a stamp export still queued on another stream must not land after this one
+    if (r.ws && r.stream != ctx->stream) HIP_TRY(hipStreamSynchronize(r.stream));
+    r.ws = ws;
+    r.ws_bytes = ws_bytes;
+    r.scene = sc;
+    r.scene_tag = prm.scene_tag;
+    r.cam_hash = prm.cam_hash;
+    r.width = width;
+    r.height = height;
+    r.path = path;
+    r.stream = ctx->stream;
+    r.seq = ++ctx->seq;
+    r.last_use = ++ctx->uses;
+    launch_export_stamp(ctx->stream, fl.w, &ctx->stamps[slot], r.seq);
+    HIP_TRY(hipGetLastError());
+    return RGS_OK;
+}
+
+// Waits, spinning on host-visible memory, until the stamp of record `slot`
+// has arrived, i.e. its frame has finished on the GPU, and copies it.
+static rgs_status wait_stamp(rgs_ctx* ctx, int slot, FrameStamp* out) {
+    const FrameRecord& r = ctx->records[slot];
+    FrameStamp* p = &ctx->stamps[slot];
+    for (uint32_t spin = 1;; ++spin) {
+        if (__atomic_load_n(&p->seq, __ATOMIC_ACQUIRE) == r.seq) break;
+        if (spin % 256 == 0) {      // the stream has drained, or failed, without it
+            const hipError_t e = hipStreamQuery(r.stream);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(&p->seq, __ATOMIC_ACQUIRE) == r.seq) break;
+                return fail(RGS_E_HIP, "the frame's stamp was not written");
+            }
+            if (e != hipErrorNotReady) return fail(RGS_E_HIP, "hipStreamQuery: %s", hipGetErrorString(e));
+        }
+#if defined(__x86_64__)
+        __builtin_ia32_pause();
+#endif
+    }
+    out->n_entries = p->n_entries;
+    out->overflow = p->overflow;
+    out->error = p->error;
+    out->scene_tag = p->scene_tag;
+    out->cam_hash = p->cam_hash;
+    out->seq = r.seq;
+    return RGS_OK;
 }
 
 FrameParams rgs::frame_params(const rgs_camera* c, float* out, const rgs_scene* sc, int32_t width,
@@ -905,8 +1002,11 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
     }
     FrameHooks hooks{hook_mark, hook_after_front, &rh};
     bool in_b = false;
-    s = enqueue_frame(st, fl, frame_params(cam, out, sc, W, H), dbg ? &dd : nullptr, dbg != nullptr, nullptr,
-                      (rh.fe || dbg) ? &hooks : nullptr, &in_b);
+    const FrameParams prm = frame_params(cam, out, sc, W, H);
+    s = enqueue_frame(st, fl, prm, dbg ? &dd : nullptr, dbg != nullptr, nullptr, (rh.fe || dbg) ? &hooks : nullptr,
+                      &in_b);
+    if (s != RGS_OK) return s;
+    s = note_frame(ctx, fl, ws, ws_bytes, sc, prm, W, H, path);
     if (s != RGS_OK) return s;
 
     if (dbg) {
@@ -1032,30 +1132,58 @@ extern "C" rgs_status rgs_render_backward(rgs_ctx* ctx, const rgs_scene* scene, 
         return fail(RGS_E_INVALID, "scratch of %llu bytes, need %llu", (unsigned long long)grads->scratch_bytes,
                     (unsigned long long)(fl.L.capacity * PARTIAL_BYTES));
     HIP_TRY(hipSetDevice(ctx->device));
-    WsHeader h;
-    s = read_header(ctx, workspace, &h);
-    if (s != RGS_OK) return s;
-    if ((h.path != (uint32_t)RGS_PATH_PLAIN && h.path != (uint32_t)(RGS_PATH_PLAIN | RGS_HW_EXP2)) ||
-        h.capacity != fl.f.capacity || h.passes != fl.L.passes)
+    const uint64_t hash = camera_hash(cam, width, height);
+    static const char* const STALE_SCENE = "the workspace's last frame is not a render of this scene in its current "
+                                           "state (another scene, or its parameters were updated since)";
+    static const char* const STALE_CAMERA = "the workspace's last frame was rendered with another camera or size";
+    uint32_t path_word = 0;
+    int slot = -1;
+    for (int i = 0; i < N_FRAME_RECORDS; ++i)
+        if (ctx->records[i].ws == workspace) slot = i;
+    const FrameRecord* r = slot >= 0 ? &ctx->records[slot] : nullptr;
+    if (r && r->ws_bytes == ws_bytes && r->width == width && r->height == height && r->scene == scene &&
+        r->scene_tag == scene->tag && r->cam_hash == hash) {
+        // the last frame this context rendered into the workspace is the one
+        // asked for: its stamp tells the outcome without a device read (and the
+        // kernels check that no other context rendered into it since)
+        FrameStamp st;
+        s = wait_stamp(ctx, slot, &st);
+        if (s != RGS_OK) return s;
+        WsHeader h{};
+        h.n_entries = st.n_entries;
+        h.overflow = st.overflow;
+        h.error = st.error;
+        h.capacity = fl.f.capacity;
+        s = header_status(h, nullptr, scene->n);
+        if (s != RGS_OK) return s;
+        path_word = (uint32_t)r->path;
+    } else {                        // otherwise the workspace itself is asked
+        WsHeader h;
+        s = read_header(ctx, workspace, &h);
+        if (s != RGS_OK) return s;
+        if ((h.path != (uint32_t)RGS_PATH_PLAIN && h.path != (uint32_t)(RGS_PATH_PLAIN | RGS_HW_EXP2)) ||
+            h.capacity != fl.f.capacity || h.passes != fl.L.passes)
+            return fail(RGS_E_INVALID, "the workspace does not hold a plain render of this size");
+        FrameParams prm;
+        HIP_TRY(hipMemcpyAsync(&prm, static_cast<const char*>(workspace) + fl.L.params, sizeof(prm),
+                               hipMemcpyDeviceToHost, ctx->stream));
+        HIP_TRY(hipStreamSynchronize(ctx->stream));
+        if (prm.scene_tag != scene->tag) return fail(RGS_E_INVALID, "%s", STALE_SCENE);
+        if (prm.cam_hash != hash) return fail(RGS_E_INVALID, "%s", STALE_CAMERA);
+        s = header_status(h, nullptr, scene->n);
+        if (s != RGS_OK) return s;
+        path_word = h.path;
+    }
+    if (path_word != (uint32_t)RGS_PATH_PLAIN && path_word != (uint32_t)(RGS_PATH_PLAIN | RGS_HW_EXP2))
         return fail(RGS_E_INVALID, "the workspace does not hold a plain render of this size");
-    FrameParams prm;
-    HIP_TRY(hipMemcpyAsync(&prm, static_cast<const char*>(workspace) + fl.L.params, sizeof(prm),
-                           hipMemcpyDeviceToHost, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-    if (prm.scene_tag != scene->tag)
-        return fail(RGS_E_INVALID, "the workspace's last frame is not a render of this scene in its current state "
-                                   "(another scene, or its parameters were updated since)");
-    if (prm.cam_hash != camera_hash(cam, width, height))
-        return fail(RGS_E_INVALID, "the workspace's last frame was rendered with another camera or size");
-    s = header_status(h, nullptr, scene->n);
-    if (s != RGS_OK) return s;
     const bool in_b = (fl.L.passes % 2) == 1;
     float4* partial = static_cast<float4*>(grads->scratch);
-    const bool train = (h.path & RGS_HW_EXP2) != 0;
-    if (train) launch_raster_backward_train(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial);
-    else launch_raster_backward(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial);
+    const bool train = (path_word & RGS_HW_EXP2) != 0;
+    const FrameKey key{scene->tag, hash};
+    if (train) launch_raster_backward_train(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial, key);
+    else launch_raster_backward(ctx->stream, fl.f, fl.w, in_b, dL_dimg, partial, key);
     GradOut go{grads->d_means, grads->d_scales, grads->d_quats, grads->d_opacity, grads->d_sh, grads->d_screen};
-    launch_grad_gaussian(ctx->stream, fl.plain, cam_dev(cam), fl.w, partial, go, train);
+    launch_grad_gaussian(ctx->stream, fl.plain, cam_dev(cam), fl.w, partial, go, train, key);
     HIP_TRY(hipGetLastError());
     return ok();
 }

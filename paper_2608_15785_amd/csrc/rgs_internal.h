@@ -165,7 +165,8 @@ struct WsHeader {
     uint32_t n_visible;
     uint32_t overflow;
     uint32_t error;           // bit 0: front-end look-back gave up;
-                              // bit 2: a sorted key named a tile outside the grid
+                              // bit 2: a sorted key named a tile outside the grid;
+                              // bit 3: a backward pass found another frame than its caller's
     uint32_t capacity;
     uint32_t path;
     uint32_t passes;
@@ -481,11 +482,23 @@ struct FrameStatus {
     uint64_t out;        // output address the frame used (checks replayed parameters)
 };
 
+// A plain render's outcome and stamp, copied by the frame's last kernel into
+// host-visible memory of the rendering context: the backward pass learns
+// whether its frame overflowed, and that the frame is the one it expects,
+// without reading the device.  seq is written last, after a system fence.
+struct FrameStamp {
+    uint64_t n_entries;
+    uint32_t overflow, error;
+    uint64_t scene_tag, cam_hash;
+    uint64_t seq;
+};
+
 ResetArgs reset_args(const WsDev& ws, uint64_t zero_bytes, const FrameDev& f, uint32_t path,
                      const FrameParams& prm);
 void launch_reset(hipStream_t s, const ResetArgs& a);
 const void* reset_kernel();          // host handle of the reset kernel (graph node lookup)
 void launch_export_status(hipStream_t s, const WsDev& ws, FrameStatus* dst);
+void launch_export_stamp(hipStream_t s, const WsDev& ws, FrameStamp* dst, uint64_t seq);
 void launch_preprocess_plain(hipStream_t s, const PlainSceneDev& sc, const FrameDev& f,
                              const WsDev& ws, const DebugDev* dbg, bool train);
 void launch_duplicate(hipStream_t s, int64_t n, const FrameDev& f, const WsDev& ws, uint32_t fe_blocks, uint32_t fe_per,
@@ -521,13 +534,20 @@ struct GradOut {
 
 void launch_update_plain(hipStream_t s, float* planes, uint64_t n_pad, int64_t n, const float* means,
                          const float* scales, const float* quats, const float* opacity, const float* sh);
+// The frame a backward pass is asked to differentiate: its scene tag and camera
+// hash.  The backward kernels compare them with the workspace's frame
+// parameters; on a mismatch they set header bit 3, write no partials, and the
+// per-Gaussian pass writes zero gradients.
+struct FrameKey {
+    uint64_t scene_tag, cam_hash;
+};
 void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                            const float* dimg, float4* partial);
+                            const float* dimg, float4* partial, FrameKey key);
 void launch_raster_backward_train(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b,
-                                  const float* dimg, float4* partial);
+                                  const float* dimg, float4* partial, FrameKey key);
 // lno_opacity: the partials' opacity slot holds dL/d(ln o) (the training
 // variant's), converted to dL/do here.
 void launch_grad_gaussian(hipStream_t s, const PlainSceneDev& sc, const CamDev& cam, const WsDev& ws,
-                          const float4* partial, const GradOut& go, bool lno_opacity);
+                          const float4* partial, const GradOut& go, bool lno_opacity, FrameKey key);
 
 }  // namespace rgs

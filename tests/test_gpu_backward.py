@@ -271,6 +271,47 @@ def test_backward_refuses_a_stale_workspace(R):
     ds2.release()
 
 
+def test_backward_finds_another_contexts_frame(R):
+    """A context differentiates the frame it last rendered into a workspace from that
+    frame's stamp, without reading the device.  If another context has rendered another
+    frame into the same workspace since, the backward kernels find the workspace's frame
+    parameters different from the caller's: they write zero gradients and flag the
+    workspace (device error bit 3), which the next check reports."""
+    import torch
+    import paper_2608_15785_amd as rgs
+    from paper_2608_15785_amd import _binding as B
+    sc = wl.make_scene(500, 1.0, -3.0, 0.5, 37)
+    cam = wl.config_camera("small", width=48, height=32)
+    cam2 = wl.look_at_camera((0.3, 0.1, -3.0), (0, 0, 0), (0, 1, 0), 60.0, 48, 32, cam.z_near, cam.z_far)
+    ds = R.upload(sc, ("plain",))
+    dimg = torch.ones((3, 32, 48), device="cuda:0")
+    ws = R.workspace(sc.n, 48, 32, "plain")
+    out = torch.empty((3, 32, 48), device="cuda:0")
+    B.render(R.ctx, ds, cam, "plain", ws, out)
+    g = rgs.render_backward(R.ctx, ds, cam, ws, dimg, screen=True)
+    torch.cuda.synchronize()
+    assert int(torch.count_nonzero(g["screen"])) > 0
+    assert B.workspace_stats(R.ctx, ws, sc.n)["device_error"] == 0
+    R2 = rgs.Renderer(0)
+    B.render(R2.ctx, ds, cam2, "plain", ws, out)               # another context, another camera
+    g = rgs.render_backward(R.ctx, ds, cam, ws, dimg, screen=True)
+    torch.cuda.synchronize()
+    for k, v in g.items():
+        assert int(torch.count_nonzero(v)) == 0, k
+    st = B.workspace_stats(R.ctx, ws, sc.n)
+    assert st["device_error"] & 8, st
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.workspace_check(R.ctx, ws, sc.n)
+    assert e.value.status == B.RGS_E_DEVICE
+    B.render(R.ctx, ds, cam, "plain", ws, out)                 # a new frame clears the flag
+    g = rgs.render_backward(R.ctx, ds, cam, ws, dimg, screen=True)
+    torch.cuda.synchronize()
+    assert B.workspace_stats(R.ctx, ws, sc.n)["device_error"] == 0
+    assert int(torch.count_nonzero(g["screen"])) > 0
+    del R2
+    ds.release()
+
+
 def test_autograd_gradients_survive_interleaved_renders(R):
     """Between a forward call and its backward: a render of another scene of the
     same size through the shared renderer, or a forward at another image size
