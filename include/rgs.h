@@ -284,6 +284,17 @@ rgs_status rgs_workspace_size(int64_t n_gaussians, int32_t width, int32_t height
 /* Entry capacity a workspace of ws_bytes provides (0 if too small). */
 rgs_status rgs_workspace_capacity(int64_t n_gaussians, int32_t width, int32_t height,
                                   int32_t path, uint64_t ws_bytes, int64_t* capacity);
+/* The same sizing by a scene: the workspace bytes a render of `scene` at
+ * width x height on `path` needs to hold hint_ndup duplicated entries
+ * (hint_ndup = 0: 4 per Gaussian, at least 65536, at most RGS_MAX_ENTRIES).
+ * The true count is known only after the front end has run; a render that
+ * needs more reports RGS_E_CAPACITY with the count in its stats.  Host-only.
+ * Errors: INVALID (NULL, bad size or path, hint_ndup > RGS_MAX_ENTRIES). */
+rgs_status rgs_render_workspace_bound(const rgs_scene* scene, int32_t width, int32_t height, int32_t path,
+                                      uint64_t hint_ndup, uint64_t* bytes);
+/* Device bytes the scene holds (rgs_scene_info's third output).  Host-only.
+ * Errors: INVALID (NULL). */
+rgs_status rgs_scene_device_bytes(const rgs_scene* scene, uint64_t* bytes);
 
 /* ---------------------------------------------------------------------------
  * Render one image (Sec. II-A, III, IV).
@@ -335,6 +346,11 @@ rgs_status rgs_workspace_check(rgs_ctx* ctx, const void* workspace, rgs_frame_st
 /* ---------------------------------------------------------------------------
  * Parity access: render as rgs_render, then copy the frame's intermediates
  * into caller-owned device buffers (any pointer may be NULL).  Synchronous.
+ * They are the outputs of each step of the pipeline: the preprocessing of
+ * Sec. III-A (EWA projection of Sec. II-A, culling, the tile extent of
+ * Sec. IV-A, the SH colour), the duplication and keys of Sec. III-B (the key
+ * encoding of Sec. IV-A, Eq. depth_quant), the sort of Sec. III-C, and the
+ * per-pixel outcome of the blending of Sec. III-D (Eq. alpha_computation).
  *   per Gaussian [n]:  depth, u, v (float64); cov2d [n][3] (Sigma'_00,
  *                      Sigma'_01, Sigma'_11, float64); rect [n][4] inclusive
  *                      tile bounds x0,x1,y0,y1 (int32, zeros when culled);

@@ -169,6 +169,9 @@ SIGNATURES = [
                                        C.POINTER(C.c_uint64)]),
     ("rgs_workspace_capacity", C.c_int32, [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                                            C.POINTER(C.c_int64)]),
+    ("rgs_render_workspace_bound", C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                               C.POINTER(C.c_uint64)]),
+    ("rgs_scene_device_bytes", C.c_int32, [C.c_void_p, C.POINTER(C.c_uint64)]),
     ("rgs_render", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(CameraC), C.c_int32, C.c_int32,
                                C.c_int32, C.c_void_p, C.c_uint64, C.c_void_p, C.POINTER(FrameStats)]),
     ("rgs_workspace_check", C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(FrameStats), C.c_int64]),
@@ -360,6 +363,18 @@ class DeviceScene:
         n, f, b = C.c_int64(), C.c_uint32(), C.c_uint64()
         _check(lib.rgs_scene_info(self.handle, C.byref(n), C.byref(f), C.byref(b)), "rgs_scene_info")
         return dict(n=int(n.value), formats=int(f.value), device_bytes=int(b.value))
+
+    def device_bytes(self) -> int:
+        b = C.c_uint64()
+        _check(lib.rgs_scene_device_bytes(self.handle, C.byref(b)), "rgs_scene_device_bytes")
+        return int(b.value)
+
+    def workspace_bound(self, width: int, height: int, path: str, hint_ndup: int = 0) -> int:
+        """Workspace bytes a render of this scene needs for hint_ndup entries (0: the default guess)."""
+        b = C.c_uint64()
+        _check(lib.rgs_render_workspace_bound(self.handle, width, height, PATHS[path], hint_ndup, C.byref(b)),
+               "rgs_render_workspace_bound")
+        return int(b.value)
 
     def release(self):
         if self.handle:

@@ -503,6 +503,12 @@ extern "C" rgs_status rgs_scene_release(rgs_ctx* ctx, rgs_scene* sc) {
     return ok();
 }
 
+extern "C" rgs_status rgs_scene_device_bytes(const rgs_scene* sc, uint64_t* bytes) {
+    if (!sc || !bytes) return fail(RGS_E_INVALID, "rgs_scene_device_bytes: NULL argument");
+    *bytes = sc->bytes;
+    return ok();
+}
+
 extern "C" rgs_status rgs_scene_info(const rgs_scene* sc, int64_t* n, uint32_t* formats,
                                      uint64_t* device_bytes) {
     if (!sc) return fail(RGS_E_INVALID, "scene is NULL");
@@ -615,6 +621,16 @@ extern "C" rgs_status rgs_workspace_size(int64_t n, int32_t width, int32_t heigh
     make_layout(n, p, path, (uint64_t)max_entries, L);
     *bytes = L.total;
     return ok();
+}
+
+extern "C" rgs_status rgs_render_workspace_bound(const rgs_scene* sc, int32_t width, int32_t height, int32_t path,
+                                                 uint64_t hint_ndup, uint64_t* bytes) {
+    if (!sc || !bytes) return fail(RGS_E_INVALID, "rgs_render_workspace_bound: NULL argument");
+    if (hint_ndup > RGS_MAX_ENTRIES)
+        return fail(RGS_E_INVALID, "hint_ndup %llu above RGS_MAX_ENTRIES", (unsigned long long)hint_ndup);
+    uint64_t entries = hint_ndup;
+    if (!entries) entries = std::min<uint64_t>(RGS_MAX_ENTRIES, std::max<uint64_t>(4ull * (uint64_t)sc->n, 65536ull));
+    return rgs_workspace_size(sc->n, width, height, path, (int64_t)entries, bytes);
 }
 
 // Largest capacity whose layout fits in ws_bytes (0 if none).

@@ -171,6 +171,9 @@ def test_null_arguments_are_rejected():
     assert B.lib.rgs_render(None, None, None, 16, 16, 0, None, 0, None, None) == B.RGS_E_INVALID
     assert B.lib.rgs_workspace_check(None, None, None, 0) == B.RGS_E_INVALID
     assert B.lib.rgs_ctx_set_timing(None, 1) == B.RGS_E_INVALID
+    b = B.C.c_uint64()
+    assert B.lib.rgs_render_workspace_bound(None, 1920, 1080, B.PATH_FAST, 0, B.C.byref(b)) == B.RGS_E_INVALID
+    assert B.lib.rgs_scene_device_bytes(None, B.C.byref(b)) == B.RGS_E_INVALID
 
 
 def test_server_config_is_validated_before_device_use():

@@ -143,6 +143,26 @@ def test_invalid_arguments(R):
         rgs.render(R.ctx, ds, bad, "fast", ws)
 
 
+def test_sizing_by_scene(R):
+    """rgs_render_workspace_bound is rgs_workspace_size with the scene's n (and a default
+    entry guess), and rgs_scene_device_bytes is rgs_scene_info's byte count."""
+    import paper_2608_15785_amd as rgs
+    from paper_2608_15785_amd import _binding as B
+    sc = wl.config_scene("small", n=3000)
+    ds = R.upload(sc, ("plain", "fast"))
+    assert ds.device_bytes() == ds.info()["device_bytes"] > 0
+    for path in ("fast", "plain"):
+        assert ds.workspace_bound(1920, 1080, path, 12345) == B.workspace_size(sc.n, 1920, 1080, path, 12345)
+        assert ds.workspace_bound(1920, 1080, path) == B.workspace_size(sc.n, 1920, 1080, path, 65536)
+        bound = ds.workspace_bound(256, 256, path, 50000)
+        assert B.workspace_capacity(sc.n, 256, 256, path, bound) >= 50000
+    with pytest.raises(rgs.RGSError):
+        ds.workspace_bound(0, 1080, "fast")
+    with pytest.raises(rgs.RGSError):
+        ds.workspace_bound(1920, 1080, "fast", B.MAX_ENTRIES + 1)
+    ds.release()
+
+
 @pytest.mark.parametrize("path", ["plain", "fast"])
 def test_1080p_keys_and_sampled_tiles(R, path):
     """1M Gaussians at 1920x1080: every key bit-exact, image on 64 sampled tiles."""
