@@ -26,15 +26,47 @@ namespace rgs {
 
 
 // ---------------------------------------------------------------------------
-// Plain attributes from [n][...] rows.
+// Plain attributes from [n][...] rows.  A block takes 256 Gaussians.  Their
+// SH rows (48 floats each, 48 KB together) are read as one contiguous span of
+// 16-byte loads into LDS, each row padded to 49 floats so that the plane-wise
+// reads below hit distinct banks; each thread then writes its Gaussian's 48
+// coefficients into the 48 SH planes, consecutive threads at consecutive
+// addresses.  Reading the rows directly, each load instruction of a wave would
+// touch 64 rows 192 bytes apart.
 
-__global__ __launch_bounds__(256) void k_update_plain(float* __restrict__ planes, uint64_t n_pad, int64_t n,
-                                                      const float* __restrict__ means,
-                                                      const float* __restrict__ scales,
-                                                      const float* __restrict__ quats,
-                                                      const float* __restrict__ opacity,
-                                                      const float* __restrict__ sh) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int UPD_THREADS = 256;
+constexpr int UPD_SH = 48;
+constexpr int UPD_ROW = UPD_SH + 1;
+
+__global__ __launch_bounds__(UPD_THREADS) void k_update_plain(float* __restrict__ planes, uint64_t n_pad, int64_t n,
+                                                              const float* __restrict__ means,
+                                                              const float* __restrict__ scales,
+                                                              const float* __restrict__ quats,
+                                                              const float* __restrict__ opacity,
+                                                              const float* __restrict__ sh) {
+    __shared__ float s_sh[UPD_THREADS * UPD_ROW];
+    const int64_t first = (int64_t)blockIdx.x * UPD_THREADS;
+    const int64_t rows = n - first < UPD_THREADS ? n - first : UPD_THREADS;
+    const int64_t words = rows * UPD_SH;
+    const float* src = sh + first * UPD_SH;
+    if (rows == UPD_THREADS && (reinterpret_cast<uintptr_t>(src) % 16) == 0) {
+        const float4* src4 = reinterpret_cast<const float4*>(src);
+        for (int q = threadIdx.x; q < UPD_THREADS * UPD_SH / 4; q += UPD_THREADS) {
+            const float4 v = src4[q];
+            const float vals[4] = {v.x, v.y, v.z, v.w};
+            const int w = 4 * q;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int we = w + e;
+                s_sh[(we / UPD_SH) * UPD_ROW + we % UPD_SH] = vals[e];
+            }
+        }
+    } else {
+        for (int64_t w = threadIdx.x; w < words; w += UPD_THREADS)
+            s_sh[(w / UPD_SH) * UPD_ROW + w % UPD_SH] = src[w];
+    }
+    __syncthreads();
+    const int64_t i = first + threadIdx.x;
     if (i >= n) return;
 #pragma unroll
     for (int k = 0; k < 3; ++k) planes[(P_MX + k) * n_pad + i] = means[3 * i + k];
@@ -44,15 +76,16 @@ __global__ __launch_bounds__(256) void k_update_plain(float* __restrict__ planes
     for (int k = 0; k < 4; ++k) planes[(P_QW + k) * n_pad + i] = quats[4 * i + k];
     planes[P_OPA * n_pad + i] = opacity[i];
     planes[P_LNO * n_pad + i] = (float)log((double)opacity[i]);
+    const float* row = s_sh + threadIdx.x * UPD_ROW;
 #pragma unroll 8
-    for (int k = 0; k < 48; ++k) planes[(P_SH0 + k) * n_pad + i] = sh[48 * i + k];
+    for (int k = 0; k < UPD_SH; ++k) planes[(P_SH0 + k) * n_pad + i] = row[k];
 }
 
 void launch_update_plain(hipStream_t s, float* planes, uint64_t n_pad, int64_t n, const float* means,
                          const float* scales, const float* quats, const float* opacity, const float* sh) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_update_plain, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, planes, n_pad, n,
-                       means, scales, quats, opacity, sh);
+    hipLaunchKernelGGL(k_update_plain, dim3((uint32_t)((n + UPD_THREADS - 1) / UPD_THREADS)), dim3(UPD_THREADS), 0,
+                       s, planes, n_pad, n, means, scales, quats, opacity, sh);
 }
 
 // ---------------------------------------------------------------------------

@@ -271,6 +271,36 @@ def test_backward_refuses_a_stale_workspace(R):
     ds2.release()
 
 
+@pytest.mark.parametrize("n", [1000, 4099])
+def test_scene_update_equals_upload(R, n):
+    """rgs_scene_update_plain writes the same planes as an upload of the same parameters:
+    a scene uploaded from other values, updated, renders like a fresh upload (a full block
+    of 256 Gaussians and a ragged last one).  Bit for bit on the plain path; the training
+    variant also reads ln o, which the upload takes from the host's log and the update from
+    the device's (both in float64, rounded to float32), so it may differ by an ulp there."""
+    import torch
+    import paper_2608_15785_amd as rgs
+    a = wl.make_scene(n, 1.0, -3.0, 0.5, 41)
+    b = wl.make_scene(n, 1.0, -3.0, 0.5, 42)
+    cam = wl.config_camera("small", width=128, height=96)
+    for path in ("plain", "plain/hw-exp2"):
+        ds_b = R.upload(b, ("plain",))
+        ref, _ = R.render(ds_b, cam, path)
+        ref = ref.clone()
+        ds_b.release()
+        ds = R.upload(a, ("plain",))
+        params = [torch.tensor(np.ascontiguousarray(x, np.float32), device="cuda:0")
+                  for x in (b.means, b.scales, b.quats, b.opacity, b.sh)]
+        rgs.scene_update_plain(R.ctx, ds, *params)
+        img, _ = R.render(ds, cam, path)
+        torch.cuda.synchronize()
+        if path == "plain":
+            assert torch.equal(img, ref)
+        else:
+            assert float((img - ref).abs().max()) <= 1e-5, path
+        ds.release()
+
+
 def test_backward_finds_another_contexts_frame(R):
     """A context differentiates the frame it last rendered into a workspace from that
     frame's stamp, without reading the device.  If another context has rendered another
