@@ -324,8 +324,10 @@ void launch_raster_backward(hipStream_t s, const FrameDev& f, const WsDev& ws, b
 // the two half-wave sums kept in LDS; at the end of a batch each entry adds its
 // four half-wave sums and writes them to its emission position.  Measured at
 // 1M / 1080p (the training step's backward call): 1.02 ms with a full-wave DPP
-// reduction per entry and per-channel colour sums, 0.88 ms as written; four
-// row sums kept instead of two, or batches of 32, made no difference.
+// reduction per entry and per-channel colour sums, 0.88 ms with the sums below;
+// four row sums kept instead of two, or batches of 32, made no difference;
+// reading the next entry's coefficients one step ahead and keeping the
+// half-wave broadcast out of the store's lane mask took it to 0.77 ms.
 
 constexpr int TB_THREADS = 128;
 constexpr int TB_BATCH = 64;
@@ -472,11 +474,21 @@ __global__ __launch_bounds__(TB_THREADS) void k_raster_backward_train(FrameDev f
         __syncthreads();
         // ---- this wave's list, back to front ----
         const uint32_t n = __builtin_amdgcn_readfirstlane(s_cnt[wave]);
+        // each step reads the next (closer) entry's exponent coefficients ahead,
+        // so that their LDS latency overlaps this step's work
+        float4 b4n = make_float4(0.f, 0.f, 0.f, 0.f), an = b4n;
+        if (n) {
+            b4n = s_b[wave][n - 1];
+            an = s_a[wave][n - 1];
+        }
         for (int k = (int)n - 1; k >= 0; --k) {
-            const float4 b4 = s_b[wave][k];
+            const float4 b4 = b4n, a = an;
+            if (k > 0) {
+                b4n = s_b[wave][k - 1];
+                an = s_a[wave][k - 1];
+            }
             const uint32_t idx = __float_as_uint(b4.z);
             if (idx >= wlast) continue;          // no pixel of the wave got this far
-            const float4 a = s_a[wave][k];
             float P0, P1;
             folded_exponents(a, b4.x, b4.y, x, y, x2, xy, y2, y21, P0, P1);
             const bool pass0 = idx < last[0] && P0 >= -LOG2_255F;
@@ -491,8 +503,13 @@ __global__ __launch_bounds__(TB_THREADS) void k_raster_backward_train(FrameDev f
             if (pass0) pair_adjoint(P0, dx, y - mg.w, mg, d[0], T[0], DS[0], g);
             if (pass1) pair_adjoint(P1, dx, y1 - mg.w, mg, d[1], T[1], DS[1], g);
             row_sums(g);
+            // row_bcast:15, taken by every lane (the compiler would otherwise move
+            // the add under the store's lane mask and broadcast through extra moves)
 #pragma unroll
-            for (int c = 0; c < 9; ++c) g[c] += dpp_moved<0x142>(g[c]);    // row_bcast:15
+            for (int c = 0; c < 9; ++c) {
+                g[c] += dpp_moved<0x142>(g[c]);
+                asm volatile("" : "+v"(g[c]));
+            }
             if ((lane & 31) == 31) {
                 const uint32_t slot = __float_as_uint(b4.w), half = lane >> 5;
 #pragma unroll

@@ -234,6 +234,34 @@ def test_backward_refuses_a_fast_frame_and_small_scratch(R):
     ds.release()
 
 
+@pytest.mark.parametrize("path", PATHS)
+def test_backward_refuses_an_overflowed_frame(R, path):
+    """A frame that overflowed its workspace has no complete lists to differentiate: the
+    backward call reports RGS_E_CAPACITY (from the frame's stamp, which the calling context
+    rendered), and again when asked through the workspace header (a workspace another
+    context rendered)."""
+    import torch
+    import paper_2608_15785_amd as rgs
+    from paper_2608_15785_amd import _binding as B
+    sc = wl.make_scene(2000, 1.0, -3.0, 0.5, 43)
+    cam = wl.config_camera("small", width=128, height=96)
+    ds = R.upload(sc, ("plain",))
+    dimg = torch.ones((3, 96, 128), device="cuda:0")
+    ws = B.new_workspace(sc.n, 128, 96, "plain", 64, 0)        # far fewer entries than the frame has
+    out = torch.empty((3, 96, 128), device="cuda:0")
+    B.render(R.ctx, ds, cam, path, ws, out)
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.render_backward(R.ctx, ds, cam, ws, dimg)
+    assert e.value.status == B.RGS_E_CAPACITY
+    R2 = rgs.Renderer(0)
+    with pytest.raises(rgs.RGSError) as e:
+        rgs.render_backward(R2.ctx, ds, cam, ws, dimg)
+    assert e.value.status == B.RGS_E_CAPACITY
+    torch.cuda.synchronize()
+    del R2
+    ds.release()
+
+
 def test_backward_refuses_a_stale_workspace(R):
     """The workspace records which scene state, camera and size its last frame
     came from; the backward call refuses any other frame."""
