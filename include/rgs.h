@@ -361,6 +361,9 @@ rgs_status rgs_workspace_check(rgs_ctx* ctx, const void* workspace, rgs_frame_st
  *   ranges [n_tiles][2] (uint32 start, end); per pixel [H][W]: T_final, n_proc
  *   (list entries visited, the stopping one included) and n_blend (pairs
  *   blended: past the skip test and not stopped)
+ *   tile_order [n_tiles] (uint32): the tile each rasterizer workgroup took
+ *   (a schedule, not a result: within each chunk of 8192 tiles, longest
+ *   lists first)
  * RGS_E_CAPACITY if entry_capacity is smaller than the frame's entry count.
  */
 typedef struct {
@@ -380,6 +383,7 @@ typedef struct {
     float* T_final;
     uint32_t* n_proc;
     uint32_t* n_blend;
+    uint32_t* tile_order;
 } rgs_debug_out;
 
 rgs_status rgs_render_debug(rgs_ctx* ctx, const rgs_scene* scene, const rgs_camera* cam,

@@ -112,7 +112,7 @@ class DebugOut(C.Structure):
                 ("keys_unsorted", C.c_void_p), ("vals_unsorted", C.c_void_p),
                 ("keys_sorted", C.c_void_p), ("vals_sorted", C.c_void_p),
                 ("entry_capacity", C.c_int64), ("ranges", C.c_void_p), ("T_final", C.c_void_p),
-                ("n_proc", C.c_void_p), ("n_blend", C.c_void_p)]
+                ("n_proc", C.c_void_p), ("n_blend", C.c_void_p), ("tile_order", C.c_void_p)]
 
 
 class Grads(C.Structure):
@@ -506,11 +506,12 @@ def render_debug(ctx: Context, scene: DeviceScene, cam, path: str, workspace, en
         T_final=torch.zeros((H, W), dtype=torch.float32, device=dev),
         n_proc=torch.zeros((H, W), dtype=torch.int32, device=dev),
         n_blend=torch.zeros((H, W), dtype=torch.int32, device=dev),
+        tile_order=torch.zeros(frame_plan(W, H)["n_tiles"], dtype=torch.int32, device=dev),
     )
     image = torch.zeros((3, H, W), dtype=torch.float32, device=dev)
     dbg = DebugOut(*(_ptr(t[k]) for k in ("depth", "u", "v", "cov2d", "rect", "visible", "color",
                                           "keys_unsorted", "vals_unsorted", "keys_sorted", "vals_sorted")),
-                   entry_capacity, *(_ptr(t[k]) for k in ("ranges", "T_final", "n_proc", "n_blend")))
+                   entry_capacity, *(_ptr(t[k]) for k in ("ranges", "T_final", "n_proc", "n_blend", "tile_order")))
     cc = camera_struct(cam)
     st = FrameStats()
     _check(lib.rgs_render_debug(ctx.handle, scene.handle, C.byref(cc), W, H, PATHS[path],
@@ -528,6 +529,7 @@ def render_debug(ctx: Context, scene: DeviceScene, cam, path: str, workspace, en
     out["n_proc"] = word & np.uint32(0x7FFFFFFF)          # pairs visited
     out["stopped"] = (word >> np.uint32(31)).astype(bool)  # blending stopped at the last of them
     out["n_blend"] = out["n_blend"].view(np.uint32)
+    out["tile_order"] = out["tile_order"].view(np.uint32)
     out["visible"] = out["visible"].astype(bool)
     out["image"] = image.cpu().numpy()
     out["stats"] = st.as_dict()

@@ -164,8 +164,8 @@ __global__ __launch_bounds__(BWD_LANES) void k_raster_backward(FrameDev f, WsDev
     __shared__ uint32_t s_band[BWD_BATCH];     // row bands the entry can reach
     __shared__ float4 s_acc4[9 * BWD_ROWS * BWD_BATCH / 4];   // per-row entry sums of the batch
     float* s_acc = reinterpret_cast<float*>(s_acc4);              // [9][BWD_ROWS][BWD_BATCH]
-    const uint32_t tile = blockIdx.x;      // row-major, as the rasterizers
-    if (tile >= (uint32_t)f.n_tiles) return;
+    if (blockIdx.x >= (uint32_t)f.n_tiles) return;
+    const uint32_t tile = f.ordered ? ws.order[blockIdx.x] : blockIdx.x;   // the rasterizers' schedule
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
     const uint32_t lane = threadIdx.x;
     const uint32_t lx = lane % TILE, ly0 = lane / TILE;
@@ -379,8 +379,8 @@ __global__ __launch_bounds__(TB_THREADS) void k_raster_backward_train(FrameDev f
     __shared__ float4 s_acc4[2 * 9 * 2 * TB_BATCH / 4];
     float (*s_acc)[9][2][TB_BATCH] = reinterpret_cast<float (*)[9][2][TB_BATCH]>(s_acc4);
     if (!frame_matches(ws, key)) return;
-    const uint32_t tile = blockIdx.x;        // row-major, as the rasterizers
-    if (tile >= (uint32_t)f.n_tiles) return;
+    if (blockIdx.x >= (uint32_t)f.n_tiles) return;
+    const uint32_t tile = f.ordered ? ws.order[blockIdx.x] : blockIdx.x;   // the rasterizers' schedule
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64, lane = tid % 64;

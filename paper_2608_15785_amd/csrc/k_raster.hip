@@ -41,12 +41,12 @@
 // pixel's final T and visited-pair count; the backward pass replays the same
 // lists with the same folding, so it recomputes every alpha bit for bit.
 //
-// Workgroup b renders tile b, in row-major order.  Workgroups are dispatched
-// to the 8 XCDs round-robin, so neighbouring tiles run on different XCDs at
-// about the same time: the tiles' uneven work spreads evenly over the XCDs,
-// and the records that neighbouring tiles share are read from the common
-// Infinity Cache while they are still there.  Giving each XCD one contiguous
-// band of tile rows (for its L2) was 4 % slower at 1M / 1080p, and bands of two
+// Workgroup b renders tile ws.order[b] (longest lists first, so that the grid
+// does not end on a few long tiles; see the tile-order kernel) in frames that
+// take the schedule, else tile b in row-major order.  Workgroups are
+// dispatched to the 8 XCDs round-robin, so the tiles' uneven work spreads
+// evenly over the XCDs.  Giving each XCD one contiguous band of tile rows
+// (for its L2) was 4 % slower than row-major at 1M / 1080p, and bands of two
 // rows dealt out round-robin 8 % slower.
 #include "rgs_fold.h"
 
@@ -65,8 +65,8 @@ __global__ __launch_bounds__(256) void k_raster_plain(FrameDev f, WsDev ws,
     __shared__ float4 s_a[256];   // u, v (tile-local), A, B
     __shared__ float4 s_b[256];   // C, opacity, r, g
     __shared__ float s_c[256];    // b
-    const uint32_t tile = blockIdx.x;
-    if (tile >= (uint32_t)f.n_tiles) return;
+    if (blockIdx.x >= (uint32_t)f.n_tiles) return;
+    const uint32_t tile = f.ordered ? ws.order[blockIdx.x] : blockIdx.x;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
     const uint32_t tid = threadIdx.x;
     const uint32_t lx = tid % TILE, ly = tid / TILE;
@@ -164,8 +164,8 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
     __shared__ float4 s_b[2][LIST_CAP];   // C5, C6, r, g
     __shared__ float2 s_c[2][LIST_CAP];   // b, list position (as float bits)
     __shared__ uint32_t s_cnt[2][2];      // [wave of the staging thread][list]
-    const uint32_t tile = blockIdx.x;
-    if (tile >= (uint32_t)f.n_tiles) return;
+    if (blockIdx.x >= (uint32_t)f.n_tiles) return;
+    const uint32_t tile = f.ordered ? ws.order[blockIdx.x] : blockIdx.x;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64, lane = tid % 64;
@@ -376,8 +376,8 @@ __global__ __launch_bounds__(FastShape<PIX>::THREADS) void k_raster_fast_px(Fram
     __shared__ float4 s_b[WAVES][CAP];               // C5, C6, r, g
     __shared__ float2 s_c[WAVES][CAP];               // b, list position (as float bits)
     __shared__ uint32_t s_cnt[WAVES][WAVES];         // [wave of the staging thread][list]
-    const uint32_t tile = blockIdx.x;
-    if (tile >= (uint32_t)f.n_tiles) return;
+    if (blockIdx.x >= (uint32_t)f.n_tiles) return;
+    const uint32_t tile = f.ordered ? ws.order[blockIdx.x] : blockIdx.x;
     const uint32_t tx = tile % (uint32_t)f.tiles_x, ty = tile / (uint32_t)f.tiles_x;
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid / 64, lane = tid % 64;

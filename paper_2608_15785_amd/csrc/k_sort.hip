@@ -469,4 +469,114 @@ void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t k
                            (uint32_t)f.b_d, (uint32_t)f.n_tiles);
 }
 
+// ---------------------------------------------------------------------------
+// The rasterizers' schedule.  A tile's time grows with its list, and list
+// lengths differ several-fold between tiles; workgroups are dispatched in
+// grid order, so a grid that ends on long tiles leaves most CUs idle while
+// they finish.  In frames that take the schedule (FrameDev::ordered),
+// workgroup b renders tile order[b], where order lists the tiles of each
+// chunk of ORDER_CHUNK longest first: each tile falls in one of ORDER_CLASSES
+// classes of equal width in entry count (up to the chunk's longest list) and
+// the classes follow one another in decreasing length (a
+// longest-processing-time-first schedule; on the tile costs of the 1M / 1080p
+// frame, 32 classes come within 0.2 % of an exact sort in a list-scheduling
+// model).  Inside a class tiles stay in row-major order, so that tiles that
+// run at about the same time still share some records in the caches.  No
+// result depends on the order.
+//
+// One workgroup per chunk, no atomics: thread i takes tiles i, i + 1024, ...
+// (round k), each wave ranks the tiles of one round within their class with
+// five ballots (as the radix passes rank digits), and a scan over the
+// (class, round, wave) counts places them.  The kernel takes about 10 us,
+// nearly all of it latency (the loads of the ranges, three barriers, the
+// stores); at 1M / 1080p the fast rasterizer went from 0.123 to 0.106 ms,
+// the plain one from 0.646 to 0.567 ms.
+
+constexpr uint32_t ORDER_THREADS = 1024;
+constexpr uint32_t ORDER_WAVES = ORDER_THREADS / 64;
+constexpr uint32_t ORDER_CHUNK = 8192;
+constexpr uint32_t ORDER_PER = ORDER_CHUNK / ORDER_THREADS;
+constexpr uint32_t ORDER_CLASS_BITS = 5;
+constexpr uint32_t ORDER_CLASSES = 1u << ORDER_CLASS_BITS;
+static_assert(ORDER_CLASSES * ORDER_WAVES * ORDER_PER == 4 * ORDER_THREADS, "four (class, k, wave) groups per thread");
+
+__global__ __launch_bounds__(ORDER_THREADS) void k_tile_order(WsDev ws, uint32_t n_tiles) {
+    constexpr uint32_t GROUPS = ORDER_CLASSES * ORDER_WAVES * ORDER_PER;
+    // tiles per (class, k, wave) group, class-major; the scan turns them into places
+    __shared__ uint4 s_grp4[GROUPS / 4];
+    __shared__ uint32_t s_red[ORDER_WAVES];
+    uint32_t* s_grp = reinterpret_cast<uint32_t*>(s_grp4);
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    const uint32_t t0 = blockIdx.x * ORDER_CHUNK;
+    const uint32_t t1 = min(t0 + ORDER_CHUNK, n_tiles);
+    s_grp4[tid] = make_uint4(0u, 0u, 0u, 0u);
+    // tile t0 + k * ORDER_THREADS + tid: its entry count, then the chunk's longest
+    const uint2* __restrict__ rg = reinterpret_cast<const uint2*>(ws.ranges);
+    uint32_t len[ORDER_PER];
+    uint32_t longest = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < ORDER_PER; ++k) {
+        const uint32_t t = t0 + k * ORDER_THREADS + tid;
+        len[k] = 0;
+        if (t < t1) {
+            const uint2 r = rg[t];
+            len[k] = r.y > r.x ? r.y - r.x : 0u;
+        }
+        longest = max(longest, len[k]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) longest = max(longest, (uint32_t)__shfl_xor((int)longest, off, 64));
+    if (lane == 0) s_red[wave] = longest;
+    __syncthreads();
+    longest = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < ORDER_WAVES; ++w) longest = max(longest, s_red[w]);
+    const float scale = (float)ORDER_CLASSES / ((float)longest + 1.0f);
+    // class (0 = longest lists) and rank among the tiles of the same (wave, k) group
+    uint32_t cls[ORDER_PER], rank[ORDER_PER];
+#pragma unroll
+    for (uint32_t k = 0; k < ORDER_PER; ++k) {
+        const bool valid = t0 + k * ORDER_THREADS + tid < t1;
+        const uint32_t c = ORDER_CLASSES - 1 - min(ORDER_CLASSES - 1, (uint32_t)((float)len[k] * scale));
+        uint32_t diff_lo = 0, diff_hi = 0;
+#pragma unroll
+        for (uint32_t b = 0; b < ORDER_CLASS_BITS; ++b) {
+            const uint32_t spread = (uint32_t)((int32_t)(c << (31 - b)) >> 31);
+            const uint64_t m = __ballot(spread != 0);
+            diff_lo = __builtin_amdgcn_bitop3_b32((uint32_t)m, spread, diff_lo, 0xBE);
+            diff_hi = __builtin_amdgcn_bitop3_b32((uint32_t)(m >> 32), spread, diff_hi, 0xBE);
+        }
+        const uint64_t vmask = __ballot(valid);
+        const uint32_t peers_lo = ~diff_lo & (uint32_t)vmask, peers_hi = ~diff_hi & (uint32_t)(vmask >> 32);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+        cls[k] = c;
+        rank[k] = below;
+        if (valid && below == 0)
+            s_grp[(c * ORDER_PER + k) * ORDER_WAVES + wave] = (uint32_t)(__popc(peers_lo) + __popc(peers_hi));
+    }
+    __syncthreads();
+    // places: exclusive scan of the group counts, four consecutive groups per thread
+    const uint4 g = s_grp4[tid];
+    const uint32_t sum4 = g.x + g.y + g.z + g.w;
+    const uint32_t incl = wave_inclusive_scan(sum4);
+    if (lane == 63) s_red[wave] = incl;
+    __syncthreads();
+    uint32_t before = incl - sum4;
+    for (uint32_t w = 0; w < wave; ++w) before += s_red[w];
+    s_grp4[tid] = make_uint4(before, before + g.x, before + g.x + g.y, before + g.x + g.y + g.z);
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < ORDER_PER; ++k) {
+        const uint32_t t = t0 + k * ORDER_THREADS + tid;
+        if (t < t1) ws.order[t0 + s_grp[(cls[k] * ORDER_PER + k) * ORDER_WAVES + wave] + rank[k]] = t;
+    }
+}
+
+void launch_tile_order(hipStream_t s, const FrameDev& f, const WsDev& ws) {
+    if (!f.ordered) return;
+    const uint32_t n_tiles = (uint32_t)f.n_tiles;
+    hipLaunchKernelGGL(k_tile_order, dim3((n_tiles + ORDER_CHUNK - 1) / ORDER_CHUNK), dim3(ORDER_THREADS), 0, s,
+                       ws, n_tiles);
+}
+
 }  // namespace rgs

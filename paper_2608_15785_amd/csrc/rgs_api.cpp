@@ -550,6 +550,8 @@ static void make_layout(int64_t n, const rgs_plan& p, int32_t path, uint64_t cap
     L.zero_end = off;
     L.params = off;                  // written by the reset kernel, outside the zeroed span
     off = align256(off + sizeof(FrameParams));
+    L.order = off;                   // written whole by the tile-order kernel
+    off = align256(off + (uint64_t)p.n_tiles * 4);
     L.records = off;
     off = align256(off + (uint64_t)n * sizeof(Record));
     L.counts = L.rects = L.depths = L.offsets = L.masks = 0;
@@ -665,6 +667,7 @@ static WsDev ws_pointers(void* base, const WsLayout& L) {
     w.params = reinterpret_cast<const FrameParams*>(b + L.params);
     w.header = reinterpret_cast<WsHeader*>(b + L.header);
     w.ranges = reinterpret_cast<uint32_t*>(b + L.ranges);
+    w.order = reinterpret_cast<uint32_t*>(b + L.order);
     w.fe_state = reinterpret_cast<uint64_t*>(b + L.fe_state);
     w.records = reinterpret_cast<Record*>(b + L.records);
     w.counts = L.counts ? reinterpret_cast<uint32_t*>(b + L.counts) : nullptr;
@@ -891,6 +894,7 @@ rgs_status rgs::prepare_frame(const rgs_scene* sc, int32_t W, int32_t H, int32_t
     f.passes = (int32_t)fl->L.passes;
     f.capacity = (uint32_t)cap;
     f.n_gaussians = (uint32_t)sc->n;
+    f.ordered = (base == RGS_PATH_PLAIN || p.n_tiles <= ORDER_MAX_TILES) ? 1u : 0u;
     fl->plain = PlainSceneDev{sc->plain, sc->n_pad, sc->n};
     fl->fast = FastSceneDev{sc->fast, sc->n_pad, sc->n, sc->plain};
     return RGS_OK;
@@ -928,6 +932,7 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
     launch_sort(st, fl.f, w, fl.L.key_bytes, fl.L.passes, fl.sort_fallback, &in_b);
     mark(3);
     launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
+    launch_tile_order(st, fl.f, w);
     mark(4);
     if (fl.path == RGS_PATH_PLAIN && (fl.opts & OPT_HW_EXP2)) launch_raster_train(st, fl.f, w, in_b, count);
     else if (fl.path == RGS_PATH_PLAIN) launch_raster_plain(st, fl.f, w, in_b, count);
@@ -1047,6 +1052,15 @@ static rgs_status render_impl(rgs_ctx* ctx, const rgs_scene* sc, const rgs_camer
             HIP_TRY(hipMemcpyAsync(dbg->n_proc, w.n_proc, (uint64_t)W * H * 4, hipMemcpyDeviceToDevice, st));
         if (dbg->n_blend)
             HIP_TRY(hipMemcpyAsync(dbg->n_blend, w.n_blend, (uint64_t)W * H * 4, hipMemcpyDeviceToDevice, st));
+        if (dbg->tile_order && fl.f.ordered) {
+            HIP_TRY(hipMemcpyAsync(dbg->tile_order, w.order, (uint64_t)fl.plan.n_tiles * 4,
+                                   hipMemcpyDeviceToDevice, st));
+        } else if (dbg->tile_order) {
+            std::vector<uint32_t> rowmajor((size_t)fl.plan.n_tiles);
+            for (size_t t = 0; t < rowmajor.size(); ++t) rowmajor[t] = (uint32_t)t;
+            HIP_TRY(hipMemcpyAsync(dbg->tile_order, rowmajor.data(), rowmajor.size() * 4, hipMemcpyHostToDevice, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
         HIP_TRY(hipGetLastError());
     }
     if (stats || dbg) {

@@ -27,11 +27,33 @@ def _log(msg):
     sys.stdout.flush()
 
 
+ORDER_CHUNK, ORDER_CLASSES, ORDER_MAX_TILES = 8192, 32, 16384
+
+
+def check_tile_order(order, ranges, path):
+    """The rasterizers' schedule.  Plain-path frames and fast-path frames of at most 16384
+    tiles: within each chunk of 8192 tiles a permutation of the chunk, longest lists first
+    up to one class width (a 32nd of the chunk's longest).  Other frames: row-major."""
+    if not (path.startswith("plain") or len(ranges) <= ORDER_MAX_TILES):
+        assert np.array_equal(order, np.arange(len(ranges))), "expected the row-major schedule"
+        return
+    lengths = ranges[:, 1].astype(np.int64) - ranges[:, 0].astype(np.int64)
+    for c0 in range(0, len(ranges), ORDER_CHUNK):
+        c1 = min(c0 + ORDER_CHUNK, len(ranges))
+        o = order[c0:c1].astype(np.int64)
+        assert np.array_equal(np.sort(o), np.arange(c0, c1)), f"chunk {c0}: not a permutation"
+        L = lengths[o]
+        width = (L.max() + 1) / ORDER_CLASSES
+        later_max = np.maximum.accumulate(L[::-1])[::-1]
+        assert np.all(later_max[1:] <= L[:-1] + width + 1), f"chunk {c0}: a longer list is scheduled later"
+
+
 def run_parity(R, scene, cam, path, tiles=None, entries=True):
     _log(f"[parity] path={path} n={scene.n} {cam.width}x{cam.height} tiles={'all' if tiles is None else len(tiles)}")
     ds = R.upload(scene, (path,))
     g = R.render_debug(ds, cam, path)
     ds.release()
+    check_tile_order(g["tile_order"], g["ranges"], path)
     fr = oracle_frame(scene, cam, path, tiles=tiles)
     compare_front_end(g, fr)
     if entries:
