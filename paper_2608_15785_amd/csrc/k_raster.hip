@@ -161,8 +161,8 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
     constexpr bool EXACT = EXPM == EXP_LIBM;
     // per-wave lists of folded Gaussians, in depth order
     __shared__ float4 s_a[2][LIST_CAP];   // C1, C2, C3, C4
-    __shared__ float4 s_b[2][LIST_CAP];   // C5, C6, r, g
-    __shared__ float2 s_c[2][LIST_CAP];   // b, list position (as float bits)
+    __shared__ float2 s_b[2][LIST_CAP];   // C5, C6
+    __shared__ float4 s_c[2][LIST_CAP];   // r, g, b, list position (as float bits)
     __shared__ uint32_t s_cnt[2][2];      // [wave of the staging thread][list]
     if (blockIdx.x >= (uint32_t)f.n_tiles) return;
     const uint32_t tile = f.ordered ? ws.order[blockIdx.x] : blockIdx.x;
@@ -213,14 +213,14 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
         if (hit0) {
             const uint32_t p = off0 + (uint32_t)__popcll(m0 & lt);
             s_a[0][p] = ca;
-            s_b[0][p] = cbv;
-            s_c[0][p] = make_float2(cb, posf);
+            s_b[0][p] = make_float2(cbv.x, cbv.y);
+            s_c[0][p] = make_float4(cbv.z, cbv.w, cb, posf);
         }
         if (hit1) {
             const uint32_t p = off1 + (uint32_t)__popcll(m1 & lt);
             s_a[1][p] = ca;
-            s_b[1][p] = cbv;
-            s_c[1][p] = make_float2(cb, posf);
+            s_b[1][p] = make_float2(cbv.x, cbv.y);
+            s_c[1][p] = make_float4(cbv.z, cbv.w, cb, posf);
         }
         const uint32_t n0 = s_cnt[0][0] + s_cnt[1][0], n1 = s_cnt[0][1] + s_cnt[1][1];
         // inert padding up to a multiple of the unroll: P = -1e30 is always skipped
@@ -228,8 +228,8 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
             const uint32_t w = tid / LIST_UNROLL, k = tid % LIST_UNROLL;
             const uint32_t p = (w ? n1 : n0) + k;
             s_a[w][p] = make_float4(0.f, 0.f, 0.f, 0.f);
-            s_b[w][p] = make_float4(0.f, -1.0e30f, 0.f, 0.f);
-            s_c[w][p] = make_float2(0.f, 0.f);
+            s_b[w][p] = make_float2(0.f, -1.0e30f);
+            s_c[w][p] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         __syncthreads();
 
@@ -237,26 +237,22 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
         // (the list length is the same for the whole wave: keep it scalar)
         const uint32_t n = __builtin_amdgcn_readfirstlane(wave ? n1 : n0);
         const float4* __restrict__ la = s_a[wave];
-        const float4* __restrict__ lb = s_b[wave];
-        const float2* __restrict__ lc = s_c[wave];
+        const float2* __restrict__ lb = s_b[wave];
+        const float4* __restrict__ lc = s_c[wave];
         if (__ballot(live0 || live1) != 0) {
             bool wave_done = false;     // every pixel of the wave has stopped
             for (uint32_t k0 = 0; k0 < n && !wave_done; k0 += LIST_UNROLL) {
                 if (COUNT) steps += LIST_UNROLL;
                 float P0s[LIST_UNROLL], P1s[LIST_UNROLL];
-                float4 ms[LIST_UNROLL];
-                float2 cs[LIST_UNROLL];
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) {
                     const float4 a = la[k0 + u];
-                    ms[u] = lb[k0 + u];
-                    cs[u] = lc[k0 + u];
-                    folded_exponents(a, ms[u].x, ms[u].y, x, y, x2, xy, y2, y21, P0s[u], P1s[u]);
+                    const float2 e = lb[k0 + u];
+                    folded_exponents(a, e.x, e.y, x, y, x2, xy, y2, y21, P0s[u], P1s[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) {
-                    const float4 m = ms[u];
-                    const float2 c = cs[u];
+                    const float4 c = lc[k0 + u];
                     const float P0 = P0s[u];
                     const float P1 = P1s[u];
                     constexpr float SKIP = EXPM == EXP_HW2 ? -LOG2_255F : -LN255F;
@@ -279,8 +275,8 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
                     }
                     const float w0 = al0 * T0, w1 = al1 * T1;
                     float Tn0 = T0 - w0, Tn1 = T1 - w1;
-                    float nr0 = fmaf(w0, m.z, r0), ng0 = fmaf(w0, m.w, g0), nb0 = fmaf(w0, c.x, b0);
-                    float nr1 = fmaf(w1, m.z, r1), ng1 = fmaf(w1, m.w, g1), nb1 = fmaf(w1, c.x, b1);
+                    float nr0 = fmaf(w0, c.x, r0), ng0 = fmaf(w0, c.y, g0), nb0 = fmaf(w0, c.z, b0);
+                    float nr1 = fmaf(w1, c.x, r1), ng1 = fmaf(w1, c.y, g1), nb1 = fmaf(w1, c.z, b1);
                     const bool s0 = Tn0 < T_MIN, s1 = Tn1 < T_MIN;
                     if (COUNT) {
                         nbl0 += (al0 > 0.0f && !s0) ? 1u : 0u;
@@ -288,7 +284,7 @@ __global__ __launch_bounds__(FAST_THREADS) void k_raster_fast(FrameDev f, WsDev 
                     }
                     if (__ballot(s0 || s1) != 0) {
                         // a pixel reached the stop: that pair is not blended
-                        const uint32_t at = __float_as_uint(c.y);
+                        const uint32_t at = __float_as_uint(c.w);
                         if (s0) {
                             live0 = false;
                             stop0 = at;
