@@ -165,11 +165,11 @@ __device__ inline uint32_t poll_range(const uint32_t* tab, uint32_t r0, uint32_t
 // waits on another without bound: the workgroups of a grid are not
 // guaranteed to run at once.
 template <typename KeyT>
-__device__ uint32_t fallback_range(const WsDev& ws, uint32_t pass, bool groups, uint32_t r0, uint32_t r1,
+__device__ uint32_t fallback_range(const WsDev& ws, uint32_t set, bool groups, uint32_t r0, uint32_t r1,
                                    const KeyT* __restrict__ kin, uint32_t n, uint32_t shift, const LookbackLds& L,
                                    bool force) {
     const uint32_t tid = threadIdx.x, d = tid % RADIX, s = tid / RADIX;
-    const uint32_t* tiles = sort_state_tiles(ws, pass & 1);
+    const uint32_t* tiles = sort_state_tiles(ws, set);
     uint32_t sum = 0;
     for (uint32_t r = r0; r < r1; ++r) {
         const bool mine = (r - r0) % SORT_SPLIT == s;
@@ -195,7 +195,7 @@ template <typename KeyT, bool FORCE>
 __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restrict__ kin,
                                                              const uint32_t* __restrict__ vin,
                                                              KeyT* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                             WsDev ws, uint32_t pass) {
+                                                             WsDev ws, uint32_t pass, uint32_t seq) {
     constexpr int ITEMS = SortTile<KeyT>::ITEMS;
     constexpr int SIZE = SortTile<KeyT>::SIZE;
     // per-wave digit counts, then each wave's offset inside the tile's digit
@@ -219,8 +219,11 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
     __syncthreads();
     const uint32_t shift = 8 * pass;
     const uint32_t n_valid = min((uint32_t)SIZE, n - tile_base);
-    uint32_t* cur_tiles = sort_state_tiles(ws, pass & 1);
-    uint32_t* cur_groups = sort_state_groups(ws, pass & 1);
+    // look-back words: set seq & 1 (launch seq of the frame's sort), the next
+    // launch's set cleared below
+    const uint32_t set = seq & 1;
+    uint32_t* cur_tiles = sort_state_tiles(ws, set);
+    uint32_t* cur_groups = sort_state_groups(ws, set);
     // the bucket sizes do not depend on this tile: start the loads first
     uint32_t bucket = 0;
     if (tid < RADIX) {
@@ -244,9 +247,9 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
     // the next pass's look-back words of this tile (its set was last read by
     // the previous pass, which has finished)
     if (tid < RADIX) {
-        st_state(&sort_state_tiles(ws, (pass + 1) & 1)[(uint64_t)vb * RADIX + tid], 0u);
+        st_state(&sort_state_tiles(ws, set ^ 1u)[(uint64_t)vb * RADIX + tid], 0u);
         if (vb % SORT_GROUP == 0)
-            st_state(&sort_state_groups(ws, (pass + 1) & 1)[(uint64_t)(vb / SORT_GROUP) * RADIX + tid], 0u);
+            st_state(&sort_state_groups(ws, set ^ 1u)[(uint64_t)(vb / SORT_GROUP) * RADIX + tid], 0u);
     }
     const uint64_t lt = lanemask_lt();
     // Lanes of a wave read counters that other lanes of the same wave wrote in
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
         if (__ballot(!ok) != 0 && lane == 0) s_missed[0] = 1;
         __syncthreads();
         if (s_missed[0]) {
-            part = fallback_range(ws, pass, false, g0, vb, kin, n, shift, L, force);
+            part = fallback_range(ws, set, false, g0, vb, kin, n, shift, L, force);
             s_part[s * RADIX + d] = part;
             __syncthreads();
             ok = !force;
@@ -352,8 +355,8 @@ __global__ __launch_bounds__(SORT_THREADS) void k_radix_pass(const KeyT* __restr
     __syncthreads();
     if (s_missed[1]) {
         // a predecessor's counts were not published in time: take both ranges again
-        part = fallback_range(ws, pass, false, g0, vb, kin, n, shift, L, force) +
-               fallback_range(ws, pass, true, 0, g, kin, n, shift, L, force);
+        part = fallback_range(ws, set, false, g0, vb, kin, n, shift, L, force) +
+               fallback_range(ws, set, true, 0, g, kin, n, shift, L, force);
         s_part[s * RADIX + d] = part;
         __syncthreads();
     }
@@ -385,11 +388,11 @@ static void sort_typed(hipStream_t s, const WsDev& ws, uint32_t passes, bool* re
         if (force)
             hipLaunchKernelGGL((k_radix_pass<KeyT, true>), grid, block, 0, s, from_a ? ka : kb,
                                from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
-                               ws, p);
+                               ws, p, p);
         else
             hipLaunchKernelGGL((k_radix_pass<KeyT, false>), grid, block, 0, s, from_a ? ka : kb,
                                from_a ? ws.vals_a : ws.vals_b, from_a ? kb : ka, from_a ? ws.vals_b : ws.vals_a,
-                               ws, p);
+                               ws, p, p);
     }
     *result_in_b = (passes % 2) == 1;
 }
@@ -401,6 +404,283 @@ void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key
     // counts its rows from the keys instead of reading the published words
     if (key_bytes == 8) sort_typed<uint64_t>(s, ws, passes, result_in_b, force);
     else sort_typed<uint32_t>(s, ws, passes, result_in_b, force);
+}
+
+// ---------------------------------------------------------------------------
+// Bucket sort of the fast path's 32-bit keys, for frames of 2^8 .. 2^BUCKET_MAX_BT
+// tile bits (FrameDev b_t).  The same stable LSD radix sort, reorganised:
+//   * one radix pass as above on the top digit (key bits 24..31) moves every
+//     entry to its digit's bucket, in input order.  With b_t >= 8 the top digit
+//     is tile >> (b_t - 8), so a bucket holds 2^(b_t - 8) whole tiles;
+//   * one workgroup per bucket then takes the bucket's three remaining digits
+//     (bits 0..23), least significant first, each a stable counting pass
+//     ranked with wave64 ballots as above.  A bucket of at most BK_CAP entries
+//     stays in LDS for all three; a larger one streams through global memory
+//     in chunks of BK_CAP, one stable pass at a time;
+//   * the same workgroup, holding its bucket sorted, writes its tiles' ranges.
+// Every pass is stable and the top digit is taken first, then bits 0..23
+// least significant first; as a stable sort on the top digit followed by a
+// stable sort on the rest leaves the keys ordered by (top digit, rest) with
+// ties in input order, the result is the LSD sort's, bit for bit.  The frame
+// then needs two sort kernels instead of four passes and the ranges kernel.
+
+constexpr int BK_THREADS = 1024;
+constexpr int BK_WAVES = BK_THREADS / 64;
+constexpr int BK_ITEMS = 16;
+constexpr uint32_t BK_CAP = BK_THREADS * BK_ITEMS;     // 16384 entries: 128 KB of keys and values
+constexpr int BK_DIGITS = 3;                             // bits 0..23 after the top digit
+
+// Block-wide: bucket blockIdx.x is [b0, b0 + cnt) of the top-digit pass's
+// output, from the front end's counts of the top digit (as that pass placed
+// it), clipped to the entries the workspace holds.
+__device__ inline void bucket_span(const WsDev& ws, uint32_t n, uint32_t* s_span, uint32_t* s_wtot, uint32_t& b0,
+                                   uint32_t& cnt) {
+    const uint32_t tid = threadIdx.x;
+    uint32_t c = 0;
+    if (tid < RADIX) {
+#pragma unroll
+        for (int h = 0; h < HIST_COPIES; ++h) c += ws.hist[((uint64_t)h * MAX_PASSES + 3) * RADIX + tid];
+    }
+    const uint32_t excl = digit_exclusive_scan(c, s_wtot);
+    if (tid == blockIdx.x) {
+        s_span[0] = excl;
+        s_span[1] = c;
+    }
+    __syncthreads();
+    b0 = s_span[0];
+    cnt = b0 < n ? min(s_span[1], n - b0) : 0u;
+}
+
+// Block-wide stable ranking of up to BK_CAP keys.  Wave w holds entries
+// [w R 64, (w + 1) R 64) of the chunk, round r and lane l holding entry
+// (w R + r) 64 + l, with R = ceil(cnt / BK_THREADS) <= BK_ITEMS rounds, so
+// that all sixteen waves share the work.  pos[r] is the key's place when the
+// chunk is ordered by the digit at `shift` (ties in entry order), s_tot[d] the
+// chunk's count of digit d and s_bs[d] its first place.  Every thread calls it
+// (barriers).
+__device__ inline void bucket_rank(const uint32_t (&k)[BK_ITEMS], uint32_t cnt, uint32_t R, uint32_t shift,
+                                   uint32_t (&pos)[BK_ITEMS], uint32_t* s_whist, uint32_t* s_tot, uint32_t* s_bs,
+                                   uint32_t* s_wtot) {
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    // entries of this wave that exist: round r, lane l holds one when r < R and r * 64 + l < lim
+    const int lim = __builtin_amdgcn_readfirstlane((int)cnt - (int)(wave * R * 64));
+    for (uint32_t i = tid; i < BK_WAVES * RADIX; i += BK_THREADS) s_whist[i] = 0;
+    __syncthreads();
+    uint32_t* my_hist = s_whist + wave * RADIX;
+#pragma unroll
+    for (int r = 0; r < BK_ITEMS; ++r) {
+        if ((uint32_t)r >= R) break;
+        // a wave's rounds read counters its lanes wrote in the round before
+        // (see the pass kernel); pos[r] holds the rank among the wave's keys
+        // of the same digit until the scan below.  The key passes through an
+        // empty asm so that the compiler does not start later rounds' ballots
+        // early: sixteen rounds of eight 64-bit masks would not fit the SGPRs.
+        asm volatile("" ::: "memory");
+        uint32_t key = k[r];
+        asm volatile("" : "+v"(key));
+        const bool valid = (int)lane < lim - r * 64;
+        const uint32_t d = (key >> shift) & (RADIX - 1);
+        uint32_t diff_lo = 0, diff_hi = 0;
+#pragma unroll
+        for (int b = 0; b < RADIX_BITS; ++b) {
+            const uint32_t spread = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+            const uint64_t m = __ballot(spread != 0);
+            diff_lo = __builtin_amdgcn_bitop3_b32((uint32_t)m, spread, diff_lo, 0xBE);
+            diff_hi = __builtin_amdgcn_bitop3_b32((uint32_t)(m >> 32), spread, diff_hi, 0xBE);
+        }
+        const uint64_t vmask = __ballot(valid);
+        const uint32_t peers_lo = ~diff_lo & (uint32_t)vmask, peers_hi = ~diff_hi & (uint32_t)(vmask >> 32);
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+        const uint32_t prev = valid ? my_hist[d] : 0u;
+        pos[r] = prev + below;
+        if (valid && below == 0) my_hist[d] = prev + (uint32_t)(__popc(peers_lo) + __popc(peers_hi));
+    }
+    __syncthreads();
+    // digit d = tid: each wave's offset inside the chunk's digit run (all
+    // sixteen counts loaded before any is rewritten)
+    uint32_t tot = 0;
+    if (tid < RADIX) {
+        uint32_t c[BK_WAVES];
+#pragma unroll
+        for (int w = 0; w < BK_WAVES; ++w) c[w] = s_whist[w * RADIX + tid];
+#pragma unroll
+        for (int w = 0; w < BK_WAVES; ++w) {
+            s_whist[w * RADIX + tid] = tot;
+            tot += c[w];
+        }
+        s_tot[tid] = tot;
+    }
+    const uint32_t bs = digit_exclusive_scan(tot, s_wtot);
+    if (tid < RADIX) s_bs[tid] = bs;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < BK_ITEMS; ++r) {
+        if ((uint32_t)r >= R) break;
+        const uint32_t d = (k[r] >> shift) & (RADIX - 1);
+        pos[r] += s_bs[d] + my_hist[d];
+    }
+}
+
+// FORCE: every bucket through the global-memory path (for tests).
+template <bool FORCE>
+__global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin, const uint32_t* vin,
+                                                            uint32_t* kout, uint32_t* vout, WsDev ws, uint32_t b_d,
+                                                            uint32_t n_tiles) {
+    __shared__ uint32_t s_keys[BK_CAP];
+    __shared__ uint32_t s_vals[BK_CAP];
+    __shared__ uint32_t s_whist[BK_WAVES * RADIX];
+    __shared__ uint32_t s_tot[RADIX];
+    __shared__ uint32_t s_bs[RADIX];
+    __shared__ uint32_t s_base[RADIX];
+    __shared__ uint32_t s_wtot[RADIX / 64];
+    __shared__ uint32_t s_span[2];
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    const uint32_t n = entry_count(ws.header);
+    uint32_t b0, cnt;
+    bucket_span(ws, n, s_span, s_wtot, b0, cnt);
+    if (cnt == 0) return;
+    // Entry e of a chunk in LDS is held in round r < R by (wave, lane) with
+    // e = (wave R + r) 64 + lane, the layout of bucket_rank; the values are
+    // read after the ranking, which needs only the keys.  The bounds are
+    // wave-uniform counts against the lane index, so that no per-entry index
+    // stays live across the passes.
+    uint32_t k[BK_ITEMS], v[BK_ITEMS], pos[BK_ITEMS];
+
+    if (!FORCE && cnt <= BK_CAP) {
+        // ---- the bucket in LDS: three stable passes ----
+        const uint32_t R = (cnt + BK_THREADS - 1) / BK_THREADS;
+        const uint32_t* wkeys = s_keys + wave * R * 64 + lane;
+        const uint32_t* wvals = s_vals + wave * R * 64 + lane;
+        const int lim = __builtin_amdgcn_readfirstlane((int)cnt - (int)(wave * R * 64));
+        for (uint32_t e = tid; e < cnt; e += BK_THREADS) {
+            s_keys[e] = kin[b0 + e];
+            s_vals[e] = vin[b0 + e];
+        }
+        __syncthreads();
+        for (int q = 0; q < BK_DIGITS; ++q) {
+#pragma unroll
+            for (int r = 0; r < BK_ITEMS; ++r)
+                k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wkeys[r * 64] : 0u;
+            bucket_rank(k, cnt, R, 8 * q, pos, s_whist, s_tot, s_bs, s_wtot);
+#pragma unroll
+            for (int r = 0; r < BK_ITEMS; ++r)
+                v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wvals[r * 64] : 0u;
+            __syncthreads();        // every entry read before any is moved
+#pragma unroll
+            for (int r = 0; r < BK_ITEMS; ++r)
+                if ((uint32_t)r < R && (int)lane < lim - r * 64) {
+                    s_keys[pos[r]] = k[r];
+                    s_vals[pos[r]] = v[r];
+                }
+            __syncthreads();
+        }
+        // sorted: write the bucket and its tiles' runs
+        for (uint32_t e = tid; e < cnt; e += BK_THREADS) {
+            const uint32_t key = s_keys[e];
+            kout[b0 + e] = key;
+            vout[b0 + e] = s_vals[e];
+            const uint32_t t = key >> b_d;
+            if (t >= n_tiles) {          // only after a failed front end
+                atomicOr(&ws.header->error, 4u);
+                continue;
+            }
+            if (e == 0 || (s_keys[e - 1] >> b_d) != t) ws.ranges[2 * t] = b0 + e;
+            if (e + 1 == cnt || (s_keys[e + 1] >> b_d) != t) ws.ranges[2 * t + 1] = b0 + e + 1;
+        }
+        return;
+    }
+
+    // ---- a bucket larger than the LDS ----
+    // Each of the three passes streams it through global memory in chunks of
+    // BK_CAP: a histogram sweep, then the chunks in order, each ranked in LDS
+    // and scattered after the chunks before it.  Pass q reads src and writes
+    // dst, alternating kout and the input buffer, so that the third pass ends
+    // in kout.  Reads of what this workgroup wrote in the previous pass bypass
+    // the CU's vector cache.
+    for (int q = 0; q < BK_DIGITS; ++q) {
+        const uint32_t shift = 8 * q;
+        const uint32_t* ks = q == 1 ? kout : kin;
+        const uint32_t* vs = q == 1 ? vout : vin;
+        uint32_t* kd = q == 1 ? const_cast<uint32_t*>(kin) : kout;
+        uint32_t* vd = q == 1 ? const_cast<uint32_t*>(vin) : vout;
+        if (tid < RADIX) s_tot[tid] = 0;
+        __syncthreads();
+        for (uint32_t i = tid; i < cnt; i += BK_THREADS)
+            atomicAdd(&s_tot[(ld_state(&ks[b0 + i]) >> shift) & (RADIX - 1)], 1u);
+        __syncthreads();
+        const uint32_t base = digit_exclusive_scan(tid < RADIX ? s_tot[tid] : 0u, s_wtot);
+        if (tid < RADIX) s_base[tid] = base;
+        __syncthreads();
+        for (uint32_t c0 = 0; c0 < cnt; c0 += BK_CAP) {
+            const uint32_t ccnt = min(BK_CAP, cnt - c0);
+            for (uint32_t e = tid; e < ccnt; e += BK_THREADS) {
+                s_keys[e] = ld_state(&ks[b0 + c0 + e]);
+                s_vals[e] = ld_state(&vs[b0 + c0 + e]);
+            }
+            __syncthreads();
+            const uint32_t R = (ccnt + BK_THREADS - 1) / BK_THREADS;
+            const uint32_t* wkeys = s_keys + wave * R * 64 + lane;
+            const uint32_t* wvals = s_vals + wave * R * 64 + lane;
+            const int lim = __builtin_amdgcn_readfirstlane((int)ccnt - (int)(wave * R * 64));
+#pragma unroll
+            for (int r = 0; r < BK_ITEMS; ++r)
+                k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wkeys[r * 64] : 0u;
+            bucket_rank(k, ccnt, R, shift, pos, s_whist, s_tot, s_bs, s_wtot);
+#pragma unroll
+            for (int r = 0; r < BK_ITEMS; ++r)
+                v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wvals[r * 64] : 0u;
+#pragma unroll
+            for (int r = 0; r < BK_ITEMS; ++r) {
+                if ((uint32_t)r < R && (int)lane < lim - r * 64) {
+                    const uint32_t d = (k[r] >> shift) & (RADIX - 1);
+                    const uint32_t dst = b0 + s_base[d] + pos[r] - s_bs[d];
+                    if (dst < n) {      // always true for consistent counts
+                        kd[dst] = k[r];
+                        vd[dst] = v[r];
+                    }
+                }
+            }
+            // the stores reach the L2 before any thread of the workgroup reads
+            // them back (the next chunk's LDS staging, the next pass, the ranges)
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid < RADIX) s_base[tid] += s_tot[tid];
+            __syncthreads();
+        }
+    }
+    for (uint32_t e = tid; e < cnt; e += BK_THREADS) {
+        const uint32_t t = ld_state(&kout[b0 + e]) >> b_d;
+        if (t >= n_tiles) {
+            atomicOr(&ws.header->error, 4u);
+            continue;
+        }
+        if (e == 0 || (ld_state(&kout[b0 + e - 1]) >> b_d) != t) ws.ranges[2 * t] = b0 + e;
+        if (e + 1 == cnt || (ld_state(&kout[b0 + e + 1]) >> b_d) != t) ws.ranges[2 * t + 1] = b0 + e + 1;
+    }
+}
+
+bool bucket_sort_applies(const FrameDev& f, uint32_t key_bytes) {
+    return key_bytes == 4 && f.b_t >= 8 && f.b_t <= BUCKET_MAX_BT;
+}
+
+void launch_sort_bucket(hipStream_t s, const FrameDev& f, const WsDev& ws, bool force, bool* result_in_b) {
+    uint32_t* ka = reinterpret_cast<uint32_t*>(ws.keys_a);
+    uint32_t* kb = reinterpret_cast<uint32_t*>(ws.keys_b);
+    // the top digit: keys_a -> keys_b, look-back set 0 (cleared by the front end)
+    if (force)
+        hipLaunchKernelGGL((k_radix_pass<uint32_t, true>), dim3(ws.sort_rows), dim3(SORT_THREADS), 0, s, ka,
+                           ws.vals_a, kb, ws.vals_b, ws, 3u, 0u);
+    else
+        hipLaunchKernelGGL((k_radix_pass<uint32_t, false>), dim3(ws.sort_rows), dim3(SORT_THREADS), 0, s, ka,
+                           ws.vals_a, kb, ws.vals_b, ws, 3u, 0u);
+    // each bucket: keys_b -> keys_a, with its tiles' ranges
+    if (force)
+        hipLaunchKernelGGL(k_bucket_sort<true>, dim3(RADIX), dim3(BK_THREADS), 0, s, kb, ws.vals_b, ka, ws.vals_a,
+                           ws, (uint32_t)f.b_d, (uint32_t)f.n_tiles);
+    else
+        hipLaunchKernelGGL(k_bucket_sort<false>, dim3(RADIX), dim3(BK_THREADS), 0, s, kb, ws.vals_b, ka, ws.vals_a,
+                           ws, (uint32_t)f.b_d, (uint32_t)f.n_tiles);
+    *result_in_b = false;
 }
 
 // ---------------------------------------------------------------------------

@@ -929,9 +929,14 @@ rgs_status rgs::enqueue_frame(hipStream_t st, const FrameLaunch& fl, const Frame
         if (s != RGS_OK) return s;
     }
     bool in_b = false;
-    launch_sort(st, fl.f, w, fl.L.key_bytes, fl.L.passes, fl.sort_fallback, &in_b);
-    mark(3);
-    launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
+    if (bucket_sort_applies(fl.f, fl.L.key_bytes)) {
+        launch_sort_bucket(st, fl.f, w, fl.sort_fallback, &in_b);     // the ranges come with it
+        mark(3);
+    } else {
+        launch_sort(st, fl.f, w, fl.L.key_bytes, fl.L.passes, fl.sort_fallback, &in_b);
+        mark(3);
+        launch_ranges(st, fl.f, w, fl.L.key_bytes, in_b);
+    }
     launch_tile_order(st, fl.f, w);
     mark(4);
     if (fl.path == RGS_PATH_PLAIN && (fl.opts & OPT_HW_EXP2)) launch_raster_train(st, fl.f, w, in_b, count);

@@ -527,6 +527,12 @@ void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t k
                    bool result_in_b);
 // The rasterizers' schedule: ws.order from the tile ranges.
 void launch_tile_order(hipStream_t s, const FrameDev& f, const WsDev& ws);
+// The fast path's bucket sort (frames of 8 .. BUCKET_MAX_BT tile bits, 32-bit
+// keys): sorted keys and values end in keys_a / vals_a, and the tile ranges
+// are written too (no launch_ranges).
+constexpr int32_t BUCKET_MAX_BT = 14;
+bool bucket_sort_applies(const FrameDev& f, uint32_t key_bytes);
+void launch_sort_bucket(hipStream_t s, const FrameDev& f, const WsDev& ws, bool force, bool* result_in_b);
 void launch_raster_plain(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count);
 void launch_raster_train(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count);
 void launch_raster_fast(hipStream_t s, const FrameDev& f, const WsDev& ws, bool result_in_b, bool count,

@@ -59,7 +59,8 @@ def run_parity(R, scene, cam, path, tiles=None, entries=True):
     if entries:
         compare_entries(g, fr)
     rep = compare_image(g["image"], fr, path)
-    rep.update(n_entries=int(g["stats"]["n_entries"]), n_visible=int(g["stats"]["n_visible"]))
+    rep.update(n_entries=int(g["stats"]["n_entries"]), n_visible=int(g["stats"]["n_visible"]),
+               max_tile_entries=int((g["ranges"][:, 1].astype(np.int64) - g["ranges"][:, 0]).max()))
     # pair evaluations agree with the oracle's count except where a decision was flagged
     mask = ~fr.flagged & ~(fr.mode_slack > 0) & ~np.isnan(fr.T_final)
     assert np.array_equal(g["n_proc"][mask], fr.n_proc[mask].astype(np.uint32)), "pair counts differ"
@@ -109,6 +110,20 @@ def test_equal_keys_keep_index_order(R, path):
     idx = np.tile(np.arange(40), 150)
     sc = base.subset(idx)
     run_parity(R, sc, wl.config_camera("small", width=128, height=96), path)
+
+
+def test_bucket_larger_than_lds(R):
+    """4000 copies of 40 Gaussians at 256x256.  The frame has 256 tiles, so each of the fast
+    sort's buckets holds one tile, and the most covered tile gets more entries than a bucket
+    the LDS can hold (16384): that bucket streams through global memory in chunks.  Keys,
+    values and ranges bit-exact (with long runs of equal keys), the image on 12 tiles."""
+    base = wl.config_scene("small", n=40)
+    sc = base.subset(np.tile(np.arange(40), 4000))
+    cam = wl.config_camera("small", width=256, height=256)
+    plan = oracle.frame_plan(cam.width, cam.height)
+    tiles = np.random.default_rng(5).choice(plan.n_tiles, 12, replace=False)
+    rep = run_parity(R, sc, cam, "fast", tiles=tiles)
+    assert rep["max_tile_entries"] > 16384, rep
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
