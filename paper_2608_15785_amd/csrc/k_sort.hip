@@ -34,6 +34,10 @@
 // Grids are sized for the workspace capacity; the entry count is read from
 // the workspace header on the device and tiles beyond it return at once, so
 // no host round trip sits between the front end and the sort.
+//
+// The fast path's frames of 2^8 .. 2^14 tiles take the top digit first and
+// the other three per bucket in LDS (the bucket sort below), which also
+// writes the tile ranges.
 #include "rgs_internal.h"
 
 namespace rgs {
