@@ -460,44 +460,51 @@ __device__ inline void bucket_span(const WsDev& ws, uint32_t n, uint32_t* s_span
 // (w R + r) 64 + l, with R = ceil(cnt / BK_THREADS) <= BK_ITEMS rounds, so
 // that all sixteen waves share the work.  pos[r] is the key's place when the
 // chunk is ordered by the digit at `shift` (ties in entry order), s_tot[d] the
-// chunk's count of digit d and s_bs[d] its first place.  Every thread calls it
-// (barriers).
+// chunk's count of digit d and s_bs[d] its first place.  s_match, 4096 words
+// of 64 bits, is scratch: the caller's LDS copy of the keys, which every
+// thread has read into k before the call.  Every thread calls it (barriers).
+//
+// The lanes of a round that share a digit are found through LDS rather than
+// with ballots: each lane ORs its bit into its digit's 64-bit mask in the
+// wave's row of s_match, reads the mask back (a wave's LDS accesses execute
+// in issue order), and the lowest lane of the digit clears it again.  Eight
+// ballots and their bit operations cost about 40 VALU instructions per
+// round, this a few VALU and three LDS accesses: the bucket kernel went from
+// 41.9 to 40.2 us at 1M / 1080p (the ballots took 4.2 us of each digit's
+// 7.7; the LDS round trips now take most of that).
 __device__ inline void bucket_rank(const uint32_t (&k)[BK_ITEMS], uint32_t cnt, uint32_t R, uint32_t shift,
                                    uint32_t (&pos)[BK_ITEMS], uint32_t* s_whist, uint32_t* s_tot, uint32_t* s_bs,
-                                   uint32_t* s_wtot) {
+                                   uint32_t* s_wtot, uint64_t* s_match) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
     // entries of this wave that exist: round r, lane l holds one when r < R and r * 64 + l < lim
     const int lim = __builtin_amdgcn_readfirstlane((int)cnt - (int)(wave * R * 64));
-    for (uint32_t i = tid; i < BK_WAVES * RADIX; i += BK_THREADS) s_whist[i] = 0;
+    __syncthreads();            // every key read: s_match may be overwritten
+    for (uint32_t i = tid; i < BK_WAVES * RADIX; i += BK_THREADS) {
+        s_whist[i] = 0;
+        s_match[i] = 0ull;
+    }
     __syncthreads();
     uint32_t* my_hist = s_whist + wave * RADIX;
+    uint64_t* my_match = s_match + wave * RADIX;
 #pragma unroll
     for (int r = 0; r < BK_ITEMS; ++r) {
         if ((uint32_t)r >= R) break;
-        // a wave's rounds read counters its lanes wrote in the round before
-        // (see the pass kernel); pos[r] holds the rank among the wave's keys
-        // of the same digit until the scan below.  The key passes through an
-        // empty asm so that the compiler does not start later rounds' ballots
-        // early: sixteen rounds of eight 64-bit masks would not fit the SGPRs.
+        // a wave's rounds read what its lanes wrote in the round before;
+        // pos[r] holds the rank among the wave's keys of the same digit until
+        // the scan below
         asm volatile("" ::: "memory");
-        uint32_t key = k[r];
-        asm volatile("" : "+v"(key));
         const bool valid = (int)lane < lim - r * 64;
-        const uint32_t d = (key >> shift) & (RADIX - 1);
-        uint32_t diff_lo = 0, diff_hi = 0;
-#pragma unroll
-        for (int b = 0; b < RADIX_BITS; ++b) {
-            const uint32_t spread = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
-            const uint64_t m = __ballot(spread != 0);
-            diff_lo = __builtin_amdgcn_bitop3_b32((uint32_t)m, spread, diff_lo, 0xBE);
-            diff_hi = __builtin_amdgcn_bitop3_b32((uint32_t)(m >> 32), spread, diff_hi, 0xBE);
-        }
-        const uint64_t vmask = __ballot(valid);
-        const uint32_t peers_lo = ~diff_lo & (uint32_t)vmask, peers_hi = ~diff_hi & (uint32_t)(vmask >> 32);
-        const uint32_t below = __builtin_amdgcn_mbcnt_hi(peers_hi, __builtin_amdgcn_mbcnt_lo(peers_lo, 0u));
+        const uint32_t d = (k[r] >> shift) & (RADIX - 1);
+        if (valid) atomicOr(&my_match[d], 1ull << lane);
+        const uint64_t peers = valid ? my_match[d] : 0ull;
+        const uint32_t below =
+            __builtin_amdgcn_mbcnt_hi((uint32_t)(peers >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)peers, 0u));
         const uint32_t prev = valid ? my_hist[d] : 0u;
         pos[r] = prev + below;
-        if (valid && below == 0) my_hist[d] = prev + (uint32_t)(__popc(peers_lo) + __popc(peers_hi));
+        if (valid && below == 0) {
+            my_hist[d] = prev + (uint32_t)__popcll(peers);
+            my_match[d] = 0ull;
+        }
     }
     __syncthreads();
     // digit d = tid: each wave's offset inside the chunk's digit run (all
@@ -530,9 +537,12 @@ template <bool FORCE>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin, const uint32_t* vin,
                                                             uint32_t* kout, uint32_t* vout, WsDev ws, uint32_t b_d,
                                                             uint32_t n_tiles) {
-    __shared__ uint32_t s_keys[BK_CAP];
+    __shared__ __align__(16) uint32_t s_keys[BK_CAP];
     __shared__ uint32_t s_vals[BK_CAP];
     __shared__ uint32_t s_whist[BK_WAVES * RADIX];
+    // the ranking's digit masks live in the keys' LDS while the keys are in registers
+    uint64_t* s_match = reinterpret_cast<uint64_t*>(s_keys);
+    static_assert(BK_WAVES * RADIX * 2 <= BK_CAP, "the masks fit the keys' LDS");
     __shared__ uint32_t s_tot[RADIX];
     __shared__ uint32_t s_bs[RADIX];
     __shared__ uint32_t s_base[RADIX];
@@ -565,7 +575,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin,
 #pragma unroll
             for (int r = 0; r < BK_ITEMS; ++r)
                 k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wkeys[r * 64] : 0u;
-            bucket_rank(k, cnt, R, 8 * q, pos, s_whist, s_tot, s_bs, s_wtot);
+            bucket_rank(k, cnt, R, 8 * q, pos, s_whist, s_tot, s_bs, s_wtot, s_match);
 #pragma unroll
             for (int r = 0; r < BK_ITEMS; ++r)
                 v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wvals[r * 64] : 0u;
@@ -629,7 +639,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin,
 #pragma unroll
             for (int r = 0; r < BK_ITEMS; ++r)
                 k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wkeys[r * 64] : 0u;
-            bucket_rank(k, ccnt, R, shift, pos, s_whist, s_tot, s_bs, s_wtot);
+            bucket_rank(k, ccnt, R, shift, pos, s_whist, s_tot, s_bs, s_wtot, s_match);
 #pragma unroll
             for (int r = 0; r < BK_ITEMS; ++r)
                 v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wvals[r * 64] : 0u;
