@@ -216,8 +216,20 @@ def frame_counts(R, ds, cam, path):
     return c
 
 
+def bucket_sorted(path, n_tiles):
+    """Whether the library sorts this frame's keys with the bucket sort (the top-digit radix
+    pass, then the other three digits per bucket in LDS, which also writes the tile ranges):
+    the fast path's 32-bit keys with 2^8 .. 2^14 tiles."""
+    b_t = max(1, int(np.ceil(np.log2(n_tiles))))
+    return path.split("/")[0] == "fast" and "no-key32" not in path.split("/") and 8 <= b_t <= 14
+
+
 def rooflines(path, counts, stage_ms, n, n_tiles):
     by = stage_bytes(path, n, counts["n_visible"], counts["n_entries"], n_tiles, counts["passes"])
+    bucket = bucket_sorted(path, n_tiles)
+    if bucket:
+        # the ranges stage holds only the rasterizers' schedule (read 8 B, write 4 B per tile)
+        by["ranges"] = 12 * n_tiles
     out = {}
     for s, b in by.items():
         ms = stage_ms.get(s, 0.0)
@@ -225,6 +237,10 @@ def rooflines(path, counts, stage_ms, n, n_tiles):
             gbs = b / (ms * 1e-3) / 1e9
             out[s] = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                           frac=round(gbs / HBM_PEAK_GBS, 4), bytes=int(b), ms=round(ms, 4))
+    if "sort" in out:
+        # Eq. sort_memory counts every pass; the bucket sort moves keys and values through
+        # HBM twice (the top-digit pass, then each bucket once) for the same four digits
+        out["sort"]["hbm_passes"] = 2 if bucket else counts["passes"]
     ms = stage_ms["raster"]
     ops = ops_per_pair(path)
     tops = counts["pairs"] * ops / (ms * 1e-3) / 1e12

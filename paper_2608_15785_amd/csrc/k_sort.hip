@@ -532,13 +532,77 @@ __device__ inline void bucket_rank(const uint32_t (&k)[BK_ITEMS], uint32_t cnt, 
     }
 }
 
+// Sorts m <= BK_CAP entries (keys ks, values vs) by key bits 0..23 in LDS,
+// three stable passes, and writes them to kd / vd.  The source may be the
+// destination (everything is in LDS before the first store).  Leaves the
+// sorted keys in s_keys.  Every thread calls it (barriers).
+__device__ inline void bucket_lds_sort(const uint32_t* ks, const uint32_t* vs, uint32_t* kd, uint32_t* vd,
+                                       uint32_t m, uint32_t* s_keys, uint32_t* s_vals, uint32_t* s_whist,
+                                       uint32_t* s_tot, uint32_t* s_bs, uint32_t* s_wtot, uint64_t* s_match) {
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
+    // Entry e is held in round r < R by (wave, lane) with e = (wave R + r) 64
+    // + lane, the layout of bucket_rank; the values are read after the
+    // ranking, which needs only the keys.  The bounds are wave-uniform counts
+    // against the lane index, so that no per-entry index stays live across
+    // the passes.
+    uint32_t k[BK_ITEMS], v[BK_ITEMS], pos[BK_ITEMS];
+    const uint32_t R = (m + BK_THREADS - 1) / BK_THREADS;
+    const uint32_t* wkeys = s_keys + wave * R * 64 + lane;
+    const uint32_t* wvals = s_vals + wave * R * 64 + lane;
+    const int lim = __builtin_amdgcn_readfirstlane((int)m - (int)(wave * R * 64));
+    for (uint32_t e = tid; e < m; e += BK_THREADS) {
+        s_keys[e] = ks[e];
+        s_vals[e] = vs[e];
+    }
+    __syncthreads();
+    for (int q = 0; q < BK_DIGITS; ++q) {
+#pragma unroll
+        for (int r = 0; r < BK_ITEMS; ++r)
+            k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wkeys[r * 64] : 0u;
+        bucket_rank(k, m, R, 8 * q, pos, s_whist, s_tot, s_bs, s_wtot, s_match);
+#pragma unroll
+        for (int r = 0; r < BK_ITEMS; ++r)
+            v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wvals[r * 64] : 0u;
+        __syncthreads();        // every entry read before any is moved
+#pragma unroll
+        for (int r = 0; r < BK_ITEMS; ++r)
+            if ((uint32_t)r < R && (int)lane < lim - r * 64) {
+                s_keys[pos[r]] = k[r];
+                s_vals[pos[r]] = v[r];
+            }
+        __syncthreads();
+    }
+    for (uint32_t e = tid; e < m; e += BK_THREADS) {
+        kd[e] = s_keys[e];
+        vd[e] = s_vals[e];
+    }
+}
+
+// The runs of the tiles in the sorted bucket [b0, b0 + cnt) of kout, read
+// back past the CU's vector cache.
+__device__ inline void bucket_ranges_global(const uint32_t* kout, uint32_t b0, uint32_t cnt, const WsDev& ws,
+                                            uint32_t b_d, uint32_t n_tiles) {
+    for (uint32_t e = threadIdx.x; e < cnt; e += BK_THREADS) {
+        const uint32_t t = ld_state(&kout[b0 + e]) >> b_d;
+        if (t >= n_tiles) {
+            atomicOr(&ws.header->error, 4u);
+            continue;
+        }
+        if (e == 0 || (ld_state(&kout[b0 + e - 1]) >> b_d) != t) ws.ranges[2 * t] = b0 + e;
+        if (e + 1 == cnt || (ld_state(&kout[b0 + e + 1]) >> b_d) != t) ws.ranges[2 * t + 1] = b0 + e + 1;
+    }
+}
+
 // FORCE: every bucket through the global-memory path (for tests).
 template <bool FORCE>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin, const uint32_t* vin,
                                                             uint32_t* kout, uint32_t* vout, WsDev ws, uint32_t b_d,
                                                             uint32_t n_tiles) {
-    __shared__ __align__(16) uint32_t s_keys[BK_CAP];
-    __shared__ uint32_t s_vals[BK_CAP];
+    // keys and values of up to BK_CAP entries; for a two-run merge, the keys
+    // of up to 2 BK_CAP entries across both arrays
+    __shared__ __align__(16) uint32_t s_lds[2 * BK_CAP];
+    uint32_t* s_keys = s_lds;
+    uint32_t* s_vals = s_lds + BK_CAP;
     __shared__ uint32_t s_whist[BK_WAVES * RADIX];
     // the ranking's digit masks live in the keys' LDS while the keys are in registers
     uint64_t* s_match = reinterpret_cast<uint64_t*>(s_keys);
@@ -553,57 +617,71 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin,
     uint32_t b0, cnt;
     bucket_span(ws, n, s_span, s_wtot, b0, cnt);
     if (cnt == 0) return;
-    // Entry e of a chunk in LDS is held in round r < R by (wave, lane) with
-    // e = (wave R + r) 64 + lane, the layout of bucket_rank; the values are
-    // read after the ranking, which needs only the keys.  The bounds are
-    // wave-uniform counts against the lane index, so that no per-entry index
-    // stays live across the passes.
-    uint32_t k[BK_ITEMS], v[BK_ITEMS], pos[BK_ITEMS];
 
-    if (!FORCE && cnt <= BK_CAP) {
-        // ---- the bucket in LDS: three stable passes ----
-        const uint32_t R = (cnt + BK_THREADS - 1) / BK_THREADS;
-        const uint32_t* wkeys = s_keys + wave * R * 64 + lane;
-        const uint32_t* wvals = s_vals + wave * R * 64 + lane;
-        const int lim = __builtin_amdgcn_readfirstlane((int)cnt - (int)(wave * R * 64));
-        for (uint32_t e = tid; e < cnt; e += BK_THREADS) {
-            s_keys[e] = kin[b0 + e];
-            s_vals[e] = vin[b0 + e];
-        }
-        __syncthreads();
-        for (int q = 0; q < BK_DIGITS; ++q) {
-#pragma unroll
-            for (int r = 0; r < BK_ITEMS; ++r)
-                k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wkeys[r * 64] : 0u;
-            bucket_rank(k, cnt, R, 8 * q, pos, s_whist, s_tot, s_bs, s_wtot, s_match);
-#pragma unroll
-            for (int r = 0; r < BK_ITEMS; ++r)
-                v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wvals[r * 64] : 0u;
-            __syncthreads();        // every entry read before any is moved
-#pragma unroll
-            for (int r = 0; r < BK_ITEMS; ++r)
-                if ((uint32_t)r < R && (int)lane < lim - r * 64) {
-                    s_keys[pos[r]] = k[r];
-                    s_vals[pos[r]] = v[r];
-                }
+    if (!FORCE && cnt <= 2 * BK_CAP) {
+        // ---- the bucket in LDS, or in two runs: each half sorted in LDS and
+        // written back in place, then the two merged ----
+        const uint32_t runs = cnt <= BK_CAP ? 1u : 2u;
+        const uint32_t cA = runs == 1 ? cnt : (cnt + 1) / 2, cB = cnt - cA;
+        for (uint32_t h = 0; h < runs; ++h) {
+            const uint32_t o = h ? cA : 0u, m = h ? cB : cA;
+            uint32_t* kd = runs == 1 ? kout : const_cast<uint32_t*>(kin);
+            uint32_t* vd = runs == 1 ? vout : const_cast<uint32_t*>(vin);
+            bucket_lds_sort(kin + b0 + o, vin + b0 + o, kd + b0 + o, vd + b0 + o, m, s_keys, s_vals, s_whist,
+                            s_tot, s_bs, s_wtot, s_match);
             __syncthreads();
         }
-        // sorted: write the bucket and its tiles' runs
-        for (uint32_t e = tid; e < cnt; e += BK_THREADS) {
-            const uint32_t key = s_keys[e];
-            kout[b0 + e] = key;
-            vout[b0 + e] = s_vals[e];
-            const uint32_t t = key >> b_d;
-            if (t >= n_tiles) {          // only after a failed front end
-                atomicOr(&ws.header->error, 4u);
-                continue;
+        if (runs == 1) {
+            // the tiles' runs, from the sorted keys still in LDS
+            for (uint32_t e = tid; e < cnt; e += BK_THREADS) {
+                const uint32_t t = s_keys[e] >> b_d;
+                if (t >= n_tiles) {          // only after a failed front end
+                    atomicOr(&ws.header->error, 4u);
+                    continue;
+                }
+                if (e == 0 || (s_keys[e - 1] >> b_d) != t) ws.ranges[2 * t] = b0 + e;
+                if (e + 1 == cnt || (s_keys[e + 1] >> b_d) != t) ws.ranges[2 * t + 1] = b0 + e + 1;
             }
-            if (e == 0 || (s_keys[e - 1] >> b_d) != t) ws.ranges[2 * t] = b0 + e;
-            if (e + 1 == cnt || (s_keys[e + 1] >> b_d) != t) ws.ranges[2 * t + 1] = b0 + e + 1;
+            return;
         }
+        // both runs' keys into LDS, read past the CU's vector cache (it may
+        // hold the first run's lines from before they were sorted)
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        for (uint32_t e = tid; e < cnt; e += BK_THREADS) s_lds[e] = ld_state(&kin[b0 + e]);
+        __syncthreads();
+        // Merge path: thread t writes outputs [t S, (t + 1) S).  Its first
+        // output takes i entries from A and o - i from B, i the least index
+        // with A[i] > B[o - i - 1]; then the two are merged sequentially, A
+        // first on equal keys (A holds the earlier entries: stable).
+        const uint32_t* A = s_lds;
+        const uint32_t* Bk = s_lds + cA;
+        const uint32_t S = (cnt + BK_THREADS - 1) / BK_THREADS;
+        const uint32_t o0 = tid * S, o1 = min(o0 + S, cnt);
+        if (o0 < cnt) {
+            uint32_t lo = o0 > cB ? o0 - cB : 0u, hi = min(o0, cA);
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) / 2;
+                if (A[mid] <= Bk[o0 - mid - 1]) lo = mid + 1;
+                else hi = mid;
+            }
+            uint32_t ia = lo, ib = o0 - lo;
+            for (uint32_t o = o0; o < o1; ++o) {
+                const bool take_a = ib >= cB || (ia < cA && A[ia] <= Bk[ib]);
+                const uint32_t src = take_a ? ia : cA + ib;
+                kout[b0 + o] = take_a ? A[ia] : Bk[ib];
+                vout[b0 + o] = ld_state(&vin[b0 + src]);
+                if (take_a) ++ia;
+                else ++ib;
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        bucket_ranges_global(kout, b0, cnt, ws, b_d, n_tiles);
         return;
     }
 
+    uint32_t k[BK_ITEMS], v[BK_ITEMS], pos[BK_ITEMS];
     // ---- a bucket larger than the LDS ----
     // Each of the three passes streams it through global memory in chunks of
     // BK_CAP: a histogram sweep, then the chunks in order, each ranked in LDS
@@ -662,15 +740,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin,
             __syncthreads();
         }
     }
-    for (uint32_t e = tid; e < cnt; e += BK_THREADS) {
-        const uint32_t t = ld_state(&kout[b0 + e]) >> b_d;
-        if (t >= n_tiles) {
-            atomicOr(&ws.header->error, 4u);
-            continue;
-        }
-        if (e == 0 || (ld_state(&kout[b0 + e - 1]) >> b_d) != t) ws.ranges[2 * t] = b0 + e;
-        if (e + 1 == cnt || (ld_state(&kout[b0 + e + 1]) >> b_d) != t) ws.ranges[2 * t + 1] = b0 + e + 1;
-    }
+    bucket_ranges_global(kout, b0, cnt, ws, b_d, n_tiles);
 }
 
 bool bucket_sort_applies(const FrameDev& f, uint32_t key_bytes) {

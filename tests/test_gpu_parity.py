@@ -112,18 +112,20 @@ def test_equal_keys_keep_index_order(R, path):
     run_parity(R, sc, wl.config_camera("small", width=128, height=96), path)
 
 
-def test_bucket_larger_than_lds(R):
-    """4000 copies of 40 Gaussians at 256x256.  The frame has 256 tiles, so each of the fast
-    sort's buckets holds one tile, and the most covered tile gets more entries than a bucket
-    the LDS can hold (16384): that bucket streams through global memory in chunks.  Keys,
+@pytest.mark.parametrize("copies", [4000, 7000])
+def test_bucket_larger_than_lds(R, copies):
+    """Copies of 40 Gaussians at 256x256.  The frame has 256 tiles, so each of the fast sort's
+    buckets holds one tile, and the most covered tiles get more entries than the LDS holds
+    (16384): with 4000 copies 20000 each, sorted as two runs in LDS and merged; with 7000
+    copies 35000 each, more than two runs, streamed through global memory in chunks.  Keys,
     values and ranges bit-exact (with long runs of equal keys), the image on 12 tiles."""
     base = wl.config_scene("small", n=40)
-    sc = base.subset(np.tile(np.arange(40), 4000))
+    sc = base.subset(np.tile(np.arange(40), copies))
     cam = wl.config_camera("small", width=256, height=256)
     plan = oracle.frame_plan(cam.width, cam.height)
     tiles = np.random.default_rng(5).choice(plan.n_tiles, 12, replace=False)
     rep = run_parity(R, sc, cam, "fast", tiles=tiles)
-    assert rep["max_tile_entries"] > 16384, rep
+    assert rep["max_tile_entries"] > (16384 if copies == 4000 else 2 * 16384), rep
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
