@@ -534,11 +534,14 @@ __device__ inline void bucket_rank(const uint32_t (&k)[BK_ITEMS], uint32_t cnt, 
 
 // Sorts m <= BK_CAP entries (keys ks, values vs) by key bits 0..23 in LDS,
 // three stable passes, and writes them to kd / vd.  The source may be the
-// destination (everything is in LDS before the first store).  Leaves the
-// sorted keys in s_keys.  Every thread calls it (barriers).
+// destination (everything is in LDS before the first store).  With `runs`,
+// the keys are a whole bucket starting at entry b0 of the frame, and the
+// tiles' runs go to ws.ranges as they are written.  Every thread calls it
+// (barriers).
 __device__ inline void bucket_lds_sort(const uint32_t* ks, const uint32_t* vs, uint32_t* kd, uint32_t* vd,
                                        uint32_t m, uint32_t* s_keys, uint32_t* s_vals, uint32_t* s_whist,
-                                       uint32_t* s_tot, uint32_t* s_bs, uint32_t* s_wtot, uint64_t* s_match) {
+                                       uint32_t* s_tot, uint32_t* s_bs, uint32_t* s_wtot, uint64_t* s_match,
+                                       bool runs, const WsDev& ws, uint32_t b0, uint32_t b_d, uint32_t n_tiles) {
     const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid / 64;
     // Entry e is held in round r < R by (wave, lane) with e = (wave R + r) 64
     // + lane, the layout of bucket_rank; the values are read after the
@@ -573,8 +576,17 @@ __device__ inline void bucket_lds_sort(const uint32_t* ks, const uint32_t* vs, u
         __syncthreads();
     }
     for (uint32_t e = tid; e < m; e += BK_THREADS) {
-        kd[e] = s_keys[e];
+        const uint32_t key = s_keys[e];
+        kd[e] = key;
         vd[e] = s_vals[e];
+        if (!runs) continue;
+        const uint32_t t = key >> b_d;
+        if (t >= n_tiles) {          // only after a failed front end
+            atomicOr(&ws.header->error, 4u);
+            continue;
+        }
+        if (e == 0 || (s_keys[e - 1] >> b_d) != t) ws.ranges[2 * t] = b0 + e;
+        if (e + 1 == m || (s_keys[e + 1] >> b_d) != t) ws.ranges[2 * t + 1] = b0 + e + 1;
     }
 }
 
@@ -628,22 +640,10 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin,
             uint32_t* kd = runs == 1 ? kout : const_cast<uint32_t*>(kin);
             uint32_t* vd = runs == 1 ? vout : const_cast<uint32_t*>(vin);
             bucket_lds_sort(kin + b0 + o, vin + b0 + o, kd + b0 + o, vd + b0 + o, m, s_keys, s_vals, s_whist,
-                            s_tot, s_bs, s_wtot, s_match);
-            __syncthreads();
+                            s_tot, s_bs, s_wtot, s_match, runs == 1, ws, b0, b_d, n_tiles);
+            if (h + 1 < runs) __syncthreads();     // the first run's LDS before the second's loads
         }
-        if (runs == 1) {
-            // the tiles' runs, from the sorted keys still in LDS
-            for (uint32_t e = tid; e < cnt; e += BK_THREADS) {
-                const uint32_t t = s_keys[e] >> b_d;
-                if (t >= n_tiles) {          // only after a failed front end
-                    atomicOr(&ws.header->error, 4u);
-                    continue;
-                }
-                if (e == 0 || (s_keys[e - 1] >> b_d) != t) ws.ranges[2 * t] = b0 + e;
-                if (e + 1 == cnt || (s_keys[e + 1] >> b_d) != t) ws.ranges[2 * t + 1] = b0 + e + 1;
-            }
-            return;
-        }
+        if (runs == 1) return;
         // both runs' keys into LDS, read past the CU's vector cache (it may
         // hold the first run's lines from before they were sorted)
         __builtin_amdgcn_s_waitcnt(0);
