@@ -701,6 +701,10 @@ def main():
     for k in ("pairs_blended", "pairs_evaluated", "evaluated_per_blended", "ops_per_pair"):
         if k in rl:
             roofline[k] = rl[k]
+    if rl["unit"] == "Tops/s":
+        # the same figure against one wave64 instruction per SIMD per four cycles (no dual
+        # issue): 39.3 T lane-ops/s, half the peak above
+        roofline["frac_single_issue_peak"] = round(rl["achieved"] / (VALU_PEAK_TOPS / 2), 4)
     if counters.get("valu_wave_insts"):
         # from the profiling run that counted them (profiles/traffic_counters.txt): VALU wave
         # instructions per launch (SQ_INSTS_VALU), the launch's duration and the clock
