@@ -553,19 +553,28 @@ __device__ inline void bucket_lds_sort(const uint32_t* ks, const uint32_t* vs, u
     const uint32_t* wkeys = s_keys + wave * R * 64 + lane;
     const uint32_t* wvals = s_vals + wave * R * 64 + lane;
     const int lim = __builtin_amdgcn_readfirstlane((int)m - (int)(wave * R * 64));
-    for (uint32_t e = tid; e < m; e += BK_THREADS) {
-        s_keys[e] = ks[e];
-        s_vals[e] = vs[e];
-    }
-    __syncthreads();
+    // The first pass takes its keys and values straight from global memory in
+    // that layout, every load of a thread in flight at once (a load loop
+    // through LDS waits for each round trip in turn).
+#pragma unroll
+    for (int r = 0; r < BK_ITEMS; ++r)
+        k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? ks[(wave * R + r) * 64 + lane] : 0u;
     for (int q = 0; q < BK_DIGITS; ++q) {
+        if (q > 0) {
 #pragma unroll
-        for (int r = 0; r < BK_ITEMS; ++r)
-            k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wkeys[r * 64] : 0u;
+            for (int r = 0; r < BK_ITEMS; ++r)
+                k[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wkeys[r * 64] : 0u;
+        }
         bucket_rank(k, m, R, 8 * q, pos, s_whist, s_tot, s_bs, s_wtot, s_match);
+        if (q == 0) {
 #pragma unroll
-        for (int r = 0; r < BK_ITEMS; ++r)
-            v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wvals[r * 64] : 0u;
+            for (int r = 0; r < BK_ITEMS; ++r)
+                v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? vs[(wave * R + r) * 64 + lane] : 0u;
+        } else {
+#pragma unroll
+            for (int r = 0; r < BK_ITEMS; ++r)
+                v[r] = (uint32_t)r < R && (int)lane < lim - r * 64 ? wvals[r * 64] : 0u;
+        }
         __syncthreads();        // every entry read before any is moved
 #pragma unroll
         for (int r = 0; r < BK_ITEMS; ++r)
