@@ -614,6 +614,26 @@ __device__ inline void bucket_ranges_global(const uint32_t* kout, uint32_t b0, u
     }
 }
 
+// dst[e] = src[e] for e < cnt, src read past the CU's vector cache, into LDS:
+// BK_LOAD_BATCH loads of a thread in flight before its LDS stores.  Every
+// thread calls it.
+constexpr uint32_t BK_LOAD_BATCH = 8;
+__device__ inline void bucket_stage(const uint32_t* src, uint32_t cnt, uint32_t* dst) {
+    for (uint32_t e0 = threadIdx.x; e0 < cnt; e0 += BK_LOAD_BATCH * BK_THREADS) {
+        uint32_t t[BK_LOAD_BATCH];
+#pragma unroll
+        for (uint32_t j = 0; j < BK_LOAD_BATCH; ++j) {
+            const uint32_t e = e0 + j * BK_THREADS;
+            t[j] = e < cnt ? ld_state(&src[e]) : 0u;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < BK_LOAD_BATCH; ++j) {
+            const uint32_t e = e0 + j * BK_THREADS;
+            if (e < cnt) dst[e] = t[j];
+        }
+    }
+}
+
 // FORCE: every bucket through the global-memory path (for tests).
 template <bool FORCE>
 __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin, const uint32_t* vin,
@@ -657,7 +677,7 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin,
         // hold the first run's lines from before they were sorted)
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        for (uint32_t e = tid; e < cnt; e += BK_THREADS) s_lds[e] = ld_state(&kin[b0 + e]);
+        bucket_stage(kin + b0, cnt, s_lds);
         __syncthreads();
         // Merge path: thread t writes outputs [t S, (t + 1) S).  Its first
         // output takes i entries from A and o - i from B, i the least index
@@ -675,13 +695,25 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin,
                 else hi = mid;
             }
             uint32_t ia = lo, ib = o0 - lo;
-            for (uint32_t o = o0; o < o1; ++o) {
-                const bool take_a = ib >= cB || (ia < cA && A[ia] <= Bk[ib]);
-                const uint32_t src = take_a ? ia : cA + ib;
-                kout[b0 + o] = take_a ? A[ia] : Bk[ib];
-                vout[b0 + o] = ld_state(&vin[b0 + src]);
-                if (take_a) ++ia;
-                else ++ib;
+            // BK_LOAD_BATCH outputs at a time: their value loads in flight together
+            for (uint32_t ob = o0; ob < o1; ob += BK_LOAD_BATCH) {
+                uint32_t key[BK_LOAD_BATCH], val[BK_LOAD_BATCH];
+#pragma unroll
+                for (uint32_t j = 0; j < BK_LOAD_BATCH; ++j) {
+                    if (ob + j >= o1) break;
+                    const bool take_a = ib >= cB || (ia < cA && A[ia] <= Bk[ib]);
+                    const uint32_t src = take_a ? ia : cA + ib;
+                    key[j] = take_a ? A[ia] : Bk[ib];
+                    val[j] = ld_state(&vin[b0 + src]);
+                    if (take_a) ++ia;
+                    else ++ib;
+                }
+#pragma unroll
+                for (uint32_t j = 0; j < BK_LOAD_BATCH; ++j) {
+                    if (ob + j >= o1) break;
+                    kout[b0 + ob + j] = key[j];
+                    vout[b0 + ob + j] = val[j];
+                }
             }
         }
         __builtin_amdgcn_s_waitcnt(0);
@@ -706,18 +738,25 @@ __global__ __launch_bounds__(BK_THREADS) void k_bucket_sort(const uint32_t* kin,
         uint32_t* vd = q == 1 ? const_cast<uint32_t*>(vin) : vout;
         if (tid < RADIX) s_tot[tid] = 0;
         __syncthreads();
-        for (uint32_t i = tid; i < cnt; i += BK_THREADS)
-            atomicAdd(&s_tot[(ld_state(&ks[b0 + i]) >> shift) & (RADIX - 1)], 1u);
+        for (uint32_t i0 = tid; i0 < cnt; i0 += BK_LOAD_BATCH * BK_THREADS) {
+            uint32_t t[BK_LOAD_BATCH];
+#pragma unroll
+            for (uint32_t j = 0; j < BK_LOAD_BATCH; ++j) {
+                const uint32_t i = i0 + j * BK_THREADS;
+                t[j] = i < cnt ? ld_state(&ks[b0 + i]) : 0u;
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < BK_LOAD_BATCH; ++j)
+                if (i0 + j * BK_THREADS < cnt) atomicAdd(&s_tot[(t[j] >> shift) & (RADIX - 1)], 1u);
+        }
         __syncthreads();
         const uint32_t base = digit_exclusive_scan(tid < RADIX ? s_tot[tid] : 0u, s_wtot);
         if (tid < RADIX) s_base[tid] = base;
         __syncthreads();
         for (uint32_t c0 = 0; c0 < cnt; c0 += BK_CAP) {
             const uint32_t ccnt = min(BK_CAP, cnt - c0);
-            for (uint32_t e = tid; e < ccnt; e += BK_THREADS) {
-                s_keys[e] = ld_state(&ks[b0 + c0 + e]);
-                s_vals[e] = ld_state(&vs[b0 + c0 + e]);
-            }
+            bucket_stage(ks + b0 + c0, ccnt, s_keys);
+            bucket_stage(vs + b0 + c0, ccnt, s_vals);
             __syncthreads();
             const uint32_t R = (ccnt + BK_THREADS - 1) / BK_THREADS;
             const uint32_t* wkeys = s_keys + wave * R * 64 + lane;
