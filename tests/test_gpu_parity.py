@@ -225,6 +225,21 @@ def test_4k_keys_and_sampled_tiles(R, path, pose):
 
 
 @pytest.mark.parametrize("path", ["plain", "fast"])
+@pytest.mark.parametrize("W,H", [(2560, 1440), (2048, 2048)])
+def test_two_schedule_chunks_keys_and_sampled_tiles(R, path, W, H):
+    """The 1M scene at 2560x1440 (14400 tiles) and 2048x2048 (16384, the most the fast path's
+    bucket sort and tile schedule take): b_t = 14, 64 tiles per bucket, and the schedule in two
+    chunks of 8192 tiles.  Every key bit-exact, the order checked, 32 sampled tiles and the last."""
+    sc = wl.config_scene("1080p")
+    cam = wl.config_camera("1080p", width=W, height=H)
+    plan = oracle.frame_plan(cam.width, cam.height)
+    assert plan.b_t == 14 and ORDER_CHUNK < plan.n_tiles <= ORDER_MAX_TILES
+    tiles = np.concatenate([np.random.default_rng(W + H).choice(plan.n_tiles, 32, replace=False),
+                            [plan.n_tiles - 1]])
+    run_parity(R, sc, cam, path, tiles=tiles)
+
+
+@pytest.mark.parametrize("path", ["plain", "fast"])
 @pytest.mark.parametrize("pose", [0, 37])
 def test_720p_keys_and_sampled_tiles(R, path, pose):
     """The serving mix's 1280x720 class (half of its requests): the 1M scene on its serving
