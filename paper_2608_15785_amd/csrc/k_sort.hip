@@ -418,9 +418,11 @@ void launch_sort(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t key
 //     is tile >> (b_t - 8), so a bucket holds 2^(b_t - 8) whole tiles;
 //   * one workgroup per bucket then takes the bucket's three remaining digits
 //     (bits 0..23), least significant first, each a stable counting pass
-//     ranked with wave64 ballots as above.  A bucket of at most BK_CAP entries
-//     stays in LDS for all three; a larger one streams through global memory
-//     in chunks of BK_CAP, one stable pass at a time;
+//     ranked through per-wave LDS digit masks (bucket_rank).  A bucket of at
+//     most BK_CAP entries stays in LDS for all three; one of at most 2 BK_CAP
+//     is sorted as two runs in LDS, each written back in place, and the two
+//     merged; a larger one streams through global memory in chunks of BK_CAP,
+//     one stable pass at a time;
 //   * the same workgroup, holding its bucket sorted, writes its tiles' ranges.
 // Every pass is stable and the top digit is taken first, then bits 0..23
 // least significant first; as a stable sort on the top digit followed by a
@@ -469,9 +471,10 @@ __device__ inline void bucket_span(const WsDev& ws, uint32_t n, uint32_t* s_span
 // wave's row of s_match, reads the mask back (a wave's LDS accesses execute
 // in issue order), and the lowest lane of the digit clears it again.  Eight
 // ballots and their bit operations cost about 40 VALU instructions per
-// round, this a few VALU and three LDS accesses: the bucket kernel went from
-// 41.9 to 40.2 us at 1M / 1080p (the ballots took 4.2 us of each digit's
-// 7.7; the LDS round trips now take most of that).
+// round, this a few VALU and five LDS accesses (the OR, the mask read, the
+// count's read and write, the clear): the bucket kernel went from 41.9 to
+// 40.2 us at 1M / 1080p.  At random digit addresses the rounds are bound by
+// the LDS's bank conflicts, about half of its busy cycles.
 __device__ inline void bucket_rank(const uint32_t (&k)[BK_ITEMS], uint32_t cnt, uint32_t R, uint32_t shift,
                                    uint32_t (&pos)[BK_ITEMS], uint32_t* s_whist, uint32_t* s_tot, uint32_t* s_bs,
                                    uint32_t* s_wtot, uint64_t* s_match) {
@@ -899,10 +902,10 @@ void launch_ranges(hipStream_t s, const FrameDev& f, const WsDev& ws, uint32_t k
 // One workgroup per chunk, no atomics: thread i takes tiles i, i + 1024, ...
 // (round k), each wave ranks the tiles of one round within their class with
 // five ballots (as the radix passes rank digits), and a scan over the
-// (class, round, wave) counts places them.  The kernel takes about 10 us,
-// nearly all of it latency (the loads of the ranges, three barriers, the
-// stores); at 1M / 1080p the fast rasterizer went from 0.123 to 0.106 ms,
-// the plain one from 0.646 to 0.567 ms.
+// (class, round, wave) counts places them.  The kernel takes about 10 us at
+// 1M / 1080p: about 3 us to load the ranges, 2.4 us of ballots on the four
+// SIMDs of a single CU, 1 us of scan and 2 us of stores; the fast rasterizer
+// went from 0.123 to 0.106 ms, the plain one from 0.646 to 0.567 ms.
 
 constexpr uint32_t ORDER_THREADS = 1024;
 constexpr uint32_t ORDER_WAVES = ORDER_THREADS / 64;
